@@ -1,0 +1,233 @@
+/*
+ * symtensor: contraction of U(1)- and SU(2)-symmetric tensors stored as
+ * charge-sector blocks, on AMD Instinct MI355X (gfx950).
+ *
+ * Terms follow the thesis (Singh, "Tensor Network States and Algorithms in the
+ * presence of Abelian and non-Abelian Symmetries", arXiv:1203.2222):
+ *
+ *  - A tensor is a multidimensional array whose indices ("legs") each carry a
+ *    direction, in or out (section "Tensors as linear maps").
+ *  - A symmetric tensor is stored by its degeneracy tensors ("blocks"): one
+ *    dense block per allowed tuple of leg labels, plus, for SU(2), one per
+ *    intermediate spin of its fusion tree (section "Block structure of
+ *    SU(2)-invariant tensors", eq:datak).  The structural tensors are never
+ *    stored.
+ *  - A leg is described by its spectrum: labels with their degeneracies
+ *    (eq:decoV).  For U(1) a label is a charge q; for SU(2) it is twice the
+ *    spin, 2j.  Labels are strictly ascending.
+ *  - U(1) charge rule: a block is allowed when sum(q, out legs) minus
+ *    sum(q, in legs) equals the tensor's total charge (0 for an invariant
+ *    tensor).  This is the invariance condition eq:Tinv with exp(i r q) on
+ *    every leg.
+ *  - SU(2) tensors here have rank 4 and one of three trees (eq:cob1, eq:cob2,
+ *    eq:deco41): OPERATOR (in,in,out,out), (1,2)->e->(3,4); LEFT
+ *    (in,in,in,out), {1,2->e; e,3->4}; RIGHT (in,in,in,out), {2,3->f; 1,f->4}.
+ *    Every node obeys the fusion rule eq:fusionrules.
+ *
+ * Data layout ("sector-major for a bipartition").  A tensor declares n_row:
+ * its first n_row legs are row legs, the rest column legs.  Its data is one
+ * row-major matrix per sector, packed back to back in ascending sector order
+ * with no padding:
+ *  - U(1): the sector of a row-label tuple is the charge flowing in through
+ *    the row legs, s = sum(q, in row legs) - sum(q, out row legs); a column
+ *    tuple belongs to s = sum(q, out col legs) - sum(q, in col legs) - qtot.
+ *  - SU(2) (n_row = 2, OPERATOR or LEFT tree): the sector is the intermediate
+ *    spin e; a row pair (j1,j2) appears in every sector e it can fuse to.
+ *  - Inside a sector, rows run over row-label tuples in lexicographic order,
+ *    each spanning the row-major product of its row-leg degeneracies; columns
+ *    likewise over column-label tuples.  This is the fuse of eq:fuse with the
+ *    last index fastest.
+ * With n_row = 0 or n_row = rank there is a single sector and the data is the
+ * canonical block list: blocks in lexicographic order of their label tuple
+ * (SU(2): intermediate spin last), each block row-major, back to back.
+ *
+ * Contraction (eq:tensormult, the five steps eq:multi1-eq:multi5, and the
+ * block-wise multiply eq:blockmult): C = A . B over A's legs axesA[i] paired
+ * with B's legs axesB[i].  Paired legs must carry identical spectra and
+ * opposite arrows.  C's legs are A's free legs (in order) then B's free legs;
+ * C has n_row = number of A's free legs and qtot = qtot(A) + qtot(B).
+ * Internally each operand is fused (permute + reshape) into per-sector
+ * matrices, one GEMM runs per sector, and the product is split into C.
+ *
+ * Memory.  Tensor handles describe data they do not own: the caller passes a
+ * device pointer (torch storage in the Python binding) and keeps it alive.
+ * The library allocates its own workspaces through the context's allocator
+ * callback (hipMalloc when none is given) and keeps them with the cached plan.
+ *
+ * Errors.  Every call returns a status; nothing throws across the ABI.  All
+ * validation happens on the host before any launch, so a failed call leaves
+ * outputs untouched.  sym_last_error() returns a thread-local message.
+ *
+ * Streams.  Kernels are launched on the hipStream_t passed as `stream` (NULL =
+ * the null stream).  The library never synchronises a stream except in
+ * sym_graph_* calls and sym_sync.
+ */
+#ifndef SYMTENSOR_H
+#define SYMTENSOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SYM_OK = 0,
+    SYM_E_ARG = 1,          /* null pointer, bad rank, bad axes or permutation      */
+    SYM_E_SPECTRUM = 2,     /* contracted legs carry different spectra              */
+    SYM_E_ARROW = 3,        /* contracted legs with the same arrow; SU(2) tree arrows */
+    SYM_E_CHARGE = 4,       /* labels not strictly ascending, negative 2j           */
+    SYM_E_DTYPE = 5,        /* unsupported data type combination                    */
+    SYM_E_NOMEM = 6,        /* allocator returned NULL                               */
+    SYM_E_HIP = 7,          /* a HIP runtime call failed                             */
+    SYM_E_UNSUPPORTED = 8,  /* valid request outside what this library implements    */
+    SYM_E_MISMATCH = 9      /* output handle does not describe the expected result  */
+};
+
+enum { SYM_U1 = 0, SYM_SU2 = 1 };                  /* group                       */
+enum { SYM_F32 = 0, SYM_BF16 = 1 };                /* element type                */
+enum { SYM_IN = 0, SYM_OUT = 1 };                  /* leg direction               */
+enum { SYM_TREE_NONE = 0, SYM_TREE_OPERATOR = 1,   /* SU(2) coupling tree         */
+       SYM_TREE_LEFT = 2, SYM_TREE_RIGHT = 3 };
+
+#define SYM_MAX_RANK 8
+
+/* One leg: n labels (ascending), their degeneracies (>= 1) and the arrow.
+ * The arrays are copied by sym_tensor_create. */
+typedef struct {
+    int32_t n;
+    const int32_t* label;   /* U(1): charge q;  SU(2): 2j >= 0 */
+    const int64_t* deg;
+    int32_t arrow;          /* SYM_IN or SYM_OUT */
+} sym_leg;
+
+typedef struct sym_ctx sym_ctx;
+typedef struct sym_tensor sym_tensor;
+typedef struct sym_graph sym_graph;
+
+typedef void* (*sym_alloc_fn)(size_t bytes, void* user);
+typedef void (*sym_free_fn)(void* ptr, void* user);
+
+/* Context: allocator bridge and plan cache.  alloc/free may be NULL (then
+ * hipMalloc/hipFree).  Creating a context touches no GPU. */
+int32_t sym_ctx_create(sym_alloc_fn alloc, sym_free_fn free_fn, void* user, sym_ctx** out);
+void sym_ctx_destroy(sym_ctx* ctx);
+/* Drop every cached plan and its workspace. */
+int32_t sym_ctx_clear(sym_ctx* ctx);
+
+/* Describe a symmetric tensor (section "Block structure"; eq:datak).
+ * group: SYM_U1 / SYM_SU2; rank <= SYM_MAX_RANK (SU(2): 4); n_row in [0, rank]
+ * (SU(2): 0, 2 or 4, and 2 only on the OPERATOR or LEFT tree); tree: SU(2)
+ * tree id (SYM_TREE_NONE for U(1)); qtot: U(1) total charge (0 = invariant;
+ * must be 0 for SU(2)); dtype: SYM_F32 or SYM_BF16; data: device pointer to
+ * numel elements in the layout described above, borrowed (may be NULL and set
+ * later with sym_tensor_set_data).  Pure host work. */
+int32_t sym_tensor_create(sym_ctx* ctx, int32_t group, int32_t rank, const sym_leg* legs,
+                          int32_t n_row, int32_t tree, int32_t qtot, int32_t dtype,
+                          void* data, sym_tensor** out);
+void sym_tensor_destroy(sym_tensor* t);
+int32_t sym_tensor_set_data(sym_tensor* t, void* data);
+int32_t sym_tensor_numel(const sym_tensor* t, int64_t* numel);
+int32_t sym_tensor_num_blocks(const sym_tensor* t, int64_t* n_blocks);
+int32_t sym_tensor_num_sectors(const sym_tensor* t, int64_t* n_sectors);
+/* Block i in canonical order: its labels[rank], intermediate spin (-1 for
+ * U(1)), element offset of its first entry in the data, shape[rank] and the
+ * element stride of each leg inside the data (any output may be NULL). */
+int32_t sym_tensor_block_info(const sym_tensor* t, int64_t i, int32_t* labels, int32_t* internal,
+                              int64_t* offset, int64_t* shape, int64_t* strides);
+/* Sector i: its label (U(1) charge or SU(2) 2e), rows, cols, element offset. */
+int32_t sym_tensor_sector_info(const sym_tensor* t, int64_t i, int32_t* label, int64_t* rows,
+                               int64_t* cols, int64_t* offset);
+
+/* PERMUTE + FUSE (eq:permute, eq:fuse, eq:split; chapter "Implementation of
+ * non-Abelian symmetries II", PERMUTE).  out's legs are in's legs reordered as
+ * out.leg[i] = in.leg[perm[i]], with n_row_out row legs and element type
+ * dtype_out (F32->BF16 rounds to nearest even).
+ *  - U(1): any permutation and bipartition; a pure block gather.
+ *  - SU(2): perm = identity changes only the layout; perm = (0,2,1,3) on a
+ *    LEFT-tree tensor recouples it to the RIGHT tree on legs (1,3,2,4) by the
+ *    F-move (eq:fmove2, F from 6j symbols by Racah's formula, FP64) followed
+ *    by the swap of legs 2 and 3 with phase (-1)^(j2+j3-f) (eq:perm11); the
+ *    output then has n_row_out = 0 or 4 (canonical block list).
+ * sym_permute_fuse_output creates the handle of the result (data may be
+ * NULL).  sym_permute_fuse writes into out, which must describe exactly that
+ * result; in and out must not overlap. */
+int32_t sym_permute_fuse_output(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm,
+                                int32_t n_row_out, int32_t dtype_out, void* data, sym_tensor** out);
+int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t n_row_out,
+                         sym_tensor* out, void* stream);
+
+/* Contraction C = A . B (see above).  compute: SYM_F32 (FP32 MFMA, FP32
+ * accumulate) or SYM_BF16 (operands rounded to BF16 on the device, BF16 MFMA,
+ * FP32 accumulate, FP32 output).  C must have dtype F32.  SU(2): A must be an
+ * OPERATOR tensor contracted on legs (2,3) with legs (0,1) of an OPERATOR or
+ * LEFT tensor B; C gets B's tree.  sym_contract_output creates C's handle
+ * (data may be NULL).  The plan (block matching, offsets, tile list) is built
+ * on the first call and cached in the context. */
+int32_t sym_contract_output(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
+                            const int32_t* axesA, const int32_t* axesB, void* data, sym_tensor** C);
+int32_t sym_contract(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
+                     const int32_t* axesA, const int32_t* axesB, int32_t compute, sym_tensor* C,
+                     void* stream);
+
+/* Backward of C = A . B for a cotangent dC (same description as C): per
+ * sector dA_s = dC_s B_s^T and dB_s = A_s^T dC_s, split back into A's and B's
+ * layouts (the adjoint of eq:blockmult).  dA or dB may be NULL to skip it;
+ * given ones must describe A and B (dtype F32). */
+int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B,
+                              const sym_tensor* dC, int32_t n, const int32_t* axesA,
+                              const int32_t* axesB, int32_t compute, sym_tensor* dA, sym_tensor* dB,
+                              void* stream);
+
+/* count independent contractions C[i] = A[i] . B[i] with the same axes: all
+ * fuses in one launch, every sector GEMM of every member in one persistent
+ * grouped-GEMM launch, all splits in one launch. */
+int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
+                             const sym_tensor* const* B, int32_t n, const int32_t* axesA,
+                             const int32_t* axesB, int32_t compute, sym_tensor* const* C,
+                             void* stream);
+
+/* Useful work of a contraction: sum over sectors of 2 M_s N_s K_s. */
+int32_t sym_contract_flops(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
+                           const int32_t* axesA, const int32_t* axesB, int64_t* flops);
+
+/* HIP graph of a batched contraction: captured once on `stream` (the plan is
+ * built first, outside the capture), replayed with sym_graph_launch.  The
+ * tensors' data pointers must stay valid and unchanged while the graph lives. */
+int32_t sym_graph_create_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
+                                 const sym_tensor* const* B, int32_t n, const int32_t* axesA,
+                                 const int32_t* axesB, int32_t compute, sym_tensor* const* C,
+                                 void* stream, sym_graph** out);
+int32_t sym_graph_launch(sym_graph* g, void* stream);
+void sym_graph_destroy(sym_graph* g);
+
+/* Kernel timing of the most recent batched contraction on a context, when
+ * enabled with sym_ctx_set_timing(ctx, 1): HIP events recorded on the launch
+ * stream around each phase; times in milliseconds, valid after the stream is
+ * synchronised.  phase: 0 = fuse, 1 = grouped GEMM, 2 = split. */
+int32_t sym_ctx_set_timing(sym_ctx* ctx, int32_t enable);
+int32_t sym_ctx_phase_ms(sym_ctx* ctx, int32_t phase, float* ms);
+
+/* Tile configuration the grouped GEMM uses for a compute type, and the
+ * autotuner's entry point: time every compiled tile variant on the plan of
+ * this contraction and keep the fastest (also written to the file named by
+ * SYM_TUNE_CACHE, when set). */
+int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
+                         const sym_tensor* const* B, int32_t n, const int32_t* axesA,
+                         const int32_t* axesB, int32_t compute, sym_tensor* const* C, void* stream,
+                         int32_t* best_variant);
+int32_t sym_ctx_set_variant(sym_ctx* ctx, int32_t compute, int32_t variant);
+int32_t sym_num_variants(int32_t compute, int32_t* count);
+
+/* SU(2) recoupling coefficient F^{jD jE}_{jA jB jC jJ} (eq:sixj), doubled
+ * spins, from the library's own FP64 tables.  Host only. */
+double sym_fmove_coeff(int32_t tjA, int32_t tjB, int32_t tjC, int32_t tjJ, int32_t tjD, int32_t tjE);
+
+const char* sym_last_error(void);
+const char* sym_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYMTENSOR_H */

@@ -1,0 +1,872 @@
+// C-ABI of the symtensor library: contexts, tensor handles, plan caches and
+// the host side of permute / contract / backward / batched / graph calls.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <functional>
+#include <sstream>
+
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+using namespace sym;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+#define HIP_CHECK(expr)                                                                    \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) throw Error(SYM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename F>
+int32_t guard(F&& f) {
+    try {
+        f();
+        return SYM_OK;
+    } catch (const Error& e) {
+        set_error(e.what());
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return SYM_E_NOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return SYM_E_ARG;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Buffer slots of a contraction launch.
+constexpr int kSlotWsIn = 0;    // fused operands (compute dtype)
+constexpr int kSlotWsOut = 1;   // GEMM outputs that still need a split (FP32)
+constexpr int kSlotUser = 2;    // user tensors from here on
+constexpr int kMaxBatch = (kMaxBufs - kSlotUser) / 3;
+
+struct ContractPlan {
+    int count = 0, compute = SYM_F32;
+    CopyProgram fuse[2];   // by source dtype (F32, BF16) -> compute dtype
+    GemmProgram gemm;
+    CopyProgram split;     // FP32 -> FP32
+    DevMemPtr ws_in, ws_out;
+    int grid = 1;
+    int64_t flops = 0;
+};
+
+struct BackwardPlan {
+    CopyProgram copy_in[2];
+    GemmProgram gemm;
+    CopyProgram split;
+    DevMemPtr ws_in, ws_out;
+    int grid = 1;
+};
+
+struct PermutePlan {
+    CopyProgram copy;
+    RecoupleProgram recouple;
+    bool is_recouple = false;
+};
+
+}  // namespace
+
+struct sym_tensor {
+    DescPtr d;
+    void* data = nullptr;
+};
+
+struct sym_ctx {
+    sym_alloc_fn alloc = nullptr;
+    sym_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    std::mutex mu;
+    std::unordered_map<std::string, std::shared_ptr<ContractPlan>> contract_plans;
+    std::unordered_map<std::string, std::shared_ptr<BackwardPlan>> backward_plans;
+    std::unordered_map<std::string, std::shared_ptr<PermutePlan>> permute_plans;
+    int variant[2] = {-1, -1};
+    int n_cu = 0;
+    bool timing = false;
+    bool events_ready = false;
+    hipEvent_t ev[4] = {};
+    std::unordered_map<std::string, int> tuned;   // plan key hash -> variant
+
+    Allocator allocator() {
+        return [this](size_t bytes) -> DevMemPtr {
+            auto m = std::make_shared<DevMem>();
+            const size_t b = std::max<size_t>(bytes, 256);
+            if (alloc) {
+                m->ptr = alloc(b, user);
+                sym_free_fn f = free_fn;
+                void* u = user;
+                m->release = [f, u](void* p) {
+                    if (f) f(p, u);
+                };
+            } else {
+                void* p = nullptr;
+                if (hipMalloc(&p, b) != hipSuccess) p = nullptr;
+                m->ptr = p;
+                m->release = [](void* q) { (void)hipFree(q); };
+            }
+            if (!m->ptr) throw Error(SYM_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+            m->bytes = b;
+            return m;
+        };
+    }
+
+    int cus() {
+        if (n_cu == 0) {
+            int dev = 0;
+            HIP_CHECK(hipGetDevice(&dev));
+            HIP_CHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+            if (n_cu <= 0) n_cu = 1;
+        }
+        return n_cu;
+    }
+
+    void ensure_events() {
+        if (events_ready) return;
+        for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
+        events_ready = true;
+    }
+};
+
+struct sym_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::shared_ptr<ContractPlan> plan;
+};
+
+namespace {
+
+std::vector<Leg> read_legs(int32_t rank, const sym_leg* legs) {
+    if (rank < 0 || rank > SYM_MAX_RANK) throw Error(SYM_E_ARG, "rank outside [0, SYM_MAX_RANK]");
+    if (rank > 0 && !legs) throw Error(SYM_E_ARG, "legs is NULL");
+    std::vector<Leg> out(static_cast<size_t>(rank));
+    for (int i = 0; i < rank; ++i) {
+        const sym_leg& l = legs[i];
+        if (l.n < 0 || (l.n > 0 && (!l.label || !l.deg))) throw Error(SYM_E_ARG, "leg arrays are NULL");
+        out[static_cast<size_t>(i)].label.assign(l.label, l.label + l.n);
+        out[static_cast<size_t>(i)].deg.assign(l.deg, l.deg + l.n);
+        out[static_cast<size_t>(i)].arrow = l.arrow;
+    }
+    return out;
+}
+
+struct PairInfo {
+    std::vector<int32_t> fa, fb, axa, axb;
+    std::vector<int32_t> perm_a, perm_b;   // A: fa ++ axa ; B: axb ++ fb
+};
+
+PairInfo check_pair(const Desc& A, const Desc& B, int32_t n, const int32_t* axesA, const int32_t* axesB) {
+    if (A.group != B.group) throw Error(SYM_E_ARG, "operands belong to different groups");
+    if (n < 0 || n > A.rank || n > B.rank) throw Error(SYM_E_ARG, "bad number of contracted legs");
+    if (n > 0 && (!axesA || !axesB)) throw Error(SYM_E_ARG, "axes are NULL");
+    PairInfo p;
+    std::vector<bool> ua(static_cast<size_t>(A.rank), false), ub(static_cast<size_t>(B.rank), false);
+    for (int i = 0; i < n; ++i) {
+        const int32_t a = axesA[i], b = axesB[i];
+        if (a < 0 || a >= A.rank || b < 0 || b >= B.rank || ua[static_cast<size_t>(a)] || ub[static_cast<size_t>(b)])
+            throw Error(SYM_E_ARG, "axes out of range or repeated");
+        ua[static_cast<size_t>(a)] = ub[static_cast<size_t>(b)] = true;
+        const Leg& la = A.legs[static_cast<size_t>(a)];
+        const Leg& lb = B.legs[static_cast<size_t>(b)];
+        if (!la.same_spectrum(lb)) throw Error(SYM_E_SPECTRUM, "contracted legs carry different spectra");
+        if (la.arrow == lb.arrow) throw Error(SYM_E_ARROW, "contracted legs must have opposite arrows");
+        p.axa.push_back(a);
+        p.axb.push_back(b);
+    }
+    for (int i = 0; i < A.rank; ++i)
+        if (!ua[static_cast<size_t>(i)]) p.fa.push_back(i);
+    for (int i = 0; i < B.rank; ++i)
+        if (!ub[static_cast<size_t>(i)]) p.fb.push_back(i);
+    if (static_cast<int>(p.fa.size() + p.fb.size()) > SYM_MAX_RANK) throw Error(SYM_E_ARG, "result rank too large");
+    p.perm_a = p.fa;
+    p.perm_a.insert(p.perm_a.end(), p.axa.begin(), p.axa.end());
+    p.perm_b = p.axb;
+    p.perm_b.insert(p.perm_b.end(), p.fb.begin(), p.fb.end());
+    if (A.group == SYM_SU2) {
+        const bool ok = A.tree == SYM_TREE_OPERATOR && n == 2 && p.axa == std::vector<int32_t>{2, 3} &&
+                        p.axb == std::vector<int32_t>{0, 1} &&
+                        (B.tree == SYM_TREE_OPERATOR || B.tree == SYM_TREE_LEFT);
+        if (!ok)
+            throw Error(SYM_E_UNSUPPORTED,
+                        "SU(2) contraction: an OPERATOR tensor on legs (2,3) with legs (0,1) of an OPERATOR or LEFT tensor");
+    }
+    return p;
+}
+
+DescPtr result_desc(const Desc& A, const Desc& B, const PairInfo& p) {
+    std::vector<Leg> legs;
+    for (int32_t i : p.fa) legs.push_back(A.legs[static_cast<size_t>(i)]);
+    for (int32_t i : p.fb) legs.push_back(B.legs[static_cast<size_t>(i)]);
+    if (A.group == SYM_SU2)
+        return make_desc(SYM_SU2, legs, 2, B.tree, 0, SYM_F32);
+    return make_desc(SYM_U1, legs, static_cast<int32_t>(p.fa.size()), SYM_TREE_NONE, A.qtot + B.qtot, SYM_F32);
+}
+
+// descriptor of A's legs (fa ++ axa) with |fa| row legs
+DescPtr fused_a(const Desc& A, const PairInfo& p, int32_t dtype, bool trans) {
+    return make_desc(A.group, permute_legs(A.legs, p.perm_a), static_cast<int32_t>(p.fa.size()), A.tree, A.qtot, dtype,
+                     workspace_opts(dtype, trans));
+}
+
+// descriptor of B's legs (axb ++ fb) with |axb| row legs
+DescPtr fused_b(const Desc& B, const PairInfo& p, int32_t dtype, bool trans) {
+    return make_desc(B.group, permute_legs(B.legs, p.perm_b), static_cast<int32_t>(p.axb.size()), B.tree, B.qtot, dtype,
+                     workspace_opts(dtype, trans));
+}
+
+std::vector<int32_t> identity(int n) {
+    std::vector<int32_t> v(static_cast<size_t>(n));
+    for (int i = 0; i < n; ++i) v[static_cast<size_t>(i)] = i;
+    return v;
+}
+
+std::vector<int32_t> inverse(const std::vector<int32_t>& p) {
+    std::vector<int32_t> q(p.size());
+    for (size_t i = 0; i < p.size(); ++i) q[static_cast<size_t>(p[i])] = static_cast<int32_t>(i);
+    return q;
+}
+
+// The layout C must have for the GEMM to write it directly.
+bool gemm_can_write(const Desc& want, const Desc& c) {
+    return c.dtype == SYM_F32 && !c.opts.trans && c.n_row == want.n_row && c.legs == want.legs &&
+           c.tree == want.tree && c.qtot == want.qtot && c.group == want.group;
+}
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+std::string axes_key(int32_t n, const int32_t* a, const int32_t* b) {
+    std::ostringstream k;
+    for (int i = 0; i < n; ++i) k << a[i] << ',' << b[i] << ';';
+    return k.str();
+}
+
+int pick_variant(sym_ctx* ctx, int compute, const std::string& key) {
+    if (ctx->variant[compute] >= 0) return ctx->variant[compute];
+    auto it = ctx->tuned.find(std::to_string(compute) + ":" + std::to_string(std::hash<std::string>{}(key)));
+    if (it != ctx->tuned.end()) return it->second;
+    return gemm_default_variant(compute);
+}
+
+std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
+                                                  const sym_tensor* const* B, int32_t n, const int32_t* axA,
+                                                  const int32_t* axB, int32_t compute, sym_tensor* const* C,
+                                                  std::string* key_out, int variant_override) {
+    if (compute != SYM_F32 && compute != SYM_BF16) throw Error(SYM_E_DTYPE, "compute must be F32 or BF16");
+    if (count < 1 || count > kMaxBatch) throw Error(SYM_E_ARG, "batch size outside [1, 84]");
+    std::ostringstream k;
+    k << "C|" << compute << '|' << axes_key(n, axA, axB);
+    std::vector<PairInfo> infos;
+    for (int i = 0; i < count; ++i) {
+        if (!A[i] || !B[i] || !C[i]) throw Error(SYM_E_ARG, "tensor handle is NULL");
+        infos.push_back(check_pair(*A[i]->d, *B[i]->d, n, axA, axB));
+        k << '#' << A[i]->d->key << '#' << B[i]->d->key << '#' << C[i]->d->key;
+    }
+    const std::string key = k.str();
+    if (key_out) *key_out = key;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->contract_plans.find(key);
+        if (it != ctx->contract_plans.end() && variant_override < 0 && it->second->gemm.variant == pick_variant(ctx, compute, key))
+            return it->second;
+    }
+    auto plan = std::make_shared<ContractPlan>();
+    plan->count = count;
+    plan->compute = compute;
+    plan->gemm.compute = compute;
+    plan->fuse[0].src_dtype = SYM_F32;
+    plan->fuse[1].src_dtype = SYM_BF16;
+    plan->fuse[0].dst_dtype = plan->fuse[1].dst_dtype = compute;
+    plan->split.src_dtype = plan->split.dst_dtype = SYM_F32;
+    int64_t in_off = 0, out_off = 0;
+    for (int i = 0; i < count; ++i) {
+        const Desc& a = *A[i]->d;
+        const Desc& b = *B[i]->d;
+        const Desc& c = *C[i]->d;
+        const PairInfo& p = infos[static_cast<size_t>(i)];
+        DescPtr want_c = result_desc(a, b, p);
+        if (c.group != want_c->group || c.legs != want_c->legs || c.qtot != want_c->qtot ||
+            (c.group == SYM_SU2 && c.tree != want_c->tree) || c.dtype != SYM_F32)
+            throw Error(SYM_E_MISMATCH, "C does not describe the contraction result");
+        DescPtr af = fused_a(a, p, compute, false);
+        DescPtr bf = fused_b(b, p, compute, true);   // stored N x K: K contiguous
+        const int64_t a_base = in_off;
+        in_off = align_up(in_off + af->numel, 64);
+        const int64_t b_base = in_off;
+        in_off = align_up(in_off + bf->numel, 64);
+        plan->fuse[a.dtype == SYM_BF16 ? 1 : 0].add(a, *af, p.perm_a, kSlotUser + i, kSlotWsIn, 0, a_base);
+        plan->fuse[b.dtype == SYM_BF16 ? 1 : 0].add(b, *bf, p.perm_b, kSlotUser + count + i, kSlotWsIn, 0, b_base);
+        if (gemm_can_write(*want_c, c)) {
+            plan->gemm.add(c, *af, *bf, kSlotUser + 2 * count + i, kSlotWsIn, kSlotWsIn, 0, a_base, b_base);
+        } else {
+            const int64_t c_base = out_off;
+            out_off = align_up(out_off + want_c->numel, 64);
+            plan->gemm.add(*want_c, *af, *bf, kSlotWsOut, kSlotWsIn, kSlotWsIn, c_base, a_base, b_base);
+            plan->split.add(*want_c, c, identity(c.rank), kSlotWsOut, kSlotUser + 2 * count + i, c_base, 0);
+        }
+    }
+    const int var = variant_override >= 0 ? variant_override : pick_variant(ctx, compute, key);
+    plan->gemm.finalize(var);
+    plan->flops = plan->gemm.flops;
+    for (auto& f : plan->fuse) f.finalize();
+    plan->split.finalize();
+    Allocator alloc = ctx->allocator();
+    if (in_off) plan->ws_in = alloc(static_cast<size_t>(in_off) * dtype_size(compute));
+    if (out_off) plan->ws_out = alloc(static_cast<size_t>(out_off) * sizeof(float));
+    for (auto& f : plan->fuse) f.upload(alloc);
+    plan->gemm.upload(alloc);
+    plan->split.upload(alloc);
+    plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, var);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->contract_plans[key] = plan;
+    return plan;
+}
+
+void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor* const* A, const sym_tensor* const* B,
+                       sym_tensor* const* C, hipStream_t s, bool allow_timing) {
+    PtrTable t{};
+    t.p[kSlotWsIn] = plan.ws_in ? plan.ws_in->ptr : nullptr;
+    t.p[kSlotWsOut] = plan.ws_out ? plan.ws_out->ptr : nullptr;
+    for (int i = 0; i < plan.count; ++i) {
+        if (!A[i]->data || !B[i]->data || !C[i]->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        t.p[kSlotUser + i] = A[i]->data;
+        t.p[kSlotUser + plan.count + i] = B[i]->data;
+        t.p[kSlotUser + 2 * plan.count + i] = C[i]->data;
+    }
+    const bool timing = allow_timing && ctx->timing;
+    if (timing) {
+        ctx->ensure_events();
+        HIP_CHECK(hipEventRecord(ctx->ev[0], s));
+    }
+    for (const auto& f : plan.fuse) HIP_CHECK(f.launch(t, s));
+    if (timing) HIP_CHECK(hipEventRecord(ctx->ev[1], s));
+    HIP_CHECK(plan.gemm.launch(t, plan.grid, s));
+    if (timing) HIP_CHECK(hipEventRecord(ctx->ev[2], s));
+    HIP_CHECK(plan.split.launch(t, s));
+    if (timing) HIP_CHECK(hipEventRecord(ctx->ev[3], s));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exports
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* sym_last_error(void) { return g_last_error.c_str(); }
+const char* sym_version(void) { return "symtensor 0.1 (gfx950)"; }
+
+int32_t sym_ctx_create(sym_alloc_fn alloc, sym_free_fn free_fn, void* user, sym_ctx** out) {
+    return guard([&] {
+        if (!out) throw Error(SYM_E_ARG, "out is NULL");
+        if ((alloc == nullptr) != (free_fn == nullptr)) throw Error(SYM_E_ARG, "give both alloc and free, or neither");
+        auto* c = new sym_ctx();
+        c->alloc = alloc;
+        c->free_fn = free_fn;
+        c->user = user;
+        if (const char* f = std::getenv("SYM_TUNE_CACHE")) {
+            std::ifstream in(f);
+            std::string k;
+            int v;
+            while (in >> k >> v) c->tuned[k] = v;
+        }
+        *out = c;
+    });
+}
+
+void sym_ctx_destroy(sym_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->events_ready)
+        for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int32_t sym_ctx_clear(sym_ctx* ctx) {
+    return guard([&] {
+        if (!ctx) throw Error(SYM_E_ARG, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->contract_plans.clear();
+        ctx->backward_plans.clear();
+        ctx->permute_plans.clear();
+    });
+}
+
+int32_t sym_tensor_create(sym_ctx* ctx, int32_t group, int32_t rank, const sym_leg* legs, int32_t n_row, int32_t tree,
+                          int32_t qtot, int32_t dtype, void* data, sym_tensor** out) {
+    (void)ctx;
+    return guard([&] {
+        if (!out) throw Error(SYM_E_ARG, "out is NULL");
+        auto* t = new sym_tensor();
+        try {
+            t->d = make_desc(group, read_legs(rank, legs), n_row, tree, qtot, dtype);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        t->data = data;
+        *out = t;
+    });
+}
+
+void sym_tensor_destroy(sym_tensor* t) { delete t; }
+
+int32_t sym_tensor_set_data(sym_tensor* t, void* data) {
+    return guard([&] {
+        if (!t) throw Error(SYM_E_ARG, "tensor is NULL");
+        t->data = data;
+    });
+}
+
+int32_t sym_tensor_numel(const sym_tensor* t, int64_t* numel) {
+    return guard([&] {
+        if (!t || !numel) throw Error(SYM_E_ARG, "NULL argument");
+        *numel = t->d->numel;
+    });
+}
+
+int32_t sym_tensor_num_blocks(const sym_tensor* t, int64_t* n) {
+    return guard([&] {
+        if (!t || !n) throw Error(SYM_E_ARG, "NULL argument");
+        *n = static_cast<int64_t>(t->d->blocks.size());
+    });
+}
+
+int32_t sym_tensor_num_sectors(const sym_tensor* t, int64_t* n) {
+    return guard([&] {
+        if (!t || !n) throw Error(SYM_E_ARG, "NULL argument");
+        *n = static_cast<int64_t>(t->d->sectors.size());
+    });
+}
+
+int32_t sym_tensor_block_info(const sym_tensor* t, int64_t i, int32_t* labels, int32_t* internal, int64_t* offset,
+                              int64_t* shape, int64_t* strides) {
+    return guard([&] {
+        if (!t) throw Error(SYM_E_ARG, "tensor is NULL");
+        if (i < 0 || i >= static_cast<int64_t>(t->d->blocks.size())) throw Error(SYM_E_ARG, "block index out of range");
+        const Block& b = t->d->blocks[static_cast<size_t>(i)];
+        for (int l = 0; l < t->d->rank; ++l) {
+            if (labels) labels[l] = b.labels[static_cast<size_t>(l)];
+            if (shape) shape[l] = b.shape[static_cast<size_t>(l)];
+            if (strides) strides[l] = b.stride[static_cast<size_t>(l)];
+        }
+        if (internal) *internal = b.internal;
+        if (offset) *offset = b.offset;
+    });
+}
+
+int32_t sym_tensor_sector_info(const sym_tensor* t, int64_t i, int32_t* label, int64_t* rows, int64_t* cols,
+                               int64_t* offset) {
+    return guard([&] {
+        if (!t) throw Error(SYM_E_ARG, "tensor is NULL");
+        if (i < 0 || i >= static_cast<int64_t>(t->d->sectors.size())) throw Error(SYM_E_ARG, "sector index out of range");
+        const Sector& s = t->d->sectors[static_cast<size_t>(i)];
+        if (label) *label = s.label;
+        if (rows) *rows = s.rows;
+        if (cols) *cols = s.cols;
+        if (offset) *offset = s.offset;
+    });
+}
+
+// ----- permute / fuse / recouple -------------------------------------------
+
+namespace {
+
+struct PermuteSpec {
+    std::vector<int32_t> perm;
+    bool recouple = false;
+};
+
+PermuteSpec check_perm(const Desc& in, const int32_t* perm) {
+    PermuteSpec s;
+    if (in.rank > 0 && !perm) throw Error(SYM_E_ARG, "perm is NULL");
+    std::vector<bool> seen(static_cast<size_t>(in.rank), false);
+    for (int i = 0; i < in.rank; ++i) {
+        const int32_t p = perm[i];
+        if (p < 0 || p >= in.rank || seen[static_cast<size_t>(p)]) throw Error(SYM_E_ARG, "not a permutation");
+        seen[static_cast<size_t>(p)] = true;
+        s.perm.push_back(p);
+    }
+    if (in.group == SYM_SU2) {
+        if (s.perm == identity(4)) return s;
+        if (s.perm == std::vector<int32_t>{0, 2, 1, 3} && in.tree == SYM_TREE_LEFT) {
+            s.recouple = true;
+            return s;
+        }
+        throw Error(SYM_E_UNSUPPORTED, "SU(2) permutations: identity, or (0,2,1,3) of a LEFT-tree tensor");
+    }
+    return s;
+}
+
+DescPtr permute_result(const Desc& in, const PermuteSpec& s, int32_t n_row_out, int32_t dtype_out) {
+    if (s.recouple) {
+        if (n_row_out != 0 && n_row_out != 4) throw Error(SYM_E_UNSUPPORTED, "recoupled tensors use n_row 0 or 4");
+        if (dtype_out != SYM_F32 || in.dtype != SYM_F32) throw Error(SYM_E_DTYPE, "recoupling works on FP32 data");
+        return make_desc(SYM_SU2, permute_legs(in.legs, s.perm), n_row_out, SYM_TREE_RIGHT, 0, SYM_F32);
+    }
+    return make_desc(in.group, permute_legs(in.legs, s.perm), n_row_out, in.tree, in.qtot, dtype_out);
+}
+
+}  // namespace
+
+int32_t sym_permute_fuse_output(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t n_row_out,
+                                int32_t dtype_out, void* data, sym_tensor** out) {
+    (void)ctx;
+    return guard([&] {
+        if (!in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        PermuteSpec s = check_perm(*in->d, perm);
+        auto* t = new sym_tensor();
+        try {
+            t->d = permute_result(*in->d, s, n_row_out, dtype_out);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        t->data = data;
+        *out = t;
+    });
+}
+
+int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t n_row_out, sym_tensor* out,
+                         void* stream) {
+    return guard([&] {
+        if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        PermuteSpec s = check_perm(*in->d, perm);
+        DescPtr want = permute_result(*in->d, s, n_row_out, out->d->dtype);
+        if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
+        if (!in->data || !out->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        std::ostringstream k;
+        k << "P|" << in->d->key << '|' << out->d->key << '|';
+        for (int32_t p : s.perm) k << p << ',';
+        std::shared_ptr<PermutePlan> plan;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->permute_plans.find(k.str());
+            if (it != ctx->permute_plans.end()) plan = it->second;
+        }
+        if (!plan) {
+            plan = std::make_shared<PermutePlan>();
+            Allocator alloc = ctx->allocator();
+            if (s.recouple) {
+                plan->is_recouple = true;
+                plan->recouple.build(*in->d, *out->d);
+                plan->recouple.upload(alloc);
+            } else {
+                plan->copy.src_dtype = in->d->dtype;
+                plan->copy.dst_dtype = out->d->dtype;
+                plan->copy.add(*in->d, *out->d, s.perm, 0, 1);
+                plan->copy.finalize();
+                plan->copy.upload(alloc);
+            }
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->permute_plans[k.str()] = plan;
+        }
+        PtrTable t{};
+        t.p[0] = in->data;
+        t.p[1] = out->data;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (plan->is_recouple) HIP_CHECK(plan->recouple.launch(t, 0, 1, st));
+        else HIP_CHECK(plan->copy.launch(t, st));
+    });
+}
+
+// ----- contraction ------------------------------------------------------------
+
+int32_t sym_contract_output(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n, const int32_t* axesA,
+                            const int32_t* axesB, void* data, sym_tensor** C) {
+    (void)ctx;
+    return guard([&] {
+        if (!A || !B || !C) throw Error(SYM_E_ARG, "NULL argument");
+        PairInfo p = check_pair(*A->d, *B->d, n, axesA, axesB);
+        auto* t = new sym_tensor();
+        try {
+            t->d = result_desc(*A->d, *B->d, p);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        t->data = data;
+        *C = t;
+    });
+}
+
+int32_t sym_contract_flops(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n, const int32_t* axesA,
+                           const int32_t* axesB, int64_t* flops) {
+    (void)ctx;
+    return guard([&] {
+        if (!A || !B || !flops) throw Error(SYM_E_ARG, "NULL argument");
+        PairInfo p = check_pair(*A->d, *B->d, n, axesA, axesB);
+        DescPtr c = result_desc(*A->d, *B->d, p);
+        GemmProgram g;
+        g.add(*c, *fused_a(*A->d, p, SYM_F32, false), *fused_b(*B->d, p, SYM_F32, true), 0, 0, 0);
+        *flops = g.flops;
+    });
+}
+
+int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A, const sym_tensor* const* B,
+                             int32_t n, const int32_t* axesA, const int32_t* axesB, int32_t compute,
+                             sym_tensor* const* C, void* stream) {
+    return guard([&] {
+        if (!ctx || !A || !B || !C) throw Error(SYM_E_ARG, "NULL argument");
+        for (int32_t first = 0; first < count; first += 64) {
+            const int32_t m = std::min<int32_t>(64, count - first);
+            auto plan = build_contract_plan(ctx, m, A + first, B + first, n, axesA, axesB, compute, C + first, nullptr, -1);
+            run_contract_plan(ctx, *plan, A + first, B + first, C + first, static_cast<hipStream_t>(stream), count <= 64);
+        }
+        if (count < 1) throw Error(SYM_E_ARG, "count must be >= 1");
+    });
+}
+
+int32_t sym_contract(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n, const int32_t* axesA,
+                     const int32_t* axesB, int32_t compute, sym_tensor* C, void* stream) {
+    return sym_contract_batched(ctx, 1, &A, &B, n, axesA, axesB, compute, &C, stream);
+}
+
+// ----- backward -----------------------------------------------------------------
+
+int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, const sym_tensor* dC, int32_t n,
+                              const int32_t* axesA, const int32_t* axesB, int32_t compute, sym_tensor* dA,
+                              sym_tensor* dB, void* stream) {
+    return guard([&] {
+        if (!ctx || !A || !B || !dC) throw Error(SYM_E_ARG, "NULL argument");
+        if (compute != SYM_F32 && compute != SYM_BF16) throw Error(SYM_E_DTYPE, "compute must be F32 or BF16");
+        PairInfo p = check_pair(*A->d, *B->d, n, axesA, axesB);
+        DescPtr cw = result_desc(*A->d, *B->d, p);
+        const Desc& dc = *dC->d;
+        if (dc.legs != cw->legs || dc.qtot != cw->qtot || dc.group != cw->group || dc.tree != cw->tree)
+            throw Error(SYM_E_MISMATCH, "dC does not describe the contraction result");
+        if (dA && (dA->d->legs != A->d->legs || dA->d->dtype != SYM_F32 || dA->d->qtot != A->d->qtot || dA->d->tree != A->d->tree))
+            throw Error(SYM_E_MISMATCH, "dA does not describe A (FP32)");
+        if (dB && (dB->d->legs != B->d->legs || dB->d->dtype != SYM_F32 || dB->d->qtot != B->d->qtot || dB->d->tree != B->d->tree))
+            throw Error(SYM_E_MISMATCH, "dB does not describe B (FP32)");
+        if (!dA && !dB) return;
+        std::ostringstream k;
+        k << "B|" << compute << '|' << axes_key(n, axesA, axesB) << '#' << A->d->key << '#' << B->d->key << '#' << dc.key
+          << '#' << (dA ? dA->d->key : "-") << '#' << (dB ? dB->d->key : "-");
+        std::shared_ptr<BackwardPlan> plan;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->backward_plans.find(k.str());
+            if (it != ctx->backward_plans.end()) plan = it->second;
+        }
+        // slots: 0 ws_in, 1 ws_out, 2 A, 3 B, 4 dC, 5 dA, 6 dB
+        if (!plan) {
+            plan = std::make_shared<BackwardPlan>();
+            plan->gemm.compute = compute;
+            for (int i = 0; i < 2; ++i) {
+                plan->copy_in[i].src_dtype = i == 0 ? SYM_F32 : SYM_BF16;
+                plan->copy_in[i].dst_dtype = compute;
+            }
+            plan->split.src_dtype = plan->split.dst_dtype = SYM_F32;
+            int64_t in_off = 0, out_off = 0;
+            auto place_in = [&](const Desc& d) {
+                const int64_t b = in_off;
+                in_off = align_up(in_off + d.numel, 64);
+                return b;
+            };
+            auto place_out = [&](const Desc& d) {
+                const int64_t b = out_off;
+                out_off = align_up(out_off + d.numel, 64);
+                return b;
+            };
+            // dC as the M x N operand of dA (K = B's free legs)
+            DescPtr dcx = make_desc(cw->group, cw->legs, cw->n_row, cw->tree, cw->qtot, compute, workspace_opts(compute, false));
+            // dC^T as the N x M operand of dB (K = A's free legs)
+            DescPtr dct = make_desc(cw->group, cw->legs, cw->n_row, cw->tree, cw->qtot, compute, workspace_opts(compute, true));
+            const int dc_slot = dc.dtype == SYM_BF16 ? 1 : 0;
+            if (dA) {
+                DescPtr x = dcx, y = fused_b(*B->d, p, compute, false), z = fused_a(*A->d, p, SYM_F32, false);
+                const int64_t xb = place_in(*x), yb = place_in(*y);
+                plan->copy_in[dc_slot].add(dc, *x, identity(dc.rank), 4, 0, 0, xb);
+                plan->copy_in[B->d->dtype == SYM_BF16 ? 1 : 0].add(*B->d, *y, p.perm_b, 3, 0, 0, yb);
+                if (gemm_can_write(*z, *dA->d) && p.perm_a == identity(A->d->rank)) {
+                    plan->gemm.add(*dA->d, *x, *y, 5, 0, 0, 0, xb, yb);
+                } else {
+                    const int64_t zb = place_out(*z);
+                    plan->gemm.add(*z, *x, *y, 1, 0, 0, zb, xb, yb);
+                    plan->split.add(*z, *dA->d, inverse(p.perm_a), 1, 5, zb, 0);
+                }
+            }
+            if (dB) {
+                DescPtr x = fused_a(*A->d, p, compute, true), y = dct, z = fused_b(*B->d, p, SYM_F32, false);
+                const int64_t xb = place_in(*x), yb = place_in(*y);
+                plan->copy_in[A->d->dtype == SYM_BF16 ? 1 : 0].add(*A->d, *x, p.perm_a, 2, 0, 0, xb);
+                plan->copy_in[dc_slot].add(dc, *y, identity(dc.rank), 4, 0, 0, yb);
+                if (gemm_can_write(*z, *dB->d) && p.perm_b == identity(B->d->rank)) {
+                    plan->gemm.add(*dB->d, *x, *y, 6, 0, 0, 0, xb, yb);
+                } else {
+                    const int64_t zb = place_out(*z);
+                    plan->gemm.add(*z, *x, *y, 1, 0, 0, zb, xb, yb);
+                    plan->split.add(*z, *dB->d, inverse(p.perm_b), 1, 6, zb, 0);
+                }
+            }
+            plan->gemm.finalize(pick_variant(ctx, compute, k.str()));
+            for (auto& c : plan->copy_in) c.finalize();
+            plan->split.finalize();
+            Allocator alloc = ctx->allocator();
+            if (in_off) plan->ws_in = alloc(static_cast<size_t>(in_off) * dtype_size(compute));
+            if (out_off) plan->ws_out = alloc(static_cast<size_t>(out_off) * sizeof(float));
+            for (auto& c : plan->copy_in) c.upload(alloc);
+            plan->gemm.upload(alloc);
+            plan->split.upload(alloc);
+            plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, plan->gemm.variant);
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->backward_plans[k.str()] = plan;
+        }
+        if (!A->data || !B->data || !dC->data || (dA && !dA->data) || (dB && !dB->data))
+            throw Error(SYM_E_ARG, "tensor has no data pointer");
+        PtrTable t{};
+        t.p[0] = plan->ws_in ? plan->ws_in->ptr : nullptr;
+        t.p[1] = plan->ws_out ? plan->ws_out->ptr : nullptr;
+        t.p[2] = A->data;
+        t.p[3] = B->data;
+        t.p[4] = dC->data;
+        t.p[5] = dA ? dA->data : nullptr;
+        t.p[6] = dB ? dB->data : nullptr;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        for (const auto& c : plan->copy_in) HIP_CHECK(c.launch(t, st));
+        HIP_CHECK(plan->gemm.launch(t, plan->grid, st));
+        HIP_CHECK(plan->split.launch(t, st));
+    });
+}
+
+// ----- graphs, timing, tuning ------------------------------------------------------
+
+int32_t sym_graph_create_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A, const sym_tensor* const* B,
+                                 int32_t n, const int32_t* axesA, const int32_t* axesB, int32_t compute,
+                                 sym_tensor* const* C, void* stream, sym_graph** out) {
+    return guard([&] {
+        if (!ctx || !out || !stream) throw Error(SYM_E_ARG, "ctx, out and a non-null stream are required");
+        if (count > 64) throw Error(SYM_E_UNSUPPORTED, "graphs take at most 64 contractions");
+        auto plan = build_contract_plan(ctx, count, A, B, n, axesA, axesB, compute, C, nullptr, -1);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        auto* g = new sym_graph();
+        g->plan = plan;
+        try {
+            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                run_contract_plan(ctx, *plan, A, B, C, s, false);
+            } catch (...) {
+                hipGraph_t dummy = nullptr;
+                (void)hipStreamEndCapture(s, &dummy);
+                if (dummy) (void)hipGraphDestroy(dummy);
+                throw;
+            }
+            HIP_CHECK(hipStreamEndCapture(s, &g->graph));
+            HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        } catch (...) {
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            if (g->graph) (void)hipGraphDestroy(g->graph);
+            delete g;
+            throw;
+        }
+        *out = g;
+    });
+}
+
+int32_t sym_graph_launch(sym_graph* g, void* stream) {
+    return guard([&] {
+        if (!g) throw Error(SYM_E_ARG, "graph is NULL");
+        HIP_CHECK(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    });
+}
+
+void sym_graph_destroy(sym_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+int32_t sym_ctx_set_timing(sym_ctx* ctx, int32_t enable) {
+    return guard([&] {
+        if (!ctx) throw Error(SYM_E_ARG, "ctx is NULL");
+        ctx->timing = enable != 0;
+    });
+}
+
+int32_t sym_ctx_phase_ms(sym_ctx* ctx, int32_t phase, float* ms) {
+    return guard([&] {
+        if (!ctx || !ms) throw Error(SYM_E_ARG, "NULL argument");
+        if (phase < 0 || phase > 2) throw Error(SYM_E_ARG, "phase must be 0, 1 or 2");
+        if (!ctx->events_ready) throw Error(SYM_E_ARG, "timing was not enabled for a contraction");
+        HIP_CHECK(hipEventElapsedTime(ms, ctx->ev[phase], ctx->ev[phase + 1]));
+    });
+}
+
+int32_t sym_num_variants(int32_t compute, int32_t* count) {
+    return guard([&] {
+        if (!count || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");
+        *count = gemm_num_variants(compute);
+    });
+}
+
+int32_t sym_ctx_set_variant(sym_ctx* ctx, int32_t compute, int32_t variant) {
+    return guard([&] {
+        if (!ctx || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");
+        if (variant >= gemm_num_variants(compute)) throw Error(SYM_E_ARG, "no such variant");
+        ctx->variant[compute] = variant < 0 ? -1 : variant;
+    });
+}
+
+int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A, const sym_tensor* const* B, int32_t n,
+                         const int32_t* axesA, const int32_t* axesB, int32_t compute, sym_tensor* const* C, void* stream,
+                         int32_t* best_variant) {
+    return guard([&] {
+        if (!ctx || !best_variant) throw Error(SYM_E_ARG, "NULL argument");
+        if (count > 64) throw Error(SYM_E_UNSUPPORTED, "tuning takes at most 64 contractions");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        ctx->ensure_events();
+        const bool was_timing = ctx->timing;
+        ctx->timing = true;
+        std::string key;
+        float best_ms = 0.f;
+        int best = -1;
+        for (int v = 0; v < gemm_num_variants(compute); ++v) {
+            auto plan = build_contract_plan(ctx, count, A, B, n, axesA, axesB, compute, C, &key, v);
+            float total = 0.f;
+            for (int rep = 0; rep < 4; ++rep) {
+                run_contract_plan(ctx, *plan, A, B, C, s, true);
+                HIP_CHECK(hipStreamSynchronize(s));
+                float ms = 0.f;
+                HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+                if (rep > 0) total += ms;   // first run warms caches
+            }
+            if (best < 0 || total < best_ms) {
+                best_ms = total;
+                best = v;
+            }
+        }
+        ctx->timing = was_timing;
+        const std::string tk = std::to_string(compute) + ":" + std::to_string(std::hash<std::string>{}(key));
+        ctx->tuned[tk] = best;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->contract_plans.erase(key);
+        }
+        if (const char* f = std::getenv("SYM_TUNE_CACHE")) {
+            std::ofstream o(f, std::ios::app);
+            o << tk << ' ' << best << '\n';
+        }
+        *best_variant = best;
+    });
+}
+
+double sym_fmove_coeff(int32_t tjA, int32_t tjB, int32_t tjC, int32_t tjJ, int32_t tjD, int32_t tjE) {
+    return fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE);
+}
+
+}  // extern "C"

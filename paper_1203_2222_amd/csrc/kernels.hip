@@ -1,0 +1,469 @@
+// HIP kernels for gfx950 (MI355X): block permute/fuse/split, the grouped
+// sector GEMM on MFMA (FP32 and BF16 with FP32 accumulation), and the SU(2)
+// recoupling of reduced blocks.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace sym {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// element conversion
+// ---------------------------------------------------------------------------
+
+// FP32 -> BF16, round to nearest even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<uint16_t>((u >> 16) | 0x0040u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+template <typename Ti, typename To>
+struct Conv;
+template <>
+struct Conv<float, float> {
+    __device__ static float f(float x) { return x; }
+};
+template <>
+struct Conv<float, uint16_t> {
+    __device__ static uint16_t f(float x) { return f32_to_bf16(x); }
+};
+template <>
+struct Conv<uint16_t, uint16_t> {
+    __device__ static uint16_t f(uint16_t x) { return x; }
+};
+template <>
+struct Conv<uint16_t, float> {
+    __device__ static float f(uint16_t x) { return bf16_to_f32(x); }
+};
+
+// ---------------------------------------------------------------------------
+// K2/K3: block permute (fuse, split, reorder).  Each workgroup walks its own
+// range of tasks; a task is a slice of one block copy.  Threads run along the
+// destination's innermost dimension, so stores are coalesced; loads are
+// coalesced whenever the copy keeps the source's innermost dimension.
+// ---------------------------------------------------------------------------
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops, const CopyTask* __restrict__ tasks,
+                                                 const int32_t* __restrict__ wg_begin, PtrTable bufs) {
+    const int w = blockIdx.x;
+    const int t_lo = wg_begin[w], t_hi = wg_begin[w + 1];
+    for (int ti = t_lo; ti < t_hi; ++ti) {
+        const CopyTask t = tasks[ti];
+        const CopyOp& op = ops[t.op];
+        const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[op.src_buf]) + op.src_off;
+        To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[op.dst_buf])) + op.dst_off;
+        const int nd = op.ndim;
+        const int inner = op.size[kMaxCopyDims - 1];
+        const int64_t s_in = op.sstride[kMaxCopyDims - 1], d_in = op.dstride[kMaxCopyDims - 1];
+        const int end = t.start + t.count;
+        for (int e = t.start + static_cast<int>(threadIdx.x); e < end; e += 256) {
+            int rem = e / inner;
+            const int i0 = e - rem * inner;
+            int64_t so = i0 * s_in, dof = i0 * d_in;
+            for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - nd; --d) {
+                const int sz = op.size[d];
+                const int q = rem / sz;
+                const int i = rem - q * sz;
+                rem = q;
+                so += i * op.sstride[d];
+                dof += i * op.dstride[d];
+            }
+            dst[dof] = Conv<Ti, To>::f(src[so]);
+        }
+    }
+}
+
+hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
+                          const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
+    if (n_wg <= 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>(n_wg)), block(256);
+    if (src_dtype == 0 && dst_dtype == 0)
+        hipLaunchKernelGGL((k_permute<float, float>), grid, block, 0, s, ops, tasks, wg_begin, bufs);
+    else if (src_dtype == 0 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_permute<float, uint16_t>), grid, block, 0, s, ops, tasks, wg_begin, bufs);
+    else if (src_dtype == 1 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_permute<uint16_t, uint16_t>), grid, block, 0, s, ops, tasks, wg_begin, bufs);
+    else
+        hipLaunchKernelGGL((k_permute<uint16_t, float>), grid, block, 0, s, ops, tasks, wg_begin, bufs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K4/K5/K6: persistent grouped GEMM over sector tiles.
+//
+// C[m][n] = sum_k A[m][k] B[n][k]; A rows and B rows are K-contiguous.  A
+// workgroup of 4 waves owns an MT x NT tile of C; wave (wm, wn) owns an
+// (MT/2) x (NT/2) sub-tile built from 32x32 MFMA blocks.  Operand tiles are
+// staged through LDS in two buffers: the next K slice is fetched into
+// registers while the current one feeds the MFMAs.
+//
+// Inside one MFMA the K index is a free relabelling as long as A and B agree:
+// lanes 0-31 feed the first half of an LDS row slice and lanes 32-63 the
+// second half, so every lane reads 16-byte vectors from LDS.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// 4 consecutive FP32 of row r starting at column c, zero outside [0,R)x[0,Cn).
+__device__ __forceinline__ v4f load_f32x4(const float* base, int64_t ld, int r, int c, int R, int Cn) {
+    v4f v = {0.f, 0.f, 0.f, 0.f};
+    if (r < R) {
+        const float* p = base + static_cast<int64_t>(r) * ld + c;
+        if (c + 3 < Cn && aligned16(p)) {
+            v = *reinterpret_cast<const v4f*>(p);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c + j < Cn) v[j] = p[j];
+        }
+    }
+    return v;
+}
+
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_gemm_f32(const GemmProb* __restrict__ probs, const GemmTile* __restrict__ tiles,
+                                                  int n_tiles, PtrTable bufs) {
+    constexpr int KT = 16;           // K slice per stage (floats)
+    constexpr int P = KT + 4;        // LDS row pitch (floats), keeps 16-byte alignment
+    constexpr int WM = MT / 2, WN = NT / 2;
+    constexpr int FM = WM / 32, FN = WN / 32;
+    constexpr int AV = MT * KT / 4 / 256;   // float4 loads per thread for A
+    constexpr int BV = NT * KT / 4 / 256;
+    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    __shared__ __attribute__((aligned(16))) float As[2][MT * P];
+    __shared__ __attribute__((aligned(16))) float Bs[2][NT * P];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int h = lane >> 5, r32 = lane & 31;
+
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const GemmTile tile = tiles[t];
+        const GemmProb p = probs[tile.prob];
+        const float* A = static_cast<const float*>(bufs.p[p.a_buf]) + p.a_off;
+        const float* B = static_cast<const float*>(bufs.p[p.b_buf]) + p.b_off;
+        float* C = static_cast<float*>(const_cast<void*>(bufs.p[p.c_buf])) + p.c_off;
+        const int m0 = tile.tm * MT, n0 = tile.tn * NT;
+
+        v16f acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+
+        v4f ra[AV], rb[BV];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) {
+                const int idx = tid + i * 256;
+                ra[i] = load_f32x4(A, p.lda, m0 + (idx >> 2), k0 + (idx & 3) * 4, p.M, p.K);
+            }
+#pragma unroll
+            for (int i = 0; i < BV; ++i) {
+                const int idx = tid + i * 256;
+                rb[i] = load_f32x4(B, p.ldb, n0 + (idx >> 2), k0 + (idx & 3) * 4, p.N, p.K);
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) {
+                const int idx = tid + i * 256;
+                *reinterpret_cast<v4f*>(&As[buf][(idx >> 2) * P + (idx & 3) * 4]) = ra[i];
+            }
+#pragma unroll
+            for (int i = 0; i < BV; ++i) {
+                const int idx = tid + i * 256;
+                *reinterpret_cast<v4f*>(&Bs[buf][(idx >> 2) * P + (idx & 3) * 4]) = rb[i];
+            }
+        };
+
+        const int nk = (p.K + KT - 1) / KT;
+        if (nk > 0) {
+            gload(0);
+            sstore(0);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * KT);
+            v4f af[FM][2], bfr[FN][2];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const float* ap = &As[cur][(wm * WM + i * 32 + r32) * P + h * 8];
+                af[i][0] = *reinterpret_cast<const v4f*>(ap);
+                af[i][1] = *reinterpret_cast<const v4f*>(ap + 4);
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const float* bp = &Bs[cur][(wn * WN + j * 32 + r32) * P + h * 8];
+                bfr[j][0] = *reinterpret_cast<const v4f*>(bp);
+                bfr[j][1] = *reinterpret_cast<const v4f*>(bp + 4);
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s >> 2][s & 3], bfr[j][s >> 2][s & 3],
+                                                                         acc[i][j], 0, 0, 0);
+            if (kt + 1 < nk) sstore(cur ^ 1);
+            __syncthreads();
+        }
+
+        // 32x32 MFMA result: lane owns column (lane & 31); register 4*i+j is
+        // row 8*i + 4*(lane >> 5) + j.
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = n0 + wn * WN + j * 32 + r32;
+                if (col >= p.N) continue;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = m0 + wm * WM + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
+                    if (row < p.M) C[static_cast<int64_t>(row) * p.ldc + col] = acc[i][j][q];
+                }
+            }
+    }
+}
+
+// 8 consecutive BF16 of row r from column c (as 4 dwords), zero outside.
+__device__ __forceinline__ u32x4 load_bf16x8(const uint16_t* base, int64_t ld, int r, int c, int R, int Cn) {
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (r < R) {
+        const uint16_t* p = base + static_cast<int64_t>(r) * ld + c;
+        if (c + 7 < Cn && aligned16(p)) {
+            v = *reinterpret_cast<const u32x4*>(p);
+        } else {
+            uint16_t tmp[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) tmp[j] = (c + j < Cn) ? p[j] : static_cast<uint16_t>(0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = static_cast<uint32_t>(tmp[2 * j]) | (static_cast<uint32_t>(tmp[2 * j + 1]) << 16);
+        }
+    }
+    return v;
+}
+
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_gemm_bf16(const GemmProb* __restrict__ probs, const GemmTile* __restrict__ tiles,
+                                                   int n_tiles, PtrTable bufs) {
+    constexpr int KT = 32;           // K slice per stage (bf16)
+    constexpr int P = KT + 8;        // LDS row pitch (bf16): 80 bytes
+    constexpr int WM = MT / 2, WN = NT / 2;
+    constexpr int FM = WM / 32, FN = WN / 32;
+    constexpr int AV = MT * KT / 8 / 256;   // 16-byte loads per thread for A
+    constexpr int BV = NT * KT / 8 / 256;
+    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][MT * P];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NT * P];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int h = lane >> 5, r32 = lane & 31;
+
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const GemmTile tile = tiles[t];
+        const GemmProb p = probs[tile.prob];
+        const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
+        const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
+        float* C = static_cast<float*>(const_cast<void*>(bufs.p[p.c_buf])) + p.c_off;
+        const int m0 = tile.tm * MT, n0 = tile.tn * NT;
+
+        v16f acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+
+        u32x4 ra[AV], rb[BV];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) {
+                const int idx = tid + i * 256;
+                ra[i] = load_bf16x8(A, p.lda, m0 + (idx >> 2), k0 + (idx & 3) * 8, p.M, p.K);
+            }
+#pragma unroll
+            for (int i = 0; i < BV; ++i) {
+                const int idx = tid + i * 256;
+                rb[i] = load_bf16x8(B, p.ldb, n0 + (idx >> 2), k0 + (idx & 3) * 8, p.N, p.K);
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) {
+                const int idx = tid + i * 256;
+                *reinterpret_cast<u32x4*>(&As[buf][(idx >> 2) * P + (idx & 3) * 8]) = ra[i];
+            }
+#pragma unroll
+            for (int i = 0; i < BV; ++i) {
+                const int idx = tid + i * 256;
+                *reinterpret_cast<u32x4*>(&Bs[buf][(idx >> 2) * P + (idx & 3) * 8]) = rb[i];
+            }
+        };
+
+        const int nk = (p.K + KT - 1) / KT;
+        if (nk > 0) {
+            gload(0);
+            sstore(0);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * KT);
+#pragma unroll
+            for (int s = 0; s < KT / 16; ++s) {
+                bf16x8 af[FM], bfr[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const uint16_t* ap = &As[cur][(wm * WM + i * 32 + r32) * P + s * 16 + h * 8];
+                    af[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap));
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const uint16_t* bp = &Bs[cur][(wn * WN + j * 32 + r32) * P + s * 16 + h * 8];
+                    bfr[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(bp));
+                }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            }
+            if (kt + 1 < nk) sstore(cur ^ 1);
+            __syncthreads();
+        }
+
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = n0 + wn * WN + j * 32 + r32;
+                if (col >= p.N) continue;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = m0 + wm * WM + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
+                    if (row < p.M) C[static_cast<int64_t>(row) * p.ldc + col] = acc[i][j][q];
+                }
+            }
+    }
+}
+
+namespace {
+const GemmVariant kF32Variants[] = {{128, 128, "f32_128x128"}, {64, 64, "f32_64x64"}, {128, 64, "f32_128x64"}};
+const GemmVariant kBF16Variants[] = {{128, 128, "bf16_128x128"}, {64, 64, "bf16_64x64"}, {128, 64, "bf16_128x64"}};
+}  // namespace
+
+int gemm_num_variants(int compute) { return compute == 0 ? 3 : 3; }
+GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
+int gemm_default_variant(int) { return 0; }
+
+int gemm_blocks_per_cu(int compute, int variant) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+    if (compute == 0) {
+        switch (variant) {
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_f32<64, 64>, 256, 0); break;
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_f32<128, 64>, 256, 0); break;
+            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_f32<128, 128>, 256, 0); break;
+        }
+    } else {
+        switch (variant) {
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<64, 64>, 256, 0); break;
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<128, 64>, 256, 0); break;
+            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<128, 128>, 256, 0); break;
+        }
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles, int32_t n_tiles,
+                       int32_t grid, const PtrTable& bufs, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    dim3 g(static_cast<unsigned>(grid)), b(256);
+    if (compute == 0) {
+        switch (variant) {
+            case 1: hipLaunchKernelGGL((k_gemm_f32<64, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
+            case 2: hipLaunchKernelGGL((k_gemm_f32<128, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
+            default: hipLaunchKernelGGL((k_gemm_f32<128, 128>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
+        }
+    } else {
+        switch (variant) {
+            case 1: hipLaunchKernelGGL((k_gemm_bf16<64, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
+            case 2: hipLaunchKernelGGL((k_gemm_bf16<128, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
+            default: hipLaunchKernelGGL((k_gemm_bf16<128, 128>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K9: SU(2) recoupling.  For one label tuple, the n input blocks P^e are
+// combined with FP64 coefficients c[f][e] = R(j2,j3,f) F^{e f}_{j1 j2 j3 j4}
+// into n output blocks with legs 2 and 3 exchanged.  Threads run along t4,
+// the innermost index of input and output blocks alike.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks,
+                                                  const FmBlk* __restrict__ out_blks, const double* __restrict__ coef,
+                                                  const FmTask* __restrict__ tasks, PtrTable bufs, int in_buf,
+                                                  int out_buf) {
+    const FmTask t = tasks[blockIdx.x];
+    const FmGroup g = groups[t.group];
+    const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
+    float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
+    const int n = g.n;
+    const int d2 = g.d[1], d3 = g.d[2], d4 = g.d[3];
+    const int e = t.start + static_cast<int>(threadIdx.x);
+    if (e >= t.start + t.count) return;
+    // output order (t1, t3, t2, t4)
+    int r = e / d4;
+    const int t4 = e - r * d4;
+    int q = r / d2;
+    const int t2 = r - q * d2;
+    const int t1 = q / d3;
+    const int t3 = q - t1 * d3;
+    double x[kMaxRecouple];
+#pragma unroll
+    for (int i = 0; i < kMaxRecouple; ++i) {
+        if (i < n) {
+            const FmBlk b = in_blks[g.in_first + i];
+            x[i] = static_cast<double>(src[b.off + t1 * b.stride[0] + t2 * b.stride[1] + t3 * b.stride[2] + t4 * b.stride[3]]);
+        }
+    }
+    const double* c = coef + g.coef_first;
+    for (int f = 0; f < n; ++f) {
+        double y = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxRecouple; ++i)
+            if (i < n) y = fma(c[f * n + i], x[i], y);
+        const FmBlk b = out_blks[g.out_first + f];
+        dst[b.off + t1 * b.stride[0] + t3 * b.stride[1] + t2 * b.stride[2] + t4 * b.stride[3]] = static_cast<float>(y);
+    }
+}
+
+hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
+                           const FmTask* tasks, int32_t n_tasks, const PtrTable& bufs, int32_t in_buf, int32_t out_buf,
+                           hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recouple, dim3(static_cast<unsigned>(n_tasks)), dim3(256), 0, s, groups, in_blks, out_blks, coef,
+                       tasks, bufs, in_buf, out_buf);
+    return hipGetLastError();
+}
+
+}  // namespace sym

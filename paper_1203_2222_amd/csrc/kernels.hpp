@@ -1,0 +1,88 @@
+// Device work descriptors shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace sym {
+
+constexpr int kMaxBufs = 256;       // distinct base pointers one launch may address
+constexpr int kMaxCopyDims = 6;     // dims of a coalesced block copy
+constexpr int kMaxRecouple = 16;    // intermediate spins of one label tuple
+
+// Base pointers of one launch, passed by value as a kernel argument.
+struct PtrTable {
+    const void* p[kMaxBufs];
+};
+
+// One block copy dst = convert(src) over a strided box (dim kMaxCopyDims-1 innermost).
+struct CopyOp {
+    int64_t src_off, dst_off;
+    int64_t sstride[kMaxCopyDims];
+    int64_t dstride[kMaxCopyDims];
+    int32_t size[kMaxCopyDims];
+    int32_t src_buf, dst_buf;
+    int32_t count;
+    int32_t ndim;
+};
+
+// A slice [start, start+count) of one CopyOp's elements (in destination order).
+struct CopyTask {
+    int32_t op, start, count, pad;
+};
+
+// One sector GEMM: C[m][n] = sum_k A[m][k] * B[n][k] (both operands K-contiguous).
+struct GemmProb {
+    int64_t a_off, b_off, c_off;
+    int32_t M, N, K;
+    int32_t lda, ldb, ldc;
+    int32_t a_buf, b_buf, c_buf;
+    int32_t pad;
+};
+
+struct GemmTile {
+    int32_t prob, tm, tn, pad;
+};
+
+// SU(2) recoupling of one label tuple (j1,j2,j3,j4): n input blocks (one per
+// intermediate spin e) and n output blocks (one per f).
+struct FmGroup {
+    int32_t n;
+    int32_t d[4];        // degeneracies of legs 1..4 of the input
+    int32_t in_first;    // index of its first FmBlk among inputs
+    int32_t out_first;   // index of its first FmBlk among outputs
+    int32_t coef_first;  // n*n coefficients, row f, column e
+};
+
+// Input blocks: strides of (t1,t2,t3,t4); output blocks: strides of (t1,t3,t2,t4).
+struct FmBlk {
+    int64_t off;
+    int64_t stride[4];
+};
+
+struct FmTask {
+    int32_t group, start, count, pad;
+};
+
+// Launchers (kernels.hip).  Every launcher returns the hipError_t of the launch.
+hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
+                          const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
+hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles,
+                       int32_t n_tiles, int32_t grid, const PtrTable& bufs, hipStream_t s);
+hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
+                           const double* coef, const FmTask* tasks, int32_t n_tasks,
+                           const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);
+
+// Tile shape of a GEMM variant (rows x cols of C per workgroup).
+struct GemmVariant {
+    int mt, nt;
+    const char* name;
+};
+int gemm_num_variants(int compute);
+GemmVariant gemm_variant(int compute, int variant);
+int gemm_default_variant(int compute);
+// Resident workgroups per CU of a variant (persistent grid sizing).
+int gemm_blocks_per_cu(int compute, int variant);
+
+}  // namespace sym

@@ -1,0 +1,331 @@
+// Plan builders: block copies (permute / fuse / split), sector GEMM lists and
+// SU(2) recoupling tables.
+#include <algorithm>
+#include <numeric>
+
+#include "plan.hpp"
+
+namespace sym {
+
+LayoutOpts workspace_opts(int32_t dtype, bool trans) {
+    LayoutOpts o;
+    o.trans = trans;
+    o.ld_align = dtype == SYM_BF16 ? 8 : 4;   // 16-byte rows
+    o.base_align = 64;                        // 128/256-byte sector bases
+    return o;
+}
+
+namespace {
+
+template <typename T>
+DevMemPtr upload_vec(const Allocator& alloc, const std::vector<T>& v) {
+    if (v.empty()) return nullptr;
+    DevMemPtr m = alloc(v.size() * sizeof(T));
+    hipError_t e = hipMemcpy(m->ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) throw Error(SYM_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// CopyProgram
+// ---------------------------------------------------------------------------
+
+void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
+                      int64_t src_base, int64_t dst_base) {
+    const int rank = dst.rank;
+    if (src.rank != rank || static_cast<int>(perm.size()) != rank) throw Error(SYM_E_ARG, "permutation rank mismatch");
+    int32_t lab[SYM_MAX_RANK];
+    for (const Block& b : dst.blocks) {
+        for (int i = 0; i < rank; ++i) lab[perm[static_cast<size_t>(i)]] = b.labels[static_cast<size_t>(i)];
+        const int32_t si = src.find_block(lab, b.internal);
+        if (si < 0) throw Error(SYM_E_MISMATCH, "destination block has no source block");
+        const Block& sb = src.blocks[static_cast<size_t>(si)];
+        // dims in destination leg order, outermost first
+        int64_t sz[SYM_MAX_RANK], ss[SYM_MAX_RANK], ds[SYM_MAX_RANK];
+        int nd = 0;
+        for (int i = 0; i < rank; ++i) {
+            if (b.shape[static_cast<size_t>(i)] == 1) continue;
+            sz[nd] = b.shape[static_cast<size_t>(i)];
+            ss[nd] = sb.stride[static_cast<size_t>(perm[static_cast<size_t>(i)])];
+            ds[nd] = b.stride[static_cast<size_t>(i)];
+            ++nd;
+        }
+        // merge an outer dim into the next inner one when both sides are contiguous across them
+        int64_t msz[SYM_MAX_RANK], mss[SYM_MAX_RANK], mds[SYM_MAX_RANK];
+        int m = 0;
+        for (int i = nd - 1; i >= 0; --i) {
+            if (m > 0 && ss[i] == mss[m - 1] * msz[m - 1] && ds[i] == mds[m - 1] * msz[m - 1]) {
+                msz[m - 1] *= sz[i];
+            } else {
+                msz[m] = sz[i];
+                mss[m] = ss[i];
+                mds[m] = ds[i];
+                ++m;
+            }
+        }
+        if (m == 0) {
+            msz[0] = 1;
+            mss[0] = 1;
+            mds[0] = 1;
+            m = 1;
+        }
+        if (m > kMaxCopyDims) throw Error(SYM_E_UNSUPPORTED, "block copy needs more than 6 strided dims");
+        if (b.size > INT32_MAX) throw Error(SYM_E_UNSUPPORTED, "block exceeds 2^31 elements");
+        CopyOp op{};
+        op.src_off = src_base + sb.offset;
+        op.dst_off = dst_base + b.offset;
+        for (int d = 0; d < kMaxCopyDims; ++d) {
+            op.size[d] = 1;
+            op.sstride[d] = 0;
+            op.dstride[d] = 0;
+        }
+        // msz[0] is innermost; right-align so that index kMaxCopyDims-1 is innermost
+        for (int k = 0; k < m; ++k) {
+            const int d = kMaxCopyDims - 1 - k;
+            op.size[d] = static_cast<int32_t>(msz[k]);
+            op.sstride[d] = mss[k];
+            op.dstride[d] = mds[k];
+        }
+        op.ndim = m;
+        op.count = static_cast<int32_t>(b.size);
+        op.src_buf = src_buf;
+        op.dst_buf = dst_buf;
+        ops.push_back(op);
+    }
+}
+
+void CopyProgram::finalize() {
+    constexpr int32_t kChunk = 4096;     // elements per task
+    constexpr int64_t kPerWg = 4096;     // elements a workgroup aims for
+    constexpr int32_t kMaxTasksPerWg = 64;
+    tasks.clear();
+    wg_begin.clear();
+    for (size_t i = 0; i < ops.size(); ++i)
+        for (int32_t s = 0; s < ops[i].count; s += kChunk)
+            tasks.push_back({static_cast<int32_t>(i), s, std::min(kChunk, ops[i].count - s), 0});
+    wg_begin.push_back(0);
+    int64_t acc = 0;
+    int32_t n_in = 0;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+        acc += tasks[t].count;
+        ++n_in;
+        if (acc >= kPerWg || n_in >= kMaxTasksPerWg) {
+            wg_begin.push_back(static_cast<int32_t>(t + 1));
+            acc = 0;
+            n_in = 0;
+        }
+    }
+    if (wg_begin.back() != static_cast<int32_t>(tasks.size())) wg_begin.push_back(static_cast<int32_t>(tasks.size()));
+}
+
+void CopyProgram::upload(const Allocator& alloc) {
+    d_ops = upload_vec(alloc, ops);
+    d_tasks = upload_vec(alloc, tasks);
+    d_wg = upload_vec(alloc, wg_begin);
+}
+
+hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
+    if (ops.empty()) return hipSuccess;
+    return launch_permute(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
+                          static_cast<const CopyTask*>(d_tasks->ptr), static_cast<const int32_t*>(d_wg->ptr),
+                          static_cast<int32_t>(wg_begin.size()) - 1, bufs, s);
+}
+
+// ---------------------------------------------------------------------------
+// GemmProgram
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// GEMM view of a sector: outer tuples (matrix rows as stored) and inner
+// tuples (the contiguous dimension).
+struct View {
+    const std::vector<Tuple>* outer;
+    const std::vector<Tuple>* inner;
+    int64_t n_outer, n_inner, ld, offset;
+};
+
+View view_of(const Desc& d, const Sector& s) {
+    if (d.opts.trans) return {&s.col_tuples, &s.row_tuples, s.cols, s.rows, s.ld, s.offset};
+    return {&s.row_tuples, &s.col_tuples, s.rows, s.cols, s.ld, s.offset};
+}
+
+bool same_tuples(const std::vector<Tuple>& a, const std::vector<Tuple>& b) {
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i)
+        if (!(a[i] == b[i]) || a[i].dim != b[i].dim) return false;
+    return true;
+}
+
+// sector index of each outer tuple (U(1): a tuple lies in one sector).
+std::unordered_map<std::string, int32_t> outer_index(const Desc& d) {
+    std::unordered_map<std::string, int32_t> m;
+    for (size_t si = 0; si < d.sectors.size(); ++si) {
+        View v = view_of(d, d.sectors[si]);
+        for (const Tuple& t : *v.outer) m[label_key(t.lab.data(), t.n, 0)] = static_cast<int32_t>(si);
+    }
+    return m;
+}
+
+}  // namespace
+
+void GemmProgram::add(const Desc& Z, const Desc& X, const Desc& Y, int z_buf, int x_buf, int y_buf, int64_t z_base,
+                      int64_t x_base, int64_t y_base) {
+    if (Z.opts.trans) throw Error(SYM_E_UNSUPPORTED, "GEMM output must not be transposed");
+    const bool su2 = Z.group == SYM_SU2;
+    std::unordered_map<std::string, int32_t> xi, yi;
+    if (!su2) {
+        xi = outer_index(X);
+        yi = outer_index(Y);
+    }
+    for (const Sector& zs : Z.sectors) {
+        GemmProb p{};
+        p.M = static_cast<int32_t>(zs.rows);
+        p.N = static_cast<int32_t>(zs.cols);
+        p.c_off = z_base + zs.offset;
+        p.ldc = static_cast<int32_t>(zs.ld);
+        p.c_buf = z_buf;
+        p.a_buf = x_buf;
+        p.b_buf = y_buf;
+        p.lda = p.ldb = 1;
+        p.K = 0;
+        int32_t xs = -1, ys = -1;
+        if (su2) {
+            xs = X.find_sector(zs.label);
+            ys = Y.find_sector(zs.label);
+        } else {
+            if (zs.row_tuples.empty() || zs.col_tuples.empty()) continue;
+            auto a = xi.find(label_key(zs.row_tuples[0].lab.data(), zs.row_tuples[0].n, 0));
+            auto b = yi.find(label_key(zs.col_tuples[0].lab.data(), zs.col_tuples[0].n, 0));
+            if (a != xi.end()) xs = a->second;
+            if (b != yi.end()) ys = b->second;
+        }
+        if (xs >= 0 && ys >= 0) {
+            View xv = view_of(X, X.sectors[static_cast<size_t>(xs)]);
+            View yv = view_of(Y, Y.sectors[static_cast<size_t>(ys)]);
+            if (!same_tuples(*xv.outer, zs.row_tuples) || !same_tuples(*yv.outer, zs.col_tuples))
+                throw Error(SYM_E_MISMATCH, "operand sectors do not line up with the output sector");
+            if (!same_tuples(*xv.inner, *yv.inner))
+                throw Error(SYM_E_MISMATCH, "contracted tuples differ between the operands");
+            p.K = static_cast<int32_t>(xv.n_inner);
+            p.a_off = x_base + xv.offset;
+            p.b_off = y_base + yv.offset;
+            p.lda = static_cast<int32_t>(xv.ld);
+            p.ldb = static_cast<int32_t>(yv.ld);
+        }
+        if (zs.rows > INT32_MAX || zs.cols > INT32_MAX) throw Error(SYM_E_UNSUPPORTED, "sector too large");
+        flops += 2 * static_cast<int64_t>(p.M) * p.N * p.K;
+        probs.push_back(p);
+    }
+}
+
+void GemmProgram::finalize(int v) {
+    variant = v;
+    const GemmVariant gv = gemm_variant(compute, v);
+    // longest-processing-time order: all tiles of one sector cost ~K, so sort
+    // sectors by K (then size) descending and emit their tiles together.
+    std::vector<int32_t> order(probs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const GemmProb& x = probs[static_cast<size_t>(a)];
+        const GemmProb& y = probs[static_cast<size_t>(b)];
+        if (x.K != y.K) return x.K > y.K;
+        return static_cast<int64_t>(x.M) * x.N > static_cast<int64_t>(y.M) * y.N;
+    });
+    tiles.clear();
+    for (int32_t pi : order) {
+        const GemmProb& p = probs[static_cast<size_t>(pi)];
+        const int tm = (p.M + gv.mt - 1) / gv.mt, tn = (p.N + gv.nt - 1) / gv.nt;
+        for (int i = 0; i < tm; ++i)
+            for (int j = 0; j < tn; ++j) tiles.push_back({pi, i, j, 0});
+    }
+}
+
+void GemmProgram::upload(const Allocator& alloc) {
+    d_probs = upload_vec(alloc, probs);
+    d_tiles = upload_vec(alloc, tiles);
+}
+
+hipError_t GemmProgram::launch(const PtrTable& bufs, int grid, hipStream_t s) const {
+    if (tiles.empty()) return hipSuccess;
+    const int g = std::max(1, std::min(grid, static_cast<int>(tiles.size())));
+    return launch_gemm(compute, variant, static_cast<const GemmProb*>(d_probs->ptr),
+                       static_cast<const GemmTile*>(d_tiles->ptr), static_cast<int32_t>(tiles.size()), g, bufs, s);
+}
+
+// ---------------------------------------------------------------------------
+// RecoupleProgram: LEFT tree (legs 1,2,3,4) -> RIGHT tree on legs (1,3,2,4)
+// ---------------------------------------------------------------------------
+
+void RecoupleProgram::build(const Desc& in, const Desc& out) {
+    if (in.group != SYM_SU2 || in.tree != SYM_TREE_LEFT || out.tree != SYM_TREE_RIGHT)
+        throw Error(SYM_E_UNSUPPORTED, "recoupling maps the LEFT tree to the RIGHT tree");
+    size_t i = 0;
+    while (i < in.blocks.size()) {
+        const Block& b0 = in.blocks[i];
+        size_t j = i;
+        // input blocks of one label tuple are adjacent in canonical order
+        while (j < in.blocks.size() &&
+               std::equal(in.blocks[j].labels.begin(), in.blocks[j].labels.begin() + 4, b0.labels.begin()))
+            ++j;
+        const int j1 = b0.labels[0], j2 = b0.labels[1], j3 = b0.labels[2], j4 = b0.labels[3];
+        std::vector<int32_t> es, fs;
+        for (size_t k = i; k < j; ++k) es.push_back(in.blocks[k].internal);
+        for (int32_t f = 0; f <= 2 * std::max(std::max(j1, j2), std::max(j3, j4)) + 1; ++f)
+            if (triangle(j2, j3, f) && triangle(j1, f, j4)) fs.push_back(f);
+        if (es.size() != fs.size()) throw Error(SYM_E_MISMATCH, "recoupling multiplicities differ");
+        const int n = static_cast<int>(es.size());
+        if (n > kMaxRecouple) throw Error(SYM_E_UNSUPPORTED, "too many intermediate spins");
+        FmGroup g{};
+        g.n = n;
+        for (int k = 0; k < 4; ++k) g.d[k] = static_cast<int32_t>(b0.shape[static_cast<size_t>(k)]);
+        g.in_first = static_cast<int32_t>(in_blks.size());
+        g.out_first = static_cast<int32_t>(out_blks.size());
+        g.coef_first = static_cast<int32_t>(coef.size());
+        for (size_t k = i; k < j; ++k) {
+            FmBlk fb{};
+            fb.off = in.blocks[k].offset;
+            for (int l = 0; l < 4; ++l) fb.stride[l] = in.blocks[k].stride[static_cast<size_t>(l)];
+            in_blks.push_back(fb);
+        }
+        const int32_t olab[4] = {j1, j3, j2, j4};
+        for (int32_t f : fs) {
+            const int32_t oi = out.find_block(olab, f);
+            if (oi < 0) throw Error(SYM_E_MISMATCH, "recoupled block missing from the output");
+            const Block& ob = out.blocks[static_cast<size_t>(oi)];
+            FmBlk fb{};
+            fb.off = ob.offset;
+            for (int l = 0; l < 4; ++l) fb.stride[l] = ob.stride[static_cast<size_t>(l)];
+            out_blks.push_back(fb);
+            // c[f][e] = (-1)^(j2+j3-f) F^{e f}_{j1 j2 j3 j4}   (eq:fmove2 then eq:perm11)
+            const double phase = (((j2 + j3 - f) / 2) % 2) ? -1.0 : 1.0;
+            for (int32_t e : es) coef.push_back(phase * fmove_coeff(j1, j2, j3, j4, e, f));
+        }
+        const int64_t elems = b0.size;
+        for (int64_t s = 0; s < elems; s += 256)
+            tasks.push_back({static_cast<int32_t>(groups.size()), static_cast<int32_t>(s),
+                             static_cast<int32_t>(std::min<int64_t>(256, elems - s)), 0});
+        groups.push_back(g);
+        i = j;
+    }
+}
+
+void RecoupleProgram::upload(const Allocator& alloc) {
+    d_groups = upload_vec(alloc, groups);
+    d_in = upload_vec(alloc, in_blks);
+    d_out = upload_vec(alloc, out_blks);
+    d_coef = upload_vec(alloc, coef);
+    d_tasks = upload_vec(alloc, tasks);
+}
+
+hipError_t RecoupleProgram::launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const {
+    if (tasks.empty()) return hipSuccess;
+    return launch_recouple(static_cast<const FmGroup*>(d_groups->ptr), static_cast<const FmBlk*>(d_in->ptr),
+                           static_cast<const FmBlk*>(d_out->ptr), static_cast<const double*>(d_coef->ptr),
+                           static_cast<const FmTask*>(d_tasks->ptr), static_cast<int32_t>(tasks.size()), bufs, in_buf,
+                           out_buf, s);
+}
+
+}  // namespace sym

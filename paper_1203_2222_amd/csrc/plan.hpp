@@ -1,0 +1,78 @@
+// Host-side plans: everything a contraction or permute needs that depends
+// only on the symmetry structure (block matching, offsets, tile lists,
+// recoupling coefficients), built once, uploaded once and cached.  This is
+// the thesis' "precompute once, reuse every iteration" (section "Permutation
+// of indices" of the tree-decomposition chapter; Abelian chapter preface).
+#pragma once
+
+#include <functional>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace sym {
+
+// Device allocation owned by a plan, released through the context allocator.
+struct DevMem {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    std::function<void(void*)> release;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() {
+        if (ptr && release) release(ptr);
+    }
+};
+using DevMemPtr = std::shared_ptr<DevMem>;
+using Allocator = std::function<DevMemPtr(size_t)>;
+
+// A batch of block copies launched together.
+struct CopyProgram {
+    std::vector<CopyOp> ops;
+    std::vector<CopyTask> tasks;
+    std::vector<int32_t> wg_begin;
+    int src_dtype = SYM_F32, dst_dtype = SYM_F32;
+    // device copies
+    DevMemPtr d_ops, d_tasks, d_wg;
+
+    // dst block j <- src block with labels dst.labels permuted back by perm
+    void add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
+             int64_t src_base = 0, int64_t dst_base = 0);
+    void finalize();
+    void upload(const Allocator& alloc);
+    bool empty() const { return ops.empty(); }
+    hipError_t launch(const PtrTable& bufs, hipStream_t s) const;
+};
+
+struct GemmProgram {
+    std::vector<GemmProb> probs;
+    std::vector<GemmTile> tiles;
+    int compute = SYM_F32;
+    int variant = 0;
+    int64_t flops = 0;
+    DevMemPtr d_probs, d_tiles;
+
+    // One GEMM per sector of Z: Z = X * Y^T (X: M x K, Y: N x K, K-contiguous).
+    void add(const Desc& Z, const Desc& X, const Desc& Y, int z_buf, int x_buf, int y_buf, int64_t z_base = 0,
+             int64_t x_base = 0, int64_t y_base = 0);
+    void finalize(int variant);
+    void upload(const Allocator& alloc);
+    hipError_t launch(const PtrTable& bufs, int grid, hipStream_t s) const;
+};
+
+struct RecoupleProgram {
+    std::vector<FmGroup> groups;
+    std::vector<FmBlk> in_blks, out_blks;
+    std::vector<double> coef;
+    std::vector<FmTask> tasks;
+    DevMemPtr d_groups, d_in, d_out, d_coef, d_tasks;
+    void build(const Desc& in, const Desc& out);
+    void upload(const Allocator& alloc);
+    hipError_t launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const;
+};
+
+// Layout the library uses for its own fused operands.
+LayoutOpts workspace_opts(int32_t dtype, bool trans);
+
+}  // namespace sym

@@ -1,0 +1,324 @@
+"""Python handles over the C-ABI: a context (torch caching allocator bridge
+and plan cache) and symmetric tensors whose data lives in a torch buffer.
+
+Every compute call here forwards to libsymtensor.so; torch provides device
+memory and the current HIP stream only.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_float, c_int32, c_int64, c_void_p
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+_GROUPS = {"U1": L.SYM_U1, "SU2": L.SYM_SU2}
+_ARROWS = {"in": L.SYM_IN, "out": L.SYM_OUT}
+_DTYPES = {"f32": L.SYM_F32, "bf16": L.SYM_BF16}
+_TORCH = {L.SYM_F32: torch.float32, L.SYM_BF16: torch.bfloat16}
+
+
+def _dtype_code(dtype) -> int:
+    if isinstance(dtype, int):
+        return dtype
+    if dtype in (torch.float32, "f32", "float32"):
+        return L.SYM_F32
+    if dtype in (torch.bfloat16, "bf16", "bfloat16"):
+        return L.SYM_BF16
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+@dataclass
+class BlockInfo:
+    labels: Tuple[int, ...]
+    internal: Optional[int]
+    offset: int
+    shape: Tuple[int, ...]
+    strides: Tuple[int, ...]
+
+
+class SymTensor:
+    """A symmetric tensor: a C handle plus the torch buffer it points into."""
+
+    def __init__(self, ctx: "Context", handle: int, data: Optional[torch.Tensor], spec, n_row: int, dtype: int):
+        self.ctx = ctx
+        self.handle = c_void_p(handle)
+        self.spec = spec
+        self.n_row = n_row
+        self.dtype = dtype
+        self.data = None
+        if data is not None:
+            self.set_data(data)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            L.lib().sym_tensor_destroy(h)
+            self.handle = None
+
+    @property
+    def rank(self) -> int:
+        return len(self.spec.legs)
+
+    def numel(self) -> int:
+        n = c_int64()
+        L.check(L.lib().sym_tensor_numel(self.handle, byref(n)))
+        return n.value
+
+    def set_data(self, data: torch.Tensor) -> None:
+        if data.dtype != _TORCH[self.dtype]:
+            raise TypeError(f"buffer dtype {data.dtype} does not match the tensor's {_TORCH[self.dtype]}")
+        if not data.is_contiguous() or data.numel() < self.numel():
+            raise ValueError("buffer must be contiguous and hold numel() elements")
+        if not data.is_cuda:
+            raise ValueError("buffer must live on the GPU")
+        self.data = data
+        L.check(L.lib().sym_tensor_set_data(self.handle, c_void_p(data.data_ptr())))
+
+    def num_blocks(self) -> int:
+        n = c_int64()
+        L.check(L.lib().sym_tensor_num_blocks(self.handle, byref(n)))
+        return n.value
+
+    def blocks(self) -> List[BlockInfo]:
+        r = self.rank
+        out = []
+        labels = (c_int32 * max(1, r))()
+        shape = (c_int64 * max(1, r))()
+        strides = (c_int64 * max(1, r))()
+        internal = c_int32()
+        off = c_int64()
+        for i in range(self.num_blocks()):
+            L.check(L.lib().sym_tensor_block_info(self.handle, i, labels, byref(internal), byref(off), shape, strides))
+            out.append(BlockInfo(tuple(labels[:r]), None if internal.value < 0 else internal.value, off.value,
+                                 tuple(shape[:r]), tuple(strides[:r])))
+        return out
+
+    def sectors(self):
+        n = c_int64()
+        L.check(L.lib().sym_tensor_num_sectors(self.handle, byref(n)))
+        out = []
+        lab, rows, cols, off = c_int32(), c_int64(), c_int64(), c_int64()
+        for i in range(n.value):
+            L.check(L.lib().sym_tensor_sector_info(self.handle, i, byref(lab), byref(rows), byref(cols), byref(off)))
+            out.append((lab.value, rows.value, cols.value, off.value))
+        return out
+
+    def block_view(self, b: BlockInfo) -> torch.Tensor:
+        """Strided view of one block inside the data buffer."""
+        return torch.as_strided(self.data, b.shape, b.strides, b.offset)
+
+
+def _legs_struct(spec):
+    keep = []
+    arr = (L.SymLeg * max(1, len(spec.legs)))()
+    for i, leg in enumerate(spec.legs):
+        lab = (ctypes.c_int32 * max(1, len(leg.labels)))(*leg.labels)
+        deg = (ctypes.c_int64 * max(1, len(leg.degs)))(*leg.degs)
+        keep += [lab, deg]
+        arr[i].n = len(leg.labels)
+        arr[i].label = lab
+        arr[i].deg = deg
+        arr[i].arrow = _ARROWS[leg.arrow]
+    return arr, keep
+
+
+def _stream(stream=None) -> c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+class _Spec:
+    """Leg description of a tensor produced by the library."""
+
+    def __init__(self, group, legs, tree=0, qtot=0):
+        self.group, self.legs, self.tree, self.qtot = group, tuple(legs), tree, qtot
+
+
+class Context:
+    """Owns a sym_ctx whose workspaces come from torch's caching allocator."""
+
+    def __init__(self, use_torch_allocator: bool = True):
+        self._alloc_cb = L.ALLOC_FN(self._alloc) if use_torch_allocator else L.ALLOC_FN()
+        self._free_cb = L.FREE_FN(self._free) if use_torch_allocator else L.FREE_FN()
+        h = c_void_p()
+        L.check(L.lib().sym_ctx_create(self._alloc_cb, self._free_cb, None, byref(h)))
+        self.handle = h
+
+    @staticmethod
+    def _alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:   # out of memory: the library reports SYM_E_NOMEM
+            return None
+
+    @staticmethod
+    def _free(ptr, user):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().sym_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    # ----- tensors -----------------------------------------------------------
+    def tensor(self, spec, n_row: int, dtype="f32", data: Optional[torch.Tensor] = None,
+               device="cuda") -> SymTensor:
+        """Handle for ``spec`` (a ``workloads.TensorSpec``-like object) with n_row
+        row legs; allocates a zeroed buffer when ``data`` is None."""
+        dt = _dtype_code(dtype)
+        legs, keep = _legs_struct(spec)
+        h = c_void_p()
+        L.check(L.lib().sym_tensor_create(self.handle, _GROUPS[spec.group], len(spec.legs), legs, n_row,
+                                          int(getattr(spec, "tree", 0)), int(getattr(spec, "qtot", 0)), dt,
+                                          None, byref(h)))
+        t = SymTensor(self, h.value, None, spec, n_row, dt)
+        if data is None:
+            data = torch.zeros(t.numel(), dtype=_TORCH[dt], device=device)
+        t.set_data(data)
+        return t
+
+    def describe(self, spec, n_row: int, dtype="f32") -> SymTensor:
+        """Handle without data (host-side queries: sizes, blocks, sectors)."""
+        dt = _dtype_code(dtype)
+        legs, keep = _legs_struct(spec)
+        h = c_void_p()
+        L.check(L.lib().sym_tensor_create(self.handle, _GROUPS[spec.group], len(spec.legs), legs, n_row,
+                                          int(getattr(spec, "tree", 0)), int(getattr(spec, "qtot", 0)), dt,
+                                          None, byref(h)))
+        return SymTensor(self, h.value, None, spec, n_row, dt)
+
+    def _wrap_output(self, h: c_void_p, spec, n_row: int, dtype: int, out_data, device) -> SymTensor:
+        t = SymTensor(self, h.value, None, spec, n_row, dtype)
+        if out_data is None:
+            out_data = torch.empty(t.numel(), dtype=_TORCH[dtype], device=device)
+        t.set_data(out_data)
+        return t
+
+    # ----- permute / fuse / recouple -------------------------------------------
+    def permute_fuse(self, t: SymTensor, perm: Sequence[int], n_row: int, dtype=None, out=None,
+                     stream=None) -> SymTensor:
+        dt = t.dtype if dtype is None else _dtype_code(dtype)
+        p = L.i32_array(perm)
+        h = c_void_p()
+        L.check(L.lib().sym_permute_fuse_output(self.handle, t.handle, p, n_row, dt, None, byref(h)))
+        legs = [t.spec.legs[i] for i in perm]
+        tree = getattr(t.spec, "tree", 0)
+        if t.spec.group == "SU2" and list(perm) == [0, 2, 1, 3]:
+            tree = L.SYM_TREE_RIGHT
+        res = self._wrap_output(h, _Spec(t.spec.group, legs, tree, getattr(t.spec, "qtot", 0)), n_row, dt,
+                                None if out is None else out, t.data.device)
+        L.check(L.lib().sym_permute_fuse(self.handle, t.handle, p, n_row, res.handle, _stream(stream)))
+        return res
+
+    # ----- contraction -------------------------------------------------------------
+    def contract_output(self, A: SymTensor, B: SymTensor, axes_a, axes_b, data=None) -> SymTensor:
+        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
+        h = c_void_p()
+        L.check(L.lib().sym_contract_output(self.handle, A.handle, B.handle, len(axes_a), aa, ab, None, byref(h)))
+        fa = [i for i in range(A.rank) if i not in axes_a]
+        fb = [i for i in range(B.rank) if i not in axes_b]
+        legs = [A.spec.legs[i] for i in fa] + [B.spec.legs[i] for i in fb]
+        tree = getattr(B.spec, "tree", 0) if A.spec.group == "SU2" else 0
+        qtot = getattr(A.spec, "qtot", 0) + getattr(B.spec, "qtot", 0)
+        n_row = 2 if A.spec.group == "SU2" else len(fa)
+        return self._wrap_output(h, _Spec(A.spec.group, legs, tree, qtot), n_row, L.SYM_F32, data, A.data.device)
+
+    def contract(self, A: SymTensor, B: SymTensor, axes_a, axes_b, compute="f32", out: SymTensor = None,
+                 stream=None) -> SymTensor:
+        C = out if out is not None else self.contract_output(A, B, axes_a, axes_b)
+        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
+        L.check(L.lib().sym_contract(self.handle, A.handle, B.handle, len(axes_a), aa, ab, _dtype_code(compute),
+                                     C.handle, _stream(stream)))
+        return C
+
+    def contract_batched(self, As, Bs, axes_a, axes_b, compute="bf16", outs=None, stream=None):
+        Cs = outs if outs is not None else [self.contract_output(a, b, axes_a, axes_b) for a, b in zip(As, Bs)]
+        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
+        L.check(L.lib().sym_contract_batched(self.handle, len(As), L.ptr_array(a.handle.value for a in As),
+                                             L.ptr_array(b.handle.value for b in Bs), len(axes_a), aa, ab,
+                                             _dtype_code(compute), L.ptr_array(c.handle.value for c in Cs),
+                                             _stream(stream)))
+        return Cs
+
+    def contract_backward(self, A, B, dC, axes_a, axes_b, compute="f32", need_a=True, need_b=True, dA=None,
+                          dB=None, stream=None):
+        if need_a and dA is None:
+            dA = self.tensor(A.spec, A.n_row, "f32", device=A.data.device)
+        if need_b and dB is None:
+            dB = self.tensor(B.spec, B.n_row, "f32", device=B.data.device)
+        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
+        L.check(L.lib().sym_contract_backward(self.handle, A.handle, B.handle, dC.handle, len(axes_a), aa, ab,
+                                              _dtype_code(compute), dA.handle if need_a else None,
+                                              dB.handle if need_b else None, _stream(stream)))
+        return (dA if need_a else None), (dB if need_b else None)
+
+    def flops(self, A, B, axes_a, axes_b) -> int:
+        f = c_int64()
+        L.check(L.lib().sym_contract_flops(self.handle, A.handle, B.handle, len(axes_a), L.i32_array(axes_a),
+                                           L.i32_array(axes_b), byref(f)))
+        return f.value
+
+    # ----- graphs, timing, tuning ------------------------------------------------
+    def graph_batched(self, As, Bs, axes_a, axes_b, compute, Cs, stream) -> "Graph":
+        h = c_void_p()
+        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
+        L.check(L.lib().sym_graph_create_batched(self.handle, len(As), L.ptr_array(a.handle.value for a in As),
+                                                 L.ptr_array(b.handle.value for b in Bs), len(axes_a), aa, ab,
+                                                 _dtype_code(compute), L.ptr_array(c.handle.value for c in Cs),
+                                                 _stream(stream), byref(h)))
+        return Graph(h, (As, Bs, Cs))
+
+    def set_timing(self, on: bool) -> None:
+        L.check(L.lib().sym_ctx_set_timing(self.handle, 1 if on else 0))
+
+    def phase_ms(self, phase: int) -> float:
+        ms = c_float()
+        L.check(L.lib().sym_ctx_phase_ms(self.handle, phase, byref(ms)))
+        return ms.value
+
+    def set_variant(self, compute, variant: int) -> None:
+        L.check(L.lib().sym_ctx_set_variant(self.handle, _dtype_code(compute), variant))
+
+    def tune_batched(self, As, Bs, axes_a, axes_b, compute, Cs, stream=None) -> int:
+        best = c_int32()
+        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
+        L.check(L.lib().sym_tune_batched(self.handle, len(As), L.ptr_array(a.handle.value for a in As),
+                                         L.ptr_array(b.handle.value for b in Bs), len(axes_a), aa, ab,
+                                         _dtype_code(compute), L.ptr_array(c.handle.value for c in Cs),
+                                         _stream(stream), byref(best)))
+        return best.value
+
+
+class Graph:
+    def __init__(self, handle: c_void_p, keep):
+        self.handle = handle
+        self._keep = keep   # the tensors whose pointers the graph captured
+
+    def launch(self, stream=None) -> None:
+        L.check(L.lib().sym_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().sym_graph_destroy(self.handle)
+            self.handle = None
+
+
+def num_variants(compute) -> int:
+    n = c_int32()
+    L.check(L.lib().sym_num_variants(_dtype_code(compute), byref(n)))
+    return n.value
+
+
+def fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE) -> float:
+    return L.lib().sym_fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE)

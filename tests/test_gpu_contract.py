@@ -1,0 +1,158 @@
+"""GPU parity of the contraction path (fuse -> grouped MFMA GEMM -> split)
+against the FP64 oracle, element by element."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import contract as K
+from oracle import tensors as T
+from tests.gpu_util import bf16_round, draw, host, rel_err, say, to_canonical
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+BF16_TOL = 3e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1203_2222_amd as P
+    return P.Context()
+
+
+def _run(ctx, c, compute, canonical_out=True):
+    g = W.generator(c.seed, "cuda")
+    a = draw(c.A, g)
+    b = draw(c.B, g)
+    A = ctx.tensor(c.A, len(c.A.legs), "f32", data=a)
+    B = ctx.tensor(c.B, len(c.B.legs), "f32", data=b)
+    C = ctx.contract(A, B, c.axes_a, c.axes_b, compute)
+    Cc = to_canonical(ctx, C) if canonical_out else C
+    fa = a.double().cpu().numpy()
+    fb = b.double().cpu().numpy()
+    return fa, fb, host(Cc)
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_config1_matches_dense_oracle(ctx, compute):
+    say(f"case config1 compute={compute}")
+    c = W.config1()
+    fa, fb, fc = _run(ctx, c, compute)
+    sc = K.result_spec(c.A, c.B, c.axes_a, c.axes_b)
+    ref = T.from_dense(sc, K.contract_dense(T.to_dense(c.A, fa), T.to_dense(c.B, fb), c.axes_a, c.axes_b))
+    assert fc.shape == ref.shape
+    err = rel_err(fc, ref)
+    say(f"  rel err {err:.3e}")
+    if compute == "f32":
+        assert err <= FP32_TOL
+    else:
+        assert err <= BF16_TOL
+        _, ref16 = K.contract_pairs(c.A, bf16_round(fa), c.B, bf16_round(fb), c.axes_a, c.axes_b)
+        assert rel_err(fc, ref16) <= 1e-5
+
+
+def test_config4_multi_tile_sectors_fp32(ctx):
+    # sectors up to 1976 wide: many 128x128 tiles and ragged edges
+    say("case config4 forward f32")
+    c = W.config4()
+    fa, fb, fc = _run(ctx, c, "f32")
+    _, ref = K.contract_sectors(c.A, fa, c.B, fb, c.axes_a, c.axes_b)
+    err = rel_err(fc, ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= FP32_TOL
+    assert np.max(np.abs(fc - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def test_sector_major_output_blocks(ctx):
+    # C left in its sector-major layout: compare block views with the oracle's blocks
+    say("case config1 sector-major output")
+    c = W.config1()
+    g = W.generator(5, "cuda")
+    a, b = draw(c.A, g), draw(c.B, g)
+    A = ctx.tensor(c.A, 4, data=a)
+    B = ctx.tensor(c.B, 4, data=b)
+    C = ctx.contract(A, B, c.axes_a, c.axes_b, "f32")
+    torch.cuda.synchronize()
+    sc, ref = K.contract_pairs(c.A, a.double().cpu().numpy(), c.B, b.double().cpu().numpy(), c.axes_a, c.axes_b)
+    ref_blocks = T.split_flat(sc, ref)
+    blocks = C.blocks()
+    assert sorted(bl.labels for bl in blocks) == sorted(k[0] for k in ref_blocks)
+    for bl in blocks:
+        got = C.block_view(bl).double().cpu().numpy()
+        np.testing.assert_allclose(got, ref_blocks[(bl.labels, None)], rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("qa,qb", [(0, 0), (1, -2)])
+def test_general_axes_charges_and_layouts(ctx, qa, qb):
+    say(f"case general axes qa={qa} qb={qb}")
+    l1 = W.u1_leg(-1, 2, [3, 1, 5, 2], "in")
+    l2 = W.u1_leg(-2, 1, [2, 7, 2, 1], "out")
+    l3 = W.u1_leg(0, 2, [9, 4, 1], "in")
+    Aspec = W.TensorSpec(W.U1, (l1, l2, l3, l2), qtot=qa)
+    Bspec = W.TensorSpec(W.U1, (l3.flipped(), l1, l2.flipped(), l1.flipped()), qtot=qb)
+    axa, axb = (2, 1), (0, 2)
+    g = W.generator(3, "cuda")
+    a, b = draw(Aspec, g), draw(Bspec, g)
+    for n_row_a, n_row_b in [(4, 4), (2, 1), (0, 3)]:
+        A = ctx.permute_fuse(ctx.tensor(Aspec, 4, data=a), (0, 1, 2, 3), n_row_a)
+        B = ctx.permute_fuse(ctx.tensor(Bspec, 4, data=b), (0, 1, 2, 3), n_row_b)
+        C = ctx.contract(A, B, axa, axb, "f32")
+        fc = host(to_canonical(ctx, C))
+        sc, ref = K.contract_pairs(Aspec, a.double().cpu().numpy(), Bspec, b.double().cpu().numpy(), axa, axb)
+        assert sc.qtot == qa + qb
+        assert rel_err(fc, ref) <= FP32_TOL
+
+
+def test_empty_sectors_are_zero_filled(ctx):
+    # contracted legs carry only charge 0: C's sectors +-1, +-2 have no
+    # contracted tuples and must come out exactly zero
+    say("case zero-K sectors")
+    lf = W.u1_leg(-1, 1, [2, 3, 2], "in")
+    lz = W.u1_leg(0, 0, [5], "out")
+    Aspec = W.TensorSpec(W.U1, (lf, lf, lz, lz))
+    lz_in = lz.flipped()
+    Bspec = W.TensorSpec(W.U1, (lz_in, lz_in, lf.flipped(), lf.flipped()))
+    g = W.generator(4, "cuda")
+    a, b = draw(Aspec, g), draw(Bspec, g)
+    A = ctx.tensor(Aspec, 4, data=a)
+    B = ctx.tensor(Bspec, 4, data=b)
+    Cspec = K.result_spec(Aspec, Bspec, (2, 3), (0, 1))
+    C = ctx.contract_output(A, B, (2, 3), (0, 1))
+    C.data.fill_(7.0)   # garbage that the zero-K tiles must overwrite
+    ctx.contract(A, B, (2, 3), (0, 1), "f32", out=C)
+    fc = host(to_canonical(ctx, C))
+    _, ref = K.contract_pairs(Aspec, a.double().cpu().numpy(), Bspec, b.double().cpu().numpy(), (2, 3), (0, 1))
+    assert T.num_elements(Cspec) == fc.size
+    assert rel_err(fc, ref) <= FP32_TOL
+    assert np.count_nonzero(ref == 0.0) > 0 and np.all(fc[ref == 0.0] == 0.0)
+
+
+def test_outer_and_full_contractions(ctx):
+    say("case outer and full contraction")
+    l1 = W.u1_leg(-1, 1, [3, 2, 4], "in")
+    Aspec = W.TensorSpec(W.U1, (l1, l1.flipped()))
+    Bspec = W.TensorSpec(W.U1, (l1, l1.flipped()))
+    g = W.generator(6, "cuda")
+    a, b = draw(Aspec, g), draw(Bspec, g)
+    A = ctx.tensor(Aspec, 2, data=a)
+    B = ctx.tensor(Bspec, 2, data=b)
+    fa, fb = a.double().cpu().numpy(), b.double().cpu().numpy()
+    C = ctx.contract(A, B, (0, 1), (1, 0), "f32")     # rank-0 result
+    fc = host(C)
+    _, ref = K.contract_pairs(Aspec, fa, Bspec, fb, (0, 1), (1, 0))
+    assert fc.size == 1 and fc[0] == pytest.approx(ref[0], rel=1e-5)
+    C = ctx.contract(A, B, (), (), "f32")              # outer product
+    fc = host(to_canonical(ctx, C))
+    _, ref = K.contract_pairs(Aspec, fa, Bspec, fb, (), ())
+    assert rel_err(fc, ref) <= FP32_TOL
+
+
+def test_repeated_calls_bitwise_deterministic(ctx):
+    say("case determinism")
+    c = W.config1()
+    g = W.generator(9, "cuda")
+    A = ctx.tensor(c.A, 4, data=draw(c.A, g))
+    B = ctx.tensor(c.B, 4, data=draw(c.B, g))
+    outs = [host(to_canonical(ctx, ctx.contract(A, B, c.axes_a, c.axes_b, comp))) for comp in ("f32", "f32", "bf16", "bf16")]
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[2], outs[3])
