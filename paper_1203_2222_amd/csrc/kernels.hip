@@ -84,6 +84,64 @@ __global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops,
     }
 }
 
+// Transposing block copy: the source is contiguous along dim tj, the
+// destination along the innermost dim.  A 64 x 64 tile is read with lanes
+// running along the source's contiguous dim, staged in LDS (row pitch 65 keeps
+// the transposed reads free of bank conflicts) and written with lanes running
+// along the destination's contiguous dim, so both sides stay coalesced.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict__ ops, const TileTask* __restrict__ tasks,
+                                                       PtrTable bufs) {
+    __shared__ Ti tile[kTile][kTile + 1];
+    const TileTask t = tasks[blockIdx.x];
+    const CopyOp& op = ops[t.op];
+    const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[op.src_buf]) + op.src_off;
+    To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[op.dst_buf])) + op.dst_off;
+    constexpr int I = kMaxCopyDims - 1;
+    const int J = op.tj;
+    int64_t so = 0, dof = 0;
+    int rem = t.outer;
+    for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d) {
+        if (d == J) continue;
+        const int sz = op.size[d];
+        const int q = rem / sz;
+        const int i = rem - q * sz;
+        rem = q;
+        so += i * op.sstride[d];
+        dof += i * op.dstride[d];
+    }
+    const int nI = op.size[I], nJ = op.size[J];
+    const int64_t sI = op.sstride[I], dI = op.dstride[I], sJ = op.sstride[J], dJ = op.dstride[J];
+    const int i0 = t.it * kTile, j0 = t.jt * kTile;
+    const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int r = 0; r < kTile / 4; ++r) {
+        const int i = i0 + hi + 4 * r, j = j0 + lo;
+        if (i < nI && j < nJ) tile[i - i0][j - j0] = src[so + i * sI + j * sJ];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = 0; r < kTile / 4; ++r) {
+        const int j = j0 + hi + 4 * r, i = i0 + lo;
+        if (i < nI && j < nJ) dst[dof + i * dI + j * dJ] = Conv<Ti, To>::f(tile[i - i0][j - j0]);
+    }
+}
+
+hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks, int32_t n_tasks,
+                                const PtrTable& bufs, hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>(n_tasks)), block(256);
+    if (src_dtype == 0 && dst_dtype == 0)
+        hipLaunchKernelGGL((k_permute_tiled<float, float>), grid, block, 0, s, ops, tasks, bufs);
+    else if (src_dtype == 0 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_permute_tiled<float, uint16_t>), grid, block, 0, s, ops, tasks, bufs);
+    else if (src_dtype == 1 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_permute_tiled<uint16_t, uint16_t>), grid, block, 0, s, ops, tasks, bufs);
+    else
+        hipLaunchKernelGGL((k_permute_tiled<uint16_t, float>), grid, block, 0, s, ops, tasks, bufs);
+    return hipGetLastError();
+}
+
 hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
     if (n_wg <= 0) return hipSuccess;

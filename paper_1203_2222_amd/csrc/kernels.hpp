@@ -25,12 +25,21 @@ struct CopyOp {
     int32_t src_buf, dst_buf;
     int32_t count;
     int32_t ndim;
+    int32_t tj;          // tiled copies: the dim that is contiguous in the source
+    int32_t pad;
 };
 
 // A slice [start, start+count) of one CopyOp's elements (in destination order).
 struct CopyTask {
     int32_t op, start, count, pad;
 };
+
+// One 64 x 64 tile of a transposing copy: rows along the destination's
+// contiguous dim (index kMaxCopyDims-1), columns along the source's (tj).
+struct TileTask {
+    int32_t op, outer, jt, it;
+};
+constexpr int kTile = 64;
 
 // One sector GEMM: C[m][n] = sum_k A[m][k] * B[n][k] (both operands K-contiguous).
 struct GemmProb {
@@ -68,6 +77,8 @@ struct FmTask {
 // Launchers (kernels.hip).  Every launcher returns the hipError_t of the launch.
 hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
+hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
+                                int32_t n_tasks, const PtrTable& bufs, hipStream_t s);
 hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles,
                        int32_t n_tiles, int32_t grid, const PtrTable& bufs, hipStream_t s);
 hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,

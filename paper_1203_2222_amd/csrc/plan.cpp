@@ -73,6 +73,11 @@ void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_
         }
         if (m > kMaxCopyDims) throw Error(SYM_E_UNSUPPORTED, "block copy needs more than 6 strided dims");
         if (b.size > INT32_MAX) throw Error(SYM_E_UNSUPPORTED, "block exceeds 2^31 elements");
+        // innermost = the destination's most contiguous dim, so that lanes write
+        // consecutive addresses (any order of the index space is valid)
+        int ord[SYM_MAX_RANK];
+        for (int k = 0; k < m; ++k) ord[k] = k;
+        std::stable_sort(ord, ord + m, [&](int x, int y) { return mds[x] < mds[y]; });
         CopyOp op{};
         op.src_off = src_base + sb.offset;
         op.dst_off = dst_base + b.offset;
@@ -81,17 +86,24 @@ void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_
             op.sstride[d] = 0;
             op.dstride[d] = 0;
         }
-        // msz[0] is innermost; right-align so that index kMaxCopyDims-1 is innermost
         for (int k = 0; k < m; ++k) {
             const int d = kMaxCopyDims - 1 - k;
-            op.size[d] = static_cast<int32_t>(msz[k]);
-            op.sstride[d] = mss[k];
-            op.dstride[d] = mds[k];
+            op.size[d] = static_cast<int32_t>(msz[ord[k]]);
+            op.sstride[d] = mss[ord[k]];
+            op.dstride[d] = mds[ord[k]];
         }
         op.ndim = m;
         op.count = static_cast<int32_t>(b.size);
         op.src_buf = src_buf;
         op.dst_buf = dst_buf;
+        op.tj = -1;
+        // a transposing copy (the source is contiguous along another dim) goes
+        // through the LDS-tiled kernel when both dims are wide enough
+        constexpr int I = kMaxCopyDims - 1;
+        if (m >= 2 && op.sstride[I] != 1 && op.size[I] >= 4) {
+            for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - m; --d)
+                if (op.sstride[d] == 1 && op.size[d] >= 4) op.tj = d;
+        }
         ops.push_back(op);
     }
 }
@@ -102,9 +114,24 @@ void CopyProgram::finalize() {
     constexpr int32_t kMaxTasksPerWg = 64;
     tasks.clear();
     wg_begin.clear();
-    for (size_t i = 0; i < ops.size(); ++i)
-        for (int32_t s = 0; s < ops[i].count; s += kChunk)
-            tasks.push_back({static_cast<int32_t>(i), s, std::min(kChunk, ops[i].count - s), 0});
+    tile_tasks.clear();
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const CopyOp& op = ops[i];
+        if (op.tj >= 0) {
+            constexpr int I = kMaxCopyDims - 1;
+            int64_t outer = 1;
+            for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d)
+                if (d != op.tj) outer *= op.size[d];
+            const int nj = (op.size[op.tj] + kTile - 1) / kTile, ni = (op.size[I] + kTile - 1) / kTile;
+            for (int64_t o = 0; o < outer; ++o)
+                for (int jt = 0; jt < nj; ++jt)
+                    for (int it = 0; it < ni; ++it)
+                        tile_tasks.push_back({static_cast<int32_t>(i), static_cast<int32_t>(o), jt, it});
+            continue;
+        }
+        for (int32_t s = 0; s < op.count; s += kChunk)
+            tasks.push_back({static_cast<int32_t>(i), s, std::min(kChunk, op.count - s), 0});
+    }
     wg_begin.push_back(0);
     int64_t acc = 0;
     int32_t n_in = 0;
@@ -124,13 +151,22 @@ void CopyProgram::upload(const Allocator& alloc) {
     d_ops = upload_vec(alloc, ops);
     d_tasks = upload_vec(alloc, tasks);
     d_wg = upload_vec(alloc, wg_begin);
+    d_tile_tasks = upload_vec(alloc, tile_tasks);
 }
 
 hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
     if (ops.empty()) return hipSuccess;
-    return launch_permute(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
-                          static_cast<const CopyTask*>(d_tasks->ptr), static_cast<const int32_t*>(d_wg->ptr),
-                          static_cast<int32_t>(wg_begin.size()) - 1, bufs, s);
+    if (!tasks.empty()) {
+        hipError_t e = launch_permute(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
+                                      static_cast<const CopyTask*>(d_tasks->ptr), static_cast<const int32_t*>(d_wg->ptr),
+                                      static_cast<int32_t>(wg_begin.size()) - 1, bufs, s);
+        if (e != hipSuccess) return e;
+    }
+    if (!tile_tasks.empty())
+        return launch_permute_tiled(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
+                                    static_cast<const TileTask*>(d_tile_tasks->ptr),
+                                    static_cast<int32_t>(tile_tasks.size()), bufs, s);
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

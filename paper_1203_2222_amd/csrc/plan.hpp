@@ -32,9 +32,10 @@ struct CopyProgram {
     std::vector<CopyOp> ops;
     std::vector<CopyTask> tasks;
     std::vector<int32_t> wg_begin;
+    std::vector<TileTask> tile_tasks;
     int src_dtype = SYM_F32, dst_dtype = SYM_F32;
     // device copies
-    DevMemPtr d_ops, d_tasks, d_wg;
+    DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks;
 
     // dst block j <- src block with labels dst.labels permuted back by perm
     void add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
