@@ -114,6 +114,94 @@ def cpu_baseline(members, As, Bs, budget_s):
     return flops / t_total / 1e12, t_total, done, flops, threads, results
 
 
+def _timed(fn, reps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def secondary(ctx, stream):
+    """Per-configuration measurements beside the headline batch (each small)."""
+    import torch
+    import workloads as W
+    out = {}
+
+    def make(c, seed=None):
+        g = W.generator(c.seed if seed is None else seed, "cuda")
+        A = ctx.tensor(c.A, 4, data=W.gaussian(ctx.describe(c.A, 4).numel(), g, "cuda"))
+        B = ctx.tensor(c.B, 4, data=W.gaussian(ctx.describe(c.B, 4).numel(), g, "cuda"))
+        return A, B, g
+
+    with torch.cuda.stream(stream):
+        # config 1: latency of one small contraction, eager vs graph replay
+        c = W.config1()
+        A, B, _ = make(c)
+        C = ctx.contract_output(A, B, c.axes_a, c.axes_b)
+        eager = _timed(lambda: ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=C, stream=stream), 200, stream)
+        graph = ctx.graph_batched([A], [B], c.axes_a, c.axes_b, "f32", [C], stream)
+        replay = _timed(lambda: graph.launch(stream), 200, stream)
+        out["u1_chi20_latency_us"] = {"eager": round(eager * 1e3, 2), "graph": round(replay * 1e3, 2),
+                                      "useful_flops": ctx.flops(A, B, c.axes_a, c.axes_b)}
+        del graph, A, B, C
+
+        # config 2: one FP32 contraction, chi = 256
+        c = W.config2()
+        A, B, _ = make(c)
+        Cs = [ctx.tensor(ctx.contract_output(A, B, c.axes_a, c.axes_b).spec, 4)]
+        fl = ctx.flops(A, B, c.axes_a, c.axes_b)
+        ms = _timed(lambda: ctx.contract_batched([A], [B], c.axes_a, c.axes_b, "f32", Cs, stream), 3, stream)
+        ph = time_phases(ctx, [A], [B], Cs, (c.axes_a, c.axes_b), "f32", 3, stream)
+        out["u1_chi256_fp32"] = {"TFLOPs": round(fl / ms / 1e9, 2), "ms": round(ms, 3),
+                                 "gemm_TFLOPs": round(fl / ph[1] / 1e9, 2),
+                                 "gemm_frac_fp32_peak": round(fl / ph[1] / 1e9 / PEAK_TFLOPS["f32"], 4)}
+        # permute bandwidth on the same tensor (the E2-style permute benchmark)
+        for perm in ((0, 2, 1, 3), (3, 2, 1, 0)):
+            P0 = ctx.permute_fuse(A, perm, 2)
+            msp = _timed(lambda: ctx.permute_into(A, perm, 2, P0, stream=stream), 5, stream)
+            out[f"permute_{''.join(map(str, perm))}_GBps"] = round(A.numel() * 8 / msp / 1e6, 1)
+            del P0
+        del A, B, Cs
+
+        # config 4: forward + hand-written backward, FP32
+        c = W.config4()
+        A, B, g = make(c)
+        C = ctx.contract_output(A, B, c.axes_a, c.axes_b)
+        dC = ctx.tensor(C.spec, C.n_row, data=W.gaussian(C.numel(), g, "cuda"))
+        dA = ctx.tensor(c.A, 4)
+        dB = ctx.tensor(c.B, 4)
+        fl = ctx.flops(A, B, c.axes_a, c.axes_b)
+        fwd = _timed(lambda: ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=C, stream=stream), 10, stream)
+        bwd = _timed(lambda: ctx.contract_backward(A, B, dC, c.axes_a, c.axes_b, "f32", dA=dA, dB=dB,
+                                                   stream=stream), 10, stream)
+        out["u1_chi128_grad_fp32"] = {"forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
+                                      "forward_TFLOPs": round(fl / fwd / 1e9, 2),
+                                      "backward_TFLOPs": round(2 * fl / bwd / 1e9, 2)}
+        del A, B, C, dC, dA, dB
+
+        # config 5: SU(2) contraction + recoupling, FP32
+        c = W.config5()
+        A, B, _ = make(c)
+        C = ctx.contract_output(A, B, c.axes_a, c.axes_b)
+        fl = ctx.flops(A, B, c.axes_a, c.axes_b)
+        ms = _timed(lambda: ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=C, stream=stream), 3, stream)
+        R = ctx.permute_fuse(C, (0, 2, 1, 3), 4)
+        msr = _timed(lambda: ctx.permute_into(C, (0, 2, 1, 3), 4, R, stream=stream), 5, stream)
+        out["su2_j4_fp32"] = {"contract_TFLOPs": round(fl / ms / 1e9, 2), "contract_ms": round(ms, 3),
+                              "recouple_ms": round(msr, 3),
+                              "recouple_GBps": round(C.numel() * 8 / msr / 1e6, 1)}
+        del A, B, C, R
+    ctx.clear()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +212,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work")
     ap.add_argument("--tune", action="store_true", help="run the GEMM autotuner before timing")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the per-configuration measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -139,6 +230,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     device = "cuda"
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, device=device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
     ctx = P.Context()
     members = W.config3_members(args.members)
     axes = (members[0].axes_a, members[0].axes_b)
@@ -238,6 +336,13 @@ def main():
                       f"host has {os.cpu_count()} CPUs, {cores} in this process's affinity",
         }
         result["rel_err_bf16_vs_fp64_oracle"] = {"max": max(errs), "members": len(errs), "tolerance": 3e-3}
+
+    if not args.no_secondary:
+        log("per-configuration measurements")
+        del As, Bs, Cs
+        ctx.clear()
+        torch.cuda.empty_cache()
+        result["per_config"] = secondary(ctx, stream)
 
     print(json.dumps(result), flush=True)
 

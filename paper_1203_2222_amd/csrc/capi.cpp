@@ -248,6 +248,26 @@ bool gemm_can_write(const Desc& want, const Desc& c) {
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// SYM_SPLIT=separate keeps the split of a canonical output as its own pass
+// (instead of the GEMM epilogue), e.g. to time the two phases apart.
+bool split_env_forced() {
+    const char* v = std::getenv("SYM_SPLIT");
+    return v && std::string(v) == "separate";
+}
+
+// Fused-operand workspace: the GEMM kernels read whole 16-byte chunks past the
+// last column of a row and rely on that padding being zero; nothing ever
+// writes it after this clear.  Plans are built outside stream capture, so the
+// device-wide synchronisation here orders the clear after any earlier use of
+// recycled memory.
+DevMemPtr zeroed(const Allocator& alloc, size_t bytes) {
+    DevMemPtr m = alloc(bytes);
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemset(m->ptr, 0, m->bytes));
+    HIP_CHECK(hipDeviceSynchronize());
+    return m;
+}
+
 std::string axes_key(int32_t n, const int32_t* a, const int32_t* b) {
     std::ostringstream k;
     for (int i = 0; i < n; ++i) k << a[i] << ',' << b[i] << ';';
@@ -311,6 +331,10 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
         plan->fuse[b.dtype == SYM_BF16 ? 1 : 0].add(b, *bf, p.perm_b, kSlotUser + count + i, kSlotWsIn, 0, b_base);
         if (gemm_can_write(*want_c, c)) {
             plan->gemm.add(c, *af, *bf, kSlotUser + 2 * count + i, kSlotWsIn, kSlotWsIn, 0, a_base, b_base);
+        } else if (!split_env_forced() &&
+                   plan->gemm.add_indirect(*want_c, c, *af, *bf, kSlotUser + 2 * count + i, kSlotWsIn, kSlotWsIn,
+                                           a_base, b_base)) {
+            // C is a canonical block list: the GEMM epilogue performs the split
         } else {
             const int64_t c_base = out_off;
             out_off = align_up(out_off + want_c->numel, 64);
@@ -319,17 +343,17 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
         }
     }
     const int var = variant_override >= 0 ? variant_override : pick_variant(ctx, compute, key);
-    plan->gemm.finalize(var);
+    plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, var);
+    plan->gemm.finalize(var, plan->grid);
     plan->flops = plan->gemm.flops;
     for (auto& f : plan->fuse) f.finalize();
     plan->split.finalize();
     Allocator alloc = ctx->allocator();
-    if (in_off) plan->ws_in = alloc(static_cast<size_t>(in_off) * dtype_size(compute));
+    if (in_off) plan->ws_in = zeroed(alloc, static_cast<size_t>(in_off) * dtype_size(compute));
     if (out_off) plan->ws_out = alloc(static_cast<size_t>(out_off) * sizeof(float));
     for (auto& f : plan->fuse) f.upload(alloc);
     plan->gemm.upload(alloc);
     plan->split.upload(alloc);
-    plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, var);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->contract_plans[key] = plan;
     return plan;
@@ -545,11 +569,9 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
     return guard([&] {
         if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
         PermuteSpec s = check_perm(*in->d, perm);
-        DescPtr want = permute_result(*in->d, s, n_row_out, out->d->dtype);
-        if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
         if (!in->data || !out->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
         std::ostringstream k;
-        k << "P|" << in->d->key << '|' << out->d->key << '|';
+        k << "P|" << in->d->key << '|' << out->d->key << '|' << n_row_out << '|';
         for (int32_t p : s.perm) k << p << ',';
         std::shared_ptr<PermutePlan> plan;
         {
@@ -558,6 +580,9 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
             if (it != ctx->permute_plans.end()) plan = it->second;
         }
         if (!plan) {
+            // validated once per structure; a cached plan implies the same check passed
+            DescPtr want = permute_result(*in->d, s, n_row_out, out->d->dtype);
+            if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
             plan = std::make_shared<PermutePlan>();
             Allocator alloc = ctx->allocator();
             if (s.recouple) {
@@ -644,10 +669,7 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
         if (!ctx || !A || !B || !dC) throw Error(SYM_E_ARG, "NULL argument");
         if (compute != SYM_F32 && compute != SYM_BF16) throw Error(SYM_E_DTYPE, "compute must be F32 or BF16");
         PairInfo p = check_pair(*A->d, *B->d, n, axesA, axesB);
-        DescPtr cw = result_desc(*A->d, *B->d, p);
         const Desc& dc = *dC->d;
-        if (dc.legs != cw->legs || dc.qtot != cw->qtot || dc.group != cw->group || dc.tree != cw->tree)
-            throw Error(SYM_E_MISMATCH, "dC does not describe the contraction result");
         if (dA && (dA->d->legs != A->d->legs || dA->d->dtype != SYM_F32 || dA->d->qtot != A->d->qtot || dA->d->tree != A->d->tree))
             throw Error(SYM_E_MISMATCH, "dA does not describe A (FP32)");
         if (dB && (dB->d->legs != B->d->legs || dB->d->dtype != SYM_F32 || dB->d->qtot != B->d->qtot || dB->d->tree != B->d->tree))
@@ -664,6 +686,9 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
         }
         // slots: 0 ws_in, 1 ws_out, 2 A, 3 B, 4 dC, 5 dA, 6 dB
         if (!plan) {
+            DescPtr cw = result_desc(*A->d, *B->d, p);
+            if (dc.legs != cw->legs || dc.qtot != cw->qtot || dc.group != cw->group || dc.tree != cw->tree)
+                throw Error(SYM_E_MISMATCH, "dC does not describe the contraction result");
             plan = std::make_shared<BackwardPlan>();
             plan->gemm.compute = compute;
             for (int i = 0; i < 2; ++i) {
@@ -713,16 +738,17 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
                     plan->split.add(*z, *dB->d, inverse(p.perm_b), 1, 6, zb, 0);
                 }
             }
-            plan->gemm.finalize(pick_variant(ctx, compute, k.str()));
+            const int var = pick_variant(ctx, compute, k.str());
+            plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, var);
+            plan->gemm.finalize(var, plan->grid);
             for (auto& c : plan->copy_in) c.finalize();
             plan->split.finalize();
             Allocator alloc = ctx->allocator();
-            if (in_off) plan->ws_in = alloc(static_cast<size_t>(in_off) * dtype_size(compute));
+            if (in_off) plan->ws_in = zeroed(alloc, static_cast<size_t>(in_off) * dtype_size(compute));
             if (out_off) plan->ws_out = alloc(static_cast<size_t>(out_off) * sizeof(float));
             for (auto& c : plan->copy_in) c.upload(alloc);
             plan->gemm.upload(alloc);
             plan->split.upload(alloc);
-            plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, plan->gemm.variant);
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->backward_plans[k.str()] = plan;
         }

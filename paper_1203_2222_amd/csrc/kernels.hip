@@ -67,19 +67,35 @@ __global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops,
         const int inner = op.size[kMaxCopyDims - 1];
         const int64_t s_in = op.sstride[kMaxCopyDims - 1], d_in = op.dstride[kMaxCopyDims - 1];
         const int end = t.start + t.count;
-        for (int e = t.start + static_cast<int>(threadIdx.x); e < end; e += 256) {
-            int rem = e / inner;
-            const int i0 = e - rem * inner;
-            int64_t so = i0 * s_in, dof = i0 * d_in;
-            for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - nd; --d) {
-                const int sz = op.size[d];
-                const int q = rem / sz;
-                const int i = rem - q * sz;
-                rem = q;
-                so += i * op.sstride[d];
-                dof += i * op.dstride[d];
+        // four independent elements per thread per pass: all loads are in
+        // flight before the first store waits on one
+        constexpr int U = 4;
+        for (int base = t.start; base < end; base += 256 * U) {
+            Ti v[U];
+            int64_t dofs[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + static_cast<int>(threadIdx.x) + u * 256;
+                ok[u] = e < end;
+                const int ee = ok[u] ? e : t.start;
+                int rem = ee / inner;
+                const int i0 = ee - rem * inner;
+                int64_t so = i0 * s_in, dof = i0 * d_in;
+                for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - nd; --d) {
+                    const int sz = op.size[d];
+                    const int q = rem / sz;
+                    const int i = rem - q * sz;
+                    rem = q;
+                    so += i * op.sstride[d];
+                    dof += i * op.dstride[d];
+                }
+                dofs[u] = dof;
+                v[u] = src[so];
             }
-            dst[dof] = Conv<Ti, To>::f(src[so]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) dst[dofs[u]] = Conv<Ti, To>::f(v[u]);
         }
     }
 }
@@ -171,27 +187,81 @@ hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const
 // second half, so every lane reads 16-byte vectors from LDS.
 // ---------------------------------------------------------------------------
 
+// Epilogue of a wave's (32 FM) x (32 FN) sub-tile starting at (mb, nb).  A
+// 32x32 MFMA result leaves lane l with column (l & 31) and, in register
+// 4*i+j, row 8*i + 4*(l >> 5) + j.  Plain outputs are row-major with ldc;
+// indirect outputs go straight to their canonical block (see GemmProb).
+template <int FM, int FN>
+__device__ __forceinline__ void store_tile(const v16f (&acc)[FM][FN], const GemmProb& p, float* C,
+                                           const EpiRow* __restrict__ rows, const EpiCol* __restrict__ cols, int mb,
+                                           int nb, int h, int r32) {
+    if (!p.indirect) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = nb + j * 32 + r32;
+                if (col >= p.N) continue;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = mb + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
+                    if (row < p.M) C[static_cast<int64_t>(row) * p.ldc + col] = acc[i][j][q];
+                }
+            }
+        return;
+    }
+    EpiCol cj[FN];
+    bool cok[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int col = nb + j * 32 + r32;
+        cok[j] = col < p.N;
+        cj[j] = cols[p.ci_off + (cok[j] ? col : 0)];
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int row = mb + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
+            if (row >= p.M) continue;
+            const EpiRow ri = rows[p.ri_off + row];
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                if (cok[j])
+                    C[ri.r0 + static_cast<int64_t>(ri.r1) * cj[j].c1 + static_cast<int64_t>(ri.r2) * cj[j].c2 + cj[j].c0] =
+                        acc[i][j][q];
+        }
+}
+
 __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// 4 consecutive FP32 of row r starting at column c, zero outside [0,R)x[0,Cn).
+// GEMM operands always come from the library's fused workspace: 16-byte
+// aligned rows whose padding past the last column is zero (the workspace is
+// cleared when allocated and no kernel ever writes the padding).  Loads are
+// therefore branch-free: the row index is clamped into the matrix (rows past
+// the end only feed output rows that the store guard drops), the column is
+// clamped into the padded row, and chunks that start past the row are zeroed.
 __device__ __forceinline__ v4f load_f32x4(const float* base, int64_t ld, int r, int c, int R, int Cn) {
-    v4f v = {0.f, 0.f, 0.f, 0.f};
-    if (r < R) {
-        const float* p = base + static_cast<int64_t>(r) * ld + c;
-        if (c + 3 < Cn && aligned16(p)) {
-            v = *reinterpret_cast<const v4f*>(p);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (c + j < Cn) v[j] = p[j];
-        }
-    }
-    return v;
+    (void)Cn;
+    const int rr = r < R ? r : R - 1;
+    const int cc = c < ld ? c : static_cast<int>(ld) - 4;
+    v4f v = *reinterpret_cast<const v4f*>(base + static_cast<int64_t>(rr) * ld + cc);
+    const v4f z = {0.f, 0.f, 0.f, 0.f};
+    return c < ld ? v : z;
+}
+
+// Address half of load_f32x4; the caller zeroes chunks with c >= ld when it
+// stores them to LDS, so nothing waits on the load right after its issue.
+__device__ __forceinline__ v4f load_f32x4_raw(const float* base, int64_t ld, int r, int c, int R) {
+    const int rr = r < R ? r : R - 1;
+    const int cc = c < ld ? c : static_cast<int>(ld) - 4;
+    return *reinterpret_cast<const v4f*>(base + static_cast<int64_t>(rr) * ld + cc);
 }
 
 template <int MT, int NT>
 __global__ __launch_bounds__(256) void k_gemm_f32(const GemmProb* __restrict__ probs, const GemmTile* __restrict__ tiles,
-                                                  int n_tiles, PtrTable bufs) {
+                                                  int n_tiles, const EpiRow* __restrict__ rows,
+                                                  const EpiCol* __restrict__ cols, PtrTable bufs) {
     constexpr int KT = 16;           // K slice per stage (floats)
     constexpr int P = KT + 4;        // LDS row pitch (floats), keeps 16-byte alignment
     constexpr int WM = MT / 2, WN = NT / 2;
@@ -227,31 +297,32 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmProb* __restrict__ p
 #pragma unroll
             for (int i = 0; i < AV; ++i) {
                 const int idx = tid + i * 256;
-                ra[i] = load_f32x4(A, p.lda, m0 + (idx >> 2), k0 + (idx & 3) * 4, p.M, p.K);
+                ra[i] = load_f32x4_raw(A, p.lda, m0 + (idx >> 2), k0 + (idx & 3) * 4, p.M);
             }
 #pragma unroll
             for (int i = 0; i < BV; ++i) {
                 const int idx = tid + i * 256;
-                rb[i] = load_f32x4(B, p.ldb, n0 + (idx >> 2), k0 + (idx & 3) * 4, p.N, p.K);
+                rb[i] = load_f32x4_raw(B, p.ldb, n0 + (idx >> 2), k0 + (idx & 3) * 4, p.N);
             }
         };
-        auto sstore = [&](int buf) {
+        const v4f zf4 = {0.f, 0.f, 0.f, 0.f};
+        auto sstore = [&](int buf, int k0) {
 #pragma unroll
             for (int i = 0; i < AV; ++i) {
                 const int idx = tid + i * 256;
-                *reinterpret_cast<v4f*>(&As[buf][(idx >> 2) * P + (idx & 3) * 4]) = ra[i];
+                *reinterpret_cast<v4f*>(&As[buf][(idx >> 2) * P + (idx & 3) * 4]) = (k0 + (idx & 3) * 4 < p.lda) ? ra[i] : zf4;
             }
 #pragma unroll
             for (int i = 0; i < BV; ++i) {
                 const int idx = tid + i * 256;
-                *reinterpret_cast<v4f*>(&Bs[buf][(idx >> 2) * P + (idx & 3) * 4]) = rb[i];
+                *reinterpret_cast<v4f*>(&Bs[buf][(idx >> 2) * P + (idx & 3) * 4]) = (k0 + (idx & 3) * 4 < p.ldb) ? rb[i] : zf4;
             }
         };
 
         const int nk = (p.K + KT - 1) / KT;
         if (nk > 0) {
             gload(0);
-            sstore(0);
+            sstore(0, 0);
         }
         __syncthreads();
         for (int kt = 0; kt < nk; ++kt) {
@@ -278,48 +349,40 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmProb* __restrict__ p
                     for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s >> 2][s & 3], bfr[j][s >> 2][s & 3],
                                                                          acc[i][j], 0, 0, 0);
-            if (kt + 1 < nk) sstore(cur ^ 1);
+            if (kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * KT);
             __syncthreads();
         }
 
         // 32x32 MFMA result: lane owns column (lane & 31); register 4*i+j is
         // row 8*i + 4*(lane >> 5) + j.
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const int col = n0 + wn * WN + j * 32 + r32;
-                if (col >= p.N) continue;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int row = m0 + wm * WM + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
-                    if (row < p.M) C[static_cast<int64_t>(row) * p.ldc + col] = acc[i][j][q];
-                }
-            }
+        store_tile<FM, FN>(acc, p, C, rows, cols, m0 + wm * WM, n0 + wn * WN, h, r32);
     }
 }
 
-// 8 consecutive BF16 of row r from column c (as 4 dwords), zero outside.
+// 8 consecutive BF16 of row r from column c (as 4 dwords); same contract as
+// load_f32x4 (workspace rows padded to 8 elements with zeros).
 __device__ __forceinline__ u32x4 load_bf16x8(const uint16_t* base, int64_t ld, int r, int c, int R, int Cn) {
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (r < R) {
-        const uint16_t* p = base + static_cast<int64_t>(r) * ld + c;
-        if (c + 7 < Cn && aligned16(p)) {
-            v = *reinterpret_cast<const u32x4*>(p);
-        } else {
-            uint16_t tmp[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) tmp[j] = (c + j < Cn) ? p[j] : static_cast<uint16_t>(0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = static_cast<uint32_t>(tmp[2 * j]) | (static_cast<uint32_t>(tmp[2 * j + 1]) << 16);
-        }
-    }
-    return v;
+    (void)Cn;
+    const int rr = r < R ? r : R - 1;
+    const int cc = c < ld ? c : static_cast<int>(ld) - 8;
+    u32x4 v = *reinterpret_cast<const u32x4*>(base + static_cast<int64_t>(rr) * ld + cc);
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    return c < ld ? v : z;
+}
+
+// Address half of load_bf16x8: the caller zeroes the chunk (c >= ld) when it
+// stores it to LDS, so that no instruction waits on the load right after it
+// is issued.
+__device__ __forceinline__ u32x4 load_bf16x8_raw(const uint16_t* base, int64_t ld, int r, int c, int R) {
+    const int rr = r < R ? r : R - 1;
+    const int cc = c < ld ? c : static_cast<int>(ld) - 8;
+    return *reinterpret_cast<const u32x4*>(base + static_cast<int64_t>(rr) * ld + cc);
 }
 
 template <int MT, int NT>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmProb* __restrict__ probs, const GemmTile* __restrict__ tiles,
-                                                   int n_tiles, PtrTable bufs) {
+                                                   int n_tiles, const EpiRow* __restrict__ rows,
+                                                  const EpiCol* __restrict__ cols, PtrTable bufs) {
     constexpr int KT = 32;           // K slice per stage (bf16)
     constexpr int P = KT + 8;        // LDS row pitch (bf16): 80 bytes
     constexpr int WM = MT / 2, WN = NT / 2;
@@ -355,31 +418,32 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmProb* __restrict__ 
 #pragma unroll
             for (int i = 0; i < AV; ++i) {
                 const int idx = tid + i * 256;
-                ra[i] = load_bf16x8(A, p.lda, m0 + (idx >> 2), k0 + (idx & 3) * 8, p.M, p.K);
+                ra[i] = load_bf16x8_raw(A, p.lda, m0 + (idx >> 2), k0 + (idx & 3) * 8, p.M);
             }
 #pragma unroll
             for (int i = 0; i < BV; ++i) {
                 const int idx = tid + i * 256;
-                rb[i] = load_bf16x8(B, p.ldb, n0 + (idx >> 2), k0 + (idx & 3) * 8, p.N, p.K);
+                rb[i] = load_bf16x8_raw(B, p.ldb, n0 + (idx >> 2), k0 + (idx & 3) * 8, p.N);
             }
         };
-        auto sstore = [&](int buf) {
+        const u32x4 zu4 = {0u, 0u, 0u, 0u};
+        auto sstore = [&](int buf, int k0) {
 #pragma unroll
             for (int i = 0; i < AV; ++i) {
                 const int idx = tid + i * 256;
-                *reinterpret_cast<u32x4*>(&As[buf][(idx >> 2) * P + (idx & 3) * 8]) = ra[i];
+                *reinterpret_cast<u32x4*>(&As[buf][(idx >> 2) * P + (idx & 3) * 8]) = (k0 + (idx & 3) * 8 < p.lda) ? ra[i] : zu4;
             }
 #pragma unroll
             for (int i = 0; i < BV; ++i) {
                 const int idx = tid + i * 256;
-                *reinterpret_cast<u32x4*>(&Bs[buf][(idx >> 2) * P + (idx & 3) * 8]) = rb[i];
+                *reinterpret_cast<u32x4*>(&Bs[buf][(idx >> 2) * P + (idx & 3) * 8]) = (k0 + (idx & 3) * 8 < p.ldb) ? rb[i] : zu4;
             }
         };
 
         const int nk = (p.K + KT - 1) / KT;
         if (nk > 0) {
             gload(0);
-            sstore(0);
+            sstore(0, 0);
         }
         __syncthreads();
         for (int kt = 0; kt < nk; ++kt) {
@@ -404,33 +468,173 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmProb* __restrict__ 
                     for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
             }
-            if (kt + 1 < nk) sstore(cur ^ 1);
+            if (kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * KT);
             __syncthreads();
         }
 
+        store_tile<FM, FN>(acc, p, C, rows, cols, m0 + wm * WM, n0 + wn * WN, h, r32);
+    }
+}
+
+// Large-tile BF16 GEMM: MT x NT workgroup tile (4 waves, each (MT/2) x (NT/2)),
+// K slices of KT staged through dynamic LDS in two buffers.  LDS rows are
+// unpadded (KT*2 bytes = KT/8 chunks of 16 bytes) and the chunk index is
+// XOR-swizzled with the Gray code of the row, so that both the 16-byte
+// stores of a wave (8 chunks x 8 rows) and the MFMA operand reads (32
+// consecutive rows, one chunk) hit distinct banks.
+template <int CH>
+__device__ __forceinline__ int swz(int r, int c) {
+    return r * CH + (c ^ ((r ^ (r >> 1)) & (CH - 1)));
+}
+
+template <int MT, int NT, int KT, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_gemm_bf16_big(const GemmProb* __restrict__ probs,
+                                                           const GemmTile* __restrict__ tiles, int n_tiles,
+                                                           const EpiRow* __restrict__ rows,
+                                                           const EpiCol* __restrict__ cols, PtrTable bufs) {
+    constexpr int CH = KT / 8;
+    constexpr int WM = MT / 2, WN = NT / 2;
+    constexpr int FM = WM / 32, FN = WN / 32;
+    constexpr int AV = MT * CH / 256, BV = NT * CH / 256;
+    static_assert(AV >= 1 && BV >= 1 && (CH & (CH - 1)) == 0, "bad tile");
+    extern __shared__ u32x4 smem[];
+    u32x4* As = smem;                  // [2][MT*CH]
+    u32x4* Bs = smem + 2 * MT * CH;    // [2][NT*CH]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int h = lane >> 5, r32 = lane & 31;
+
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const GemmTile tile = tiles[t];
+        const GemmProb p = probs[tile.prob];
+        const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
+        const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
+        float* C = static_cast<float*>(const_cast<void*>(bufs.p[p.c_buf])) + p.c_off;
+        const int m0 = tile.tm * MT, n0 = tile.tn * NT;
+
+        v16f acc[FM][FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const int col = n0 + wn * WN + j * 32 + r32;
-                if (col >= p.N) continue;
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int row = m0 + wm * WM + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
-                    if (row < p.M) C[static_cast<int64_t>(row) * p.ldc + col] = acc[i][j][q];
-                }
+                for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+
+        u32x4 ra[AV], rb[BV];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) {
+                const int idx = tid + i * 256;
+                ra[i] = load_bf16x8_raw(A, p.lda, m0 + idx / CH, k0 + (idx % CH) * 8, p.M);
             }
+#pragma unroll
+            for (int i = 0; i < BV; ++i) {
+                const int idx = tid + i * 256;
+                rb[i] = load_bf16x8_raw(B, p.ldb, n0 + idx / CH, k0 + (idx % CH) * 8, p.N);
+            }
+        };
+        const u32x4 zero4 = {0u, 0u, 0u, 0u};
+        auto sstore = [&](int buf, int k0) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) {
+                const int idx = tid + i * 256;
+                As[buf * MT * CH + swz<CH>(idx / CH, idx % CH)] = (k0 + (idx % CH) * 8 < p.lda) ? ra[i] : zero4;
+            }
+#pragma unroll
+            for (int i = 0; i < BV; ++i) {
+                const int idx = tid + i * 256;
+                Bs[buf * NT * CH + swz<CH>(idx / CH, idx % CH)] = (k0 + (idx % CH) * 8 < p.ldb) ? rb[i] : zero4;
+            }
+        };
+
+        const int nk = (p.K + KT - 1) / KT;
+        if (nk > 0) {
+            gload(0);
+            sstore(0, 0);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * KT);
+            __builtin_amdgcn_sched_barrier(0);
+            const u32x4* Ac = As + cur * MT * CH;
+            const u32x4* Bc = Bs + cur * NT * CH;
+            // operand fragments in two register sets: the reads for K step
+            // s+1 are issued before the MFMAs of step s (the scheduling
+            // barriers keep the compiler from sinking them to their use)
+            u32x4 af[2][FM], bfr[2][FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) af[0][i] = Ac[swz<CH>(wm * WM + i * 32 + r32, h)];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bfr[0][j] = Bc[swz<CH>(wn * WN + j * 32 + r32, h)];
+#pragma unroll
+            for (int s = 0; s < KT / 16; ++s) {
+                const int cs = s & 1;
+                if (s + 1 < KT / 16) {
+                    const int c = 2 * (s + 1) + h;
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) af[cs ^ 1][i] = Ac[swz<CH>(wm * WM + i * 32 + r32, c)];
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) bfr[cs ^ 1][j] = Bc[swz<CH>(wn * WN + j * 32 + r32, c)];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[cs][i]),
+                                                                             __builtin_bit_cast(bf16x8, bfr[cs][j]),
+                                                                             acc[i][j], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * KT);
+            __syncthreads();
+        }
+
+        store_tile<FM, FN>(acc, p, C, rows, cols, m0 + wm * WM, n0 + wn * WN, h, r32);
     }
+}
+
+template <int MT, int NT, int KT, int OCC>
+hipError_t launch_big(const GemmProb* probs, const GemmTile* tiles, int32_t n_tiles, int32_t grid,
+                      const EpiRow* rows, const EpiCol* cols, const PtrTable& bufs, hipStream_t s) {
+    constexpr size_t lds = 2 * (MT + NT) * (KT / 8) * 16;
+    static bool configured = false;
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, OCC>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    hipLaunchKernelGGL((k_gemm_bf16_big<MT, NT, KT, OCC>), dim3(static_cast<unsigned>(grid)), dim3(256), lds, s, probs,
+                       tiles, n_tiles, rows, cols, bufs);
+    return hipGetLastError();
+}
+
+template <int MT, int NT, int KT, int OCC>
+int occupancy_big() {
+    constexpr size_t lds = 2 * (MT + NT) * (KT / 8) * 16;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, OCC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_big<MT, NT, KT, OCC>, 256, lds) != hipSuccess) n = 1;
+    return n > 0 ? n : 1;
 }
 
 namespace {
 const GemmVariant kF32Variants[] = {{128, 128, "f32_128x128"}, {64, 64, "f32_64x64"}, {128, 64, "f32_128x64"}};
-const GemmVariant kBF16Variants[] = {{128, 128, "bf16_128x128"}, {64, 64, "bf16_64x64"}, {128, 64, "bf16_128x64"}};
+const GemmVariant kBF16Variants[] = {{256, 256, "bf16_256x256_k64"}, {256, 128, "bf16_256x128_k64"},
+                                     {128, 128, "bf16_128x128_k64"}, {128, 128, "bf16_128x128_k32"},
+                                     {64, 64, "bf16_64x64_k32"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 3 : 3; }
+int gemm_num_variants(int compute) { return compute == 0 ? 3 : 5; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
-int gemm_default_variant(int) { return 0; }
+// Defaults from measurements on MI355X: for BF16 the 128x128 tile with two
+// resident workgroups per CU hides the LDS-store phase of one workgroup behind
+// the other's MFMAs and beats the single 256x256 workgroup.
+int gemm_default_variant(int compute) { return compute == 0 ? 0 : 2; }
 
 int gemm_blocks_per_cu(int compute, int variant) {
     int n = 0;
@@ -443,30 +647,34 @@ int gemm_blocks_per_cu(int compute, int variant) {
         }
     } else {
         switch (variant) {
-            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<64, 64>, 256, 0); break;
-            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<128, 64>, 256, 0); break;
-            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<128, 128>, 256, 0); break;
+            case 1: return occupancy_big<256, 128, 64, 1>();
+            case 2: return occupancy_big<128, 128, 64, 2>();
+            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<128, 128>, 256, 0); break;
+            case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<64, 64>, 256, 0); break;
+            default: return occupancy_big<256, 256, 64, 1>();
         }
     }
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles, int32_t n_tiles,
-                       int32_t grid, const PtrTable& bufs, hipStream_t s) {
+                       int32_t grid, const EpiRow* rows, const EpiCol* cols, const PtrTable& bufs, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     dim3 g(static_cast<unsigned>(grid)), b(256);
     if (compute == 0) {
         switch (variant) {
-            case 1: hipLaunchKernelGGL((k_gemm_f32<64, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
-            case 2: hipLaunchKernelGGL((k_gemm_f32<128, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
-            default: hipLaunchKernelGGL((k_gemm_f32<128, 128>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
+            case 1: hipLaunchKernelGGL((k_gemm_f32<64, 64>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
+            case 2: hipLaunchKernelGGL((k_gemm_f32<128, 64>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
+            default: hipLaunchKernelGGL((k_gemm_f32<128, 128>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
         }
-    } else {
-        switch (variant) {
-            case 1: hipLaunchKernelGGL((k_gemm_bf16<64, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
-            case 2: hipLaunchKernelGGL((k_gemm_bf16<128, 64>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
-            default: hipLaunchKernelGGL((k_gemm_bf16<128, 128>), g, b, 0, s, probs, tiles, n_tiles, bufs); break;
-        }
+        return hipGetLastError();
+    }
+    switch (variant) {
+        case 1: return launch_big<256, 128, 64, 1>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
+        case 2: return launch_big<128, 128, 64, 2>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
+        case 3: hipLaunchKernelGGL((k_gemm_bf16<128, 128>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
+        case 4: hipLaunchKernelGGL((k_gemm_bf16<64, 64>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
+        default: return launch_big<256, 256, 64, 1>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
     }
     return hipGetLastError();
 }

@@ -42,12 +42,32 @@ struct TileTask {
 constexpr int kTile = 64;
 
 // One sector GEMM: C[m][n] = sum_k A[m][k] * B[n][k] (both operands K-contiguous).
+// With `indirect` set, element (m, n) is stored at
+//   c_off + row.r0 + row.r1 * col.c1 + row.r2 * col.c2 + col.c0
+// (row = rows[ri_off + m], col = cols[ci_off + n]): the split into a
+// canonical block list, done by the epilogue instead of a separate pass.
 struct GemmProb {
     int64_t a_off, b_off, c_off;
+    int64_t ri_off, ci_off;
     int32_t M, N, K;
     int32_t lda, ldb, ldc;
     int32_t a_buf, b_buf, c_buf;
-    int32_t pad;
+    int32_t indirect;
+};
+
+// Canonical block list of a row-legs-first tensor: block (rt, ct) of a sector
+// starts at base(rt) + d(rt) * colcum(ct) and is row-major, so the element at
+// row offset t_r in rt and column offset t_c in ct sits at
+// base(rt) + t_r * d(ct) + d(rt) * colcum(ct) + t_c.
+struct EpiRow {
+    int64_t r0;   // base(rt)
+    int32_t r1;   // t_r
+    int32_t r2;   // d(rt)
+};
+struct EpiCol {
+    int64_t c2;   // colcum(ct)
+    int32_t c0;   // t_c
+    int32_t c1;   // d(ct)
 };
 
 struct GemmTile {
@@ -80,7 +100,8 @@ hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
                                 int32_t n_tasks, const PtrTable& bufs, hipStream_t s);
 hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles,
-                       int32_t n_tiles, int32_t grid, const PtrTable& bufs, hipStream_t s);
+                       int32_t n_tiles, int32_t grid, const EpiRow* rows, const EpiCol* cols,
+                       const PtrTable& bufs, hipStream_t s);
 hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
                            const double* coef, const FmTask* tasks, int32_t n_tasks,
                            const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);

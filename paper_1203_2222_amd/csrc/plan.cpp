@@ -257,7 +257,59 @@ void GemmProgram::add(const Desc& Z, const Desc& X, const Desc& Y, int z_buf, in
     }
 }
 
-void GemmProgram::finalize(int v) {
+bool GemmProgram::add_indirect(const Desc& Z, const Desc& out, const Desc& X, const Desc& Y, int z_buf, int x_buf,
+                               int y_buf, int64_t x_base, int64_t y_base) {
+    if (Z.group != SYM_U1 || out.group != SYM_U1 || out.n_row != out.rank || out.opts.trans ||
+        out.dtype != SYM_F32 || out.legs != Z.legs || out.qtot != Z.qtot || Z.opts.trans)
+        return false;
+    // check the address formula against every block before committing
+    const size_t p0 = probs.size();
+    std::vector<EpiRow> rows_add;
+    std::vector<EpiCol> cols_add;
+    std::vector<int64_t> ri(Z.sectors.size()), ci(Z.sectors.size());
+    int32_t lab[SYM_MAX_RANK];
+    for (size_t si = 0; si < Z.sectors.size(); ++si) {
+        const Sector& zs = Z.sectors[si];
+        ri[si] = static_cast<int64_t>(erows.size() + rows_add.size());
+        ci[si] = static_cast<int64_t>(ecols.size() + cols_add.size());
+        const int nr = Z.n_row, nc = Z.rank - Z.n_row;
+        for (size_t r = 0; r < zs.row_tuples.size(); ++r) {
+            const Tuple& rt = zs.row_tuples[r];
+            int64_t base = -1;
+            for (size_t c = 0; c < zs.col_tuples.size(); ++c) {
+                const Tuple& ct = zs.col_tuples[c];
+                for (int l = 0; l < nr; ++l) lab[l] = rt.lab[static_cast<size_t>(l)];
+                for (int l = 0; l < nc; ++l) lab[nr + l] = ct.lab[static_cast<size_t>(l)];
+                const int32_t bi = out.find_block(lab, -1);
+                if (bi < 0) return false;
+                const int64_t off = out.blocks[static_cast<size_t>(bi)].offset;
+                if (c == 0) base = off;
+                if (off != base + rt.dim * zs.col_off[c]) return false;
+            }
+            for (int64_t t = 0; t < rt.dim; ++t)
+                rows_add.push_back({base, static_cast<int32_t>(t), static_cast<int32_t>(rt.dim)});
+        }
+        for (size_t c = 0; c < zs.col_tuples.size(); ++c) {
+            const Tuple& ct = zs.col_tuples[c];
+            for (int64_t t = 0; t < ct.dim; ++t)
+                cols_add.push_back({zs.col_off[c], static_cast<int32_t>(t), static_cast<int32_t>(ct.dim)});
+        }
+    }
+    add(Z, X, Y, z_buf, x_buf, y_buf, 0, x_base, y_base);
+    if (probs.size() - p0 != Z.sectors.size()) throw Error(SYM_E_MISMATCH, "indirect GEMM sector count");
+    for (size_t si = 0; si < Z.sectors.size(); ++si) {
+        GemmProb& p = probs[p0 + si];
+        p.indirect = 1;
+        p.c_off = 0;
+        p.ri_off = ri[si];
+        p.ci_off = ci[si];
+    }
+    erows.insert(erows.end(), rows_add.begin(), rows_add.end());
+    ecols.insert(ecols.end(), cols_add.begin(), cols_add.end());
+    return true;
+}
+
+void GemmProgram::finalize(int v, int grid) {
     variant = v;
     const GemmVariant gv = gemm_variant(compute, v);
     // longest-processing-time order: all tiles of one sector cost ~K, so sort
@@ -270,25 +322,50 @@ void GemmProgram::finalize(int v) {
         if (x.K != y.K) return x.K > y.K;
         return static_cast<int64_t>(x.M) * x.N > static_cast<int64_t>(y.M) * y.N;
     });
-    tiles.clear();
+    // inside a sector, walk tiles in groups of kGroupM tile rows, column by
+    // column, so that consecutive tiles share A row panels and B column panels
+    constexpr int kGroupM = 8;
+    std::vector<GemmTile> seq;
     for (int32_t pi : order) {
         const GemmProb& p = probs[static_cast<size_t>(pi)];
         const int tm = (p.M + gv.mt - 1) / gv.mt, tn = (p.N + gv.nt - 1) / gv.nt;
-        for (int i = 0; i < tm; ++i)
-            for (int j = 0; j < tn; ++j) tiles.push_back({pi, i, j, 0});
+        for (int g0 = 0; g0 < tm; g0 += kGroupM)
+            for (int j = 0; j < tn; ++j)
+                for (int i = g0; i < std::min(tm, g0 + kGroupM); ++i) seq.push_back({pi, i, j, 0});
+    }
+    // The persistent grid runs `grid` workgroups; workgroup w sits on XCD
+    // w % 8 and takes tiles w, w + grid, ...  Give each XCD a contiguous run
+    // of the sequence per round, so that the tiles one XCD holds at a time
+    // share its L2.
+    tiles.assign(seq.size(), GemmTile{});
+    const int64_t g = std::max(8, grid - grid % 8);
+    const int64_t n = static_cast<int64_t>(seq.size());
+    const int64_t per = g / 8;
+    for (int64_t r0 = 0; r0 < n; r0 += g) {
+        const int64_t len = std::min(g, n - r0);
+        if (len < g) {
+            for (int64_t k = 0; k < len; ++k) tiles[static_cast<size_t>(r0 + k)] = seq[static_cast<size_t>(r0 + k)];
+            break;
+        }
+        for (int64_t w = 0; w < g; ++w)
+            tiles[static_cast<size_t>(r0 + w)] = seq[static_cast<size_t>(r0 + (w % 8) * per + w / 8)];
     }
 }
 
 void GemmProgram::upload(const Allocator& alloc) {
     d_probs = upload_vec(alloc, probs);
     d_tiles = upload_vec(alloc, tiles);
+    d_rows = upload_vec(alloc, erows);
+    d_cols = upload_vec(alloc, ecols);
 }
 
 hipError_t GemmProgram::launch(const PtrTable& bufs, int grid, hipStream_t s) const {
     if (tiles.empty()) return hipSuccess;
     const int g = std::max(1, std::min(grid, static_cast<int>(tiles.size())));
     return launch_gemm(compute, variant, static_cast<const GemmProb*>(d_probs->ptr),
-                       static_cast<const GemmTile*>(d_tiles->ptr), static_cast<int32_t>(tiles.size()), g, bufs, s);
+                       static_cast<const GemmTile*>(d_tiles->ptr), static_cast<int32_t>(tiles.size()), g,
+                       d_rows ? static_cast<const EpiRow*>(d_rows->ptr) : nullptr,
+                       d_cols ? static_cast<const EpiCol*>(d_cols->ptr) : nullptr, bufs, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -52,12 +52,19 @@ struct GemmProgram {
     int compute = SYM_F32;
     int variant = 0;
     int64_t flops = 0;
-    DevMemPtr d_probs, d_tiles;
+    std::vector<EpiRow> erows;
+    std::vector<EpiCol> ecols;
+    DevMemPtr d_probs, d_tiles, d_rows, d_cols;
 
     // One GEMM per sector of Z: Z = X * Y^T (X: M x K, Y: N x K, K-contiguous).
     void add(const Desc& Z, const Desc& X, const Desc& Y, int z_buf, int x_buf, int y_buf, int64_t z_base = 0,
              int64_t x_base = 0, int64_t y_base = 0);
-    void finalize(int variant);
+    // Same GEMMs over the sectors of Z (sector-major, U(1)), each stored by
+    // the epilogue straight into the canonical block list `out` (buffer z_buf).
+    // Returns false (and adds nothing) when `out` is not a U(1) canonical list.
+    bool add_indirect(const Desc& Z, const Desc& out, const Desc& X, const Desc& Y, int z_buf, int x_buf, int y_buf,
+                      int64_t x_base, int64_t y_base);
+    void finalize(int variant, int grid);
     void upload(const Allocator& alloc);
     hipError_t launch(const PtrTable& bufs, int grid, hipStream_t s) const;
 };

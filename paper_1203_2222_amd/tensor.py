@@ -163,10 +163,18 @@ class Context:
         except Exception:
             pass
 
+    def clear(self):
+        """Drop every cached plan and its workspace."""
+        L.check(L.lib().sym_ctx_clear(self.handle))
+
     def close(self):
-        if getattr(self, "handle", None) is not None and self.handle.value:
-            L.lib().sym_ctx_destroy(self.handle)
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
             self.handle = None
+            try:
+                L.lib().sym_ctx_destroy(h)
+            except Exception:   # interpreter shutdown: modules already torn down
+                pass
 
     def __del__(self):
         self.close()
@@ -206,6 +214,12 @@ class Context:
         return t
 
     # ----- permute / fuse / recouple -------------------------------------------
+    def permute_into(self, t: SymTensor, perm: Sequence[int], n_row: int, out: SymTensor, stream=None) -> SymTensor:
+        """Permute/fuse ``t`` into an existing handle (no host-side output creation)."""
+        L.check(L.lib().sym_permute_fuse(self.handle, t.handle, L.i32_array(perm), n_row, out.handle,
+                                         _stream(stream)))
+        return out
+
     def permute_fuse(self, t: SymTensor, perm: Sequence[int], n_row: int, dtype=None, out=None,
                      stream=None) -> SymTensor:
         dt = t.dtype if dtype is None else _dtype_code(dtype)

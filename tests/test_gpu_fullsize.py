@@ -1,0 +1,168 @@
+"""Parity at the benchmark configurations' full sizes, on outputs the FP64
+oracle computes one by one:
+
+* config 2 (U(1), chi=256, FP32): sampled dense output entries summed from the
+  definition (dense slices of A and B materialised from their blocks);
+* config 3 (64-member batch, BF16, the benchmark's graph-replayed launch):
+  sampled entries of sampled members, error against the unrounded inputs;
+* config 5 (SU(2), chi=576): sampled reduced blocks of C by the block-wise
+  multiply, and the recoupled blocks of sampled label tuples.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import contract as K
+from oracle import recouple as RC
+from oracle import su2
+from oracle import tensors as T
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1203_2222_amd as P
+    return P.Context()
+
+
+def _dense_index(spec, labels, t):
+    """Dense position of degeneracy index t inside the block with these labels (U(1))."""
+    out = []
+    for leg, q, ti in zip(spec.legs, labels, t):
+        offs, _ = T.leg_offsets(T.U1, leg)
+        out.append(offs[q] + int(ti))
+    return tuple(out)
+
+
+def _sample_points(C, rng, n):
+    """n (block, position) samples of a sector-major result, with their device values."""
+    blocks = C.blocks()
+    torch.cuda.synchronize()
+    picks = rng.choice(len(blocks), n)
+    out = []
+    for i in picks:
+        b = blocks[int(i)]
+        t = tuple(int(rng.integers(0, s)) for s in b.shape)
+        off = b.offset + sum(ti * st for ti, st in zip(t, b.strides))
+        out.append((b, t, float(C.data[off].item())))
+    return out
+
+
+def test_config2_fp32_sampled(ctx):
+    say("case config2 full size fp32")
+    c = W.config2()
+    g = W.generator(c.seed, "cuda")
+    a = W.gaussian(T.num_elements(c.A), g, "cuda")
+    b = W.gaussian(T.num_elements(c.B), g, "cuda")
+    A = ctx.tensor(c.A, 4, data=a)
+    B = ctx.tensor(c.B, 4, data=b)
+    C = ctx.contract(A, B, c.axes_a, c.axes_b, "f32")
+    rng = np.random.default_rng(0)
+    pts = _sample_points(C, rng, 200)
+    fa = a.double().cpu().numpy()
+    fb = b.double().cpu().numpy()
+    sc = K.result_spec(c.A, c.B, c.axes_a, c.axes_b)
+    dense_pts = [_dense_index(sc, bl.labels, t) for bl, t, _ in pts]
+    ref = K.sample_u1(c.A, fa, c.B, fb, c.axes_a, c.axes_b, dense_pts)
+    got = np.array([v for _, _, v in pts])
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say(f"  sampled rel err {err:.3e}")
+    assert err <= 1e-5
+    del A, B, C, a, b
+    torch.cuda.empty_cache()
+
+
+def test_config3_batched_bf16_graph_sampled(ctx):
+    say("case config3 full batch bf16 graph replay")
+    members = W.config3_members()
+    As, Bs, Cs = [], [], []
+    for m in members:
+        g = W.generator(m.seed, "cuda")
+        A = ctx.tensor(m.A, 4, data=W.gaussian(T.num_elements(m.A), g, "cuda"))
+        B = ctx.tensor(m.B, 4, data=W.gaussian(T.num_elements(m.B), g, "cuda"))
+        C0 = ctx.contract_output(A, B, m.axes_a, m.axes_b)
+        Cs.append(ctx.tensor(C0.spec, 4))
+        As.append(A)
+        Bs.append(B)
+    stream = torch.cuda.Stream()
+    graph = ctx.graph_batched(As, Bs, (2, 3), (0, 1), "bf16", Cs, stream)
+    graph.launch(stream)
+    graph.launch(stream)
+    stream.synchronize()
+    rng = np.random.default_rng(1)
+    errs = []
+    for i in [0, 1, 3, 5, 9, 63]:
+        m = members[i]
+        pts = _sample_points(Cs[i], rng, 40)
+        fa = As[i].data.double().cpu().numpy()
+        fb = Bs[i].data.double().cpu().numpy()
+        sc = K.result_spec(m.A, m.B, m.axes_a, m.axes_b)
+        ref = K.sample_u1(m.A, fa, m.B, fb, m.axes_a, m.axes_b, [_dense_index(sc, bl.labels, t) for bl, t, _ in pts])
+        got = np.array([v for _, _, v in pts])
+        errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    say(f"  sampled rel errs {['%.2e' % e for e in errs]}")
+    assert max(errs) <= 3e-3
+    del graph, As, Bs, Cs
+    torch.cuda.empty_cache()
+
+
+def test_config5_su2_sampled(ctx):
+    say("case config5 full size su2")
+    c = W.config5()
+    g = W.generator(c.seed, "cuda")
+    a = W.gaussian(T.num_elements(c.A), g, "cuda")
+    b = W.gaussian(T.num_elements(c.B), g, "cuda")
+    A = ctx.tensor(c.A, 4, data=a)
+    B = ctx.tensor(c.B, 4, data=b)
+    C = ctx.contract(A, B, c.axes_a, c.axes_b, "f32")
+    R = ctx.permute_fuse(C, (0, 2, 1, 3), 4)
+    torch.cuda.synchronize()
+    da = T.split_flat(c.A, a.double().cpu().numpy())
+    db = T.split_flat(c.B, b.double().cpu().numpy())
+    sc = K.result_spec(c.A, c.B, c.axes_a, c.axes_b)
+
+    def c_block(labels, e):
+        # C^e = sum over (jx, jy) of A^e[(j1,j2,jx,jy)] . B^e[(jx,jy,j3,j4)]  (eq:blockmult over coupled spins)
+        j1, j2, j3, j4 = labels
+        acc = None
+        for (la, ea), pa in da.items():
+            if la[0] != j1 or la[1] != j2 or ea != e:
+                continue
+            pb = db.get(((la[2], la[3], j3, j4), e))
+            if pb is None:
+                continue
+            term = np.tensordot(pa, pb, axes=([2, 3], [0, 1]))
+            acc = term if acc is None else acc + term
+        return acc
+
+    rng = np.random.default_rng(2)
+    blocks = C.blocks()
+    num, den = 0.0, 0.0
+    for i in rng.choice(len(blocks), 12, replace=False):
+        bl = blocks[int(i)]
+        ref = c_block(bl.labels, bl.internal)
+        got = C.block_view(bl).double().cpu().numpy()
+        num += np.sum((got - ref) ** 2)
+        den += np.sum(ref ** 2)
+    say(f"  C blocks rel err {np.sqrt(num / den):.3e}")
+    assert np.sqrt(num / den) <= 1e-5
+    # recoupled blocks of sampled label tuples: all e of the tuple through F and R
+    rblocks = {(bl.labels, bl.internal): bl for bl in R.blocks()}
+    num, den = 0.0, 0.0
+    tuples = sorted({bl.labels for bl in blocks})
+    for k in rng.choice(len(tuples), 8, replace=False):
+        j1, j2, j3, j4 = tuples[int(k)]
+        es = T.su2_internals(T.TREE_LEFT, (j1, j2, j3, j4))
+        ce = {e: c_block((j1, j2, j3, j4), e) for e in es}
+        for f in T.su2_internals(T.TREE_RIGHT, (j1, j2, j3, j4)):
+            ref = sum(su2.fmove(j1, j2, j3, j4, e, f) * ce[e] for e in es)
+            ref = su2.swap_phase(j2, j3, f) * np.transpose(ref, (0, 2, 1, 3))
+            bl = rblocks[((j1, j3, j2, j4), f)]
+            got = R.block_view(bl).double().cpu().numpy()
+            num += np.sum((got - ref) ** 2)
+            den += np.sum(ref ** 2)
+    say(f"  recoupled blocks rel err {np.sqrt(num / den):.3e}")
+    assert np.sqrt(num / den) <= 1e-5
