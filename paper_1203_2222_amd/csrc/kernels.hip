@@ -487,22 +487,28 @@ __device__ __forceinline__ int swz(int r, int c) {
     return r * CH + (c ^ ((r ^ (r >> 1)) & (CH - 1)));
 }
 
-template <int MT, int NT, int KT, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_gemm_bf16_big(const GemmProb* __restrict__ probs,
-                                                           const GemmTile* __restrict__ tiles, int n_tiles,
-                                                           const EpiRow* __restrict__ rows,
-                                                           const EpiCol* __restrict__ cols, PtrTable bufs) {
+// WGM x WGN waves per workgroup, each owning an (MT/WGM) x (NT/WGN) sub-tile.
+// STORE_AT: the K step after whose MFMAs the next slice is written to LDS
+// (KT/16 = after all of them); storing earlier overlaps the LDS writes with
+// the remaining MFMAs of the slice.
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC, int STORE_AT>
+__global__ __launch_bounds__(64 * WGM * WGN, OCC) void k_gemm_bf16_big(const GemmProb* __restrict__ probs,
+                                                                       const GemmTile* __restrict__ tiles, int n_tiles,
+                                                                       const EpiRow* __restrict__ rows,
+                                                                       const EpiCol* __restrict__ cols, PtrTable bufs) {
+    constexpr int NTHR = 64 * WGM * WGN;
     constexpr int CH = KT / 8;
-    constexpr int WM = MT / 2, WN = NT / 2;
+    constexpr int WM = MT / WGM, WN = NT / WGN;
     constexpr int FM = WM / 32, FN = WN / 32;
-    constexpr int AV = MT * CH / 256, BV = NT * CH / 256;
-    static_assert(AV >= 1 && BV >= 1 && (CH & (CH - 1)) == 0, "bad tile");
+    constexpr int AV = MT * CH / NTHR, BV = NT * CH / NTHR;
+    constexpr int S = KT / 16;
+    static_assert(AV >= 1 && BV >= 1 && (CH & (CH - 1)) == 0 && FM >= 1 && FN >= 1, "bad tile");
     extern __shared__ u32x4 smem[];
     u32x4* As = smem;                  // [2][MT*CH]
     u32x4* Bs = smem + 2 * MT * CH;    // [2][NT*CH]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
     const int h = lane >> 5, r32 = lane & 31;
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
@@ -525,12 +531,12 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16_big(const GemmProb* __re
         auto gload = [&](int k0) {
 #pragma unroll
             for (int i = 0; i < AV; ++i) {
-                const int idx = tid + i * 256;
+                const int idx = tid + i * NTHR;
                 ra[i] = load_bf16x8_raw(A, p.lda, m0 + idx / CH, k0 + (idx % CH) * 8, p.M);
             }
 #pragma unroll
             for (int i = 0; i < BV; ++i) {
-                const int idx = tid + i * 256;
+                const int idx = tid + i * NTHR;
                 rb[i] = load_bf16x8_raw(B, p.ldb, n0 + idx / CH, k0 + (idx % CH) * 8, p.N);
             }
         };
@@ -538,12 +544,12 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16_big(const GemmProb* __re
         auto sstore = [&](int buf, int k0) {
 #pragma unroll
             for (int i = 0; i < AV; ++i) {
-                const int idx = tid + i * 256;
+                const int idx = tid + i * NTHR;
                 As[buf * MT * CH + swz<CH>(idx / CH, idx % CH)] = (k0 + (idx % CH) * 8 < p.lda) ? ra[i] : zero4;
             }
 #pragma unroll
             for (int i = 0; i < BV; ++i) {
-                const int idx = tid + i * 256;
+                const int idx = tid + i * NTHR;
                 Bs[buf * NT * CH + swz<CH>(idx / CH, idx % CH)] = (k0 + (idx % CH) * 8 < p.ldb) ? rb[i] : zero4;
             }
         };
@@ -569,9 +575,9 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16_big(const GemmProb* __re
 #pragma unroll
             for (int j = 0; j < FN; ++j) bfr[0][j] = Bc[swz<CH>(wn * WN + j * 32 + r32, h)];
 #pragma unroll
-            for (int s = 0; s < KT / 16; ++s) {
+            for (int s = 0; s < S; ++s) {
                 const int cs = s & 1;
-                if (s + 1 < KT / 16) {
+                if (s + 1 < S) {
                     const int c = 2 * (s + 1) + h;
 #pragma unroll
                     for (int i = 0; i < FM; ++i) af[cs ^ 1][i] = Ac[swz<CH>(wm * WM + i * 32 + r32, c)];
@@ -587,8 +593,10 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16_big(const GemmProb* __re
                                                                              __builtin_bit_cast(bf16x8, bfr[cs][j]),
                                                                              acc[i][j], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);
+                // the other LDS buffer was last read before the previous barrier
+                if (s == STORE_AT && kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * KT);
             }
-            if (kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * KT);
+            if (STORE_AT >= S && kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * KT);
             __syncthreads();
         }
 
@@ -596,45 +604,61 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_bf16_big(const GemmProb* __re
     }
 }
 
-template <int MT, int NT, int KT, int OCC>
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC, int SA>
 hipError_t launch_big(const GemmProb* probs, const GemmTile* tiles, int32_t n_tiles, int32_t grid,
                       const EpiRow* rows, const EpiCol* cols, const PtrTable& bufs, hipStream_t s) {
     constexpr size_t lds = 2 * (MT + NT) * (KT / 8) * 16;
     static bool configured = false;
     if (!configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, OCC>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, WGM, WGN, OCC, SA>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
         configured = true;
     }
-    hipLaunchKernelGGL((k_gemm_bf16_big<MT, NT, KT, OCC>), dim3(static_cast<unsigned>(grid)), dim3(256), lds, s, probs,
-                       tiles, n_tiles, rows, cols, bufs);
+    hipLaunchKernelGGL((k_gemm_bf16_big<MT, NT, KT, WGM, WGN, OCC, SA>), dim3(static_cast<unsigned>(grid)),
+                       dim3(64 * WGM * WGN), lds, s, probs, tiles, n_tiles, rows, cols, bufs);
     return hipGetLastError();
 }
 
-template <int MT, int NT, int KT, int OCC>
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC, int SA>
 int occupancy_big() {
     constexpr size_t lds = 2 * (MT + NT) * (KT / 8) * 16;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, OCC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, WGM, WGN, OCC, SA>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_big<MT, NT, KT, OCC>, 256, lds) != hipSuccess) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_big<MT, NT, KT, WGM, WGN, OCC, SA>,
+                                                     64 * WGM * WGN, lds) != hipSuccess)
+        n = 1;
     return n > 0 ? n : 1;
 }
+
+// BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
+// grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel.
+#define SYM_BF16_BIG_VARIANTS(X)              \
+    X(0, 256, 256, 64, 2, 2, 1, 4)            \
+    X(1, 256, 128, 64, 2, 2, 1, 4)            \
+    X(2, 128, 128, 64, 2, 2, 2, 4)            \
+    X(5, 256, 256, 64, 2, 4, 2, 4)            \
+    X(6, 256, 128, 64, 4, 2, 2, 1)            \
+    X(7, 128, 128, 64, 2, 2, 2, 1)            \
+    X(8, 256, 128, 64, 4, 2, 2, 4)
 
 namespace {
 const GemmVariant kF32Variants[] = {{128, 128, "f32_128x128"}, {64, 64, "f32_64x64"}, {128, 64, "f32_128x64"}};
 const GemmVariant kBF16Variants[] = {{256, 256, "bf16_256x256_k64"}, {256, 128, "bf16_256x128_k64"},
                                      {128, 128, "bf16_128x128_k64"}, {128, 128, "bf16_128x128_k32"},
-                                     {64, 64, "bf16_64x64_k32"}};
+                                     {64, 64, "bf16_64x64_k32"},      {256, 256, "bf16_256x256_k64_8w"},
+                                     {256, 128, "bf16_256x128_k64_8w_early"},
+                                     {128, 128, "bf16_128x128_k64_early"}, {256, 128, "bf16_256x128_k64_8w"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 3 : 5; }
+int gemm_num_variants(int compute) { return compute == 0 ? 3 : 9; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
-// Defaults from measurements on MI355X: for BF16 the 128x128 tile with two
-// resident workgroups per CU hides the LDS-store phase of one workgroup behind
-// the other's MFMAs and beats the single 256x256 workgroup.
-int gemm_default_variant(int compute) { return compute == 0 ? 0 : 2; }
+// Defaults from measurements on MI355X.  The batched BF16 GEMM is bound by
+// operand re-reads beyond L2, so the largest tile wins: 256x256 with 8 waves
+// (two per SIMD, so one wave's LDS phase overlaps the other's MFMAs) ran the
+// 64-member batch at 838 TFLOP/s against 406 for 128x128.
+int gemm_default_variant(int compute) { return compute == 0 ? 0 : 5; }
 
 int gemm_blocks_per_cu(int compute, int variant) {
     int n = 0;
@@ -647,11 +671,13 @@ int gemm_blocks_per_cu(int compute, int variant) {
         }
     } else {
         switch (variant) {
-            case 1: return occupancy_big<256, 128, 64, 1>();
-            case 2: return occupancy_big<128, 128, 64, 2>();
+#define SYM_OCC_CASE(V, MT, NT, KT, WGM, WGN, OCC, SA) \
+    case V: return occupancy_big<MT, NT, KT, WGM, WGN, OCC, SA>();
+            SYM_BF16_BIG_VARIANTS(SYM_OCC_CASE)
+#undef SYM_OCC_CASE
             case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<128, 128>, 256, 0); break;
             case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<64, 64>, 256, 0); break;
-            default: return occupancy_big<256, 256, 64, 1>();
+            default: break;
         }
     }
     return (e == hipSuccess && n > 0) ? n : 1;
@@ -670,11 +696,13 @@ hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const Ge
         return hipGetLastError();
     }
     switch (variant) {
-        case 1: return launch_big<256, 128, 64, 1>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
-        case 2: return launch_big<128, 128, 64, 2>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
+#define SYM_LAUNCH_CASE(V, MT, NT, KT, WGM, WGN, OCC, SA) \
+    case V: return launch_big<MT, NT, KT, WGM, WGN, OCC, SA>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
+        SYM_BF16_BIG_VARIANTS(SYM_LAUNCH_CASE)
+#undef SYM_LAUNCH_CASE
         case 3: hipLaunchKernelGGL((k_gemm_bf16<128, 128>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
         case 4: hipLaunchKernelGGL((k_gemm_bf16<64, 64>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
-        default: return launch_big<256, 256, 64, 1>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
