@@ -56,8 +56,11 @@ class SymTensor:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            L.lib().sym_tensor_destroy(h)
             self.handle = None
+            try:
+                L.lib().sym_tensor_destroy(h)
+            except Exception:   # interpreter shutdown: modules already torn down
+                pass
 
     @property
     def rank(self) -> int:
@@ -323,9 +326,13 @@ class Graph:
         L.check(L.lib().sym_graph_launch(self.handle, _stream(stream)))
 
     def __del__(self):
-        if getattr(self, "handle", None) is not None and self.handle.value:
-            L.lib().sym_graph_destroy(self.handle)
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
             self.handle = None
+            try:
+                L.lib().sym_graph_destroy(h)
+            except Exception:   # interpreter shutdown
+                pass
 
 
 def num_variants(compute) -> int:

@@ -128,3 +128,26 @@ def test_separate_split_pass_matches_epilogue_split():
             os.environ.pop("SYM_SPLIT", None)
     for a, b in zip(outs["epilogue"], outs["separate"]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_bf16_stored_inputs(ctx, compute):
+    # A and B stored as BF16: the fuse widens (F32 compute) or copies (BF16
+    # compute) them; either way the result is the exact contraction of the
+    # stored values up to FP32 accumulation
+    say(f"case bf16-stored inputs, {compute} compute")
+    members = _members()
+    As, Bs, Cs, hin = [], [], [], []
+    for m in members:
+        g = W.generator(m.seed, "cuda")
+        a = W.gaussian(ctx.describe(m.A, 4).numel(), g, "cuda").to(torch.bfloat16)
+        b = W.gaussian(ctx.describe(m.B, 4).numel(), g, "cuda").to(torch.bfloat16)
+        A, B = ctx.tensor(m.A, 4, "bf16", data=a), ctx.tensor(m.B, 4, "bf16", data=b)
+        Cs.append(ctx.tensor(ctx.contract_output(A, B, m.axes_a, m.axes_b).spec, 4))
+        As.append(A)
+        Bs.append(B)
+        hin.append((a.double().cpu().numpy(), b.double().cpu().numpy()))
+    ctx.contract_batched(As, Bs, (2, 3), (0, 1), compute, Cs)
+    for m, C, (fa, fb) in zip(members, Cs, hin):
+        _, ref = K.contract_pairs(m.A, fa, m.B, fb, m.axes_a, m.axes_b)
+        assert rel_err(host(C), ref) <= 1e-5, (m.name, compute)

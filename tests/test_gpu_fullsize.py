@@ -3,8 +3,9 @@ oracle computes one by one:
 
 * config 2 (U(1), chi=256, FP32): sampled dense output entries summed from the
   definition (dense slices of A and B materialised from their blocks);
-* config 3 (64-member batch, BF16, the benchmark's graph-replayed launch):
-  sampled entries of sampled members, error against the unrounded inputs;
+* config 3 (64-member batch, BF16-stored inputs, the benchmark's graph-replayed
+  launch): sampled entries of sampled members, error against the unrounded
+  draws and against the stored BF16 values;
 * config 5 (SU(2), chi=576): sampled reduced blocks of C by the block-wise
   multiply, and the recoupled blocks of sampled label tuples.
 """
@@ -17,7 +18,7 @@ from oracle import contract as K
 from oracle import recouple as RC
 from oracle import su2
 from oracle import tensors as T
-from tests.gpu_util import say
+from tests.gpu_util import bf16_round, say
 
 pytestmark = pytest.mark.gpu
 
@@ -78,11 +79,18 @@ def test_config2_fp32_sampled(ctx):
 def test_config3_batched_bf16_graph_sampled(ctx):
     say("case config3 full batch bf16 graph replay")
     members = W.config3_members()
-    As, Bs, Cs = [], [], []
-    for m in members:
+    # inputs stored as BF16 (RNE from the seeded FP32 draws), as the benchmark does
+    As, Bs, Cs, raw = [], [], [], {}
+    sampled = [0, 1, 3, 5, 9, 63]
+    for i, m in enumerate(members):
         g = W.generator(m.seed, "cuda")
-        A = ctx.tensor(m.A, 4, data=W.gaussian(T.num_elements(m.A), g, "cuda"))
-        B = ctx.tensor(m.B, 4, data=W.gaussian(T.num_elements(m.B), g, "cuda"))
+        a = W.gaussian(T.num_elements(m.A), g, "cuda")
+        b = W.gaussian(T.num_elements(m.B), g, "cuda")
+        if i in sampled:
+            raw[i] = (a.double().cpu().numpy(), b.double().cpu().numpy())
+        A = ctx.tensor(m.A, 4, "bf16", data=a.to(torch.bfloat16))
+        B = ctx.tensor(m.B, 4, "bf16", data=b.to(torch.bfloat16))
+        del a, b
         C0 = ctx.contract_output(A, B, m.axes_a, m.axes_b)
         Cs.append(ctx.tensor(C0.spec, 4))
         As.append(A)
@@ -93,18 +101,22 @@ def test_config3_batched_bf16_graph_sampled(ctx):
     graph.launch(stream)
     stream.synchronize()
     rng = np.random.default_rng(1)
-    errs = []
-    for i in [0, 1, 3, 5, 9, 63]:
+    errs, errs16 = [], []
+    for i in sampled:
         m = members[i]
         pts = _sample_points(Cs[i], rng, 40)
-        fa = As[i].data.double().cpu().numpy()
-        fb = Bs[i].data.double().cpu().numpy()
         sc = K.result_spec(m.A, m.B, m.axes_a, m.axes_b)
-        ref = K.sample_u1(m.A, fa, m.B, fb, m.axes_a, m.axes_b, [_dense_index(sc, bl.labels, t) for bl, t, _ in pts])
+        dense = [_dense_index(sc, bl.labels, t) for bl, t, _ in pts]
         got = np.array([v for _, _, v in pts])
+        fa, fb = raw[i]
+        ref = K.sample_u1(m.A, fa, m.B, fb, m.axes_a, m.axes_b, dense)
         errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    say(f"  sampled rel errs {['%.2e' % e for e in errs]}")
+        # against the oracle on the stored (rounded) values: only FP32 accumulation error is left
+        ref16 = K.sample_u1(m.A, bf16_round(fa), m.B, bf16_round(fb), m.axes_a, m.axes_b, dense)
+        errs16.append(np.linalg.norm(got - ref16) / np.linalg.norm(ref16))
+    say(f"  sampled rel errs {['%.2e' % e for e in errs]} (stored values: {['%.2e' % e for e in errs16]})")
     assert max(errs) <= 3e-3
+    assert max(errs16) <= 1e-5
     del graph, As, Bs, Cs
     torch.cuda.empty_cache()
 
