@@ -219,6 +219,10 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
                          int32_t* best_variant);
 int32_t sym_ctx_set_variant(sym_ctx* ctx, int32_t compute, int32_t variant);
 int32_t sym_num_variants(int32_t compute, int32_t* count);
+/* Name of a tile variant (static storage, never freed), and the variant a
+ * context uses for a compute type when nothing was set or tuned. */
+int32_t sym_variant_name(int32_t compute, int32_t variant, const char** name);
+int32_t sym_default_variant(int32_t compute, int32_t* variant);
 
 /* SU(2) recoupling coefficient F^{jD jE}_{jA jB jC jJ} (eq:sixj), doubled
  * spins, from the library's own FP64 tables.  Host only. */

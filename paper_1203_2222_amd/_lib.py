@@ -62,6 +62,8 @@ SIGNATURES = {
     "sym_tune_batched": (c_int32, [P, c_int32, PP, PP, c_int32, I32P, I32P, c_int32, PP, P, I32P]),
     "sym_ctx_set_variant": (c_int32, [P, c_int32, c_int32]),
     "sym_num_variants": (c_int32, [c_int32, I32P]),
+    "sym_variant_name": (c_int32, [c_int32, c_int32, POINTER(c_char_p)]),
+    "sym_default_variant": (c_int32, [c_int32, I32P]),
     "sym_fmove_coeff": (c_double, [c_int32] * 6),
     "sym_last_error": (c_char_p, []),
     "sym_version": (c_char_p, []),

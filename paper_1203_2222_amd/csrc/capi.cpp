@@ -840,6 +840,21 @@ int32_t sym_num_variants(int32_t compute, int32_t* count) {
     });
 }
 
+int32_t sym_variant_name(int32_t compute, int32_t variant, const char** name) {
+    return guard([&] {
+        if (!name || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");
+        if (variant < 0 || variant >= gemm_num_variants(compute)) throw Error(SYM_E_ARG, "no such variant");
+        *name = gemm_variant(compute, variant).name;
+    });
+}
+
+int32_t sym_default_variant(int32_t compute, int32_t* variant) {
+    return guard([&] {
+        if (!variant || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");
+        *variant = gemm_default_variant(compute);
+    });
+}
+
 int32_t sym_ctx_set_variant(sym_ctx* ctx, int32_t compute, int32_t variant) {
     return guard([&] {
         if (!ctx || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");

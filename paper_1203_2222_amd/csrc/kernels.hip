@@ -47,6 +47,11 @@ struct Conv<uint16_t, float> {
     __device__ static float f(uint16_t x) { return bf16_to_f32(x); }
 };
 
+// floor(n / d) for 0 <= n < 2^31 from the divisor's multiplier and shift
+__device__ __forceinline__ int div_by(int n, uint32_t mag, int shf) {
+    return static_cast<int>((static_cast<uint64_t>(static_cast<uint32_t>(n)) * mag) >> (31 + shf));
+}
+
 // ---------------------------------------------------------------------------
 // K2/K3: block permute (fuse, split, reorder).  Each workgroup walks its own
 // range of tasks; a task is a slice of one block copy.  Threads run along the
@@ -67,9 +72,9 @@ __global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops,
         const int inner = op.size[kMaxCopyDims - 1];
         const int64_t s_in = op.sstride[kMaxCopyDims - 1], d_in = op.dstride[kMaxCopyDims - 1];
         const int end = t.start + t.count;
-        // four independent elements per thread per pass: all loads are in
-        // flight before the first store waits on one
-        constexpr int U = 4;
+        // U independent elements per thread per pass (16 bytes of 2-byte
+        // elements): all loads are in flight before the first store waits
+        constexpr int U = sizeof(Ti) == 2 ? 8 : 4;
         for (int base = t.start; base < end; base += 256 * U) {
             Ti v[U];
             int64_t dofs[U];
@@ -79,13 +84,12 @@ __global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops,
                 const int e = base + static_cast<int>(threadIdx.x) + u * 256;
                 ok[u] = e < end;
                 const int ee = ok[u] ? e : t.start;
-                int rem = ee / inner;
+                int rem = div_by(ee, op.mag[kMaxCopyDims - 1], op.shf[kMaxCopyDims - 1]);
                 const int i0 = ee - rem * inner;
                 int64_t so = i0 * s_in, dof = i0 * d_in;
                 for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - nd; --d) {
-                    const int sz = op.size[d];
-                    const int q = rem / sz;
-                    const int i = rem - q * sz;
+                    const int q = div_by(rem, op.mag[d], op.shf[d]);
+                    const int i = rem - q * op.size[d];
                     rem = q;
                     so += i * op.sstride[d];
                     dof += i * op.dstride[d];
@@ -106,10 +110,8 @@ __global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops,
 // the transposed reads free of bank conflicts) and written with lanes running
 // along the destination's contiguous dim, so both sides stay coalesced.
 template <typename Ti, typename To>
-__global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict__ ops, const TileTask* __restrict__ tasks,
-                                                       PtrTable bufs) {
-    __shared__ Ti tile[kTile][kTile + 1];
-    const TileTask t = tasks[blockIdx.x];
+__device__ __forceinline__ void tile_copy(const CopyOp* __restrict__ ops, const TileTask t, const PtrTable& bufs,
+                                          Ti (&tile)[kTile][kTile + 1]) {
     const CopyOp& op = ops[t.op];
     const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[op.src_buf]) + op.src_off;
     To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[op.dst_buf])) + op.dst_off;
@@ -119,9 +121,8 @@ __global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict_
     int rem = t.outer;
     for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d) {
         if (d == J) continue;
-        const int sz = op.size[d];
-        const int q = rem / sz;
-        const int i = rem - q * sz;
+        const int q = div_by(rem, op.mag[d], op.shf[d]);
+        const int i = rem - q * op.size[d];
         rem = q;
         so += i * op.sstride[d];
         dof += i * op.dstride[d];
@@ -143,18 +144,30 @@ __global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict_
     }
 }
 
+// Each workgroup walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict__ ops, const TileTask* __restrict__ tasks,
+                                                       int n_tasks, PtrTable bufs) {
+    __shared__ Ti tile[kTile][kTile + 1];
+    for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+        tile_copy<Ti, To>(ops, tasks[ti], bufs, tile);
+        __syncthreads();   // every read of the tile is done before the next task writes it
+    }
+}
+
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks, int32_t n_tasks,
-                                const PtrTable& bufs, hipStream_t s) {
+                                int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
     if (n_tasks <= 0) return hipSuccess;
-    dim3 grid(static_cast<unsigned>(n_tasks)), block(256);
+    if (n_wg <= 0) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(n_wg)), block(256);
     if (src_dtype == 0 && dst_dtype == 0)
-        hipLaunchKernelGGL((k_permute_tiled<float, float>), grid, block, 0, s, ops, tasks, bufs);
+        hipLaunchKernelGGL((k_permute_tiled<float, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
     else if (src_dtype == 0 && dst_dtype == 1)
-        hipLaunchKernelGGL((k_permute_tiled<float, uint16_t>), grid, block, 0, s, ops, tasks, bufs);
+        hipLaunchKernelGGL((k_permute_tiled<float, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
     else if (src_dtype == 1 && dst_dtype == 1)
-        hipLaunchKernelGGL((k_permute_tiled<uint16_t, uint16_t>), grid, block, 0, s, ops, tasks, bufs);
+        hipLaunchKernelGGL((k_permute_tiled<uint16_t, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
     else
-        hipLaunchKernelGGL((k_permute_tiled<uint16_t, float>), grid, block, 0, s, ops, tasks, bufs);
+        hipLaunchKernelGGL((k_permute_tiled<uint16_t, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
     return hipGetLastError();
 }
 
@@ -632,8 +645,268 @@ int occupancy_big() {
     return n > 0 ? n : 1;
 }
 
+// ---------------------------------------------------------------------------
+// K6 with direct loads: operand slices go from global memory straight into
+// LDS (16-byte buffer loads with the LDS bit: no staging registers, no LDS
+// store instructions) through a ring of ST stages.  Iteration kt computes
+// slice kt, needs slice kt + 1 in LDS (its last K step already reads the
+// first fragments of the next slice, so no MFMA waits on LDS after a
+// barrier) and keeps slices kt + 2 .. kt + ST - 2 in flight.
+//
+// A wave's load fills a 1 KB window of LDS, lane l at byte 16 l, so the row
+// swizzle moves to the global side: LDS slot (r, c') receives chunk
+// c' ^ f(r) of row r.  Each operand is addressed through a buffer resource
+// whose base is the tile's first row and whose size ends at the tile's last
+// valid row; rows past M, chunks past the padded row length and slices past
+// K get an offset beyond that size, which the buffer unit's range check
+// turns into zeros without accessing memory.  Requires lda, ldb multiples of
+// 8 elements with zeros in columns [K, ld) (the planner's operand layouts)
+// and MT * ld * 2 < 2^31 bytes (checked on the host).
+// ---------------------------------------------------------------------------
+constexpr int kDlMaxLd = 1 << 21;
+
+// LDS slot of 16-byte chunk c of row r for rows of CH chunks.  The LDS serves
+// a 16-byte-per-lane read 16 lanes at a time from 64 four-byte banks (256
+// bytes), and a fragment read has 16 consecutive rows at one chunk: XOR-ing
+// the chunk with (r / (16 / CH)) puts those rows on 16 distinct 16-byte bank
+// groups.
+template <int CH>
+__device__ __forceinline__ int swz16(int r, int c) {
+    return r * CH + (c ^ ((r / (16 / CH)) & (CH - 1)));
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    // 0x00020000: raw (untyped) 32-bit data format, the gfx9 default
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0), static_cast<int>(bytes),
+                                             0x00020000);
+}
+
+__device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, u32x4* lds_window, uint32_t voffset) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_window, 16, voffset, 0, 0,
+                                             0);
+}
+
+// s_waitcnt immediate that waits until at most n vector memory operations of
+// this wave are outstanding (expcnt and lgkmcnt left unconstrained)
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
+
+// OPT bit 0: raise the wave's issue priority while it issues MFMAs; bit 1:
+// interleave the next step's fragment reads with the MFMAs one by one.
+template <int MT, int NT, int KT, int WGM, int WGN, int ST, int OPT>
+__global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmProb* __restrict__ probs,
+                                                                    const GemmTile* __restrict__ tiles, int n_tiles,
+                                                                    const EpiRow* __restrict__ rows,
+                                                                    const EpiCol* __restrict__ cols, PtrTable bufs) {
+    constexpr int NTHR = 64 * WGM * WGN;
+    constexpr int CH = KT / 8;
+    constexpr int WM = MT / WGM, WN = NT / WGN;
+    constexpr int FM = WM / 32, FN = WN / 32;
+    constexpr int AV = MT * CH / NTHR, BV = NT * CH / NTHR;
+    constexpr int SA = MT * CH, SB = NT * CH;
+    constexpr int S = KT / 16;
+    static_assert(AV >= 1 && BV >= 1 && AV * NTHR == SA && BV * NTHR == SB && (CH & (CH - 1)) == 0 && CH <= 16 &&
+                      ST >= 3 && S % 2 == 0,
+                  "bad tile");
+    extern __shared__ u32x4 smem[];
+    u32x4* As = smem;            // [ST][SA]
+    u32x4* Bs = smem + ST * SA;  // [ST][SB]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int h = lane >> 5, r32 = lane & 31;
+
+    // the LDS slot of each of this thread's loads, and the row and column
+    // (in elements, within a slice) whose chunk it receives
+    int a_row[AV], a_col[AV], b_row[BV], b_col[BV];
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+        const int p = tid + i * NTHR, r = p / CH;
+        a_row[i] = r;
+        a_col[i] = ((p % CH) ^ ((r / (16 / CH)) & (CH - 1))) * 8;
+    }
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+        const int p = tid + i * NTHR, r = p / CH;
+        b_row[i] = r;
+        b_col[i] = ((p % CH) ^ ((r / (16 / CH)) & (CH - 1))) * 8;
+    }
+
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const GemmTile tile = tiles[t];
+        const GemmProb p = probs[tile.prob];
+        const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
+        const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
+        float* C = static_cast<float*>(const_cast<void*>(bufs.p[p.c_buf])) + p.c_off;
+        const int m0 = tile.tm * MT, n0 = tile.tn * NT;
+
+        // the previous tile's loads and stores are complete and every wave is
+        // done reading its stages before this tile's loads overwrite them
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+
+        const int a_rows = min(MT, p.M - m0), b_rows = min(NT, p.N - n0);
+        const __amdgpu_buffer_rsrc_t ra =
+            make_rsrc(A + static_cast<int64_t>(m0) * p.lda, static_cast<uint32_t>(a_rows) * p.lda * 2u);
+        const __amdgpu_buffer_rsrc_t rb =
+            make_rsrc(B + static_cast<int64_t>(n0) * p.ldb, static_cast<uint32_t>(b_rows) * p.ldb * 2u);
+        uint32_t a_vo[AV], b_vo[BV];
+#pragma unroll
+        for (int i = 0; i < AV; ++i) a_vo[i] = (static_cast<uint32_t>(a_row[i]) * p.lda + a_col[i]) * 2u;
+#pragma unroll
+        for (int i = 0; i < BV; ++i) b_vo[i] = (static_cast<uint32_t>(b_row[i]) * p.ldb + b_col[i]) * 2u;
+
+        const int nk = (p.K + KT - 1) / KT;
+        // slices at or past nk are issued too (all lanes out of range, so
+        // they only write zeros to a stage nobody reads): that keeps the
+        // number of loads in flight, and so the wait below, the same for
+        // every slice
+        auto issue = [&](int kt, int stage) {
+            const int k0 = kt * KT;
+            const bool live = kt < nk;
+#pragma unroll
+            for (int i = 0; i < AV; ++i) {
+                const uint32_t vo = (live && k0 + a_col[i] < p.lda) ? a_vo[i] + 2u * k0 : 0x80000000u;
+                load_to_lds(ra, As + stage * SA + i * NTHR + wave * 64, vo);
+            }
+#pragma unroll
+            for (int i = 0; i < BV; ++i) {
+                const uint32_t vo = (live && k0 + b_col[i] < p.ldb) ? b_vo[i] + 2u * k0 : 0x80000000u;
+                load_to_lds(rb, Bs + stage * SB + i * NTHR + wave * 64, vo);
+            }
+        };
+
+        v16f acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+
+        // fragments of one K step (16) of the slice in stage st
+        u32x4 af[2][FM], bfr[2][FN];
+        auto frags = [&](int st, int step, int set) {
+            const u32x4* Ac = As + st * SA;
+            const u32x4* Bc = Bs + st * SB;
+            const int c = 2 * step + h;
+#pragma unroll
+            for (int i = 0; i < FM; ++i) af[set][i] = Ac[swz16<CH>(wm * WM + i * 32 + r32, c)];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bfr[set][j] = Bc[swz16<CH>(wn * WN + j * 32 + r32, c)];
+        };
+
+#pragma unroll
+        for (int s = 0; s < ST - 1; ++s) issue(s, s);
+        // slice 0 visible to every wave
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((ST - 2) * (AV + BV)));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        frags(0, 0, 0);
+        int sr = 0, sw = ST - 1;
+        for (int kt = 0; kt < nk; ++kt) {
+            // slices kt and kt + 1 have landed for this wave; after the
+            // barrier for every wave, and every wave is done with iteration
+            // kt - 1, so stage sw (slice kt - 1) is free
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm((ST - 3) * (AV + BV)));
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            issue(kt + ST - 1, sw);
+            __builtin_amdgcn_sched_barrier(0);
+            const int sn = sr + 1 == ST ? 0 : sr + 1;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int cs = s & 1;
+                // the last step fetches the first fragments of slice kt + 1,
+                // so the MFMAs never wait on LDS after the barrier
+                const int st = s + 1 < S ? sr : sn, step = s + 1 < S ? s + 1 : 0;
+                if constexpr ((OPT & 2) == 0) {
+                    frags(st, step, cs ^ 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if constexpr ((OPT & 1) != 0) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[cs][i]),
+                                                                             __builtin_bit_cast(bf16x8, bfr[cs][j]),
+                                                                             acc[i][j], 0, 0, 0);
+                        if constexpr ((OPT & 2) != 0) {
+                            // after MFMA number f, read fragment f of the next step
+                            // (B fragments first: the next step opens with A0 x B0)
+                            const int f = i * FN + j;
+                            const u32x4* Ac = As + st * SA;
+                            const u32x4* Bc = Bs + st * SB;
+                            const int c = 2 * step + h;
+                            if (f < FN) bfr[cs ^ 1][f] = Bc[swz16<CH>(wn * WN + f * 32 + r32, c)];
+                            else if (f < FM + FN)
+                                af[cs ^ 1][f - FN] = Ac[swz16<CH>(wm * WM + (f - FN) * 32 + r32, c)];
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    }
+                if constexpr ((OPT & 1) != 0) __builtin_amdgcn_s_setprio(0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            sr = sn;
+            sw = sw + 1 == ST ? 0 : sw + 1;
+        }
+
+        store_tile<FM, FN>(acc, p, C, rows, cols, m0 + wm * WM, n0 + wn * WN, h, r32);
+    }
+    // no load may still be writing LDS when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+}
+
+template <int MT, int NT, int KT, int ST>
+constexpr size_t dl_lds_bytes() {
+    return static_cast<size_t>(ST) * (MT + NT) * (KT / 8) * 16;
+}
+
+template <int MT, int NT, int KT, int WGM, int WGN, int ST, int OPT>
+hipError_t launch_dl(const GemmProb* probs, const GemmTile* tiles, int32_t n_tiles, int32_t grid, const EpiRow* rows,
+                     const EpiCol* cols, const PtrTable& bufs, hipStream_t s) {
+    constexpr size_t lds = dl_lds_bytes<MT, NT, KT, ST>();
+    static bool configured = false;
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_dl<MT, NT, KT, WGM, WGN, ST, OPT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    hipLaunchKernelGGL((k_gemm_bf16_dl<MT, NT, KT, WGM, WGN, ST, OPT>), dim3(static_cast<unsigned>(grid)),
+                       dim3(64 * WGM * WGN), lds, s, probs, tiles, n_tiles, rows, cols, bufs);
+    return hipGetLastError();
+}
+
+template <int MT, int NT, int KT, int WGM, int WGN, int ST, int OPT>
+int occupancy_dl() {
+    constexpr size_t lds = dl_lds_bytes<MT, NT, KT, ST>();
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_dl<MT, NT, KT, WGM, WGN, ST, OPT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_dl<MT, NT, KT, WGM, WGN, ST, OPT>, 64 * WGM * WGN,
+                                                     lds) != hipSuccess)
+        n = 1;
+    return n > 0 ? n : 1;
+}
+
+// direct-load variants: (variant, MT, NT, KT, WGM, WGN, stages)
+#define SYM_BF16_DL_VARIANTS(X)        \
+    X(9, 256, 256, 32, 2, 4, 4, 0)     \
+    X(10, 256, 256, 32, 2, 4, 5, 0)    \
+    X(11, 256, 256, 32, 2, 2, 5, 0)    \
+    X(12, 256, 256, 32, 2, 4, 5, 1)    \
+    X(13, 256, 256, 32, 2, 4, 5, 2)    \
+    X(14, 256, 256, 32, 2, 4, 5, 3)    \
+    X(15, 256, 256, 32, 2, 2, 5, 1)
+
+bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 15; }
+int gemm_direct_max_ld() { return kDlMaxLd; }
+
 // BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
-// grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel.
+// grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel;
+// v9-v15 k_gemm_bf16_dl.
 #define SYM_BF16_BIG_VARIANTS(X)              \
     X(0, 256, 256, 64, 2, 2, 1, 4)            \
     X(1, 256, 128, 64, 2, 2, 1, 4)            \
@@ -644,21 +917,38 @@ int occupancy_big() {
     X(8, 256, 128, 64, 4, 2, 2, 4)
 
 namespace {
-const GemmVariant kF32Variants[] = {{128, 128, "f32_128x128"}, {64, 64, "f32_64x64"}, {128, 64, "f32_128x64"}};
-const GemmVariant kBF16Variants[] = {{256, 256, "bf16_256x256_k64"}, {256, 128, "bf16_256x128_k64"},
-                                     {128, 128, "bf16_128x128_k64"}, {128, 128, "bf16_128x128_k32"},
-                                     {64, 64, "bf16_64x64_k32"},      {256, 256, "bf16_256x256_k64_8w"},
-                                     {256, 128, "bf16_256x128_k64_8w_early"},
-                                     {128, 128, "bf16_128x128_k64_early"}, {256, 128, "bf16_256x128_k64_8w"}};
+const GemmVariant kF32Variants[] = {{128, 128, "k_gemm_f32 128x128"},
+                                    {64, 64, "k_gemm_f32 64x64"},
+                                    {128, 64, "k_gemm_f32 128x64"}};
+const GemmVariant kBF16Variants[] = {{256, 256, "k_gemm_bf16_big 256x256 k64 4w"},
+                                     {256, 128, "k_gemm_bf16_big 256x128 k64 4w"},
+                                     {128, 128, "k_gemm_bf16_big 128x128 k64 4w occ2"},
+                                     {128, 128, "k_gemm_bf16 128x128 k32"},
+                                     {64, 64, "k_gemm_bf16 64x64 k32"},
+                                     {256, 256, "k_gemm_bf16_big 256x256 k64 8w"},
+                                     {256, 128, "k_gemm_bf16_big 256x128 k64 8w early-store"},
+                                     {128, 128, "k_gemm_bf16_big 128x128 k64 4w early-store"},
+                                     {256, 128, "k_gemm_bf16_big 256x128 k64 8w"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 4-stage"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio interleaved"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 3 : 9; }
+int gemm_num_variants(int compute) { return compute == 0 ? 3 : 16; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
-// Defaults from measurements on MI355X.  The batched BF16 GEMM is bound by
-// operand re-reads beyond L2, so the largest tile wins: 256x256 with 8 waves
-// (two per SIMD, so one wave's LDS phase overlaps the other's MFMAs) ran the
-// 64-member batch at 838 TFLOP/s against 406 for 128x128.
-int gemm_default_variant(int compute) { return compute == 0 ? 0 : 5; }
+// Defaults from measurements on MI355X.  256x256 tiles (operand re-reads
+// beyond L2 fall with the tile size: 128x128 ran the 64-member batch at 406
+// TFLOP/s) with 8 waves, two per SIMD, fed by direct loads through a
+// five-stage LDS ring: 917 TFLOP/s on the batch and 1158 on one 8192^3
+// product, against 774-802 and 832 for the register-staged 256x256 kernel
+// on the same GPU.  The ranking moved between GPUs of the pool, which is
+// what the autotuner is for.
+int gemm_default_variant(int compute) { return compute == 0 ? 0 : 10; }
+int gemm_default_variant_wide(int compute) { return compute == 0 ? 0 : 5; }
 
 int gemm_blocks_per_cu(int compute, int variant) {
     int n = 0;
@@ -675,6 +965,10 @@ int gemm_blocks_per_cu(int compute, int variant) {
     case V: return occupancy_big<MT, NT, KT, WGM, WGN, OCC, SA>();
             SYM_BF16_BIG_VARIANTS(SYM_OCC_CASE)
 #undef SYM_OCC_CASE
+#define SYM_OCC_DL_CASE(V, MT, NT, KT, WGM, WGN, ST, OPT) \
+    case V: return occupancy_dl<MT, NT, KT, WGM, WGN, ST, OPT>();
+            SYM_BF16_DL_VARIANTS(SYM_OCC_DL_CASE)
+#undef SYM_OCC_DL_CASE
             case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<128, 128>, 256, 0); break;
             case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<64, 64>, 256, 0); break;
             default: break;
@@ -700,6 +994,10 @@ hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const Ge
     case V: return launch_big<MT, NT, KT, WGM, WGN, OCC, SA>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
         SYM_BF16_BIG_VARIANTS(SYM_LAUNCH_CASE)
 #undef SYM_LAUNCH_CASE
+#define SYM_LAUNCH_DL_CASE(V, MT, NT, KT, WGM, WGN, ST, OPT) \
+    case V: return launch_dl<MT, NT, KT, WGM, WGN, ST, OPT>(probs, tiles, n_tiles, grid, rows, cols, bufs, s);
+        SYM_BF16_DL_VARIANTS(SYM_LAUNCH_DL_CASE)
+#undef SYM_LAUNCH_DL_CASE
         case 3: hipLaunchKernelGGL((k_gemm_bf16<128, 128>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
         case 4: hipLaunchKernelGGL((k_gemm_bf16<64, 64>), g, b, 0, s, probs, tiles, n_tiles, rows, cols, bufs); break;
         default: return hipErrorInvalidValue;

@@ -22,6 +22,9 @@ struct CopyOp {
     int64_t sstride[kMaxCopyDims];
     int64_t dstride[kMaxCopyDims];
     int32_t size[kMaxCopyDims];
+    // floor(n / size[d]) = (n * mag[d]) >> (31 + shf[d]) for 0 <= n < 2^31
+    uint32_t mag[kMaxCopyDims];
+    int32_t shf[kMaxCopyDims];
     int32_t src_buf, dst_buf;
     int32_t count;
     int32_t ndim;
@@ -97,8 +100,9 @@ struct FmTask {
 // Launchers (kernels.hip).  Every launcher returns the hipError_t of the launch.
 hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
+// grid: workgroups, each taking tasks w, w + grid, ...
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
-                                int32_t n_tasks, const PtrTable& bufs, hipStream_t s);
+                                int32_t n_tasks, int32_t grid, const PtrTable& bufs, hipStream_t s);
 hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles,
                        int32_t n_tiles, int32_t grid, const EpiRow* rows, const EpiCol* cols,
                        const PtrTable& bufs, hipStream_t s);
@@ -114,6 +118,12 @@ struct GemmVariant {
 int gemm_num_variants(int compute);
 GemmVariant gemm_variant(int compute, int variant);
 int gemm_default_variant(int compute);
+// Default for problems whose row lengths rule out the direct-load variants.
+int gemm_default_variant_wide(int compute);
+// Direct-load BF16 variants address each operand tile through a 32-bit
+// buffer range: they take row lengths (lda, ldb) below gemm_direct_max_ld().
+bool gemm_variant_direct(int compute, int variant);
+int gemm_direct_max_ld();
 // Resident workgroups per CU of a variant (persistent grid sizing).
 int gemm_blocks_per_cu(int compute, int variant);
 

@@ -32,6 +32,21 @@ DevMemPtr upload_vec(const Allocator& alloc, const std::vector<T>& v) {
 // CopyProgram
 // ---------------------------------------------------------------------------
 
+// Division by an invariant divisor for dividends below 2^31: with
+// s = ceil(log2 d) and m = ceil(2^(31+s) / d) < 2^32, the error of n m / 2^(31+s)
+// against n / d is below n (m d - 2^(31+s)) / (d 2^(31+s)) < 2^-s <= 1/d, too
+// small to move the floor (round-up multiplier method, Granlund and
+// Montgomery, PLDI 1994).
+static void set_divisor(CopyOp& op, int d) {
+    const uint64_t v = static_cast<uint64_t>(std::max(1, op.size[d]));
+    int s = 0;
+    while ((uint64_t{1} << s) < v) ++s;
+    const uint64_t m = ((uint64_t{1} << (31 + s)) + v - 1) / v;
+    if (m >= (uint64_t{1} << 32)) throw Error(SYM_E_UNSUPPORTED, "division multiplier out of range");
+    op.mag[d] = static_cast<uint32_t>(m);
+    op.shf[d] = s;
+}
+
 void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
                       int64_t src_base, int64_t dst_base) {
     const int rank = dst.rank;
@@ -92,6 +107,7 @@ void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_
             op.sstride[d] = mss[ord[k]];
             op.dstride[d] = mds[ord[k]];
         }
+        for (int d = 0; d < kMaxCopyDims; ++d) set_divisor(op, d);
         op.ndim = m;
         op.count = static_cast<int32_t>(b.size);
         op.src_buf = src_buf;
@@ -123,9 +139,11 @@ void CopyProgram::finalize() {
             for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d)
                 if (d != op.tj) outer *= op.size[d];
             const int nj = (op.size[op.tj] + kTile - 1) / kTile, ni = (op.size[I] + kTile - 1) / kTile;
+            // tiles adjacent along the source's contiguous dim share the
+            // cache lines at their boundary: keep them next to each other
             for (int64_t o = 0; o < outer; ++o)
-                for (int jt = 0; jt < nj; ++jt)
-                    for (int it = 0; it < ni; ++it)
+                for (int it = 0; it < ni; ++it)
+                    for (int jt = 0; jt < nj; ++jt)
                         tile_tasks.push_back({static_cast<int32_t>(i), static_cast<int32_t>(o), jt, it});
             continue;
         }
@@ -145,6 +163,20 @@ void CopyProgram::finalize() {
         }
     }
     if (wg_begin.back() != static_cast<int32_t>(tasks.size())) wg_begin.push_back(static_cast<int32_t>(tasks.size()));
+    // The tiled kernel runs tile_grid workgroups; workgroup w sits on XCD
+    // w % 8 and takes tasks w, w + tile_grid, ...  Each round of tile_grid
+    // tasks gives every XCD a contiguous run of the sequence, so that tiles
+    // sharing boundary lines meet in the same L2.
+    const int64_t n = static_cast<int64_t>(tile_tasks.size());
+    tile_grid = static_cast<int32_t>(std::min<int64_t>(n, kTileGridMax));
+    if (tile_grid >= 8) {
+        const int64_t g = tile_grid - tile_grid % 8, per = g / 8;
+        tile_grid = static_cast<int32_t>(g);
+        std::vector<TileTask> seq(tile_tasks);
+        for (int64_t r0 = 0; r0 + g <= n; r0 += g)
+            for (int64_t w = 0; w < g; ++w)
+                tile_tasks[static_cast<size_t>(r0 + w)] = seq[static_cast<size_t>(r0 + (w % 8) * per + w / 8)];
+    }
 }
 
 void CopyProgram::upload(const Allocator& alloc) {
@@ -165,7 +197,7 @@ hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
     if (!tile_tasks.empty())
         return launch_permute_tiled(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
                                     static_cast<const TileTask*>(d_tile_tasks->ptr),
-                                    static_cast<int32_t>(tile_tasks.size()), bufs, s);
+                                    static_cast<int32_t>(tile_tasks.size()), tile_grid, bufs, s);
     return hipSuccess;
 }
 
@@ -310,6 +342,14 @@ bool GemmProgram::add_indirect(const Desc& Z, const Desc& out, const Desc& X, co
 }
 
 void GemmProgram::finalize(int v, int grid) {
+    if (gemm_variant_direct(compute, v)) {
+        // direct-load kernels address a tile's rows through a 32-bit range
+        for (const GemmProb& p : probs)
+            if (p.lda >= gemm_direct_max_ld() || p.ldb >= gemm_direct_max_ld()) {
+                v = gemm_default_variant_wide(compute);
+                break;
+            }
+    }
     variant = v;
     const GemmVariant gv = gemm_variant(compute, v);
     // longest-processing-time order: all tiles of one sector cost ~K, so sort

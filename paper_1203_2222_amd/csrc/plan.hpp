@@ -33,6 +33,8 @@ struct CopyProgram {
     std::vector<CopyTask> tasks;
     std::vector<int32_t> wg_begin;
     std::vector<TileTask> tile_tasks;
+    int32_t tile_grid = 0;   // workgroups of the tiled kernel (a multiple of 8 once there are 8 tasks)
+    static constexpr int32_t kTileGridMax = 8192;
     int src_dtype = SYM_F32, dst_dtype = SYM_F32;
     // device copies
     DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks;

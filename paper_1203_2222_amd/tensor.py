@@ -7,7 +7,7 @@ memory and the current HIP stream only.
 from __future__ import annotations
 
 import ctypes
-from ctypes import byref, c_float, c_int32, c_int64, c_void_p
+from ctypes import byref, c_char_p, c_float, c_int32, c_int64, c_void_p
 from dataclasses import dataclass
 from typing import List, Optional, Sequence, Tuple
 
@@ -338,6 +338,18 @@ class Graph:
 def num_variants(compute) -> int:
     n = c_int32()
     L.check(L.lib().sym_num_variants(_dtype_code(compute), byref(n)))
+    return n.value
+
+
+def variant_name(compute, variant: int) -> str:
+    name = c_char_p()
+    L.check(L.lib().sym_variant_name(_dtype_code(compute), int(variant), byref(name)))
+    return name.value.decode()
+
+
+def default_variant(compute) -> int:
+    n = c_int32()
+    L.check(L.lib().sym_default_variant(_dtype_code(compute), byref(n)))
     return n.value
 
 

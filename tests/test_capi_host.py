@@ -152,3 +152,14 @@ def test_error_paths():
     assert L.lib().sym_tensor_numel(None, None) == 1
     assert L.lib().sym_ctx_create(L.ALLOC_FN(), L.FREE_FN(), None, None) == 1
     assert "NULL" in L.lib().sym_last_error().decode()
+
+
+def test_variant_names_and_default():
+    import paper_1203_2222_amd as P
+    for compute in ("f32", "bf16"):
+        n = P.num_variants(compute)
+        names = [P.variant_name(compute, v) for v in range(n)]
+        assert len(set(names)) == n and all(names)
+        assert 0 <= P.default_variant(compute) < n
+    with pytest.raises(P.SymError):
+        P.variant_name("bf16", P.num_variants("bf16"))

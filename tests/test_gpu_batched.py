@@ -151,3 +151,24 @@ def test_bf16_stored_inputs(ctx, compute):
     for m, C, (fa, fb) in zip(members, Cs, hin):
         _, ref = K.contract_pairs(m.A, fa, m.B, fb, m.axes_a, m.axes_b)
         assert rel_err(host(C), ref) <= 1e-5, (m.name, compute)
+
+
+def test_bf16_variants_bitwise_equal(ctx):
+    # every BF16 variant runs the same MFMA over the same K steps in the same
+    # order, so tile shape, staging (registers or direct LDS loads) and stage
+    # count must not change a single bit of the result
+    say("case bf16 variants bitwise")
+    import paper_1203_2222_amd as P
+    members = _members()
+    As, Bs, Cs, hin = _build(ctx, members)
+    outs = {}
+    for v in range(P.num_variants("bf16")):
+        ctx.set_variant("bf16", v)
+        for C in Cs:
+            C.data.fill_(float("nan"))
+        ctx.contract_batched(As, Bs, (2, 3), (0, 1), "bf16", Cs)
+        outs[v] = [host(C).copy() for C in Cs]
+    ctx.set_variant("bf16", -1)
+    for v, o in outs.items():
+        for m, a, b in zip(members, outs[0], o):
+            assert np.array_equal(a, b), (v, m.name)
