@@ -104,6 +104,129 @@ __global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops,
     }
 }
 
+// Row copy: the task's source elements form one contiguous run.  They are
+// staged through LDS with 16-byte loads from 16-byte aligned addresses (a
+// range-checked buffer resource ends at the source buffer, so the loads past
+// the run's last element read zeros instead of memory beyond it), then every
+// destination row is written in 16-byte aligned chunks gathered from LDS;
+// the partial chunks at either end of a row take element stores.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+template <typename To>
+struct Pack;
+template <>
+struct Pack<float> {
+    static constexpr int V = 4;
+    __device__ static u32x4_t f(const float (&v)[4]) {
+        return u32x4_t{__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3])};
+    }
+};
+template <>
+struct Pack<uint16_t> {
+    static constexpr int V = 8;
+    __device__ static u32x4_t f(const uint16_t (&v)[8]) {
+        u32x4_t r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = static_cast<uint32_t>(v[2 * i]) | (static_cast<uint32_t>(v[2 * i + 1]) << 16);
+        return r;
+    }
+};
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_copy_rows(const CopyOp* __restrict__ ops, const RowTask* __restrict__ tasks,
+                                                   int n_tasks, PtrTable bufs) {
+    constexpr int VI = 16 / sizeof(Ti);
+    constexpr int VO = Pack<To>::V;
+    constexpr int I = kMaxCopyDims - 1;
+    __shared__ __attribute__((aligned(16))) Ti stage[kRowStage + 2 * VI];
+    for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+        const RowTask t = tasks[ti];
+        const CopyOp& op = ops[t.op];
+        const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[op.src_buf]);
+        To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[op.dst_buf]));
+        const int L = op.size[I];
+        const int64_t ldd = op.ndim > 1 ? op.dstride[I - 1] : 0;
+        const int64_t s0 = op.src_off + static_cast<int64_t>(t.row0) * L + t.col0;
+        const int n = t.nrows == 1 ? t.ncols : t.nrows * L;
+        // stage source elements [a0, s0 + n) at LDS index (element - a0)
+        const bool vec_src = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+        const int64_t a0 = vec_src ? (s0 & ~static_cast<int64_t>(VI - 1)) : s0;
+        if (vec_src) {
+            const int span = static_cast<int>(s0 + n - a0);
+            const int64_t avail = op.src_len - a0;
+            const int lim = static_cast<int>(avail < span + VI ? avail : span + VI);
+            // the range check works on whole 4-byte words: a 2-byte element
+            // sharing its word with the end of the buffer is loaded below
+            const int full = static_cast<int>(lim * sizeof(Ti)) & ~3;
+            const __amdgpu_buffer_rsrc_t r =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<Ti*>(src + a0), static_cast<short>(0), full, 0x00020000);
+            const int nvec = (span + VI - 1) / VI;
+            for (int v = threadIdx.x; v < nvec; v += 256)
+                reinterpret_cast<u32x4_t*>(stage)[v] =
+                    __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(r, v * 16, 0, 0));
+            const int e_full = full / static_cast<int>(sizeof(Ti));
+            if (e_full < lim && e_full < span) {
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    for (int e = e_full; e < lim && e < span; ++e) stage[e] = src[a0 + e];
+            }
+        } else {
+            for (int e = threadIdx.x; e < n; e += 256) stage[e] = src[s0 + e];
+        }
+        __syncthreads();
+        const int off = static_cast<int>(s0 - a0);
+        const int cols = t.ncols;
+        const int maxch = (cols + 2 * VO - 2) / VO;
+        const int items = t.nrows * maxch;
+        const bool vec_dst = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+        const float inv = 1.f / static_cast<float>(maxch);
+        for (int it = threadIdx.x; it < items; it += 256) {
+            int q = static_cast<int>(static_cast<float>(it) * inv);
+            int j = it - q * maxch;
+            if (j < 0) {
+                --q;
+                j += maxch;
+            } else if (j >= maxch) {
+                ++q;
+                j -= maxch;
+            }
+            const int64_t d0 = op.dst_off + static_cast<int64_t>(t.row0 + q) * ldd + t.col0;
+            const int delta = vec_dst ? static_cast<int>(d0 & (VO - 1)) : 0;
+            const int c_lo = j * VO - delta;
+            const Ti* row = stage + off + q * L;
+            if (vec_dst && c_lo >= 0 && c_lo + VO <= cols) {
+                To v[VO];
+#pragma unroll
+                for (int u = 0; u < VO; ++u) v[u] = Conv<Ti, To>::f(row[c_lo + u]);
+                *reinterpret_cast<u32x4_t*>(dst + d0 + c_lo) = Pack<To>::f(v);
+            } else {
+#pragma unroll
+                for (int u = 0; u < VO; ++u) {
+                    const int c = c_lo + u;
+                    if (c >= 0 && c < cols) dst[d0 + c] = Conv<Ti, To>::f(row[c]);
+                }
+            }
+        }
+        __syncthreads();   // the stage is free for the next task
+    }
+}
+
+hipError_t launch_copy_rows(int src_dtype, int dst_dtype, const CopyOp* ops, const RowTask* tasks, int32_t n_tasks,
+                            int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    if (n_wg <= 0) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(n_wg)), block(256);
+    if (src_dtype == 0 && dst_dtype == 0)
+        hipLaunchKernelGGL((k_copy_rows<float, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    else if (src_dtype == 0 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_copy_rows<float, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    else if (src_dtype == 1 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_copy_rows<uint16_t, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    else
+        hipLaunchKernelGGL((k_copy_rows<uint16_t, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    return hipGetLastError();
+}
+
 // Transposing block copy: the source is contiguous along dim tj, the
 // destination along the innermost dim.  A 64 x 64 tile is read with lanes
 // running along the source's contiguous dim, staged in LDS (row pitch 65 keeps

@@ -29,13 +29,22 @@ struct CopyOp {
     int32_t count;
     int32_t ndim;
     int32_t tj;          // tiled copies: the dim that is contiguous in the source
-    int32_t pad;
+    int32_t rowcopy;     // rows of a contiguous source run along the destination's rows
+    int64_t src_len;     // elements readable from the source buffer's base pointer
 };
 
 // A slice [start, start+count) of one CopyOp's elements (in destination order).
 struct CopyTask {
     int32_t op, start, count, pad;
 };
+
+// Row copies: rows [row0, row0 + nrows), columns [col0, col0 + ncols) of a
+// CopyOp whose inner dim is contiguous on both sides and whose source rows
+// follow each other (nrows > 1 only with whole rows).
+struct RowTask {
+    int32_t op, row0, nrows, col0, ncols, pad0, pad1, pad2;
+};
+constexpr int kRowStage = 8192;   // source elements one row task stages through LDS
 
 // One 64 x 64 tile of a transposing copy: rows along the destination's
 // contiguous dim (index kMaxCopyDims-1), columns along the source's (tj).
@@ -100,6 +109,8 @@ struct FmTask {
 // Launchers (kernels.hip).  Every launcher returns the hipError_t of the launch.
 hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
+hipError_t launch_copy_rows(int src_dtype, int dst_dtype, const CopyOp* ops, const RowTask* tasks, int32_t n_tasks,
+                            int32_t grid, const PtrTable& bufs, hipStream_t s);
 // grid: workgroups, each taking tasks w, w + grid, ...
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
                                 int32_t n_tasks, int32_t grid, const PtrTable& bufs, hipStream_t s);

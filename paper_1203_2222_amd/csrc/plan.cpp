@@ -113,6 +113,13 @@ void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_
         op.src_buf = src_buf;
         op.dst_buf = dst_buf;
         op.tj = -1;
+        op.src_len = src_base + src.numel;
+        // rows of one contiguous source run, written along contiguous destination rows
+        constexpr int II = kMaxCopyDims - 1;
+        op.rowcopy = (m <= 2 && op.sstride[II] == 1 && op.dstride[II] == 1 &&
+                      (m == 1 || op.sstride[II - 1] == op.size[II]))
+                         ? 1
+                         : 0;
         // a transposing copy (the source is contiguous along another dim) goes
         // through the LDS-tiled kernel when both dims are wide enough
         constexpr int I = kMaxCopyDims - 1;
@@ -131,6 +138,7 @@ void CopyProgram::finalize() {
     tasks.clear();
     wg_begin.clear();
     tile_tasks.clear();
+    row_tasks.clear();
     for (size_t i = 0; i < ops.size(); ++i) {
         const CopyOp& op = ops[i];
         if (op.tj >= 0) {
@@ -145,6 +153,20 @@ void CopyProgram::finalize() {
                 for (int it = 0; it < ni; ++it)
                     for (int jt = 0; jt < nj; ++jt)
                         tile_tasks.push_back({static_cast<int32_t>(i), static_cast<int32_t>(o), jt, it});
+            continue;
+        }
+        if (op.rowcopy) {
+            constexpr int II = kMaxCopyDims - 1;
+            const int32_t L = op.size[II], R = op.ndim > 1 ? op.size[II - 1] : 1;
+            if (L <= kRowStage) {
+                const int32_t per = std::max<int32_t>(1, kRowStage / L);
+                for (int32_t r = 0; r < R; r += per)
+                    row_tasks.push_back({static_cast<int32_t>(i), r, std::min(per, R - r), 0, L, 0, 0, 0});
+            } else {
+                for (int32_t r = 0; r < R; ++r)
+                    for (int32_t c = 0; c < L; c += kRowStage)
+                        row_tasks.push_back({static_cast<int32_t>(i), r, 1, c, std::min(kRowStage, L - c), 0, 0, 0});
+            }
             continue;
         }
         for (int32_t s = 0; s < op.count; s += kChunk)
@@ -184,6 +206,7 @@ void CopyProgram::upload(const Allocator& alloc) {
     d_tasks = upload_vec(alloc, tasks);
     d_wg = upload_vec(alloc, wg_begin);
     d_tile_tasks = upload_vec(alloc, tile_tasks);
+    d_row_tasks = upload_vec(alloc, row_tasks);
 }
 
 hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
@@ -192,6 +215,13 @@ hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
         hipError_t e = launch_permute(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
                                       static_cast<const CopyTask*>(d_tasks->ptr), static_cast<const int32_t*>(d_wg->ptr),
                                       static_cast<int32_t>(wg_begin.size()) - 1, bufs, s);
+        if (e != hipSuccess) return e;
+    }
+    if (!row_tasks.empty()) {
+        const int32_t n = static_cast<int32_t>(row_tasks.size());
+        hipError_t e = launch_copy_rows(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
+                                        static_cast<const RowTask*>(d_row_tasks->ptr), n,
+                                        std::min<int32_t>(n, kTileGridMax), bufs, s);
         if (e != hipSuccess) return e;
     }
     if (!tile_tasks.empty())

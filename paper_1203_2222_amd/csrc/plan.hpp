@@ -33,11 +33,12 @@ struct CopyProgram {
     std::vector<CopyTask> tasks;
     std::vector<int32_t> wg_begin;
     std::vector<TileTask> tile_tasks;
+    std::vector<RowTask> row_tasks;
     int32_t tile_grid = 0;   // workgroups of the tiled kernel (a multiple of 8 once there are 8 tasks)
     static constexpr int32_t kTileGridMax = 8192;
     int src_dtype = SYM_F32, dst_dtype = SYM_F32;
     // device copies
-    DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks;
+    DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks, d_row_tasks;
 
     // dst block j <- src block with labels dst.labels permuted back by perm
     void add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
