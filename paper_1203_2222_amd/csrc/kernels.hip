@@ -161,14 +161,12 @@ __global__ __launch_bounds__(256) void k_copy_rows(const CopyOp* __restrict__ op
             const __amdgpu_buffer_rsrc_t r =
                 __builtin_amdgcn_make_buffer_rsrc(const_cast<Ti*>(src + a0), static_cast<short>(0), full, 0x00020000);
             const int nvec = (span + VI - 1) / VI;
-            for (int v = threadIdx.x; v < nvec; v += 256)
+            const int e_full = full / static_cast<int>(sizeof(Ti));
+            for (int v = threadIdx.x; v < nvec; v += 256) {
                 reinterpret_cast<u32x4_t*>(stage)[v] =
                     __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(r, v * 16, 0, 0));
-            const int e_full = full / static_cast<int>(sizeof(Ti));
-            if (e_full < lim && e_full < span) {
-                __syncthreads();
-                if (threadIdx.x == 0)
-                    for (int e = e_full; e < lim && e < span; ++e) stage[e] = src[a0 + e];
+                for (int e = v * VI > e_full ? v * VI : e_full; e < (v + 1) * VI && e < lim; ++e)
+                    stage[e] = src[a0 + e];
             }
         } else {
             for (int e = threadIdx.x; e < n; e += 256) stage[e] = src[s0 + e];
@@ -267,6 +265,96 @@ __device__ __forceinline__ void tile_copy(const CopyOp* __restrict__ ops, const 
     }
 }
 
+// Vectorized transposing copy for tiles whose destination rows are
+// contiguous (unit stride along the destination's inner dim).  A tile is
+// TI (destination-contiguous dim) x kTile (source-contiguous dim); TI is
+// long so that a tile writes long destination row segments and few partial
+// cache lines.  Each source row of the tile is staged with 16-byte loads
+// from its aligned-down start (row r's first element lands at LDS column
+// off[r]), and each destination row is written in 16-byte aligned chunks
+// gathered down an LDS column, with element stores only at the ends.  The
+// source is read through one range-checked buffer resource per tile that
+// ends at the source buffer.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict__ ops,
+                                                       const TileTask* __restrict__ tasks, int n_tasks,
+                                                       PtrTable bufs) {
+    constexpr int VI = 16 / sizeof(Ti);
+    constexpr int VO = Pack<To>::V;
+    constexpr int RW = kTile + 2 * VI;             // staged row width (elements), 16-byte multiple
+    constexpr int NV = (kTile + 2 * VI - 2) / VI;  // vectors that cover one row segment
+    constexpr int TI = vtile_rows(sizeof(Ti));
+    constexpr int NC = (TI + 2 * VO - 2) / VO;     // chunks that cover one destination row segment
+    constexpr int I = kMaxCopyDims - 1;
+    __shared__ __attribute__((aligned(16))) Ti tile[TI * RW];
+    __shared__ int row_off[TI];
+    for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+        const TileTask t = tasks[ti];
+        const CopyOp& op = ops[t.op];
+        const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[op.src_buf]);
+        To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[op.dst_buf]));
+        const int J = op.tj;
+        int64_t so = op.src_off, dof = op.dst_off;
+        int rem = t.outer;
+        for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d) {
+            if (d == J) continue;
+            const int q = div_by(rem, op.mag[d], op.shf[d]);
+            const int i = rem - q * op.size[d];
+            rem = q;
+            so += i * op.sstride[d];
+            dof += i * op.dstride[d];
+        }
+        const int i0 = t.it * TI, j0 = t.jt * kTile;
+        const int ni = min(TI, op.size[I] - i0), nj = min(kTile, op.size[J] - j0);
+        const int64_t sI = op.sstride[I], dJ = op.dstride[J];
+        // row r of the tile: source elements [so + (i0 + r) sI + j0, + nj)
+        const int64_t base = (so + i0 * sI + j0) & ~static_cast<int64_t>(VI - 1);
+        const int64_t avail = op.src_len - base;
+        const int64_t cap = (int64_t{1} << 30) / static_cast<int64_t>(sizeof(Ti));
+        const int lim = static_cast<int>(avail < cap ? avail : cap);
+        const int full = static_cast<int>(lim * sizeof(Ti)) & ~3;
+        const int e_full = full / static_cast<int>(sizeof(Ti));
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<Ti*>(src + base), static_cast<short>(0), full, 0x00020000);
+        for (int it = threadIdx.x; it < TI * NV; it += 256) {
+            const int r = it / NV, v = it - r * NV;
+            if (r >= ni) continue;
+            const int64_t start = so + (i0 + r) * sI + j0;
+            const int64_t a = start & ~static_cast<int64_t>(VI - 1);
+            const int off = static_cast<int>(start - a);
+            if (v == 0) row_off[r] = off;
+            if (v * VI >= off + nj) continue;
+            const int e0 = static_cast<int>(a - base) + v * VI;   // element index from the resource base
+            reinterpret_cast<u32x4_t*>(tile + r * RW)[v] =
+                __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, e0 * static_cast<int>(sizeof(Ti)), 0, 0));
+            for (int e = e0 > e_full ? e0 : e_full; e < e0 + VI && e < lim; ++e) tile[r * RW + v * VI + (e - e0)] = src[base + e];
+        }
+        __syncthreads();
+        const bool vec_dst = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+        for (int it = threadIdx.x; it < kTile * NC; it += 256) {
+            const int c = it / kTile, j = it - c * kTile;   // lanes run along j: consecutive LDS columns
+            if (j >= nj) continue;
+            const int64_t d0 = dof + (j0 + j) * dJ + i0;
+            const int delta = vec_dst ? static_cast<int>(d0 & (VO - 1)) : 0;
+            const int c_lo = c * VO - delta;
+            if (c_lo >= ni || c_lo + VO <= 0) continue;
+            if (vec_dst && c_lo >= 0 && c_lo + VO <= ni) {
+                To v[VO];
+#pragma unroll
+                for (int u = 0; u < VO; ++u) v[u] = Conv<Ti, To>::f(tile[(c_lo + u) * RW + row_off[c_lo + u] + j]);
+                *reinterpret_cast<u32x4_t*>(dst + d0 + c_lo) = Pack<To>::f(v);
+            } else {
+#pragma unroll
+                for (int u = 0; u < VO; ++u) {
+                    const int r = c_lo + u;
+                    if (r >= 0 && r < ni) dst[d0 + r] = Conv<Ti, To>::f(tile[r * RW + row_off[r] + j]);
+                }
+            }
+        }
+        __syncthreads();   // the tile is free for the next task
+    }
+}
+
 // Each workgroup walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...
 template <typename Ti, typename To>
 __global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict__ ops, const TileTask* __restrict__ tasks,
@@ -276,6 +364,22 @@ __global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict_
         tile_copy<Ti, To>(ops, tasks[ti], bufs, tile);
         __syncthreads();   // every read of the tile is done before the next task writes it
     }
+}
+
+hipError_t launch_transpose_vec(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
+                                int32_t n_tasks, int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    if (n_wg <= 0) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(n_wg)), block(256);
+    if (src_dtype == 0 && dst_dtype == 0)
+        hipLaunchKernelGGL((k_transpose_vec<float, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    else if (src_dtype == 0 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_transpose_vec<float, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    else if (src_dtype == 1 && dst_dtype == 1)
+        hipLaunchKernelGGL((k_transpose_vec<uint16_t, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    else
+        hipLaunchKernelGGL((k_transpose_vec<uint16_t, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
+    return hipGetLastError();
 }
 
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks, int32_t n_tasks,

@@ -52,6 +52,9 @@ struct TileTask {
     int32_t op, outer, jt, it;
 };
 constexpr int kTile = 64;
+// rows (destination-contiguous extent) of a vectorized transposing tile, by
+// source element size
+constexpr int vtile_rows(int src_elem_bytes) { return src_elem_bytes == 2 ? 256 : 128; }
 
 // One sector GEMM: C[m][n] = sum_k A[m][k] * B[n][k] (both operands K-contiguous).
 // With `indirect` set, element (m, n) is stored at
@@ -111,6 +114,8 @@ hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
 hipError_t launch_copy_rows(int src_dtype, int dst_dtype, const CopyOp* ops, const RowTask* tasks, int32_t n_tasks,
                             int32_t grid, const PtrTable& bufs, hipStream_t s);
+hipError_t launch_transpose_vec(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
+                                int32_t n_tasks, int32_t grid, const PtrTable& bufs, hipStream_t s);
 // grid: workgroups, each taking tasks w, w + grid, ...
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
                                 int32_t n_tasks, int32_t grid, const PtrTable& bufs, hipStream_t s);

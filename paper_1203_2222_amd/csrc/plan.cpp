@@ -138,6 +138,7 @@ void CopyProgram::finalize() {
     tasks.clear();
     wg_begin.clear();
     tile_tasks.clear();
+    vtile_tasks.clear();
     row_tasks.clear();
     for (size_t i = 0; i < ops.size(); ++i) {
         const CopyOp& op = ops[i];
@@ -146,13 +147,20 @@ void CopyProgram::finalize() {
             int64_t outer = 1;
             for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d)
                 if (d != op.tj) outer *= op.size[d];
-            const int nj = (op.size[op.tj] + kTile - 1) / kTile, ni = (op.size[I] + kTile - 1) / kTile;
+            // destination rows of unit stride take the vectorized kernel, as
+            // long as one tile's source rows span less than 2^29 bytes
+            const int esz = src_dtype == SYM_BF16 ? 2 : 4;
+            const int ti = vtile_rows(esz);
+            const bool vec = op.dstride[I] == 1 && op.sstride[I] > 0 && op.sstride[I] * ti * esz < (int64_t{1} << 29);
+            const int nj = (op.size[op.tj] + kTile - 1) / kTile;
+            const int ni = (op.size[I] + (vec ? ti : kTile) - 1) / (vec ? ti : kTile);
+            std::vector<TileTask>& list = vec ? vtile_tasks : tile_tasks;
             // tiles adjacent along the source's contiguous dim share the
             // cache lines at their boundary: keep them next to each other
             for (int64_t o = 0; o < outer; ++o)
                 for (int it = 0; it < ni; ++it)
                     for (int jt = 0; jt < nj; ++jt)
-                        tile_tasks.push_back({static_cast<int32_t>(i), static_cast<int32_t>(o), jt, it});
+                        list.push_back({static_cast<int32_t>(i), static_cast<int32_t>(o), jt, it});
             continue;
         }
         if (op.rowcopy) {
@@ -189,16 +197,22 @@ void CopyProgram::finalize() {
     // w % 8 and takes tasks w, w + tile_grid, ...  Each round of tile_grid
     // tasks gives every XCD a contiguous run of the sequence, so that tiles
     // sharing boundary lines meet in the same L2.
-    const int64_t n = static_cast<int64_t>(tile_tasks.size());
-    tile_grid = static_cast<int32_t>(std::min<int64_t>(n, kTileGridMax));
-    if (tile_grid >= 8) {
-        const int64_t g = tile_grid - tile_grid % 8, per = g / 8;
-        tile_grid = static_cast<int32_t>(g);
-        std::vector<TileTask> seq(tile_tasks);
+    tile_grid = xcd_order(tile_tasks);
+    vtile_grid = xcd_order(vtile_tasks);
+}
+
+int32_t CopyProgram::xcd_order(std::vector<TileTask>& list) {
+    const int64_t n = static_cast<int64_t>(list.size());
+    int32_t grid = static_cast<int32_t>(std::min<int64_t>(n, kTileGridMax));
+    if (grid >= 8) {
+        const int64_t g = grid - grid % 8, per = g / 8;
+        grid = static_cast<int32_t>(g);
+        std::vector<TileTask> seq(list);
         for (int64_t r0 = 0; r0 + g <= n; r0 += g)
             for (int64_t w = 0; w < g; ++w)
-                tile_tasks[static_cast<size_t>(r0 + w)] = seq[static_cast<size_t>(r0 + (w % 8) * per + w / 8)];
+                list[static_cast<size_t>(r0 + w)] = seq[static_cast<size_t>(r0 + (w % 8) * per + w / 8)];
     }
+    return grid;
 }
 
 void CopyProgram::upload(const Allocator& alloc) {
@@ -207,6 +221,7 @@ void CopyProgram::upload(const Allocator& alloc) {
     d_wg = upload_vec(alloc, wg_begin);
     d_tile_tasks = upload_vec(alloc, tile_tasks);
     d_row_tasks = upload_vec(alloc, row_tasks);
+    d_vtile_tasks = upload_vec(alloc, vtile_tasks);
 }
 
 hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
@@ -222,6 +237,12 @@ hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
         hipError_t e = launch_copy_rows(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
                                         static_cast<const RowTask*>(d_row_tasks->ptr), n,
                                         std::min<int32_t>(n, kTileGridMax), bufs, s);
+        if (e != hipSuccess) return e;
+    }
+    if (!vtile_tasks.empty()) {
+        hipError_t e = launch_transpose_vec(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
+                                            static_cast<const TileTask*>(d_vtile_tasks->ptr),
+                                            static_cast<int32_t>(vtile_tasks.size()), vtile_grid, bufs, s);
         if (e != hipSuccess) return e;
     }
     if (!tile_tasks.empty())

@@ -34,11 +34,13 @@ struct CopyProgram {
     std::vector<int32_t> wg_begin;
     std::vector<TileTask> tile_tasks;
     std::vector<RowTask> row_tasks;
-    int32_t tile_grid = 0;   // workgroups of the tiled kernel (a multiple of 8 once there are 8 tasks)
+    std::vector<TileTask> vtile_tasks;   // transposes with unit-stride destination rows
+    int32_t tile_grid = 0;   // workgroups of the tiled kernels (a multiple of 8 once there are 8 tasks)
+    int32_t vtile_grid = 0;
     static constexpr int32_t kTileGridMax = 8192;
     int src_dtype = SYM_F32, dst_dtype = SYM_F32;
     // device copies
-    DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks, d_row_tasks;
+    DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks, d_row_tasks, d_vtile_tasks;
 
     // dst block j <- src block with labels dst.labels permuted back by perm
     void add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
@@ -46,6 +48,8 @@ struct CopyProgram {
     void finalize();
     void upload(const Allocator& alloc);
     bool empty() const { return ops.empty(); }
+    // XCD-aware order of a tile list for a persistent grid; returns the grid
+    static int32_t xcd_order(std::vector<TileTask>& list);
     hipError_t launch(const PtrTable& bufs, hipStream_t s) const;
 };
 
