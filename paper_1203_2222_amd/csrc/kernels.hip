@@ -270,24 +270,38 @@ __device__ __forceinline__ void tile_copy(const CopyOp* __restrict__ ops, const 
 // TI (destination-contiguous dim) x kTile (source-contiguous dim); TI is
 // long so that a tile writes long destination row segments and few partial
 // cache lines.  Each source row of the tile is staged with 16-byte loads
-// from its aligned-down start (row r's first element lands at LDS column
-// off[r]), and each destination row is written in 16-byte aligned chunks
-// gathered down an LDS column, with element stores only at the ends.  The
-// source is read through one range-checked buffer resource per tile that
-// ends at the source buffer.
+// from its aligned-down start; row r sits at LDS column rot(r) + off[r],
+// where the rotation rot(r) = VI ((r / 8) mod 8) puts rows 8 apart on
+// different banks.  Destination rows are written in 16-byte aligned chunks,
+// eight lanes per row on eight consecutive chunks (128 contiguous bytes),
+// each chunk gathered down an LDS column; element stores only at the ends.
+// The source is read through one range-checked buffer resource per tile
+// that ends at the source buffer.
+template <typename Ti>
+struct TransposeShape {
+    static constexpr int VI = 16 / sizeof(Ti);
+    static constexpr int RW = kTile + 2 * VI + 7 * VI;   // staged row width incl. rotation room
+    static constexpr int TI = vtile_rows(sizeof(Ti));
+    static constexpr size_t lds_bytes = static_cast<size_t>(TI) * RW * sizeof(Ti) + TI * sizeof(int);
+};
+
 template <typename Ti, typename To>
 __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict__ ops,
                                                        const TileTask* __restrict__ tasks, int n_tasks,
                                                        PtrTable bufs) {
-    constexpr int VI = 16 / sizeof(Ti);
+    using Sh = TransposeShape<Ti>;
+    constexpr int VI = Sh::VI, RW = Sh::RW, TI = Sh::TI;
     constexpr int VO = Pack<To>::V;
-    constexpr int RW = kTile + 2 * VI;             // staged row width (elements), 16-byte multiple
-    constexpr int NV = (kTile + 2 * VI - 2) / VI;  // vectors that cover one row segment
-    constexpr int TI = vtile_rows(sizeof(Ti));
-    constexpr int NC = (TI + 2 * VO - 2) / VO;     // chunks that cover one destination row segment
+    constexpr int NV = (kTile + 2 * VI - 2) / VI;   // vectors that cover one source row segment
+    constexpr int NC = (TI + 2 * VO - 2) / VO;      // chunks that cover one destination row segment
+    constexpr int NH = (NC + 7) / 8;                // groups of eight chunks
     constexpr int I = kMaxCopyDims - 1;
-    __shared__ __attribute__((aligned(16))) Ti tile[TI * RW];
-    __shared__ int row_off[TI];
+    static_assert((RW * sizeof(Ti)) % 16 == 0, "LDS rows must stay 16-byte aligned");
+    extern __shared__ u32x4_t lds_raw[];
+    Ti* tile = reinterpret_cast<Ti*>(lds_raw);
+    int* row_off = reinterpret_cast<int*>(tile + TI * RW);
+    auto rot = [](int r) { return VI * ((r >> 3) & 7); };
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
         const TileTask t = tasks[ti];
         const CopyOp& op = ops[t.op];
@@ -322,18 +336,21 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
             const int64_t start = so + (i0 + r) * sI + j0;
             const int64_t a = start & ~static_cast<int64_t>(VI - 1);
             const int off = static_cast<int>(start - a);
-            if (v == 0) row_off[r] = off;
+            if (v == 0) row_off[r] = rot(r) + off;
             if (v * VI >= off + nj) continue;
             const int e0 = static_cast<int>(a - base) + v * VI;   // element index from the resource base
-            reinterpret_cast<u32x4_t*>(tile + r * RW)[v] =
+            Ti* row = tile + r * RW + rot(r);
+            reinterpret_cast<u32x4_t*>(row)[v] =
                 __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, e0 * static_cast<int>(sizeof(Ti)), 0, 0));
-            for (int e = e0 > e_full ? e0 : e_full; e < e0 + VI && e < lim; ++e) tile[r * RW + v * VI + (e - e0)] = src[base + e];
+            for (int e = e0 > e_full ? e0 : e_full; e < e0 + VI && e < lim; ++e) row[v * VI + (e - e0)] = src[base + e];
         }
         __syncthreads();
         const bool vec_dst = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
-        for (int it = threadIdx.x; it < kTile * NC; it += 256) {
-            const int c = it / kTile, j = it - c * kTile;   // lanes run along j: consecutive LDS columns
-            if (j >= nj) continue;
+        // wave item (g, h): lane (jj, cc) writes chunk 8 h + cc of destination row j0 + 8 g + jj
+        for (int wi = wave; wi < (kTile / 8) * NH; wi += 4) {
+            const int g = wi / NH, h = wi - g * NH;
+            const int j = 8 * g + (lane >> 3), c = 8 * h + (lane & 7);
+            if (j >= nj || c >= NC) continue;
             const int64_t d0 = dof + (j0 + j) * dJ + i0;
             const int delta = vec_dst ? static_cast<int>(d0 & (VO - 1)) : 0;
             const int c_lo = c * VO - delta;
@@ -355,6 +372,22 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
     }
 }
 
+template <typename Ti, typename To>
+hipError_t launch_tv(const CopyOp* ops, const TileTask* tasks, int32_t n_tasks, int32_t n_wg, const PtrTable& bufs,
+                     hipStream_t s) {
+    constexpr size_t lds = TransposeShape<Ti>::lds_bytes;
+    static bool configured = false;
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transpose_vec<Ti, To>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    hipLaunchKernelGGL((k_transpose_vec<Ti, To>), dim3(static_cast<unsigned>(n_wg)), dim3(256), lds, s, ops, tasks,
+                       n_tasks, bufs);
+    return hipGetLastError();
+}
+
 // Each workgroup walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...
 template <typename Ti, typename To>
 __global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict__ ops, const TileTask* __restrict__ tasks,
@@ -370,16 +403,10 @@ hipError_t launch_transpose_vec(int src_dtype, int dst_dtype, const CopyOp* ops,
                                 int32_t n_tasks, int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
     if (n_tasks <= 0) return hipSuccess;
     if (n_wg <= 0) return hipErrorInvalidValue;
-    dim3 grid(static_cast<unsigned>(n_wg)), block(256);
-    if (src_dtype == 0 && dst_dtype == 0)
-        hipLaunchKernelGGL((k_transpose_vec<float, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
-    else if (src_dtype == 0 && dst_dtype == 1)
-        hipLaunchKernelGGL((k_transpose_vec<float, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
-    else if (src_dtype == 1 && dst_dtype == 1)
-        hipLaunchKernelGGL((k_transpose_vec<uint16_t, uint16_t>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
-    else
-        hipLaunchKernelGGL((k_transpose_vec<uint16_t, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
-    return hipGetLastError();
+    if (src_dtype == 0 && dst_dtype == 0) return launch_tv<float, float>(ops, tasks, n_tasks, n_wg, bufs, s);
+    if (src_dtype == 0 && dst_dtype == 1) return launch_tv<float, uint16_t>(ops, tasks, n_tasks, n_wg, bufs, s);
+    if (src_dtype == 1 && dst_dtype == 1) return launch_tv<uint16_t, uint16_t>(ops, tasks, n_tasks, n_wg, bufs, s);
+    return launch_tv<uint16_t, float>(ops, tasks, n_tasks, n_wg, bufs, s);
 }
 
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks, int32_t n_tasks,

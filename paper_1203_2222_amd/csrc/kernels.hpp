@@ -54,7 +54,7 @@ struct TileTask {
 constexpr int kTile = 64;
 // rows (destination-contiguous extent) of a vectorized transposing tile, by
 // source element size
-constexpr int vtile_rows(int src_elem_bytes) { return src_elem_bytes == 2 ? 256 : 128; }
+constexpr int vtile_rows(int src_elem_bytes) { return src_elem_bytes == 2 ? 128 : 64; }
 
 // One sector GEMM: C[m][n] = sum_k A[m][k] * B[n][k] (both operands K-contiguous).
 // With `indirect` set, element (m, n) is stored at
