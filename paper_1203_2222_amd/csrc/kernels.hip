@@ -477,6 +477,9 @@ __device__ __forceinline__ void store_tile(const v16f (&acc)[FM][FN], const Gemm
             }
         return;
     }
+    // canonical-block output: 32-bit offsets from the buffer base (the host
+    // checks the bounds that make this exact) and range-checked buffer stores
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(C, static_cast<short>(0), 0x7fffffff, 0x00020000);
     EpiCol cj[FN];
     bool cok[FN];
 #pragma unroll
@@ -494,9 +497,12 @@ __device__ __forceinline__ void store_tile(const v16f (&acc)[FM][FN], const Gemm
             const EpiRow ri = rows[p.ri_off + row];
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                if (cok[j])
-                    C[ri.r0 + static_cast<int64_t>(ri.r1) * cj[j].c1 + static_cast<int64_t>(ri.r2) * cj[j].c2 + cj[j].c0] =
-                        acc[i][j][q];
+                if (cok[j]) {
+                    const uint32_t e = static_cast<uint32_t>(ri.r0 + cj[j].c0) +
+                                       __umul24(static_cast<uint32_t>(ri.r1), static_cast<uint32_t>(cj[j].c1)) +
+                                       __umul24(static_cast<uint32_t>(ri.r2), static_cast<uint32_t>(cj[j].c2));
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[i][j][q]), rc, e * 4u, 0, 0);
+                }
         }
 }
 

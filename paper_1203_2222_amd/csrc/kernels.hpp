@@ -73,16 +73,20 @@ struct GemmProb {
 // Canonical block list of a row-legs-first tensor: block (rt, ct) of a sector
 // starts at base(rt) + d(rt) * colcum(ct) and is row-major, so the element at
 // row offset t_r in rt and column offset t_c in ct sits at
-// base(rt) + t_r * d(ct) + d(rt) * colcum(ct) + t_c.
+// base(rt) + t_r * d(ct) + d(rt) * colcum(ct) + t_c.  All terms are 32-bit:
+// the planner uses this form only for outputs below 2^29 elements whose
+// tuple dimensions and column offsets are below 2^24 (24-bit multiplies).
 struct EpiRow {
-    int64_t r0;   // base(rt)
+    int32_t r0;   // base(rt)
     int32_t r1;   // t_r
     int32_t r2;   // d(rt)
+    int32_t pad;
 };
 struct EpiCol {
-    int64_t c2;   // colcum(ct)
+    int32_t c2;   // colcum(ct)
     int32_t c0;   // t_c
     int32_t c1;   // d(ct)
+    int32_t pad;
 };
 
 struct GemmTile {

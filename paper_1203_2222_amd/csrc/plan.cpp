@@ -345,6 +345,16 @@ bool GemmProgram::add_indirect(const Desc& Z, const Desc& out, const Desc& X, co
     if (Z.group != SYM_U1 || out.group != SYM_U1 || out.n_row != out.rank || out.opts.trans ||
         out.dtype != SYM_F32 || out.legs != Z.legs || out.qtot != Z.qtot || Z.opts.trans)
         return false;
+    // 32-bit address terms, 24-bit factors (see EpiRow)
+    constexpr int64_t k24 = int64_t{1} << 24;
+    if (out.numel >= (int64_t{1} << 29)) return false;   // byte offsets below 2^31
+    for (const Sector& zs : Z.sectors) {
+        if (zs.cols >= k24) return false;
+        for (const Tuple& t : zs.row_tuples)
+            if (t.dim >= k24) return false;
+        for (const Tuple& t : zs.col_tuples)
+            if (t.dim >= k24) return false;
+    }
     // check the address formula against every block before committing
     const size_t p0 = probs.size();
     std::vector<EpiRow> rows_add;
@@ -370,12 +380,12 @@ bool GemmProgram::add_indirect(const Desc& Z, const Desc& out, const Desc& X, co
                 if (off != base + rt.dim * zs.col_off[c]) return false;
             }
             for (int64_t t = 0; t < rt.dim; ++t)
-                rows_add.push_back({base, static_cast<int32_t>(t), static_cast<int32_t>(rt.dim)});
+                rows_add.push_back({static_cast<int32_t>(base), static_cast<int32_t>(t), static_cast<int32_t>(rt.dim), 0});
         }
         for (size_t c = 0; c < zs.col_tuples.size(); ++c) {
             const Tuple& ct = zs.col_tuples[c];
             for (int64_t t = 0; t < ct.dim; ++t)
-                cols_add.push_back({zs.col_off[c], static_cast<int32_t>(t), static_cast<int32_t>(ct.dim)});
+                cols_add.push_back({static_cast<int32_t>(zs.col_off[c]), static_cast<int32_t>(t), static_cast<int32_t>(ct.dim), 0});
         }
     }
     add(Z, X, Y, z_buf, x_buf, y_buf, 0, x_base, y_base);
