@@ -213,6 +213,23 @@ def secondary(ctx, stream):
                                       "backward_TFLOPs": round(2 * fl / bwd / 1e9, 2)}
         del A, B, C, dC, dA, dB
 
+        # a network-update step at config 4's shapes: chain X0.X1.X2.X3 with the
+        # gradient of <chain, G> for every X (plans reused; eager vs one HIP graph)
+        from paper_1203_2222_amd.chain import Chain
+        c = W.config4()
+        g4 = W.generator(c.seed, "cuda")
+        xs = [ctx.tensor(c.A, 4, data=W.gaussian(ctx.describe(c.A, 4).numel(), g4, "cuda")) for _ in range(4)]
+        ch = Chain(ctx, xs, [(c.axes_a, c.axes_b)] * 3)
+        gg = W.gaussian(ch.output.numel(), g4, "cuda")
+        fl = ch.flops()
+        eager = _timed(lambda: ch.iteration(gg, stream=stream), 5, stream)
+        graph = ch.capture(gg)
+        replay = _timed(lambda: graph.replay(), 5, stream)
+        out["chain4_u1_chi128_fp32_step"] = {"eager_ms": round(eager, 3), "graph_ms": round(replay, 3),
+                                             "useful_flops": int(fl),
+                                             "graph_TFLOPs": round(fl / replay / 1e9, 2)}
+        del graph, ch, xs, gg
+
         # config 5: SU(2) contraction + recoupling, FP32
         c = W.config5()
         A, B, _ = make(c)
