@@ -230,6 +230,26 @@ def secondary(ctx, stream):
                                              "graph_TFLOPs": round(fl / replay / 1e9, 2)}
         del graph, ch, xs, gg
 
+        # fermion parity (Z2 with swap factors): legs (64 even, 64 odd); A's
+        # contracted legs are taken in the order (3, 2), so its fuse swaps two
+        # legs and applies the swap factors
+        zl = W.Leg((0, 1), (64, 64), W.IN)
+        zA = W.TensorSpec(W.Z2F, (zl, zl, zl.flipped(), zl.flipped()))
+        zB = W.TensorSpec(W.Z2F, (zl, zl, zl.flipped(), zl.flipped()))
+        gz = W.generator(7, "cuda")
+        A = ctx.tensor(zA, 4, data=W.gaussian(ctx.describe(zA, 4).numel(), gz, "cuda"))
+        B = ctx.tensor(zB, 4, data=W.gaussian(ctx.describe(zB, 4).numel(), gz, "cuda"))
+        zax = ((3, 2), (0, 1))
+        fl = ctx.flops(A, B, *zax)
+        C = ctx.contract_output(A, B, *zax)
+        res = {"useful_flops": int(fl), "axes": [list(zax[0]), list(zax[1])]}
+        for comp in ("f32", "bf16"):
+            msz = _timed(lambda: ctx.contract(A, B, *zax, comp, out=C, stream=stream), 3, stream)
+            res[f"{comp}_TFLOPs"] = round(fl / msz / 1e9, 2)
+            res[f"{comp}_ms"] = round(msz, 3)
+        out["z2f_chi128_contract"] = res
+        del A, B, C
+
         # config 5: SU(2) contraction + recoupling, FP32
         c = W.config5()
         A, B, _ = make(c)

@@ -85,7 +85,21 @@ enum {
     SYM_E_MISMATCH = 9      /* output handle does not describe the expected result  */
 };
 
-enum { SYM_U1 = 0, SYM_SU2 = 1 };                  /* group                       */
+/* Groups.  Abelian ones (section "Conclusions and outlook": fusion rules of
+ * composite groups and of fermion parity) use one int32 label per irrep:
+ *   SYM_U1   charge q; a block is allowed when sum_out q - sum_in q = qtot.
+ *   SYM_Z2   parity p in {0, 1}; the same rule modulo 2 (qtot in {0, 1}).
+ *   SYM_U1U1 a pair (q1, q2) with -2048 <= q1, q2 < 2048, stored as
+ *            q1 * 65536 + q2 (label order is then (q1, q2) lexicographic);
+ *            the U(1) rule holds for each component (qtot stored the same way).
+ *   SYM_Z2F  fermion parity: the Z2 rule, and every permutation of legs
+ *            multiplies a block by the swap factor R(1,1->0) = -1 once for
+ *            each pair of odd legs whose order it reverses (R = 1 otherwise,
+ *            F = 1); a contraction moves A's contracted legs behind its free
+ *            legs and B's in front of its own, in the order axesA / axesB
+ *            give, then multiplies.
+ *   SYM_SU2  doubled spin 2j >= 0 on rank-4 trees (see sym_tensor_create). */
+enum { SYM_U1 = 0, SYM_SU2 = 1, SYM_Z2 = 2, SYM_U1U1 = 3, SYM_Z2F = 4 };   /* group */
 enum { SYM_F32 = 0, SYM_BF16 = 1 };                /* element type                */
 enum { SYM_IN = 0, SYM_OUT = 1 };                  /* leg direction               */
 enum { SYM_TREE_NONE = 0, SYM_TREE_OPERATOR = 1,   /* SU(2) coupling tree         */
@@ -97,7 +111,7 @@ enum { SYM_TREE_NONE = 0, SYM_TREE_OPERATOR = 1,   /* SU(2) coupling tree       
  * The arrays are copied by sym_tensor_create. */
 typedef struct {
     int32_t n;
-    const int32_t* label;   /* U(1): charge q;  SU(2): 2j >= 0 */
+    const int32_t* label;   /* see the group list: q, p, encoded (q1, q2), or 2j */
     const int64_t* deg;
     int32_t arrow;          /* SYM_IN or SYM_OUT */
 } sym_leg;
@@ -117,10 +131,11 @@ void sym_ctx_destroy(sym_ctx* ctx);
 int32_t sym_ctx_clear(sym_ctx* ctx);
 
 /* Describe a symmetric tensor (section "Block structure"; eq:datak).
- * group: SYM_U1 / SYM_SU2; rank <= SYM_MAX_RANK (SU(2): 4); n_row in [0, rank]
- * (SU(2): 0, 2 or 4, and 2 only on the OPERATOR or LEFT tree); tree: SU(2)
- * tree id (SYM_TREE_NONE for U(1)); qtot: U(1) total charge (0 = invariant;
- * must be 0 for SU(2)); dtype: SYM_F32 or SYM_BF16; data: device pointer to
+ * group: one of the groups above; rank <= SYM_MAX_RANK (SU(2): 4); n_row in
+ * [0, rank] (SU(2): 0, 2 or 4, and 2 only on the OPERATOR or LEFT tree); tree:
+ * SU(2) tree id (SYM_TREE_NONE for the Abelian groups); qtot: total charge of
+ * an Abelian tensor (0 = invariant; must be 0 for SU(2)); dtype: SYM_F32 or
+ * SYM_BF16; data: device pointer to
  * numel elements in the layout described above, borrowed (may be NULL and set
  * later with sym_tensor_set_data).  Pure host work. */
 int32_t sym_tensor_create(sym_ctx* ctx, int32_t group, int32_t rank, const sym_leg* legs,

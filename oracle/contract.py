@@ -53,8 +53,8 @@ def result_spec(spec_a, spec_b, axes_a, axes_b):
     fa = [i for i in range(len(spec_a.legs)) if i not in axes_a]
     fb = [i for i in range(len(spec_b.legs)) if i not in axes_b]
     legs = [spec_a.legs[i] for i in fa] + [spec_b.legs[i] for i in fb]
-    if spec_a.group == T.U1:
-        return _Spec(T.U1, legs, qtot=spec_a.qtot + spec_b.qtot)
+    if spec_a.group in T.ABELIAN:
+        return _Spec(spec_a.group, legs, qtot=T.combine_qtot(spec_a.group, spec_a.qtot, spec_b.qtot))
     if not (spec_a.tree == T.TREE_OPERATOR and tuple(axes_a) == (2, 3) and tuple(axes_b) == (0, 1)
             and spec_b.tree in (T.TREE_OPERATOR, T.TREE_LEFT)):
         raise ValueError("SU(2) contraction supported: operator A legs 3,4 with B legs 1,2")
@@ -77,8 +77,25 @@ def contract_dense(dense_a: np.ndarray, dense_b: np.ndarray, axes_a, axes_b) -> 
     return np.einsum(expr, dense_a, dense_b, optimize=False)
 
 
+def contract_dense_graded(spec_a, dense_a, spec_b, dense_b, axes_a, axes_b) -> np.ndarray:
+    """The contraction as a permutation of each operand followed by a sum:
+    A's contracted legs moved behind its free legs (in the order of axes_a),
+    B's in front of its free legs (order of axes_b), then the last m legs of
+    A' summed against the first m legs of B'.  The permutations carry the
+    swap factors of fermion parity (``tensors.permute_dense``); for every other
+    group this is contract_dense."""
+    fa = [i for i in range(len(spec_a.legs)) if i not in axes_a]
+    fb = [i for i in range(len(spec_b.legs)) if i not in axes_b]
+    pa = T.permute_dense(spec_a, dense_a, fa + list(axes_a))
+    pb = T.permute_dense(spec_b, dense_b, list(axes_b) + fb)
+    m = len(axes_a)
+    return np.tensordot(pa, pb, axes=(list(range(len(fa), len(fa) + m)), list(range(m))))
+
+
 def contract_pairs(spec_a, flat_a, spec_b, flat_b, axes_a, axes_b):
-    """Pairwise block contraction; returns (spec_c, flat_c) in canonical order."""
+    """Pairwise block contraction; returns (spec_c, flat_c) in canonical order.
+    Fermion parity: each pair also takes the swap factors of moving A's and
+    B's contracted legs into place (see contract_dense_graded)."""
     spec_c = result_spec(spec_a, spec_b, axes_a, axes_b)
     da = T.split_flat(spec_a, np.asarray(flat_a, dtype=np.float64))
     db = T.split_flat(spec_b, np.asarray(flat_b, dtype=np.float64))
@@ -97,6 +114,9 @@ def contract_pairs(spec_a, flat_a, spec_b, flat_b, axes_a, axes_b):
             lc = tuple(la[i] for i in fa) + tuple(lb[i] for i in fb)
             ec = eb if spec_a.group == T.SU2 else None
             prod = np.tensordot(pa, pb, axes=(list(axes_a), list(axes_b)))
+            if spec_a.group == T.Z2F:
+                prod = prod * (T.perm_sign(T.Z2F, la, fa + list(axes_a)) *
+                               T.perm_sign(T.Z2F, lb, list(axes_b) + fb))
             if (lc, ec) in out:
                 out[(lc, ec)] = out[(lc, ec)] + prod
             else:

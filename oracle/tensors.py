@@ -18,6 +18,14 @@ plain on 'out' legs.  Invariance for every r requires
 sum(q on out legs) - sum(q on in legs) = 0; a covariant tensor carries the
 total charge ``qtot`` on the right-hand side instead.
 
+Other Abelian groups (section "Conclusions and outlook"): Z2 with parity
+labels p in {0, 1} fuses by addition modulo 2; a composite group such as
+U(1) x U(1) carries a tuple (q1, q2) per irrep and fuses each component by
+its own rule.  Fermion parity (group "Z2F") has the Z2 rule and, in
+addition, the swap tensor of that section: exchanging two legs multiplies an
+entry by -1 when both legs carry odd parity and by +1 otherwise (the
+recoupling coefficients F are all 1).  ``permute_dense`` applies it.
+
 SU(2) rule.  Rank-4 tensors on three trees, each node obeying the fusion rule
 (eq:fusionrules):
   OPERATOR (in,in,out,out): Q^e = sum_me C_{j1 j2->e} C_{j3 j4->e}
@@ -37,6 +45,8 @@ from . import su2
 
 IN, OUT = "in", "out"
 U1, SU2 = "U1", "SU2"
+Z2, U1xU1, Z2F = "Z2", "U1xU1", "Z2F"
+ABELIAN = (U1, Z2, U1xU1, Z2F)
 TREE_NONE, TREE_OPERATOR, TREE_LEFT, TREE_RIGHT = 0, 1, 2, 3
 
 _SU2_ARROWS = {
@@ -88,6 +98,69 @@ def allowed_u1(labels: Sequence[int], arrows: Sequence[str], qtot: int) -> bool:
     return flux == qtot
 
 
+def allowed_abelian(group: str, labels, arrows: Sequence[str], qtot) -> bool:
+    """Charge rule of an Abelian group: the charge carried out minus the
+    charge carried in equals qtot (Z2: modulo 2; U(1) x U(1): per component)."""
+    if group == U1:
+        return allowed_u1(labels, arrows, qtot)
+    if group in (Z2, Z2F):
+        return (sum(p if a == OUT else -p for p, a in zip(labels, arrows)) - qtot) % 2 == 0
+    if group == U1xU1:
+        return all(allowed_u1([lab[c] for lab in labels], arrows, qtot[c]) for c in range(2))
+    raise ValueError("not an Abelian group")
+
+
+def combine_qtot(group: str, qa, qb):
+    """Total charge of a product of two Abelian tensors."""
+    if group in (Z2, Z2F):
+        return (qa + qb) % 2
+    if group == U1xU1:
+        return (qa[0] + qb[0], qa[1] + qb[1])
+    return qa + qb
+
+
+def leg_parity(leg) -> np.ndarray:
+    """Parity (label mod 2) of every basis index of a Z2 / Z2F leg."""
+    return np.concatenate([np.full(d, lab % 2, dtype=np.int64) for lab, d in zip(leg.labels, leg.degs)])
+
+
+def perm_sign(group: str, labels: Sequence, perm: Sequence[int]) -> int:
+    """Swap factor of one block under a leg permutation (new leg k is old leg
+    perm[k]): -1 to the number of odd-odd leg pairs whose order flips, for
+    fermion parity; +1 for every other group."""
+    if group != Z2F:
+        return 1
+    pos = {old: new for new, old in enumerate(perm)}
+    n, odd = len(perm), 0
+    for a in range(n):
+        for b in range(a + 1, n):
+            if pos[a] > pos[b] and labels[a] % 2 == 1 and labels[b] % 2 == 1:
+                odd += 1
+    return -1 if odd % 2 else 1
+
+
+def permute_dense(spec, dense: np.ndarray, perm: Sequence[int]) -> np.ndarray:
+    """Dense tensor with legs reordered: new leg k is old leg perm[k].  For
+    fermion parity every pair of legs whose order flips contributes the swap
+    factor (-1)^(p_a p_b) of its two indices."""
+    dense = np.asarray(dense, dtype=np.float64)
+    if spec.group == Z2F:
+        n = dense.ndim
+        pos = {old: new for new, old in enumerate(perm)}
+        expo = np.zeros(dense.shape, dtype=np.int64)
+        par = [leg_parity(l) for l in spec.legs]
+        for a in range(n):
+            for b in range(a + 1, n):
+                if pos[a] > pos[b]:
+                    shape_a = [1] * n
+                    shape_a[a] = dense.shape[a]
+                    shape_b = [1] * n
+                    shape_b[b] = dense.shape[b]
+                    expo = expo + par[a].reshape(shape_a) * par[b].reshape(shape_b)
+        dense = dense * np.where(expo % 2 == 1, -1.0, 1.0)
+    return np.transpose(dense, perm)
+
+
 def su2_internals(tree: int, tj: Sequence[int]) -> List[int]:
     """Intermediate spins (doubled, ascending) compatible with the tree."""
     j1, j2, j3, j4 = tj
@@ -114,6 +187,12 @@ def validate(spec) -> None:
             raise ValueError("arrows do not match the SU(2) tree")
         if any(lab < 0 for l in spec.legs for lab in l.labels):
             raise ValueError("negative spin")
+    elif spec.group in (Z2, Z2F):
+        if any(lab not in (0, 1) for l in spec.legs for lab in l.labels) or spec.qtot not in (0, 1):
+            raise ValueError("parity labels are 0 or 1")
+    elif spec.group == U1xU1:
+        if any(not (isinstance(lab, tuple) and len(lab) == 2) for l in spec.legs for lab in l.labels):
+            raise ValueError("U(1) x U(1) labels are pairs")
     elif spec.group != U1:
         raise ValueError("unknown group")
 
@@ -126,8 +205,8 @@ def blocks(spec) -> List[Block]:
     out, off = [], 0
     for labels in itertools.product(*[l.labels for l in spec.legs]):
         shape = tuple(degmap[i][lab] for i, lab in enumerate(labels))
-        if spec.group == U1:
-            if not allowed_u1(labels, arrows, spec.qtot):
+        if spec.group in ABELIAN:
+            if not allowed_abelian(spec.group, labels, arrows, spec.qtot):
                 continue
             internals = [None]
         else:
@@ -191,7 +270,7 @@ def to_dense(spec, flat: np.ndarray) -> np.ndarray:
     for (labels, e), p in data.items():
         sl = _slices(spec, labels)
         p = np.asarray(p, dtype=np.float64)
-        if spec.group == U1:
+        if spec.group in ABELIAN:
             dense[sl] = p
         else:
             q = structural(spec.tree, labels, e)
@@ -209,7 +288,7 @@ def from_dense(spec, dense: np.ndarray) -> np.ndarray:
     out = {}
     for b in blocks(spec):
         sub = dense[_slices(spec, b.labels)]
-        if spec.group == U1:
+        if spec.group in ABELIAN:
             out[b.key] = np.array(sub)
         else:
             q = structural(spec.tree, b.labels, b.internal)

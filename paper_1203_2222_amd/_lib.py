@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymtenso
 SYM_OK = 0
 STATUS_NAMES = {0: "SYM_OK", 1: "SYM_E_ARG", 2: "SYM_E_SPECTRUM", 3: "SYM_E_ARROW", 4: "SYM_E_CHARGE",
                 5: "SYM_E_DTYPE", 6: "SYM_E_NOMEM", 7: "SYM_E_HIP", 8: "SYM_E_UNSUPPORTED", 9: "SYM_E_MISMATCH"}
-SYM_U1, SYM_SU2 = 0, 1
+SYM_U1, SYM_SU2, SYM_Z2, SYM_U1U1, SYM_Z2F = 0, 1, 2, 3, 4
 SYM_F32, SYM_BF16 = 0, 1
 SYM_IN, SYM_OUT = 0, 1
 SYM_TREE_NONE, SYM_TREE_OPERATOR, SYM_TREE_LEFT, SYM_TREE_RIGHT = 0, 1, 2, 3

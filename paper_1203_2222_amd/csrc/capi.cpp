@@ -213,7 +213,8 @@ DescPtr result_desc(const Desc& A, const Desc& B, const PairInfo& p) {
     for (int32_t i : p.fb) legs.push_back(B.legs[static_cast<size_t>(i)]);
     if (A.group == SYM_SU2)
         return make_desc(SYM_SU2, legs, 2, B.tree, 0, SYM_F32);
-    return make_desc(SYM_U1, legs, static_cast<int32_t>(p.fa.size()), SYM_TREE_NONE, A.qtot + B.qtot, SYM_F32);
+    return make_desc(A.group, legs, static_cast<int32_t>(p.fa.size()), SYM_TREE_NONE, combine_qtot(A.group, A.qtot, B.qtot),
+                     SYM_F32);
 }
 
 // descriptor of A's legs (fa ++ axa) with |fa| row legs

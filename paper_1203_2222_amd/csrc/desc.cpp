@@ -81,7 +81,7 @@ int64_t deg_of(const Leg& l, int32_t label) {
 void validate(int32_t group, const std::vector<Leg>& legs, int32_t n_row, int32_t tree, int32_t qtot,
               int32_t dtype) {
     const int rank = static_cast<int>(legs.size());
-    if (group != SYM_U1 && group != SYM_SU2) throw Error(SYM_E_ARG, "unknown group");
+    if (!is_abelian(group) && group != SYM_SU2) throw Error(SYM_E_ARG, "unknown group");
     if (rank > SYM_MAX_RANK) throw Error(SYM_E_ARG, "rank exceeds SYM_MAX_RANK");
     if (n_row < 0 || n_row > rank) throw Error(SYM_E_ARG, "n_row outside [0, rank]");
     if (dtype != SYM_F32 && dtype != SYM_BF16) throw Error(SYM_E_DTYPE, "dtype must be F32 or BF16");
@@ -93,8 +93,23 @@ void validate(int32_t group, const std::vector<Leg>& legs, int32_t n_row, int32_
             if (i && l.label[i] <= l.label[i - 1]) throw Error(SYM_E_CHARGE, "labels must be strictly ascending");
         }
     }
-    if (group == SYM_U1) {
-        if (tree != SYM_TREE_NONE) throw Error(SYM_E_ARG, "U(1) tensors take SYM_TREE_NONE");
+    if (is_abelian(group)) {
+        if (tree != SYM_TREE_NONE) throw Error(SYM_E_ARG, "Abelian tensors take SYM_TREE_NONE");
+        if (group == SYM_Z2 || group == SYM_Z2F) {
+            if (qtot != 0 && qtot != 1) throw Error(SYM_E_CHARGE, "parity qtot must be 0 or 1");
+            for (const Leg& l : legs)
+                for (int32_t lab : l.label)
+                    if (lab != 0 && lab != 1) throw Error(SYM_E_CHARGE, "parity labels are 0 or 1");
+        } else if (group == SYM_U1U1) {
+            auto ok = [](int32_t v) {
+                const int32_t q1 = (v + 32768) >> 16, q2 = v - q1 * 65536;
+                return q1 >= -2048 && q1 < 2048 && q2 >= -2048 && q2 < 2048;
+            };
+            if (!ok(qtot)) throw Error(SYM_E_CHARGE, "U(1) x U(1) qtot components outside [-2048, 2048)");
+            for (const Leg& l : legs)
+                for (int32_t lab : l.label)
+                    if (!ok(lab)) throw Error(SYM_E_CHARGE, "U(1) x U(1) label components outside [-2048, 2048)");
+        }
         return;
     }
     if (rank != 4) throw Error(SYM_E_UNSUPPORTED, "SU(2) tensors here have rank 4");
@@ -160,6 +175,11 @@ void finish_sectors(Desc& d) {
     d.numel = off;
 }
 
+// Abelian groups: the sector of a row tuple is the charge flowing in through
+// the row legs (folded for the parity groups); a column tuple joins the
+// sector whose charge it carries out (minus qtot).  With the encoded
+// U(1) x U(1) labels, bounded components make the sum of codes the code of
+// the componentwise sums, so equality of codes is the componentwise rule.
 void build_u1(Desc& d) {
     const int rank = d.rank, nr = d.n_row;
     std::vector<Tuple> rows = enumerate(d.legs, 0, nr);
@@ -167,12 +187,12 @@ void build_u1(Desc& d) {
     auto rho = [&](const Tuple& t) {
         int32_t s = 0;
         for (int i = 0; i < t.n; ++i) s += (d.legs[static_cast<size_t>(i)].arrow == SYM_IN ? 1 : -1) * t.lab[static_cast<size_t>(i)];
-        return s;
+        return fold(d.group, s);
     };
     auto kap = [&](const Tuple& t) {
         int32_t s = 0;
         for (int i = 0; i < t.n; ++i) s += (d.legs[static_cast<size_t>(nr + i)].arrow == SYM_OUT ? 1 : -1) * t.lab[static_cast<size_t>(i)];
-        return s - d.qtot;
+        return fold(d.group, s - d.qtot);
     };
     std::map<int32_t, std::vector<Tuple>> rmap, cmap;
     for (const Tuple& t : rows) rmap[rho(t)].push_back(t);
@@ -301,7 +321,7 @@ DescPtr make_desc(int32_t group, const std::vector<Leg>& legs, int32_t n_row, in
     d->legs = legs;
     if (group == SYM_SU2 && opts.trans && n_row != 2)
         throw Error(SYM_E_UNSUPPORTED, "transposed SU(2) layout needs n_row = 2");
-    if (group == SYM_U1) build_u1(*d);
+    if (is_abelian(group)) build_u1(*d);
     else build_su2(*d);
     for (size_t i = 0; i < d->blocks.size(); ++i)
         d->block_index[label_key(d->blocks[i].labels.data(), d->rank, d->blocks[i].internal)] = static_cast<int32_t>(i);

@@ -22,6 +22,13 @@ struct Error : std::runtime_error {
     Error(int32_t s, const std::string& m) : std::runtime_error(m), status(s) {}
 };
 
+// Abelian groups: one int32 label per irrep, fusion by (signed) addition
+// followed by fold() (identity for U(1) and the encoded U(1) x U(1), modulo 2
+// for the parity groups).
+inline bool is_abelian(int32_t g) { return g == SYM_U1 || g == SYM_Z2 || g == SYM_U1U1 || g == SYM_Z2F; }
+inline int32_t fold(int32_t g, int32_t s) { return (g == SYM_Z2 || g == SYM_Z2F) ? ((s % 2) + 2) % 2 : s; }
+inline int32_t combine_qtot(int32_t g, int32_t a, int32_t b) { return fold(g, a + b); }
+
 struct Leg {
     std::vector<int32_t> label;
     std::vector<int64_t> deg;

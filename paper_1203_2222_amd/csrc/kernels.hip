@@ -47,6 +47,12 @@ struct Conv<uint16_t, float> {
     __device__ static float f(uint16_t x) { return bf16_to_f32(x); }
 };
 
+// sign change of a converted element (exact: flips the sign bit)
+__device__ __forceinline__ float flip(float x, int neg) { return neg ? -x : x; }
+__device__ __forceinline__ uint16_t flip(uint16_t x, int neg) {
+    return static_cast<uint16_t>(x ^ (neg ? 0x8000u : 0u));
+}
+
 // floor(n / d) for 0 <= n < 2^31 from the divisor's multiplier and shift
 __device__ __forceinline__ int div_by(int n, uint32_t mag, int shf) {
     return static_cast<int>((static_cast<uint64_t>(static_cast<uint32_t>(n)) * mag) >> (31 + shf));
@@ -99,7 +105,7 @@ __global__ __launch_bounds__(256) void k_permute(const CopyOp* __restrict__ ops,
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u]) dst[dofs[u]] = Conv<Ti, To>::f(v[u]);
+                if (ok[u]) dst[dofs[u]] = flip(Conv<Ti, To>::f(v[u]), op.neg);
         }
     }
 }
@@ -195,13 +201,13 @@ __global__ __launch_bounds__(256) void k_copy_rows(const CopyOp* __restrict__ op
             if (vec_dst && c_lo >= 0 && c_lo + VO <= cols) {
                 To v[VO];
 #pragma unroll
-                for (int u = 0; u < VO; ++u) v[u] = Conv<Ti, To>::f(row[c_lo + u]);
+                for (int u = 0; u < VO; ++u) v[u] = flip(Conv<Ti, To>::f(row[c_lo + u]), op.neg);
                 *reinterpret_cast<u32x4_t*>(dst + d0 + c_lo) = Pack<To>::f(v);
             } else {
 #pragma unroll
                 for (int u = 0; u < VO; ++u) {
                     const int c = c_lo + u;
-                    if (c >= 0 && c < cols) dst[d0 + c] = Conv<Ti, To>::f(row[c]);
+                    if (c >= 0 && c < cols) dst[d0 + c] = flip(Conv<Ti, To>::f(row[c]), op.neg);
                 }
             }
         }
@@ -261,7 +267,7 @@ __device__ __forceinline__ void tile_copy(const CopyOp* __restrict__ ops, const 
 #pragma unroll 4
     for (int r = 0; r < kTile / 4; ++r) {
         const int j = j0 + hi + 4 * r, i = i0 + lo;
-        if (i < nI && j < nJ) dst[dof + i * dI + j * dJ] = Conv<Ti, To>::f(tile[i - i0][j - j0]);
+        if (i < nI && j < nJ) dst[dof + i * dI + j * dJ] = flip(Conv<Ti, To>::f(tile[i - i0][j - j0]), op.neg);
     }
 }
 
@@ -358,13 +364,13 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
             if (vec_dst && c_lo >= 0 && c_lo + VO <= ni) {
                 To v[VO];
 #pragma unroll
-                for (int u = 0; u < VO; ++u) v[u] = Conv<Ti, To>::f(tile[(c_lo + u) * RW + row_off[c_lo + u] + j]);
+                for (int u = 0; u < VO; ++u) v[u] = flip(Conv<Ti, To>::f(tile[(c_lo + u) * RW + row_off[c_lo + u] + j]), op.neg);
                 *reinterpret_cast<u32x4_t*>(dst + d0 + c_lo) = Pack<To>::f(v);
             } else {
 #pragma unroll
                 for (int u = 0; u < VO; ++u) {
                     const int r = c_lo + u;
-                    if (r >= 0 && r < ni) dst[d0 + r] = Conv<Ti, To>::f(tile[r * RW + row_off[r] + j]);
+                    if (r >= 0 && r < ni) dst[d0 + r] = flip(Conv<Ti, To>::f(tile[r * RW + row_off[r] + j]), op.neg);
                 }
             }
         }

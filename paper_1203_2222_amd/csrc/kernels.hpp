@@ -31,6 +31,8 @@ struct CopyOp {
     int32_t tj;          // tiled copies: the dim that is contiguous in the source
     int32_t rowcopy;     // rows of a contiguous source run along the destination's rows
     int64_t src_len;     // elements readable from the source buffer's base pointer
+    int32_t neg;         // 1: the block changes sign (fermionic swap factors)
+    int32_t pad;
 };
 
 // A slice [start, start+count) of one CopyOp's elements (in destination order).

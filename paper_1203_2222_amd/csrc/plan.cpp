@@ -108,6 +108,15 @@ void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_
             op.dstride[d] = mds[ord[k]];
         }
         for (int d = 0; d < kMaxCopyDims; ++d) set_divisor(op, d);
+        // fermion parity: R(1,1->0) = -1 for every pair of odd legs whose
+        // order the permutation reverses (dst leg i is src leg perm[i])
+        op.neg = 0;
+        if (src.group == SYM_Z2F)
+            for (int i = 0; i < rank; ++i)
+                for (int j = i + 1; j < rank; ++j)
+                    if (perm[static_cast<size_t>(i)] > perm[static_cast<size_t>(j)] &&
+                        (b.labels[static_cast<size_t>(i)] & 1) && (b.labels[static_cast<size_t>(j)] & 1))
+                        op.neg ^= 1;
         op.ndim = m;
         op.count = static_cast<int32_t>(b.size);
         op.src_buf = src_buf;
@@ -342,7 +351,7 @@ void GemmProgram::add(const Desc& Z, const Desc& X, const Desc& Y, int z_buf, in
 
 bool GemmProgram::add_indirect(const Desc& Z, const Desc& out, const Desc& X, const Desc& Y, int z_buf, int x_buf,
                                int y_buf, int64_t x_base, int64_t y_base) {
-    if (Z.group != SYM_U1 || out.group != SYM_U1 || out.n_row != out.rank || out.opts.trans ||
+    if (!is_abelian(Z.group) || out.group != Z.group || out.n_row != out.rank || out.opts.trans ||
         out.dtype != SYM_F32 || out.legs != Z.legs || out.qtot != Z.qtot || Z.opts.trans)
         return false;
     // 32-bit address terms, 24-bit factors (see EpiRow)

@@ -15,7 +15,23 @@ import torch
 
 from . import _lib as L
 
-_GROUPS = {"U1": L.SYM_U1, "SU2": L.SYM_SU2}
+_GROUPS = {"U1": L.SYM_U1, "SU2": L.SYM_SU2, "Z2": L.SYM_Z2, "U1xU1": L.SYM_U1U1, "Z2F": L.SYM_Z2F}
+
+
+def _label_code(group, lab) -> int:
+    """int32 label of the C-ABI: U(1) x U(1) pairs (q1, q2) as q1 * 65536 + q2."""
+    if group == "U1xU1":
+        q1, q2 = lab
+        return int(q1) * 65536 + int(q2)
+    return int(lab)
+
+
+def _qtot_sum(group, a, b):
+    if group in ("Z2", "Z2F"):
+        return (a + b) % 2
+    if group == "U1xU1":
+        return (a[0] + b[0], a[1] + b[1])
+    return a + b
 _ARROWS = {"in": L.SYM_IN, "out": L.SYM_OUT}
 _DTYPES = {"f32": L.SYM_F32, "bf16": L.SYM_BF16}
 _TORCH = {L.SYM_F32: torch.float32, L.SYM_BF16: torch.bfloat16}
@@ -119,7 +135,7 @@ def _legs_struct(spec):
     keep = []
     arr = (L.SymLeg * max(1, len(spec.legs)))()
     for i, leg in enumerate(spec.legs):
-        lab = (ctypes.c_int32 * max(1, len(leg.labels)))(*leg.labels)
+        lab = (ctypes.c_int32 * max(1, len(leg.labels)))(*[_label_code(spec.group, x) for x in leg.labels])
         deg = (ctypes.c_int64 * max(1, len(leg.degs)))(*leg.degs)
         keep += [lab, deg]
         arr[i].n = len(leg.labels)
@@ -191,7 +207,7 @@ class Context:
         legs, keep = _legs_struct(spec)
         h = c_void_p()
         L.check(L.lib().sym_tensor_create(self.handle, _GROUPS[spec.group], len(spec.legs), legs, n_row,
-                                          int(getattr(spec, "tree", 0)), int(getattr(spec, "qtot", 0)), dt,
+                                          int(getattr(spec, "tree", 0)), _label_code(spec.group, getattr(spec, "qtot", 0)), dt,
                                           None, byref(h)))
         t = SymTensor(self, h.value, None, spec, n_row, dt)
         if data is None:
@@ -205,7 +221,7 @@ class Context:
         legs, keep = _legs_struct(spec)
         h = c_void_p()
         L.check(L.lib().sym_tensor_create(self.handle, _GROUPS[spec.group], len(spec.legs), legs, n_row,
-                                          int(getattr(spec, "tree", 0)), int(getattr(spec, "qtot", 0)), dt,
+                                          int(getattr(spec, "tree", 0)), _label_code(spec.group, getattr(spec, "qtot", 0)), dt,
                                           None, byref(h)))
         return SymTensor(self, h.value, None, spec, n_row, dt)
 
@@ -247,7 +263,7 @@ class Context:
         fb = [i for i in range(B.rank) if i not in axes_b]
         legs = [A.spec.legs[i] for i in fa] + [B.spec.legs[i] for i in fb]
         tree = getattr(B.spec, "tree", 0) if A.spec.group == "SU2" else 0
-        qtot = getattr(A.spec, "qtot", 0) + getattr(B.spec, "qtot", 0)
+        qtot = _qtot_sum(A.spec.group, getattr(A.spec, "qtot", 0), getattr(B.spec, "qtot", 0))
         n_row = 2 if A.spec.group == "SU2" else len(fa)
         return self._wrap_output(h, _Spec(A.spec.group, legs, tree, qtot), n_row, L.SYM_F32, data, A.data.device)
 

@@ -163,3 +163,42 @@ def test_variant_names_and_default():
         assert 0 <= P.default_variant(compute) < n
     with pytest.raises(P.SymError):
         P.variant_name("bf16", P.num_variants("bf16"))
+
+
+def _abelian_specs():
+    z = lambda d0, d1, a: W.Leg((0, 1), (d0, d1), a)
+    uu = lambda a: W.Leg(((-1, 0), (0, -1), (0, 0), (0, 1), (1, 0)), (1, 2, 2, 1, 2), a)
+    return [
+        W.TensorSpec(W.Z2, (z(2, 3, W.IN), z(1, 2, W.IN), z(3, 1, W.OUT), z(2, 2, W.OUT)), qtot=1),
+        W.TensorSpec(W.Z2F, (z(2, 1, W.IN), z(1, 2, W.IN), z(2, 2, W.OUT), z(1, 3, W.OUT))),
+        W.TensorSpec(W.U1xU1, (uu(W.IN), uu(W.IN), uu(W.OUT), uu(W.OUT)), qtot=(0, 0)),
+        W.TensorSpec(W.U1xU1, (uu(W.IN), uu(W.OUT), uu(W.OUT)), qtot=(1, -1)),
+    ]
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_abelian_group_layouts_match_oracle(k):
+    # Z2, fermion parity and U(1) x U(1): block enumeration, order, offsets and
+    # shapes of the canonical layout (U(1) x U(1) labels travel as q1*65536+q2)
+    from paper_1203_2222_amd.tensor import _label_code
+    spec = _abelian_specs()[k]
+    ctx = _ctx()
+    t = ctx.describe(spec, n_row=len(spec.legs))
+    ob = T.blocks(spec)
+    lb = t.blocks()
+    assert t.numel() == T.num_elements(spec)
+    assert [tuple(b.labels) for b in lb] == [tuple(_label_code(spec.group, x) for x in b.labels) for b in ob]
+    assert [b.offset for b in lb] == [b.offset for b in ob]
+    assert [b.shape for b in lb] == [b.shape for b in ob]
+
+
+def test_abelian_label_validation():
+    from paper_1203_2222_amd import SymError
+    ctx = _ctx()
+    bad = W.TensorSpec(W.Z2, (W.Leg((0, 2), (1, 1), W.IN), W.Leg((0, 1), (1, 1), W.OUT)))
+    with pytest.raises(SymError):
+        ctx.describe(bad, 2)
+    big = W.TensorSpec(W.U1xU1, (W.Leg(((0, 0), (0, 3000)), (1, 1), W.IN), W.Leg(((0, 0),), (1,), W.OUT)),
+                       qtot=(0, 0))
+    with pytest.raises(SymError):
+        ctx.describe(big, 2)

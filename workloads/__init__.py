@@ -29,6 +29,7 @@ from typing import List, Sequence, Tuple
 IN, OUT = "in", "out"
 
 U1, SU2 = "U1", "SU2"
+Z2, U1xU1, Z2F = "Z2", "U1xU1", "Z2F"   # parity, composite U(1) x U(1), fermion parity
 
 # SU(2) coupling structures of a rank-4 tensor (2j labels on every leg):
 #   OPERATOR: legs (in,in,out,out); (1,2) fuse to e, and e splits to (3,4)
