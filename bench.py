@@ -142,7 +142,18 @@ def _timed(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def secondary(ctx, stream):
+def cpu_baseline_svd(spec, flat_dev):
+    """The oracle's block SVD (numpy, singular values only) of the same sectors."""
+    import os
+    from oracle import svd as SV
+    flat = flat_dev.double().cpu().numpy()
+    t0 = time.perf_counter()
+    SV.block_singular_values(spec, flat, 2)
+    return {"value": round(time.perf_counter() - t0, 3), "unit": "s", "kind": "oracle",
+            "cores": len(os.sched_getaffinity(0)), "sample": "all 17 sectors, singular values only"}
+
+
+def secondary(ctx, stream, with_cpu=True):
     """Per-configuration measurements beside the headline batch (each small)."""
     import torch
     import workloads as W
@@ -249,6 +260,24 @@ def secondary(ctx, stream):
             res[f"{comp}_ms"] = round(msz, 3)
         out["z2f_chi128_contract"] = res
         del A, B, C
+
+        # block-wise FP64 SVD of config 4's A split after two legs (17 sectors,
+        # up to 1976 x 1976), with the oracle's numpy SVD of the same sectors
+        c = W.config4()
+        g4 = W.generator(c.seed, "cuda")
+        a4 = W.gaussian(ctx.describe(c.A, 4).numel(), g4, "cuda")
+        A = ctx.tensor(c.A, 4, data=a4)
+        F = ctx.permute_fuse(A, (0, 1, 2, 3), 2, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, S, _, sweeps, shapes = ctx.svd(F, stream=stream)
+        torch.cuda.synchronize()
+        gpu_s = time.perf_counter() - t0
+        out["svd_u1_chi128_fp64"] = {"gpu_s": round(gpu_s, 3), "jacobi_sweeps": int(sweeps),
+                                     "sectors": len(shapes), "max_k": max(k for _, _, _, k in shapes)}
+        if with_cpu:
+            out["svd_u1_chi128_fp64"]["cpu_baseline"] = cpu_baseline_svd(c.A, a4)
+        del A, F, S, a4
 
         # config 5: SU(2) contraction + recoupling, FP32
         c = W.config5()
@@ -450,7 +479,7 @@ def main():
         del As, Bs, Cs, A32, B32
         ctx.clear()
         torch.cuda.empty_cache()
-        result["per_config"] = secondary(ctx, stream)
+        result["per_config"] = secondary(ctx, stream, with_cpu=not args.no_cpu_baseline)
 
     print(json.dumps(result), flush=True)
 

@@ -239,6 +239,37 @@ int32_t sym_num_variants(int32_t compute, int32_t* count);
 int32_t sym_variant_name(int32_t compute, int32_t variant, const char** name);
 int32_t sym_default_variant(int32_t compute, int32_t* variant);
 
+/* Block-wise singular value decomposition (section "Factorization of a
+ * matrix" of the symmetric tensor network chapter; eq:svd0, eq:svd1): every
+ * sector matrix T_s of T's layout (rows = T's first n_row legs, M_s x N_s) is
+ * factorised independently in FP64 as T_s = U_s diag(s_s) Vt_s, k_s =
+ * min(M_s, N_s), singular values descending.  U, S, Vt are FP64 device
+ * buffers, sector after sector in T's sector order (sectors with no rows or
+ * no columns skipped): U_s row-major M_s x k_s, s_s k_s values, Vt_s row-major
+ * k_s x N_s; sym_svd_sizes gives their element counts.  One-sided Jacobi with
+ * plane rotations, all sectors together, until a sweep rotates nothing
+ * (|a.b| <= 1e-15 |a||b| for every pair) or max_sweeps sweeps; sweeps (host,
+ * may be NULL) receives the number run.  The call synchronises `stream` once
+ * per sweep (the stopping decision is taken on the host).  Singular vectors
+ * of zero singular values are returned as zeros.  SYM_E_UNSUPPORTED for a
+ * sector with min(M_s, N_s) > 4096.  The caller owns the outputs; the FP64
+ * workspaces belong to the context (cached per structure), so calls on one
+ * structure must not overlap. */
+int32_t sym_svd_sizes(const sym_tensor* T, int64_t* u_elems, int64_t* s_elems, int64_t* vt_elems);
+int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double* Vt, int32_t* sweeps,
+                int32_t max_sweeps, void* stream);
+/* Global truncation of a block SVD (host; S is a host copy of sym_svd's S):
+ * the singular values of all sectors are taken in descending order, each
+ * counting w_s times (1 for the Abelian groups, 2e + 1 for the SU(2) sector
+ * of coupled spin e: the multiplicity of s_s in the SVD of the full matrix),
+ * and kept while the running total stays within chi_max and the value
+ * exceeds tol; the first value that does not fit ends the cut.  keep[i]
+ * (one per sector of T, 0 for skipped sectors) receives the number kept in
+ * sector i; discarded (may be NULL) the sum of w_s s^2 over dropped values,
+ * the squared Frobenius norm of the truncation error. */
+int32_t sym_svd_truncate(const sym_tensor* T, const double* S, int64_t chi_max, double tol, int32_t* keep,
+                         double* discarded);
+
 /* SU(2) recoupling coefficient F^{jD jE}_{jA jB jC jJ} (eq:sixj), doubled
  * spins, from the library's own FP64 tables.  Host only. */
 double sym_fmove_coeff(int32_t tjA, int32_t tjB, int32_t tjC, int32_t tjJ, int32_t tjD, int32_t tjE);

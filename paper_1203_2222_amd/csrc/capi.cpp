@@ -87,6 +87,17 @@ struct sym_tensor {
     void* data = nullptr;
 };
 
+// Block-wise SVD of one tensor structure: per-sector problems and FP64
+// workspaces for the Jacobi vectors and rotations.
+struct SvdPlan {
+    std::vector<SvdProb> probs;
+    std::vector<int32_t> pair_start;   // prefix sums of kp_s / 2
+    int32_t max_kp = 0;
+    int64_t u_elems = 0, s_elems = 0, vt_elems = 0, w_elems = 0, q_elems = 0;
+    DevMemPtr d_probs, d_pairs, w, q, flag;
+    int32_t flag_host = 0;
+};
+
 struct sym_ctx {
     sym_alloc_fn alloc = nullptr;
     sym_free_fn free_fn = nullptr;
@@ -95,6 +106,7 @@ struct sym_ctx {
     std::unordered_map<std::string, std::shared_ptr<ContractPlan>> contract_plans;
     std::unordered_map<std::string, std::shared_ptr<BackwardPlan>> backward_plans;
     std::unordered_map<std::string, std::shared_ptr<PermutePlan>> permute_plans;
+    std::unordered_map<std::string, std::shared_ptr<SvdPlan>> svd_plans;
     int variant[2] = {-1, -1};
     int n_cu = 0;
     bool timing = false;
@@ -427,6 +439,7 @@ int32_t sym_ctx_clear(sym_ctx* ctx) {
         ctx->contract_plans.clear();
         ctx->backward_plans.clear();
         ctx->permute_plans.clear();
+        ctx->svd_plans.clear();
     });
 }
 
@@ -904,6 +917,137 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             o << tk << ' ' << best << '\n';
         }
         *best_variant = best;
+    });
+}
+
+// ----- block-wise SVD -------------------------------------------------------
+
+namespace {
+
+std::shared_ptr<SvdPlan> svd_plan_of(const Desc& d) {
+    auto plan = std::make_shared<SvdPlan>();
+    if (d.opts.trans) throw Error(SYM_E_UNSUPPORTED, "transposed layouts have no SVD");
+    for (const Sector& sc : d.sectors) {
+        if (sc.rows == 0 || sc.cols == 0) continue;
+        SvdProb p{};
+        p.M = static_cast<int32_t>(sc.rows);
+        p.N = static_cast<int32_t>(sc.cols);
+        p.ld = static_cast<int32_t>(sc.ld);
+        p.k = std::min(p.M, p.N);
+        p.L = std::max(p.M, p.N);
+        if (p.k > kSvdMaxK) throw Error(SYM_E_UNSUPPORTED, "sector with min(rows, cols) above 4096");
+        p.rows_are_vectors = p.M <= p.N ? 1 : 0;
+        p.src_off = sc.offset;
+        p.w_off = plan->w_elems;
+        p.q_off = plan->q_elems;
+        p.u_off = plan->u_elems;
+        p.s_off = plan->s_elems;
+        p.vt_off = plan->vt_elems;
+        plan->w_elems += static_cast<int64_t>(p.k) * p.L;
+        plan->q_elems += static_cast<int64_t>(p.k) * p.k;
+        plan->u_elems += static_cast<int64_t>(p.M) * p.k;
+        plan->s_elems += p.k;
+        plan->vt_elems += static_cast<int64_t>(p.k) * p.N;
+        plan->probs.push_back(p);
+    }
+    plan->pair_start.push_back(0);
+    for (const SvdProb& p : plan->probs) {
+        const int32_t kp = p.k + (p.k & 1);
+        plan->pair_start.push_back(plan->pair_start.back() + kp / 2);
+        plan->max_kp = std::max(plan->max_kp, kp);
+    }
+    return plan;
+}
+
+}  // namespace
+
+int32_t sym_svd_sizes(const sym_tensor* T, int64_t* u_elems, int64_t* s_elems, int64_t* vt_elems) {
+    return guard([&] {
+        if (!T || !u_elems || !s_elems || !vt_elems) throw Error(SYM_E_ARG, "NULL argument");
+        auto plan = svd_plan_of(*T->d);
+        *u_elems = plan->u_elems;
+        *s_elems = plan->s_elems;
+        *vt_elems = plan->vt_elems;
+    });
+}
+
+int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double* Vt, int32_t* sweeps,
+                int32_t max_sweeps, void* stream) {
+    // one plan per structure; calls with the same structure on one context
+    // share its workspaces, so they must not overlap in time
+    return guard([&] {
+        if (!ctx || !T || !U || !S || !Vt) throw Error(SYM_E_ARG, "NULL argument");
+        if (!T->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        if (max_sweeps < 1) throw Error(SYM_E_ARG, "max_sweeps must be >= 1");
+        const std::string key = "S|" + T->d->key;
+        std::shared_ptr<SvdPlan> plan;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->svd_plans.find(key);
+            if (it != ctx->svd_plans.end()) plan = it->second;
+        }
+        if (!plan) {
+            plan = svd_plan_of(*T->d);
+            Allocator alloc = ctx->allocator();
+            if (!plan->probs.empty()) {
+                plan->d_probs = alloc(plan->probs.size() * sizeof(SvdProb));
+                HIP_CHECK(hipMemcpy(plan->d_probs->ptr, plan->probs.data(), plan->probs.size() * sizeof(SvdProb),
+                                    hipMemcpyHostToDevice));
+                plan->d_pairs = alloc(plan->pair_start.size() * sizeof(int32_t));
+                HIP_CHECK(hipMemcpy(plan->d_pairs->ptr, plan->pair_start.data(),
+                                    plan->pair_start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+                plan->w = alloc(static_cast<size_t>(plan->w_elems) * sizeof(double));
+                plan->q = alloc(static_cast<size_t>(plan->q_elems) * sizeof(double));
+                plan->flag = alloc(sizeof(int32_t));
+            }
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->svd_plans[key] = plan;
+        }
+        if (plan->probs.empty()) return;
+        int32_t done = 0;
+        HIP_CHECK(launch_svd(T->d->dtype, T->data, static_cast<const SvdProb*>(plan->d_probs->ptr),
+                             static_cast<const int32_t*>(plan->d_pairs->ptr), static_cast<int32_t>(plan->probs.size()),
+                             plan->pair_start.back(), plan->max_kp, static_cast<double*>(plan->w->ptr),
+                             static_cast<double*>(plan->q->ptr), U, S, Vt, static_cast<int32_t*>(plan->flag->ptr),
+                             &plan->flag_host, max_sweeps, &done, static_cast<hipStream_t>(stream)));
+        if (sweeps) *sweeps = done;
+    });
+}
+
+int32_t sym_svd_truncate(const sym_tensor* T, const double* S, int64_t chi_max, double tol, int32_t* keep,
+                         double* discarded) {
+    return guard([&] {
+        if (!T || !S || !keep) throw Error(SYM_E_ARG, "NULL argument");
+        if (chi_max < 0) throw Error(SYM_E_ARG, "chi_max must be >= 0");
+        auto plan = svd_plan_of(*T->d);
+        // (value, weight, sector) over every singular value; an SU(2) sector
+        // of coupled spin e (label 2e) stands for 2e + 1 equal values
+        struct Item { double v; int32_t w; int32_t s; };
+        std::vector<Item> items;
+        std::vector<int32_t> weight;
+        size_t pi = 0;
+        for (size_t si = 0; si < T->d->sectors.size(); ++si) {
+            const Sector& sc = T->d->sectors[si];
+            keep[si] = 0;
+            if (sc.rows == 0 || sc.cols == 0) continue;
+            const SvdProb& p = plan->probs[pi++];
+            const int32_t w = T->d->group == SYM_SU2 ? sc.label + 1 : 1;
+            for (int32_t j = 0; j < p.k; ++j) items.push_back({S[p.s_off + j], w, static_cast<int32_t>(si)});
+        }
+        std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.v > b.v; });
+        int64_t used = 0;
+        double lost = 0.0;
+        bool open = true;
+        for (const Item& it : items) {
+            if (open && it.v > tol && used + it.w <= chi_max) {
+                used += it.w;
+                ++keep[it.s];
+            } else {
+                open = false;   // keep exactly the largest values: stop at the first that does not fit
+                lost += it.w * it.v * it.v;
+            }
+        }
+        if (discarded) *discarded = lost;
     });
 }
 

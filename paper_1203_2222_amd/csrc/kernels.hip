@@ -1272,6 +1272,232 @@ hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const Ge
 }
 
 // ---------------------------------------------------------------------------
+// Block-wise SVD (eq:svd0, eq:svd1): every sector matrix is factorised on its
+// own, in FP64, by one-sided Jacobi (Hestenes): the k vectors are
+// orthogonalised pairwise by plane rotations, the same rotations accumulate
+// in Q; at convergence the vector norms are the singular values, the
+// normalised vectors one set of singular vectors and Q the other.  A sweep
+// is a sequence of rounds of the round-robin (circle) schedule; one launch
+// runs one round of every sector at once (one wave per pair, disjoint pairs),
+// so the launch boundary orders the rounds and the whole GPU works on them.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double as_f64(T x);
+template <>
+__device__ __forceinline__ double as_f64<float>(float x) { return static_cast<double>(x); }
+template <>
+__device__ __forceinline__ double as_f64<uint16_t>(uint16_t x) { return static_cast<double>(bf16_to_f32(x)); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// player at slot j of round r in the circle schedule over kp (even) players
+__device__ __forceinline__ int rr_player(int j, int r, int kp) { return j == 0 ? 0 : 1 + (j - 1 + r) % (kp - 1); }
+
+// vectors in FP64 (rows of the sector matrix, or its columns) and Q = I
+template <typename Ti>
+__global__ __launch_bounds__(256) void k_svd_load(const Ti* __restrict__ src, const SvdProb* __restrict__ probs,
+                                                   double* __restrict__ Wg, double* __restrict__ Qg) {
+    const SvdProb p = probs[blockIdx.y];
+    const int64_t nw = static_cast<int64_t>(p.k) * p.L, nq = static_cast<int64_t>(p.k) * p.k;
+    for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < nw + nq; idx += static_cast<int64_t>(gridDim.x) * 256) {
+        if (idx < nw) {
+            const int j = static_cast<int>(idx / p.L), x = static_cast<int>(idx - static_cast<int64_t>(j) * p.L);
+            const int64_t e =
+                p.rows_are_vectors ? static_cast<int64_t>(j) * p.ld + x : static_cast<int64_t>(x) * p.ld + j;
+            Wg[p.w_off + idx] = as_f64(src[p.src_off + e]);
+        } else {
+            const int64_t q = idx - nw;
+            Qg[p.q_off + q] = (q / p.k == q % p.k) ? 1.0 : 0.0;
+        }
+    }
+}
+
+// round r of the current sweep for every sector; pair_start[s] is the number
+// of pairs (kp_s / 2) of the sectors before s
+__global__ __launch_bounds__(256) void k_svd_round(const SvdProb* __restrict__ probs, int n_probs,
+                                                    const int32_t* __restrict__ pair_start, int r,
+                                                    double* __restrict__ Wg, double* __restrict__ Qg,
+                                                    int32_t* __restrict__ rotated) {
+    const int lane = threadIdx.x & 63;
+    const int pid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pid >= pair_start[n_probs]) return;
+    int lo = 0, hi = n_probs - 1;   // sector of this pair
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pair_start[mid] <= pid) lo = mid;
+        else hi = mid - 1;
+    }
+    const SvdProb p = probs[lo];
+    const int k = p.k, L = p.L, kp = k + (k & 1);
+    if (k < 2 || r >= kp - 1) return;
+    const int pi = pid - pair_start[lo];
+    const int a = rr_player(pi, r, kp), b = rr_player(kp - 1 - pi, r, kp);
+    if (a >= k || b >= k) return;
+    const int pp = a < b ? a : b, qq = a < b ? b : a;
+    double* wp = Wg + p.w_off + static_cast<int64_t>(pp) * L;
+    double* wq = Wg + p.w_off + static_cast<int64_t>(qq) * L;
+    // vectors of up to 64 * kRegs elements stay in registers between the
+    // dot products and the rotation (one read and one write of each)
+    constexpr int kRegs = 32;
+    double ub[kRegs], vb[kRegs];
+    const bool in_regs = L <= 64 * kRegs;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kRegs; ++i) {
+            const int x = lane + 64 * i;
+            ub[i] = x < L ? wp[x] : 0.0;
+            vb[i] = x < L ? wq[x] : 0.0;
+            al = fma(ub[i], ub[i], al);
+            be = fma(vb[i], vb[i], be);
+            ga = fma(ub[i], vb[i], ga);
+        }
+    } else {
+        for (int x = lane; x < L; x += 64) {
+            const double u = wp[x], v = wq[x];
+            al = fma(u, u, al);
+            be = fma(v, v, be);
+            ga = fma(u, v, ga);
+        }
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    if (fabs(ga) <= 1e-15 * sqrt(al * be)) return;
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kRegs; ++i) {
+            const int x = lane + 64 * i;
+            if (x < L) {
+                wp[x] = c * ub[i] - sn * vb[i];
+                wq[x] = sn * ub[i] + c * vb[i];
+            }
+        }
+    } else {
+        for (int x = lane; x < L; x += 64) {
+            const double u = wp[x], v = wq[x];
+            wp[x] = c * u - sn * v;
+            wq[x] = sn * u + c * v;
+        }
+    }
+    double* qp = Qg + p.q_off + static_cast<int64_t>(pp) * k;
+    double* qv = Qg + p.q_off + static_cast<int64_t>(qq) * k;
+    for (int x = lane; x < k; x += 64) {
+        const double u = qp[x], v = qv[x];
+        qp[x] = c * u - sn * v;
+        qv[x] = sn * u + c * v;
+    }
+    if (lane == 0) rotated[0] = 1;
+}
+
+// norms, descending order (bitonic sort in LDS) and the outputs; one
+// workgroup per sector
+__global__ __launch_bounds__(512) void k_svd_finish(const SvdProb* __restrict__ probs, const double* __restrict__ Wg,
+                                                     const double* __restrict__ Qg, double* __restrict__ Ug,
+                                                     double* __restrict__ Sg, double* __restrict__ Vtg) {
+    constexpr int NT = 512, NW = NT / 64;
+    __shared__ double sval[kSvdMaxK];
+    __shared__ int order[kSvdMaxK];
+    const SvdProb p = probs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k = p.k, L = p.L;
+    const double* W = Wg + p.w_off;
+    const double* Q = Qg + p.q_off;
+    int kq = 1;
+    while (kq < k) kq <<= 1;
+    for (int j = wave; j < kq; j += NW) {
+        double n2 = 0.0;
+        if (j < k)
+            for (int x = lane; x < L; x += 64) n2 = fma(W[static_cast<int64_t>(j) * L + x], W[static_cast<int64_t>(j) * L + x], n2);
+        n2 = wave_sum(n2);
+        if (lane == 0) {
+            sval[j] = j < k ? sqrt(n2) : -1.0;
+            order[j] = j;
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= kq; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < kq; i += NT) {
+                const int jx = i ^ stride;
+                if (jx > i) {
+                    const bool desc = (i & size) == 0;
+                    const double vi = sval[i], vj = sval[jx];
+                    if (desc ? (vi < vj) : (vi > vj)) {
+                        sval[i] = vj;
+                        sval[jx] = vi;
+                        const int t = order[i];
+                        order[i] = order[jx];
+                        order[jx] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int j = tid; j < k; j += NT) Sg[p.s_off + j] = sval[j];
+    // normalised vectors on one side, rotation rows on the other
+    for (int64_t idx = tid; idx < static_cast<int64_t>(k) * L; idx += NT) {
+        const int j = static_cast<int>(idx / L), x = static_cast<int>(idx - static_cast<int64_t>(j) * L);
+        const double sv = sval[j];
+        const double val = sv > 0.0 ? W[static_cast<int64_t>(order[j]) * L + x] / sv : 0.0;
+        if (p.rows_are_vectors) Vtg[p.vt_off + static_cast<int64_t>(j) * p.N + x] = val;   // Vt[j][x], x < N
+        else Ug[p.u_off + static_cast<int64_t>(x) * k + j] = val;                          // U[x][j], x < M
+    }
+    for (int64_t idx = tid; idx < static_cast<int64_t>(k) * k; idx += NT) {
+        const int j = static_cast<int>(idx / k), i = static_cast<int>(idx - static_cast<int64_t>(j) * k);
+        const double g = Q[static_cast<int64_t>(order[j]) * k + i];
+        if (p.rows_are_vectors) Ug[p.u_off + static_cast<int64_t>(i) * k + j] = g;   // U[i][j] = G[v][i], i < M = k
+        else Vtg[p.vt_off + static_cast<int64_t>(j) * p.N + i] = g;                   // Vt[j][i] = G[v][i], i < N = k
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
+                      int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
+                      double* Vt, int32_t* flag, int32_t* flag_host, int32_t max_sweeps, int32_t* sweeps_done,
+                      hipStream_t s) {
+    if (n_probs <= 0) return hipSuccess;
+    dim3 lgrid(256, static_cast<unsigned>(n_probs));
+    if (src_dtype == 0)
+        hipLaunchKernelGGL((k_svd_load<float>), lgrid, dim3(256), 0, s, static_cast<const float*>(src), probs, W, Q);
+    else
+        hipLaunchKernelGGL((k_svd_load<uint16_t>), lgrid, dim3(256), 0, s, static_cast<const uint16_t*>(src), probs, W,
+                           Q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int sweep = 0;
+    const unsigned rgrid = static_cast<unsigned>((n_pairs + 3) / 4);
+    while (sweep < max_sweeps && max_kp > 1 && rgrid > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flag, 1, 0);
+        for (int r = 0; r < max_kp - 1; ++r)
+            hipLaunchKernelGGL(k_svd_round, dim3(rgrid), dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, flag);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        ++sweep;
+        // the sweep count is decided on the host: one small copy per sweep
+        e = hipMemcpyAsync(flag_host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        if (*flag_host == 0) break;
+    }
+    if (sweeps_done) *sweeps_done = sweep;
+    hipLaunchKernelGGL(k_svd_finish, dim3(static_cast<unsigned>(n_probs)), dim3(512), 0, s, probs, W, Q, U, S, Vt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // K9: SU(2) recoupling.  For one label tuple, the n input blocks P^e are
 // combined with FP64 coefficients c[f][e] = R(j2,j3,f) F^{e f}_{j1 j2 j3 j4}
 // into n output blocks with legs 2 and 3 exchanged.  Threads run along t4,

@@ -146,6 +146,23 @@ int gemm_default_variant_wide(int compute);
 // buffer range: they take row lengths (lda, ldb) below gemm_direct_max_ld().
 bool gemm_variant_direct(int compute, int variant);
 int gemm_direct_max_ld();
+// One sector of a block-wise SVD (one-sided Jacobi, FP64).  The k = min(M, N)
+// vectors that get orthogonalised are the rows of the sector matrix when
+// M <= N, its columns otherwise; each has length L = max(M, N).
+struct SvdProb {
+    int64_t src_off;              // element offset of the sector matrix (row-major, ld)
+    int64_t w_off, q_off;         // FP64 workspace: vectors (k x L), rotations (k x k)
+    int64_t u_off, s_off, vt_off; // outputs: U (M x k), S (k), Vt (k x N), row-major
+    int32_t M, N, ld, k, L, rows_are_vectors, pad0, pad1;
+};
+constexpr int kSvdMaxK = 4096;    // k sorted in LDS
+// Jacobi sweeps until one rotates nothing or max_sweeps; synchronises the
+// stream once per sweep (the stopping decision is taken on the host).
+hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
+                      int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
+                      double* Vt, int32_t* flag, int32_t* flag_host, int32_t max_sweeps, int32_t* sweeps_done,
+                      hipStream_t s);
+
 // Resident workgroups per CU of a variant (persistent grid sizing).
 int gemm_blocks_per_cu(int compute, int variant);
 

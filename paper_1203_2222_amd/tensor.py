@@ -296,6 +296,36 @@ class Context:
                                               dB.handle if need_b else None, _stream(stream)))
         return (dA if need_a else None), (dB if need_b else None)
 
+    # ----- block-wise SVD ----------------------------------------------------------
+    def svd(self, t: SymTensor, max_sweeps: int = 60, stream=None):
+        """FP64 SVD of every sector matrix of ``t`` (rows = its first n_row legs).
+        Returns (U, S, Vt, sweeps, shapes): flat FP64 device buffers sector
+        after sector (U_s row-major M x k, S_s descending, Vt_s row-major k x N),
+        the number of Jacobi sweeps run, and [(label, M, N, k)] per sector used.
+        Synchronises the stream once per sweep."""
+        u, sv, v = c_int64(), c_int64(), c_int64()
+        L.check(L.lib().sym_svd_sizes(t.handle, byref(u), byref(sv), byref(v)))
+        shapes = [(lab, m, n, min(m, n)) for lab, m, n, _ in t.sectors() if m > 0 and n > 0]
+        dev = t.data.device
+        U = torch.empty(max(1, u.value), dtype=torch.float64, device=dev)[: u.value]
+        S = torch.empty(max(1, sv.value), dtype=torch.float64, device=dev)[: sv.value]
+        Vt = torch.empty(max(1, v.value), dtype=torch.float64, device=dev)[: v.value]
+        sweeps = c_int32()
+        L.check(L.lib().sym_svd(self.handle, t.handle, c_void_p(U.data_ptr()), c_void_p(S.data_ptr()),
+                                c_void_p(Vt.data_ptr()), byref(sweeps), int(max_sweeps), _stream(stream)))
+        return U, S, Vt, sweeps.value, shapes
+
+    def svd_truncate(self, t: SymTensor, s_host, chi_max: int, tol: float = 0.0):
+        """Global weighted cut of a block SVD: (kept per sector of t, discarded weight)."""
+        import numpy as np
+        s_host = np.ascontiguousarray(s_host, dtype=np.float64)
+        n = len(t.sectors())
+        keep = (c_int32 * max(1, n))()
+        lost = ctypes.c_double()
+        L.check(L.lib().sym_svd_truncate(t.handle, c_void_p(s_host.ctypes.data), int(chi_max), float(tol), keep,
+                                         byref(lost)))
+        return list(keep[:n]), lost.value
+
     def flops(self, A, B, axes_a, axes_b) -> int:
         f = c_int64()
         L.check(L.lib().sym_contract_flops(self.handle, A.handle, B.handle, len(axes_a), L.i32_array(axes_a),

@@ -1,0 +1,75 @@
+"""Oracle pins for the block-wise SVD and its global truncation.
+
+Pinned against the dense matrix of the same tensor (rows = the first two
+legs): its singular values are the union of the sector values, each SU(2)
+sector's values repeated 2e + 1 times; the truncation's discarded weight is
+the dense tail beyond the kept count (Eckart-Young)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import svd as SV
+from oracle import tensors as T
+
+
+def _dense_matrix(spec, flat, n_row=2):
+    d = T.to_dense(spec, flat)
+    r = int(np.prod(d.shape[:n_row]))
+    return d.reshape(r, -1)
+
+
+def _spectrum(values, spec):
+    out = []
+    for s, v in values.items():
+        out += list(v) * SV.multiplicity(spec, s)
+    return np.sort(np.array(out))[::-1]
+
+
+def _u1_cases():
+    c1 = W.config1().A
+    li = W.u1_leg(-2, 2, [1, 2, 3, 2, 1], W.IN)
+    lo = W.u1_leg(-1, 1, [2, 3, 2], W.OUT)
+    cov = W.TensorSpec(W.U1, (li, li, lo, lo), qtot=1)      # sectors of unequal rows and columns
+    return [c1, cov]
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_u1_block_values_are_the_dense_spectrum(k):
+    spec = _u1_cases()[k]
+    flat = np.random.default_rng(k).standard_normal(T.num_elements(spec))
+    vals = SV.block_singular_values(spec, flat, 2)
+    mats = SV.sector_matrices(spec, flat, 2)
+    assert any(m.shape[0] < m.shape[1] for m in mats.values()) or k == 0
+    assert any(m.shape[0] > m.shape[1] for m in mats.values()) or k == 0
+    dense = np.linalg.svd(_dense_matrix(spec, flat), compute_uv=False)
+    blocks = _spectrum(vals, spec)
+    np.testing.assert_allclose(dense[:blocks.size], blocks, rtol=1e-12, atol=1e-12)
+    assert np.all(np.abs(dense[blocks.size:]) < 1e-12)
+
+
+def test_su2_values_repeat_2e_plus_1_times():
+    spec = W.su2_pair(2, [2, 1, 2])[0]          # OPERATOR tree, spins 0, 1/2, 1
+    flat = np.random.default_rng(3).standard_normal(T.num_elements(spec))
+    vals = SV.block_singular_values(spec, flat, 2)
+    dense = np.linalg.svd(_dense_matrix(spec, flat), compute_uv=False)
+    blocks = _spectrum(vals, spec)
+    np.testing.assert_allclose(dense[:blocks.size], blocks, rtol=1e-12, atol=1e-12)
+    assert np.all(np.abs(dense[blocks.size:]) < 1e-12)
+    # weighting by 1 (a planted mistake) would not reproduce the dense spectrum
+    flat_only = np.sort(np.concatenate(list(vals.values())))[::-1]
+    assert flat_only.size < blocks.size
+
+
+@pytest.mark.parametrize("which", ["u1", "su2"])
+def test_truncation_discards_the_dense_tail(which):
+    spec = _u1_cases()[0] if which == "u1" else W.su2_pair(2, [2, 1, 2])[0]
+    flat = np.random.default_rng(4).standard_normal(T.num_elements(spec))
+    vals = SV.block_singular_values(spec, flat, 2)
+    dense = np.linalg.svd(_dense_matrix(spec, flat), compute_uv=False)
+    for chi in (1, 7, 20, 10 ** 6):
+        keep, lost = SV.truncate(spec, vals, chi)
+        used = sum(SV.multiplicity(spec, s) * n for s, n in keep.items())
+        assert used <= chi
+        np.testing.assert_allclose(lost, float(np.sum(dense[used:] ** 2)), rtol=1e-10, atol=1e-12)
+        if chi >= dense.size:
+            assert lost < 1e-20
