@@ -13,8 +13,23 @@ p = (1,3,2,4), carried out as two closed-form moves:
 ``recouple_by_projection`` reaches the same blocks without any 6j symbol:
 permute the dense tensor and project it on the structural tensors of the
 target tree.
+
+``permute_tree`` is the general rank-4 case of the same 6j-free route: any
+permutation p of the legs, any target tree (OPERATOR, LEFT or RIGHT), and a
+REVERSE (section "Reversal of indices") of every leg whose arrow the target
+tree changes.  That is PERMUTE with the matrix Gamma(tree, p, tree') of
+eq:permsu2, with the cups of eq:cupj attached to the reversed legs.
+
+Reading taken for the orientation of a reversal (the text only says that a
+cup bends an outgoing leg "from the left"): the leg's spin index m is summed
+against the ROW index of the matrix, T'[.., n, ..] = sum_m T[.., m, ..] M[m, n],
+with M = cup_j for an outgoing leg and M = cap_j for an incoming one; the
+degeneracy index is untouched.  Since cup_j cap_j = cap_j cup_j = 1
+(eq:wiggle), reversing a leg twice returns the tensor.
 """
 from __future__ import annotations
+
+from collections import namedtuple
 
 import numpy as np
 
@@ -22,6 +37,9 @@ from . import su2
 from . import tensors as T
 
 PERM = (0, 2, 1, 3)
+
+
+_Leg = namedtuple("_Leg", "labels degs arrow")
 
 
 class _Spec:
@@ -61,3 +79,44 @@ def recouple_by_projection(spec, flat):
     out_spec = target_spec(spec)
     dense = T.to_dense(spec, flat)
     return out_spec, T.from_dense(out_spec, np.transpose(dense, PERM))
+
+
+def reverse_leg_dense(leg, dense: np.ndarray, axis: int) -> np.ndarray:
+    """Reverse one SU(2) leg of a dense tensor: an outgoing leg through the cup
+    (eq:cup, eq:cupj), an incoming one through the cap (eq:cap, eq:capj), each
+    acting as the identity on the degeneracy index (see the module note for
+    the orientation)."""
+    offs, _ = T.leg_offsets(T.SU2, leg)
+    moved = np.moveaxis(np.asarray(dense, dtype=np.float64), axis, 0)
+    res = np.zeros_like(moved)
+    for lab, d in zip(leg.labels, leg.degs):
+        n = lab + 1
+        mat = su2.cup(lab) if leg.arrow == T.OUT else su2.cap(lab)
+        o = offs[lab]
+        blk = moved[o:o + d * n].reshape((d, n) + moved.shape[1:])
+        res[o:o + d * n] = np.einsum("tm...,mk->tk...", blk, mat).reshape((d * n,) + moved.shape[1:])
+    return np.moveaxis(res, 0, axis)
+
+
+def tree_spec(spec, perm, tree_out):
+    """Description of the result of permute_tree: leg i is the input's leg
+    perm[i] (same spectrum), with the arrow tree_out puts in slot i."""
+    arrows = T._SU2_ARROWS[tree_out]
+    legs = [_Leg(tuple(spec.legs[p].labels), tuple(spec.legs[p].degs), arrows[i]) for i, p in enumerate(perm)]
+    return _Spec(T.SU2, legs, tree_out)
+
+
+def permute_tree(spec, flat, perm, tree_out):
+    """Blocks of the tensor with legs permuted by perm and recoupled to
+    tree_out, by the 6j-free route: the dense tensor, its legs transposed,
+    the legs whose arrow changes reversed, then projected on the structural
+    tensors of tree_out.  Returns (out_spec, flat blocks, the dense tensor
+    that was projected)."""
+    if spec.group != T.SU2:
+        raise ValueError("permute_tree acts on SU(2) tensors")
+    out_spec = tree_spec(spec, perm, tree_out)
+    dense = np.transpose(T.to_dense(spec, flat), perm)
+    for i, p in enumerate(perm):
+        if spec.legs[p].arrow != out_spec.legs[i].arrow:
+            dense = reverse_leg_dense(spec.legs[p], dense, i)
+    return out_spec, T.from_dense(out_spec, dense), dense
