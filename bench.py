@@ -290,11 +290,21 @@ def secondary(ctx, stream, with_cpu=True):
         # K2 on the config-5 tensor: A's reduced blocks into its e-sector matrices
         F = ctx.permute_fuse(A, (0, 1, 2, 3), 2)
         msf = _timed(lambda: ctx.permute_into(A, (0, 1, 2, 3), 2, F, stream=stream), 5, stream)
+        # general PERMUTE: C's in-legs cycled (1,2,0) on the LEFT tree, sector-major
+        # for a next contraction; and A's leg 2 reversed (OPERATOR -> LEFT)
+        T1 = ctx.permute_tree(C, (1, 2, 0, 3), W.TREE_LEFT, 2)
+        mst = _timed(lambda: ctx.permute_tree_into(C, (1, 2, 0, 3), W.TREE_LEFT, 2, T1, stream=stream), 5, stream)
+        T2 = ctx.permute_tree(A, (0, 1, 2, 3), W.TREE_LEFT, 4)
+        msv = _timed(lambda: ctx.permute_tree_into(A, (0, 1, 2, 3), W.TREE_LEFT, 4, T2, stream=stream), 5, stream)
         out["su2_j4_fp32"] = {"contract_TFLOPs": round(fl / ms / 1e9, 2), "contract_ms": round(ms, 3),
                               "recouple_ms": round(msr, 3),
                               "recouple_GBps": round(C.numel() * 8 / msr / 1e6, 1),
+                              "permute_120_left_ms": round(mst, 3),
+                              "permute_120_left_GBps": round(C.numel() * 8 / mst / 1e6, 1),
+                              "reverse_leg2_ms": round(msv, 3),
+                              "reverse_leg2_GBps": round(A.numel() * 8 / msv / 1e6, 1),
                               "fuse_ms": round(msf, 3), "fuse_GBps": round(A.numel() * 8 / msf / 1e6, 1)}
-        del A, B, C, R, F
+        del A, B, C, R, F, T1, T2
     ctx.clear()
     torch.cuda.empty_cache()
     return out

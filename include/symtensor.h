@@ -173,6 +173,38 @@ int32_t sym_permute_fuse_output(sym_ctx* ctx, const sym_tensor* in, const int32_
 int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t n_row_out,
                          sym_tensor* out, void* stream);
 
+/* General SU(2) PERMUTE of a rank-4 tensor to a chosen tree (the routine
+ * PERMUTE with the matrix Gamma(tree, p, tree') of eq:permsu2 and eq:Gamma),
+ * combined with REVERSE (section "Reversal of indices") of every leg whose
+ * arrow the target tree changes.  out's leg i is in's leg perm[i] with the
+ * same spectrum and the arrow of slot i of tree_out (OPERATOR
+ * (in,in,out,out), LEFT or RIGHT (in,in,in,out)); any permutation and any of
+ * the three trees is accepted.  For each label tuple the output blocks are
+ * y_f = sum_e Gamma[f][e] x_e (legs permuted), Gamma composed on the host in
+ * FP64 from F-moves (eq:fmove2, 6j by Racah's formula), swap factors
+ * (-1)^(ja+jb-jc) (eq:braid3) and, per reversed leg, the bend factor
+ * sqrt((2e+1)/(2j4+1)) or its inverse; the combination runs on the device in
+ * FP64 on FP32 data.  Reversal convention: an outgoing leg is reversed by the
+ * cup (eq:cupj) and an incoming one by the cap (eq:capj), the leg's m index
+ * summed against the matrix's row index.
+ * in: SU(2), FP32, any layout; n_row_out: 0 or 4, or 2 when tree_out is
+ * OPERATOR or LEFT.  SYM_E_UNSUPPORTED for Abelian tensors (use
+ * sym_permute_fuse).  sym_permute_tree_output creates the result's handle
+ * (data may be NULL); sym_permute_tree writes into out, which must describe
+ * exactly that result; in and out must not overlap.  The plan (Gamma of
+ * every label tuple) is built on the first call and cached. */
+int32_t sym_permute_tree_output(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t tree_out,
+                                int32_t n_row_out, void* data, sym_tensor** out);
+int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t tree_out,
+                         int32_t n_row_out, sym_tensor* out, void* stream);
+/* The Gamma of sym_permute_tree for one label tuple, on the host: spins[4]
+ * are the doubled spins of the input's legs; on return *n is the number of
+ * intermediate spins, es[*n] the input tree's (ascending), fs[*n] the output
+ * tree's, gamma[f * n + e] the coefficients.  cap is the capacity of es and
+ * fs (gamma holds cap * cap); SYM_E_ARG when *n would exceed it.  No GPU. */
+int32_t sym_su2_gamma(int32_t tree_in, const int32_t* perm, int32_t tree_out, const int32_t* spins, int32_t cap,
+                      int32_t* n, int32_t* es, int32_t* fs, double* gamma);
+
 /* Contraction C = A . B (see above).  compute: SYM_F32 (FP32 MFMA, FP32
  * accumulate) or SYM_BF16 (operands rounded to BF16 on the device, BF16 MFMA,
  * FP32 accumulate, FP32 output).  C must have dtype F32.  SU(2): A must be an

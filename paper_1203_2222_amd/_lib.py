@@ -49,6 +49,9 @@ SIGNATURES = {
     "sym_tensor_sector_info": (c_int32, [P, c_int64, I32P, I64P, I64P, I64P]),
     "sym_permute_fuse_output": (c_int32, [P, P, I32P, c_int32, c_int32, P, PP]),
     "sym_permute_fuse": (c_int32, [P, P, I32P, c_int32, P, P]),
+    "sym_permute_tree_output": (c_int32, [P, P, I32P, c_int32, c_int32, P, PP]),
+    "sym_permute_tree": (c_int32, [P, P, I32P, c_int32, c_int32, P, P]),
+    "sym_su2_gamma": (c_int32, [c_int32, I32P, c_int32, I32P, c_int32, I32P, I32P, I32P, POINTER(c_double)]),
     "sym_contract_output": (c_int32, [P, P, P, c_int32, I32P, I32P, P, PP]),
     "sym_contract": (c_int32, [P, P, P, c_int32, I32P, I32P, c_int32, P, P]),
     "sym_contract_backward": (c_int32, [P, P, P, P, c_int32, I32P, I32P, c_int32, P, P, P]),

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsymtensor.so")
 
-SOURCES = ["desc.cpp", "group.cpp", "plan.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["desc.cpp", "group.cpp", "newtree.cpp", "plan.cpp", "capi.cpp", "kernels.hip"]
 
 # Packed FP32 instructions are kept out of every kernel (they have produced
 # silent wrong results on this hardware); the host pass ignores the feature.

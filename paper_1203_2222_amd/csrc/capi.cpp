@@ -601,7 +601,7 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
             Allocator alloc = ctx->allocator();
             if (s.recouple) {
                 plan->is_recouple = true;
-                plan->recouple.build(*in->d, *out->d);
+                plan->recouple.build(*in->d, *out->d, s.perm);
                 plan->recouple.upload(alloc);
             } else {
                 plan->copy.src_dtype = in->d->dtype;
@@ -619,6 +619,110 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
         hipStream_t st = static_cast<hipStream_t>(stream);
         if (plan->is_recouple) HIP_CHECK(plan->recouple.launch(t, 0, 1, st));
         else HIP_CHECK(plan->copy.launch(t, st));
+    });
+}
+
+// ----- SU(2) PERMUTE to a chosen tree, with REVERSE --------------------------------
+
+namespace {
+
+std::vector<int32_t> check_tree_perm(const Desc& in, const int32_t* perm, int32_t tree_out) {
+    if (in.group != SYM_SU2)
+        throw Error(SYM_E_UNSUPPORTED, "sym_permute_tree acts on SU(2) tensors (Abelian ones use sym_permute_fuse)");
+    if (tree_out != SYM_TREE_OPERATOR && tree_out != SYM_TREE_LEFT && tree_out != SYM_TREE_RIGHT)
+        throw Error(SYM_E_ARG, "tree_out must be OPERATOR, LEFT or RIGHT");
+    if (!perm) throw Error(SYM_E_ARG, "perm is NULL");
+    std::vector<int32_t> p(perm, perm + 4);
+    std::vector<bool> seen(4, false);
+    for (int32_t v : p) {
+        if (v < 0 || v >= 4 || seen[static_cast<size_t>(v)]) throw Error(SYM_E_ARG, "not a permutation");
+        seen[static_cast<size_t>(v)] = true;
+    }
+    return p;
+}
+
+DescPtr tree_result(const Desc& in, const std::vector<int32_t>& perm, int32_t tree_out, int32_t n_row_out) {
+    if (in.dtype != SYM_F32) throw Error(SYM_E_DTYPE, "recoupling works on FP32 data");
+    static const int32_t op_arrows[4] = {SYM_IN, SYM_IN, SYM_OUT, SYM_OUT};
+    static const int32_t fuse_arrows[4] = {SYM_IN, SYM_IN, SYM_IN, SYM_OUT};
+    const int32_t* arrows = tree_out == SYM_TREE_OPERATOR ? op_arrows : fuse_arrows;
+    std::vector<Leg> legs = permute_legs(in.legs, perm);
+    for (size_t i = 0; i < 4; ++i) legs[i].arrow = arrows[i];
+    return make_desc(SYM_SU2, legs, n_row_out, tree_out, 0, SYM_F32);
+}
+
+}  // namespace
+
+int32_t sym_permute_tree_output(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t tree_out,
+                                int32_t n_row_out, void* data, sym_tensor** out) {
+    (void)ctx;
+    return guard([&] {
+        if (!in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        const std::vector<int32_t> p = check_tree_perm(*in->d, perm, tree_out);
+        auto* t = new sym_tensor();
+        try {
+            t->d = tree_result(*in->d, p, tree_out, n_row_out);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        t->data = data;
+        *out = t;
+    });
+}
+
+int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t tree_out,
+                         int32_t n_row_out, sym_tensor* out, void* stream) {
+    return guard([&] {
+        if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        const std::vector<int32_t> p = check_tree_perm(*in->d, perm, tree_out);
+        if (!in->data || !out->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        std::ostringstream k;
+        k << "T|" << in->d->key << '|' << out->d->key << '|' << n_row_out << '|' << tree_out << '|';
+        for (int32_t v : p) k << v << ',';
+        std::shared_ptr<PermutePlan> plan;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->permute_plans.find(k.str());
+            if (it != ctx->permute_plans.end()) plan = it->second;
+        }
+        if (!plan) {
+            DescPtr want = tree_result(*in->d, p, tree_out, n_row_out);
+            if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
+            plan = std::make_shared<PermutePlan>();
+            plan->is_recouple = true;
+            plan->recouple.build(*in->d, *out->d, p);
+            plan->recouple.upload(ctx->allocator());
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->permute_plans[k.str()] = plan;
+        }
+        PtrTable t{};
+        t.p[0] = in->data;
+        t.p[1] = out->data;
+        HIP_CHECK(plan->recouple.launch(t, 0, 1, static_cast<hipStream_t>(stream)));
+    });
+}
+
+int32_t sym_su2_gamma(int32_t tree_in, const int32_t* perm, int32_t tree_out, const int32_t* spins, int32_t cap,
+                      int32_t* n, int32_t* es, int32_t* fs, double* gamma) {
+    return guard([&] {
+        if (!perm || !spins || !n || !es || !fs || !gamma) throw Error(SYM_E_ARG, "NULL argument");
+        std::vector<bool> seen(4, false);
+        for (int i = 0; i < 4; ++i) {
+            if (perm[i] < 0 || perm[i] >= 4 || seen[static_cast<size_t>(perm[i])]) throw Error(SYM_E_ARG, "not a permutation");
+            seen[static_cast<size_t>(perm[i])] = true;
+            if (spins[i] < 0) throw Error(SYM_E_ARG, "negative spin");
+        }
+        const TreeMoves mv = tree_moves(tree_in, perm, tree_out);
+        std::vector<int32_t> e, f;
+        std::vector<double> g;
+        tree_gamma(mv, spins, e, f, g);
+        const int32_t m = static_cast<int32_t>(e.size());
+        if (m > cap) throw Error(SYM_E_ARG, "capacity too small for the intermediate spins");
+        *n = m;
+        std::copy(e.begin(), e.end(), es);
+        std::copy(f.begin(), f.end(), fs);
+        std::copy(g.begin(), g.end(), gamma);
     });
 }
 

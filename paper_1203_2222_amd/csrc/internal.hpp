@@ -109,4 +109,23 @@ inline bool triangle(int a, int b, int c) {
 double fmove_coeff(int tA, int tB, int tC, int tJ, int tD, int tE);
 double sixj(int a, int b, int c, int d, int e, int f);
 
+// Rank-4 SU(2) PERMUTE with recoupling and reversal (newtree.cpp).  A state
+// is a tree kind (0 OPERATOR, 1 LEFT, 2 RIGHT) with the input leg in each
+// slot; moves[k] takes states[k] to states[k + 1].
+struct TreeState {
+    int kind;
+    std::array<int, 4> slot;
+};
+struct TreeMoves {
+    std::vector<TreeState> states;
+    std::vector<int> moves;
+};
+// Shortest sequence of moves from the tree tree_in on legs (0,1,2,3) to
+// tree_out on legs (perm[0], .., perm[3]).
+TreeMoves tree_moves(int32_t tree_in, const int32_t* perm, int32_t tree_out);
+// Gamma of one label tuple (j[leg] = doubled spin of input leg leg): es and fs
+// are the input's and output's intermediate spins, coef[f][e] row-major.
+void tree_gamma(const TreeMoves& mv, const int32_t* j, std::vector<int32_t>& es, std::vector<int32_t>& fs,
+                std::vector<double>& coef);
+
 }  // namespace sym

@@ -1498,10 +1498,12 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
 }
 
 // ---------------------------------------------------------------------------
-// K9: SU(2) recoupling.  For one label tuple, the n input blocks P^e are
-// combined with FP64 coefficients c[f][e] = R(j2,j3,f) F^{e f}_{j1 j2 j3 j4}
-// into n output blocks with legs 2 and 3 exchanged.  Threads run along t4,
-// the innermost index of input and output blocks alike.
+// K9: SU(2) PERMUTE with recoupling.  For one label tuple, the n input
+// blocks P^e are combined with the FP64 coefficients Gamma[f][e] of the
+// permutation and tree change into the n output blocks.  The output's axis k
+// is the input's axis perm[k]; the host hands over the input strides already
+// in output-axis order, so the kernel only walks the output block row-major.
+// Threads run along the output's innermost axis.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks,
                                                   const FmBlk* __restrict__ out_blks, const double* __restrict__ coef,
@@ -1512,22 +1514,21 @@ __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ gr
     const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
     float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
     const int n = g.n;
-    const int d2 = g.d[1], d3 = g.d[2], d4 = g.d[3];
+    const int d1 = g.d[1], d2 = g.d[2], d3 = g.d[3];
     const int e = t.start + static_cast<int>(threadIdx.x);
     if (e >= t.start + t.count) return;
-    // output order (t1, t3, t2, t4)
-    int r = e / d4;
-    const int t4 = e - r * d4;
-    int q = r / d2;
+    int r = e / d3;
+    const int t3 = e - r * d3;
+    const int q = r / d2;
     const int t2 = r - q * d2;
-    const int t1 = q / d3;
-    const int t3 = q - t1 * d3;
+    const int t0 = q / d1;
+    const int t1 = q - t0 * d1;
     double x[kMaxRecouple];
 #pragma unroll
     for (int i = 0; i < kMaxRecouple; ++i) {
         if (i < n) {
             const FmBlk b = in_blks[g.in_first + i];
-            x[i] = static_cast<double>(src[b.off + t1 * b.stride[0] + t2 * b.stride[1] + t3 * b.stride[2] + t4 * b.stride[3]]);
+            x[i] = static_cast<double>(src[b.off + t0 * b.stride[0] + t1 * b.stride[1] + t2 * b.stride[2] + t3 * b.stride[3]]);
         }
     }
     const double* c = coef + g.coef_first;
@@ -1537,7 +1538,7 @@ __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ gr
         for (int i = 0; i < kMaxRecouple; ++i)
             if (i < n) y = fma(c[f * n + i], x[i], y);
         const FmBlk b = out_blks[g.out_first + f];
-        dst[b.off + t1 * b.stride[0] + t3 * b.stride[1] + t2 * b.stride[2] + t4 * b.stride[3]] = static_cast<float>(y);
+        dst[b.off + t0 * b.stride[0] + t1 * b.stride[1] + t2 * b.stride[2] + t3 * b.stride[3]] = static_cast<float>(y);
     }
 }
 

@@ -95,17 +95,19 @@ struct GemmTile {
     int32_t prob, tm, tn, pad;
 };
 
-// SU(2) recoupling of one label tuple (j1,j2,j3,j4): n input blocks (one per
-// intermediate spin e) and n output blocks (one per f).
+// SU(2) PERMUTE with recoupling of one label tuple: n input blocks (one per
+// intermediate spin e of the input tree) and n output blocks (one per f of
+// the output tree).
 struct FmGroup {
     int32_t n;
-    int32_t d[4];        // degeneracies of legs 1..4 of the input
+    int32_t d[4];        // block dims in output-axis order
     int32_t in_first;    // index of its first FmBlk among inputs
     int32_t out_first;   // index of its first FmBlk among outputs
     int32_t coef_first;  // n*n coefficients, row f, column e
 };
 
-// Input blocks: strides of (t1,t2,t3,t4); output blocks: strides of (t1,t3,t2,t4).
+// Element strides of a block along the output's axes 0..3 (for an input
+// block: its stride along input axis perm[k]).
 struct FmBlk {
     int64_t off;
     int64_t stride[4];

@@ -482,10 +482,13 @@ hipError_t GemmProgram::launch(const PtrTable& bufs, int grid, hipStream_t s) co
 // RecoupleProgram: LEFT tree (legs 1,2,3,4) -> RIGHT tree on legs (1,3,2,4)
 // ---------------------------------------------------------------------------
 
-void RecoupleProgram::build(const Desc& in, const Desc& out) {
-    if (in.group != SYM_SU2 || in.tree != SYM_TREE_LEFT || out.tree != SYM_TREE_RIGHT)
-        throw Error(SYM_E_UNSUPPORTED, "recoupling maps the LEFT tree to the RIGHT tree");
+void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm) {
+    if (in.group != SYM_SU2 || out.group != SYM_SU2 || in.rank != 4 || out.rank != 4 || perm.size() != 4)
+        throw Error(SYM_E_UNSUPPORTED, "recoupling acts on rank-4 SU(2) tensors");
+    const TreeMoves mv = tree_moves(in.tree, perm.data(), out.tree);
     size_t i = 0;
+    std::vector<int32_t> es, fs;
+    std::vector<double> gamma;
     while (i < in.blocks.size()) {
         const Block& b0 = in.blocks[i];
         size_t j = i;
@@ -493,27 +496,26 @@ void RecoupleProgram::build(const Desc& in, const Desc& out) {
         while (j < in.blocks.size() &&
                std::equal(in.blocks[j].labels.begin(), in.blocks[j].labels.begin() + 4, b0.labels.begin()))
             ++j;
-        const int j1 = b0.labels[0], j2 = b0.labels[1], j3 = b0.labels[2], j4 = b0.labels[3];
-        std::vector<int32_t> es, fs;
-        for (size_t k = i; k < j; ++k) es.push_back(in.blocks[k].internal);
-        for (int32_t f = 0; f <= 2 * std::max(std::max(j1, j2), std::max(j3, j4)) + 1; ++f)
-            if (triangle(j2, j3, f) && triangle(j1, f, j4)) fs.push_back(f);
-        if (es.size() != fs.size()) throw Error(SYM_E_MISMATCH, "recoupling multiplicities differ");
+        tree_gamma(mv, b0.labels.data(), es, fs, gamma);
         const int n = static_cast<int>(es.size());
+        if (static_cast<size_t>(n) != j - i) throw Error(SYM_E_MISMATCH, "input blocks do not match the tree");
         if (n > kMaxRecouple) throw Error(SYM_E_UNSUPPORTED, "too many intermediate spins");
         FmGroup g{};
         g.n = n;
-        for (int k = 0; k < 4; ++k) g.d[k] = static_cast<int32_t>(b0.shape[static_cast<size_t>(k)]);
+        // output axis k is input axis perm[k]
+        for (int k = 0; k < 4; ++k) g.d[k] = static_cast<int32_t>(b0.shape[static_cast<size_t>(perm[k])]);
         g.in_first = static_cast<int32_t>(in_blks.size());
         g.out_first = static_cast<int32_t>(out_blks.size());
         g.coef_first = static_cast<int32_t>(coef.size());
         for (size_t k = i; k < j; ++k) {
+            if (in.blocks[k].internal != es[k - i]) throw Error(SYM_E_MISMATCH, "input intermediate spins out of order");
             FmBlk fb{};
             fb.off = in.blocks[k].offset;
-            for (int l = 0; l < 4; ++l) fb.stride[l] = in.blocks[k].stride[static_cast<size_t>(l)];
+            for (int l = 0; l < 4; ++l) fb.stride[l] = in.blocks[k].stride[static_cast<size_t>(perm[l])];
             in_blks.push_back(fb);
         }
-        const int32_t olab[4] = {j1, j3, j2, j4};
+        int32_t olab[4];
+        for (int l = 0; l < 4; ++l) olab[l] = b0.labels[static_cast<size_t>(perm[l])];
         for (int32_t f : fs) {
             const int32_t oi = out.find_block(olab, f);
             if (oi < 0) throw Error(SYM_E_MISMATCH, "recoupled block missing from the output");
@@ -522,10 +524,8 @@ void RecoupleProgram::build(const Desc& in, const Desc& out) {
             fb.off = ob.offset;
             for (int l = 0; l < 4; ++l) fb.stride[l] = ob.stride[static_cast<size_t>(l)];
             out_blks.push_back(fb);
-            // c[f][e] = (-1)^(j2+j3-f) F^{e f}_{j1 j2 j3 j4}   (eq:fmove2 then eq:perm11)
-            const double phase = (((j2 + j3 - f) / 2) % 2) ? -1.0 : 1.0;
-            for (int32_t e : es) coef.push_back(phase * fmove_coeff(j1, j2, j3, j4, e, f));
         }
+        coef.insert(coef.end(), gamma.begin(), gamma.end());
         const int64_t elems = b0.size;
         for (int64_t s = 0; s < elems; s += 256)
             tasks.push_back({static_cast<int32_t>(groups.size()), static_cast<int32_t>(s),

@@ -82,7 +82,8 @@ struct RecoupleProgram {
     std::vector<double> coef;
     std::vector<FmTask> tasks;
     DevMemPtr d_groups, d_in, d_out, d_coef, d_tasks;
-    void build(const Desc& in, const Desc& out);
+    // Gamma(tree, perm, tree') of every label tuple; out's leg k is in's leg perm[k]
+    void build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm);
     void upload(const Allocator& alloc);
     hipError_t launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const;
 };

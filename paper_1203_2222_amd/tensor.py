@@ -151,6 +151,17 @@ def _stream(stream=None) -> c_void_p:
     return c_void_p(stream.cuda_stream)
 
 
+class _Leg:
+    """Spectrum and arrow of one leg of a tensor produced by the library."""
+
+    def __init__(self, labels, degs, arrow):
+        self.labels, self.degs, self.arrow = tuple(labels), tuple(degs), arrow
+
+
+_TREE_ARROWS = {L.SYM_TREE_OPERATOR: ("in", "in", "out", "out"), L.SYM_TREE_LEFT: ("in", "in", "in", "out"),
+                L.SYM_TREE_RIGHT: ("in", "in", "in", "out")}
+
+
 class _Spec:
     """Leg description of a tensor produced by the library."""
 
@@ -253,6 +264,26 @@ class Context:
                                 None if out is None else out, t.data.device)
         L.check(L.lib().sym_permute_fuse(self.handle, t.handle, p, n_row, res.handle, _stream(stream)))
         return res
+
+    def permute_tree(self, t: SymTensor, perm: Sequence[int], tree: int, n_row: int = 0, out=None,
+                     stream=None) -> SymTensor:
+        """SU(2) PERMUTE to the tree ``tree`` (L.SYM_TREE_*), reversing every leg
+        whose arrow that tree changes (sym_permute_tree)."""
+        p = L.i32_array(perm)
+        h = c_void_p()
+        L.check(L.lib().sym_permute_tree_output(self.handle, t.handle, p, tree, n_row, None, byref(h)))
+        arrows = _TREE_ARROWS[tree]
+        legs = [_Leg(t.spec.legs[j].labels, t.spec.legs[j].degs, arrows[i]) for i, j in enumerate(perm)]
+        res = self._wrap_output(h, _Spec(t.spec.group, legs, tree, 0), n_row, L.SYM_F32, out, t.data.device)
+        L.check(L.lib().sym_permute_tree(self.handle, t.handle, p, tree, n_row, res.handle, _stream(stream)))
+        return res
+
+    def permute_tree_into(self, t: SymTensor, perm: Sequence[int], tree: int, n_row: int, out: SymTensor,
+                          stream=None) -> SymTensor:
+        """permute_tree into an existing handle (no host-side output creation)."""
+        L.check(L.lib().sym_permute_tree(self.handle, t.handle, L.i32_array(perm), tree, n_row, out.handle,
+                                         _stream(stream)))
+        return out
 
     # ----- contraction -------------------------------------------------------------
     def contract_output(self, A: SymTensor, B: SymTensor, axes_a, axes_b, data=None) -> SymTensor:
@@ -397,6 +428,19 @@ def default_variant(compute) -> int:
     n = c_int32()
     L.check(L.lib().sym_default_variant(_dtype_code(compute), byref(n)))
     return n.value
+
+
+def su2_gamma(tree_in: int, perm: Sequence[int], tree_out: int, spins: Sequence[int]):
+    """(input intermediate spins, output intermediate spins, Gamma[f][e]) of
+    sym_permute_tree for one label tuple of doubled spins (host only)."""
+    cap = 2 * max(spins) + 2
+    n = ctypes.c_int32()
+    es = (ctypes.c_int32 * cap)()
+    fs = (ctypes.c_int32 * cap)()
+    g = (ctypes.c_double * (cap * cap))()
+    L.check(L.lib().sym_su2_gamma(tree_in, L.i32_array(perm), tree_out, L.i32_array(spins), cap, byref(n), es, fs, g))
+    k = n.value
+    return list(es[:k]), list(fs[:k]), [[g[f * k + e] for e in range(k)] for f in range(k)]
 
 
 def fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE) -> float:
