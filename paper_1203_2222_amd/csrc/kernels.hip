@@ -494,21 +494,62 @@ __device__ __forceinline__ void store_tile(const v16f (&acc)[FM][FN], const Gemm
         cok[j] = col < p.N;
         cj[j] = cols[p.ci_off + (cok[j] ? col : 0)];
     }
+    // branch-free (see store_tile_tab): elements outside the matrix get the
+    // out-of-range offset 0x80000000 and the buffer store drops them
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int row = mb + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
-            if (row >= p.M) continue;
-            const EpiRow ri = rows[p.ri_off + row];
+            const bool rok = row < p.M;
+            const EpiRow ri = rows[p.ri_off + (rok ? row : p.M - 1)];
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-                if (cok[j]) {
-                    const uint32_t e = static_cast<uint32_t>(ri.r0 + cj[j].c0) +
-                                       __umul24(static_cast<uint32_t>(ri.r1), static_cast<uint32_t>(cj[j].c1)) +
-                                       __umul24(static_cast<uint32_t>(ri.r2), static_cast<uint32_t>(cj[j].c2));
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[i][j][q]), rc, e * 4u, 0, 0);
-                }
+            for (int j = 0; j < FN; ++j) {
+                const uint32_t e = static_cast<uint32_t>(ri.r0 + cj[j].c0) +
+                                   __umul24(static_cast<uint32_t>(ri.r1), static_cast<uint32_t>(cj[j].c1)) +
+                                   __umul24(static_cast<uint32_t>(ri.r2), static_cast<uint32_t>(cj[j].c2));
+                const uint32_t vo = (rok && cok[j]) ? e * 4u : 0x80000000u;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[i][j][q]), rc, vo, 0, 0);
+            }
+        }
+}
+
+// Canonical-block epilogue with the tile's row terms staged in LDS: tab[r]
+// holds the EpiRow of tile row r (rows past M repeat the last row's terms),
+// so no store waits on a memory load.  The code is branch-free: an element
+// outside the matrix gets the out-of-range offset 0x80000000, which the
+// buffer store drops; branches around each store would make the compiler
+// wait for every store before the next (vector memory operations complete
+// in order and its wait analysis is conservative across branches).  mt0: the
+// tile's first row; ml: this wave's first row inside the tile.
+template <int FM, int FN>
+__device__ __forceinline__ void store_tile_tab(const v16f (&acc)[FM][FN], const GemmProb& p, float* C,
+                                               const EpiRow* tab, const EpiCol* __restrict__ cols, int mt0, int ml,
+                                               int nb, int h, int r32) {
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(C, static_cast<short>(0), 0x7fffffff, 0x00020000);
+    EpiCol cj[FN];
+    bool cok[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int col = nb + j * 32 + r32;
+        cok[j] = col < p.N;
+        cj[j] = cols[p.ci_off + (cok[j] ? col : 0)];
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int rl = ml + i * 32 + (q >> 2) * 8 + h * 4 + (q & 3);
+            const bool rok = mt0 + rl < p.M;
+            const EpiRow ri = tab[rl];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const uint32_t e = static_cast<uint32_t>(ri.r0 + cj[j].c0) +
+                                   __umul24(static_cast<uint32_t>(ri.r1), static_cast<uint32_t>(cj[j].c1)) +
+                                   __umul24(static_cast<uint32_t>(ri.r2), static_cast<uint32_t>(cj[j].c2));
+                const uint32_t vo = (rok && cok[j]) ? e * 4u : 0x80000000u;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[i][j][q]), rc, vo, 0, 0);
+            }
         }
 }
 
@@ -557,6 +598,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmProb* __restrict__ p
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
+        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const float* A = static_cast<const float*>(bufs.p[p.a_buf]) + p.a_off;
         const float* B = static_cast<const float*>(bufs.p[p.b_buf]) + p.b_off;
@@ -678,6 +720,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmProb* __restrict__ 
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
+        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
         const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
@@ -792,6 +835,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void k_gemm_bf16_big(const Gem
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
+        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
         const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
@@ -999,6 +1043,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmPr
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
+        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
         const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
@@ -1118,7 +1163,18 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmPr
             sw = sw + 1 == ST ? 0 : sw + 1;
         }
 
-        store_tile<FM, FN>(acc, p, C, rows, cols, m0 + wm * WM, n0 + wn * WN, h, r32);
+        if (p.indirect) {
+            // the stages are free once the trailing (all zero) slice loads
+            // have landed and every wave is past its last fragment reads
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            __builtin_amdgcn_s_barrier();
+            EpiRow* tab = reinterpret_cast<EpiRow*>(smem);
+            for (int r = tid; r < MT; r += NTHR) tab[r] = rows[p.ri_off + min(m0 + r, p.M - 1)];
+            __syncthreads();
+            store_tile_tab<FM, FN>(acc, p, C, tab, cols, m0, wm * WM, n0 + wn * WN, h, r32);
+        } else {
+            store_tile<FM, FN>(acc, p, C, rows, cols, m0 + wm * WM, n0 + wn * WN, h, r32);
+        }
     }
     // no load may still be writing LDS when the workgroup ends
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
@@ -1165,14 +1221,16 @@ int occupancy_dl() {
     X(12, 256, 256, 32, 2, 4, 5, 1)    \
     X(13, 256, 256, 32, 2, 4, 5, 2)    \
     X(14, 256, 256, 32, 2, 4, 5, 3)    \
-    X(15, 256, 256, 32, 2, 2, 5, 1)
+    X(15, 256, 256, 32, 2, 2, 5, 1)    \
+    X(16, 256, 256, 32, 2, 2, 5, 2)    \
+    X(17, 256, 256, 32, 2, 2, 5, 3)
 
-bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 15; }
+bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 17; }
 int gemm_direct_max_ld() { return kDlMaxLd; }
 
 // BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
 // grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel;
-// v9-v15 k_gemm_bf16_dl.
+// v9-v17 k_gemm_bf16_dl.
 #define SYM_BF16_BIG_VARIANTS(X)              \
     X(0, 256, 256, 64, 2, 2, 1, 4)            \
     X(1, 256, 128, 64, 2, 2, 1, 4)            \
@@ -1201,10 +1259,12 @@ const GemmVariant kBF16Variants[] = {{256, 256, "k_gemm_bf16_big 256x256 k64 4w"
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio interleaved"},
-                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"}};
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage interleaved"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio interleaved"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 3 : 16; }
+int gemm_num_variants(int compute) { return compute == 0 ? 3 : 18; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
 // Defaults from measurements on MI355X.  256x256 tiles (operand re-reads
 // beyond L2 fall with the tile size: 128x128 ran the 64-member batch at 406
