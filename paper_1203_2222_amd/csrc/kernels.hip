@@ -598,7 +598,6 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmProb* __restrict__ p
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
-        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const float* A = static_cast<const float*>(bufs.p[p.a_buf]) + p.a_off;
         const float* B = static_cast<const float*>(bufs.p[p.b_buf]) + p.b_off;
@@ -720,7 +719,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmProb* __restrict__ 
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
-        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
         const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
@@ -835,7 +833,6 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void k_gemm_bf16_big(const Gem
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
-        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
         const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;
@@ -1043,7 +1040,6 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmPr
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const GemmTile tile = tiles[t];
-        if (tile.prob < 0) continue;   // padding entry of the schedule
         const GemmProb p = probs[tile.prob];
         const uint16_t* A = static_cast<const uint16_t*>(bufs.p[p.a_buf]) + p.a_off;
         const uint16_t* B = static_cast<const uint16_t*>(bufs.p[p.b_buf]) + p.b_off;

@@ -446,65 +446,24 @@ void GemmProgram::finalize(int v, int grid) {
             for (int j = 0; j < tn; ++j)
                 for (int i = g0; i < std::min(tm, g0 + kGroupM); ++i) seq.push_back({pi, i, j, 0});
     }
-    // The persistent grid runs g workgroups; workgroup w sits on XCD w % 8 and
-    // takes entries w, w + g, ...  The entries are laid out so that XCD x runs
-    // a sequence S_x of its own, per = g / 8 entries per round, made of chunks
-    // of per consecutive tiles of seq: the tiles one XCD holds at a time then
-    // share A row panels and B column panels in its L2.
-    tiles.clear();
-    const int64_t g = std::max(8, grid - grid % 8), per = g / 8;
+    // The persistent grid runs `grid` workgroups; workgroup w sits on XCD
+    // w % 8 and takes tiles w, w + grid, ...  Give each XCD a contiguous run
+    // of the sequence per round, so that the tiles one XCD holds at a time
+    // share its L2.  (Putting the XCDs out of phase, so that they write their
+    // C tiles at different times, measured no faster.)
+    tiles.assign(seq.size(), GemmTile{});
+    const int64_t g = std::max(8, grid - grid % 8);
     const int64_t n = static_cast<int64_t>(seq.size());
-    if (n < 4 * g) {
-        // small problems: plain rounds, each XCD a contiguous run per round
-        tiles.assign(seq.size(), GemmTile{});
-        for (int64_t r0 = 0; r0 < n; r0 += g) {
-            const int64_t len = std::min(g, n - r0);
-            for (int64_t w = 0; w < len; ++w)
-                tiles[static_cast<size_t>(r0 + w)] =
-                    len < g ? seq[static_cast<size_t>(r0 + w)] : seq[static_cast<size_t>(r0 + (w % 8) * per + w / 8)];
+    const int64_t per = g / 8;
+    for (int64_t r0 = 0; r0 < n; r0 += g) {
+        const int64_t len = std::min(g, n - r0);
+        if (len < g) {
+            for (int64_t k = 0; k < len; ++k) tiles[static_cast<size_t>(r0 + k)] = seq[static_cast<size_t>(r0 + k)];
+            break;
         }
-        return;
+        for (int64_t w = 0; w < g; ++w)
+            tiles[static_cast<size_t>(r0 + w)] = seq[static_cast<size_t>(r0 + (w % 8) * per + w / 8)];
     }
-    // The XCDs are put out of phase: XCD x first runs chunks of the cheapest
-    // tiles (the end of seq) worth about x/8 of the costliest tile.  The XCDs
-    // then finish their tiles, and write their C tiles to memory, at
-    // different times instead of all at once.  The remaining chunks go in
-    // order to the XCD with the least work so far.
-    auto cost = [&](const GemmTile& t) { return (probs[static_cast<size_t>(t.prob)].K + 31) / 32 + 4; };
-    auto chunk_cost = [&](int64_t b, int64_t e) {
-        int64_t c = 0;
-        for (int64_t k = b; k < e; ++k) c = std::max<int64_t>(c, cost(seq[static_cast<size_t>(k)]));
-        return c;
-    };
-    const GemmTile pad{-1, 0, 0, 0};
-    std::vector<std::vector<GemmTile>> S(8);
-    std::vector<int64_t> load(8, 0);
-    const int64_t top = cost(seq[0]);
-    int64_t tail = n;
-    for (int x = 1; x < 8; ++x)
-        while (load[static_cast<size_t>(x)] * 8 < top * x && tail - per >= n / 2) {
-            load[static_cast<size_t>(x)] += chunk_cost(tail - per, tail);
-            S[static_cast<size_t>(x)].insert(S[static_cast<size_t>(x)].end(), seq.begin() + (tail - per), seq.begin() + tail);
-            tail -= per;
-        }
-    for (int64_t c0 = 0; c0 < tail; c0 += per) {
-        const int64_t c1 = std::min(tail, c0 + per);
-        const size_t x = static_cast<size_t>(std::min_element(load.begin(), load.end()) - load.begin());
-        load[x] += chunk_cost(c0, c1);
-        S[x].insert(S[x].end(), seq.begin() + c0, seq.begin() + c1);
-        S[x].resize(S[x].size() + static_cast<size_t>(per - (c1 - c0)), pad);
-    }
-    size_t rounds = 0;
-    for (const auto& sx : S) rounds = std::max(rounds, (sx.size() + static_cast<size_t>(per) - 1) / static_cast<size_t>(per));
-    tiles.assign(rounds * static_cast<size_t>(g), pad);
-    for (int x = 0; x < 8; ++x)
-        for (size_t k = 0; k < S[static_cast<size_t>(x)].size(); ++k) {
-            const size_t r = k / static_cast<size_t>(per), i = k % static_cast<size_t>(per);
-            tiles[r * static_cast<size_t>(g) + i * 8 + static_cast<size_t>(x)] = S[static_cast<size_t>(x)][k];
-        }
-    int64_t live = 0;
-    for (const GemmTile& t : tiles) live += t.prob >= 0;
-    if (live != n) throw Error(SYM_E_MISMATCH, "GEMM schedule lost tiles");
 }
 
 void GemmProgram::upload(const Allocator& alloc) {
