@@ -1217,16 +1217,14 @@ int occupancy_dl() {
     X(12, 256, 256, 32, 2, 4, 5, 1)    \
     X(13, 256, 256, 32, 2, 4, 5, 2)    \
     X(14, 256, 256, 32, 2, 4, 5, 3)    \
-    X(15, 256, 256, 32, 2, 2, 5, 1)    \
-    X(16, 256, 256, 32, 2, 2, 5, 2)    \
-    X(17, 256, 256, 32, 2, 2, 5, 3)
+    X(15, 256, 256, 32, 2, 2, 5, 1)
 
-bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 17; }
+bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 15; }
 int gemm_direct_max_ld() { return kDlMaxLd; }
 
 // BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
 // grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel;
-// v9-v17 k_gemm_bf16_dl.
+// v9-v15 k_gemm_bf16_dl.
 #define SYM_BF16_BIG_VARIANTS(X)              \
     X(0, 256, 256, 64, 2, 2, 1, 4)            \
     X(1, 256, 128, 64, 2, 2, 1, 4)            \
@@ -1255,12 +1253,10 @@ const GemmVariant kBF16Variants[] = {{256, 256, "k_gemm_bf16_big 256x256 k64 4w"
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio interleaved"},
-                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"},
-                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage interleaved"},
-                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio interleaved"}};
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 3 : 18; }
+int gemm_num_variants(int compute) { return compute == 0 ? 3 : 16; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
 // Defaults from measurements on MI355X.  256x256 tiles (operand re-reads
 // beyond L2 fall with the tile size: 128x128 ran the 64-member batch at 406
