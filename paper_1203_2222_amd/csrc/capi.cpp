@@ -64,6 +64,7 @@ struct ContractPlan {
     DevMemPtr ws_in, ws_out;
     int grid = 1;
     int64_t flops = 0;
+    int requested_variant = -1;   // the variant asked for (the GEMM may run a fallback)
 };
 
 struct BackwardPlan {
@@ -313,7 +314,8 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         auto it = ctx->contract_plans.find(key);
-        if (it != ctx->contract_plans.end() && variant_override < 0 && it->second->gemm.variant == pick_variant(ctx, compute, key))
+        if (it != ctx->contract_plans.end() && variant_override < 0 &&
+            it->second->requested_variant == pick_variant(ctx, compute, key))
             return it->second;
     }
     auto plan = std::make_shared<ContractPlan>();
@@ -356,6 +358,7 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
         }
     }
     const int var = variant_override >= 0 ? variant_override : pick_variant(ctx, compute, key);
+    plan->requested_variant = var;
     plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, var);
     plan->gemm.finalize(var, plan->grid);
     plan->flops = plan->gemm.flops;
