@@ -1555,7 +1555,9 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
 // permutation and tree change into the n output blocks.  The output's axis k
 // is the input's axis perm[k]; the host hands over the input strides already
 // in output-axis order, so the kernel only walks the output block row-major.
-// Threads run along the output's innermost axis.
+// Threads run along the output's innermost axis; a workgroup takes up to
+// kRecoupleChunk elements of one tuple, several per thread, so that the
+// tuple's metadata is read once for many elements.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks,
                                                   const FmBlk* __restrict__ out_blks, const double* __restrict__ coef,
@@ -1565,32 +1567,34 @@ __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ gr
     const FmGroup g = groups[t.group];
     const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
     float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
+    const FmBlk* __restrict__ ib = in_blks + g.in_first;
+    const FmBlk* __restrict__ ob = out_blks + g.out_first;
+    const double* __restrict__ c = coef + g.coef_first;
     const int n = g.n;
     const int d1 = g.d[1], d2 = g.d[2], d3 = g.d[3];
-    const int e = t.start + static_cast<int>(threadIdx.x);
-    if (e >= t.start + t.count) return;
-    int r = e / d3;
-    const int t3 = e - r * d3;
-    const int q = r / d2;
-    const int t2 = r - q * d2;
-    const int t0 = q / d1;
-    const int t1 = q - t0 * d1;
-    double x[kMaxRecouple];
-#pragma unroll
-    for (int i = 0; i < kMaxRecouple; ++i) {
-        if (i < n) {
-            const FmBlk b = in_blks[g.in_first + i];
-            x[i] = static_cast<double>(src[b.off + t0 * b.stride[0] + t1 * b.stride[1] + t2 * b.stride[2] + t3 * b.stride[3]]);
-        }
-    }
-    const double* c = coef + g.coef_first;
-    for (int f = 0; f < n; ++f) {
-        double y = 0.0;
+    auto rel = [](const FmBlk& b, int t0, int t1, int t2, int t3) {
+        return static_cast<uint32_t>(t0 * b.stride[0] + t1 * b.stride[1] + t2 * b.stride[2] + t3 * b.stride[3]);
+    };
+    const int end = t.start + t.count;
+    for (int e = t.start + static_cast<int>(threadIdx.x); e < end; e += 256) {
+        const int r = div_by(e, g.mag[3], g.shf[3]);
+        const int t3 = e - r * d3;
+        const int q = div_by(r, g.mag[2], g.shf[2]);
+        const int t2 = r - q * d2;
+        const int t0 = div_by(q, g.mag[1], g.shf[1]);
+        const int t1 = q - t0 * d1;
+        const uint32_t ri0 = rel(ib[0], t0, t1, t2, t3), ro0 = rel(ob[0], t0, t1, t2, t3);
+        double x[kMaxRecouple];
 #pragma unroll
         for (int i = 0; i < kMaxRecouple; ++i)
-            if (i < n) y = fma(c[f * n + i], x[i], y);
-        const FmBlk b = out_blks[g.out_first + f];
-        dst[b.off + t0 * b.stride[0] + t1 * b.stride[1] + t2 * b.stride[2] + t3 * b.stride[3]] = static_cast<float>(y);
+            if (i < n) x[i] = static_cast<double>(src[ib[i].off + (g.same_in ? ri0 : rel(ib[i], t0, t1, t2, t3))]);
+        for (int f = 0; f < n; ++f) {
+            double y = 0.0;
+#pragma unroll
+            for (int i = 0; i < kMaxRecouple; ++i)
+                if (i < n) y = fma(c[f * n + i], x[i], y);
+            dst[ob[f].off + (g.same_out ? ro0 : rel(ob[f], t0, t1, t2, t3))] = static_cast<float>(y);
+        }
     }
 }
 

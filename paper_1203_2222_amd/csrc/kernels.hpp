@@ -10,6 +10,7 @@ namespace sym {
 constexpr int kMaxBufs = 256;       // distinct base pointers one launch may address
 constexpr int kMaxCopyDims = 6;     // dims of a coalesced block copy
 constexpr int kMaxRecouple = 16;    // intermediate spins of one label tuple
+constexpr int kRecoupleChunk = 2048;   // elements of one label tuple per workgroup task
 
 // Base pointers of one launch, passed by value as a kernel argument.
 struct PtrTable {
@@ -101,16 +102,22 @@ struct GemmTile {
 struct FmGroup {
     int32_t n;
     int32_t d[4];        // block dims in output-axis order
+    uint32_t mag[4];     // division by d[k] for k = 1..3 (multiplier and shift,
+    int32_t shf[4];      // floor(x / d) = (x * mag) >> (31 + shf) for x < 2^31)
+    int32_t same_in;     // all input blocks share their strides
+    int32_t same_out;    // all output blocks share their strides
     int32_t in_first;    // index of its first FmBlk among inputs
     int32_t out_first;   // index of its first FmBlk among outputs
     int32_t coef_first;  // n*n coefficients, row f, column e
 };
 
 // Element strides of a block along the output's axes 0..3 (for an input
-// block: its stride along input axis perm[k]).
+// block: its stride along input axis perm[k]); every element of the block
+// lies below 2^31 elements from its first one.
 struct FmBlk {
     int64_t off;
-    int64_t stride[4];
+    int32_t stride[4];
+    int32_t pad[2];
 };
 
 struct FmTask {

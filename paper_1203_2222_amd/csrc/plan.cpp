@@ -40,13 +40,23 @@ DevMemPtr upload_vec(const Allocator& alloc, const std::vector<T>& v) {
 // against n / d is below n (m d - 2^(31+s)) / (d 2^(31+s)) < 2^-s <= 1/d, too
 // small to move the floor (round-up multiplier method, Granlund and
 // Montgomery, PLDI 1994).
-static void set_divisor(CopyOp& op, int d) {
-    const uint64_t v = static_cast<uint64_t>(std::max(1, op.size[d]));
+// Round-up multiplier m = ceil(2^(31+s) / v), s = ceil(log2 v): then
+// floor(x / v) = (x m) >> (31 + s) for every 0 <= x < 2^31.
+static void magic_divisor(int32_t divisor, uint32_t& mag, int32_t& shf) {
+    const uint64_t v = static_cast<uint64_t>(std::max(1, divisor));
     int s = 0;
     while ((uint64_t{1} << s) < v) ++s;
     const uint64_t m = ((uint64_t{1} << (31 + s)) + v - 1) / v;
     if (m >= (uint64_t{1} << 32)) throw Error(SYM_E_UNSUPPORTED, "division multiplier out of range");
-    op.mag[d] = static_cast<uint32_t>(m);
+    mag = static_cast<uint32_t>(m);
+    shf = s;
+}
+
+static void set_divisor(CopyOp& op, int d) {
+    uint32_t m;
+    int32_t s;
+    magic_divisor(op.size[d], m, s);
+    op.mag[d] = m;
     op.shf[d] = s;
 }
 
@@ -507,33 +517,48 @@ void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<i
         FmGroup g{};
         g.n = n;
         // output axis k is input axis perm[k]
-        for (int k = 0; k < 4; ++k) g.d[k] = static_cast<int32_t>(b0.shape[static_cast<size_t>(perm[k])]);
+        for (int k = 0; k < 4; ++k) {
+            g.d[k] = static_cast<int32_t>(b0.shape[static_cast<size_t>(perm[k])]);
+            magic_divisor(g.d[k], g.mag[k], g.shf[k]);
+        }
         g.in_first = static_cast<int32_t>(in_blks.size());
         g.out_first = static_cast<int32_t>(out_blks.size());
         g.coef_first = static_cast<int32_t>(coef.size());
+        // 32-bit element offsets inside a block
+        auto narrow = [&](const Block& b, const int32_t* axis) {
+            FmBlk fb{};
+            fb.off = b.offset;
+            int64_t span = 0;
+            for (int l = 0; l < 4; ++l) {
+                const int64_t st = b.stride[static_cast<size_t>(axis[l])];
+                span += (b.shape[static_cast<size_t>(axis[l])] - 1) * st;
+                if (st < 0 || st >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block stride beyond 32 bits");
+                fb.stride[l] = static_cast<int32_t>(st);
+            }
+            if (span >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block span beyond 32 bits");
+            return fb;
+        };
+        static const int32_t ident[4] = {0, 1, 2, 3};
+        g.same_in = g.same_out = 1;
         for (size_t k = i; k < j; ++k) {
             if (in.blocks[k].internal != es[k - i]) throw Error(SYM_E_MISMATCH, "input intermediate spins out of order");
-            FmBlk fb{};
-            fb.off = in.blocks[k].offset;
-            for (int l = 0; l < 4; ++l) fb.stride[l] = in.blocks[k].stride[static_cast<size_t>(perm[l])];
-            in_blks.push_back(fb);
+            in_blks.push_back(narrow(in.blocks[k], perm.data()));
+            for (int l = 0; l < 4; ++l) g.same_in &= in_blks.back().stride[l] == in_blks[static_cast<size_t>(g.in_first)].stride[l];
         }
         int32_t olab[4];
         for (int l = 0; l < 4; ++l) olab[l] = b0.labels[static_cast<size_t>(perm[l])];
         for (int32_t f : fs) {
             const int32_t oi = out.find_block(olab, f);
             if (oi < 0) throw Error(SYM_E_MISMATCH, "recoupled block missing from the output");
-            const Block& ob = out.blocks[static_cast<size_t>(oi)];
-            FmBlk fb{};
-            fb.off = ob.offset;
-            for (int l = 0; l < 4; ++l) fb.stride[l] = ob.stride[static_cast<size_t>(l)];
-            out_blks.push_back(fb);
+            out_blks.push_back(narrow(out.blocks[static_cast<size_t>(oi)], ident));
+            for (int l = 0; l < 4; ++l) g.same_out &= out_blks.back().stride[l] == out_blks[static_cast<size_t>(g.out_first)].stride[l];
         }
         coef.insert(coef.end(), gamma.begin(), gamma.end());
         const int64_t elems = b0.size;
-        for (int64_t s = 0; s < elems; s += 256)
+        if (elems >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block too large to recouple");
+        for (int64_t s = 0; s < elems; s += kRecoupleChunk)
             tasks.push_back({static_cast<int32_t>(groups.size()), static_cast<int32_t>(s),
-                             static_cast<int32_t>(std::min<int64_t>(256, elems - s)), 0});
+                             static_cast<int32_t>(std::min<int64_t>(kRecoupleChunk, elems - s)), 0});
         groups.push_back(g);
         i = j;
     }
