@@ -92,10 +92,10 @@ struct sym_tensor {
 // workspaces for the Jacobi vectors and rotations.
 struct SvdPlan {
     std::vector<SvdProb> probs;
-    std::vector<int32_t> pair_start;   // prefix sums of kp_s / 2
-    int32_t max_kp = 0;
+    std::vector<int32_t> pair_start;   // prefix sums of the block pairs per sector
+    int32_t max_kp = 0;                // largest (even) block count
     int64_t u_elems = 0, s_elems = 0, vt_elems = 0, w_elems = 0, q_elems = 0;
-    DevMemPtr d_probs, d_pairs, w, q, flag;
+    DevMemPtr d_probs, d_pairs, w, q, scale, flag;
     int32_t flag_host = 0;
 };
 
@@ -1059,9 +1059,11 @@ std::shared_ptr<SvdPlan> svd_plan_of(const Desc& d) {
     }
     plan->pair_start.push_back(0);
     for (const SvdProb& p : plan->probs) {
-        const int32_t kp = p.k + (p.k & 1);
-        plan->pair_start.push_back(plan->pair_start.back() + kp / 2);
-        plan->max_kp = std::max(plan->max_kp, kp);
+        // block pairs of the block-Jacobi rounds: blocks of kSvdBlock vectors,
+        // their count rounded up to even
+        const int32_t nb = (p.k + kSvdBlock - 1) / kSvdBlock, nbp = nb + (nb & 1);
+        plan->pair_start.push_back(plan->pair_start.back() + nbp / 2);
+        plan->max_kp = std::max(plan->max_kp, nbp);
     }
     return plan;
 }
@@ -1106,6 +1108,7 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
                 plan->w = alloc(static_cast<size_t>(plan->w_elems) * sizeof(double));
                 plan->q = alloc(static_cast<size_t>(plan->q_elems) * sizeof(double));
                 plan->flag = alloc(sizeof(int32_t));
+                plan->scale = alloc(plan->probs.size() * sizeof(double));
             }
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->svd_plans[key] = plan;
@@ -1115,7 +1118,8 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
         HIP_CHECK(launch_svd(T->d->dtype, T->data, static_cast<const SvdProb*>(plan->d_probs->ptr),
                              static_cast<const int32_t*>(plan->d_pairs->ptr), static_cast<int32_t>(plan->probs.size()),
                              plan->pair_start.back(), plan->max_kp, static_cast<double*>(plan->w->ptr),
-                             static_cast<double*>(plan->q->ptr), U, S, Vt, static_cast<int32_t*>(plan->flag->ptr),
+                             static_cast<double*>(plan->q->ptr), U, S, Vt, static_cast<double*>(plan->scale->ptr),
+                             static_cast<int32_t*>(plan->flag->ptr),
                              &plan->flag_host, max_sweeps, &done, static_cast<hipStream_t>(stream)));
         if (sweeps) *sweeps = done;
     });

@@ -1329,9 +1329,10 @@ hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const Ge
 // orthogonalised pairwise by plane rotations, the same rotations accumulate
 // in Q; at convergence the vector norms are the singular values, the
 // normalised vectors one set of singular vectors and Q the other.  A sweep
-// is a sequence of rounds of the round-robin (circle) schedule; one launch
-// runs one round of every sector at once (one wave per pair, disjoint pairs),
-// so the launch boundary orders the rounds and the whole GPU works on them.
+// is a sequence of rounds of the round-robin (circle) schedule over blocks of
+// vectors; one launch runs one round of every sector at once (one workgroup
+// per pair of blocks, disjoint pairs), so the launch boundary orders the
+// rounds and the whole GPU works on them.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ double as_f64(T x);
@@ -1350,103 +1351,247 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ int rr_player(int j, int r, int kp) { return j == 0 ? 0 : 1 + (j - 1 + r) % (kp - 1); }
 
 // vectors in FP64 (rows of the sector matrix, or its columns) and Q = I
+// and each sector's squared Frobenius norm (scale[s], cleared beforehand; the
+// rotations keep it)
 template <typename Ti>
 __global__ __launch_bounds__(256) void k_svd_load(const Ti* __restrict__ src, const SvdProb* __restrict__ probs,
-                                                   double* __restrict__ Wg, double* __restrict__ Qg) {
+                                                   double* __restrict__ Wg, double* __restrict__ Qg,
+                                                   double* __restrict__ scale) {
+    __shared__ double part[4];
     const SvdProb p = probs[blockIdx.y];
     const int64_t nw = static_cast<int64_t>(p.k) * p.L, nq = static_cast<int64_t>(p.k) * p.k;
+    double ss = 0.0;
     for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < nw + nq; idx += static_cast<int64_t>(gridDim.x) * 256) {
         if (idx < nw) {
             const int j = static_cast<int>(idx / p.L), x = static_cast<int>(idx - static_cast<int64_t>(j) * p.L);
             const int64_t e =
                 p.rows_are_vectors ? static_cast<int64_t>(j) * p.ld + x : static_cast<int64_t>(x) * p.ld + j;
-            Wg[p.w_off + idx] = as_f64(src[p.src_off + e]);
+            const double v = as_f64(src[p.src_off + e]);
+            Wg[p.w_off + idx] = v;
+            ss = fma(v, v, ss);
         } else {
             const int64_t q = idx - nw;
             Qg[p.q_off + q] = (q / p.k == q % p.k) ? 1.0 : 0.0;
         }
     }
+    ss = wave_sum(ss);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&scale[blockIdx.y], part[0] + part[1] + part[2] + part[3]);
 }
 
-// round r of the current sweep for every sector; pair_start[s] is the number
-// of pairs (kp_s / 2) of the sectors before s
-__global__ __launch_bounds__(256) void k_svd_round(const SvdProb* __restrict__ probs, int n_probs,
-                                                    const int32_t* __restrict__ pair_start, int r,
-                                                    double* __restrict__ Wg, double* __restrict__ Qg,
-                                                    int32_t* __restrict__ rotated) {
-    const int lane = threadIdx.x & 63;
-    const int pid = blockIdx.x * 4 + (threadIdx.x >> 6);
+// One round of block Jacobi over every sector: the vectors of a sector form blocks
+// of kSvdBlock; a workgroup takes one pair of blocks (2b vectors, round-robin
+// schedule over the blocks) and
+//   1. forms their Gram matrix G (2b x 2b) in FP64, streaming the vectors
+//      through LDS in chunks of 4096 / 2b entries (16 loads in flight per
+//      thread);
+//   2. diagonalises G, or nearly (at most three sweeps), by cyclic two-sided
+//      Jacobi in LDS (b disjoint plane rotations per step, the same rotation
+//      as the one-sided method's, accumulated in V);
+//   3. replaces the 2b vectors, and their 2b rows of Q, by their products
+//      with V.
+// The vectors are read twice and written once per round instead of once per
+// scalar round, and a sweep has nb - 1 rounds instead of k - 1.  The sweep
+// counts as converged for the pair when the first Jacobi sweep on G finds
+// every off-diagonal entry below 1e-15 of the geometric mean of its diagonal
+// entries (the one-sided method's test).  Vectors past k are zero and are
+// never written.
+__global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ probs, int n_probs,
+                                                     const int32_t* __restrict__ pair_start, int r,
+                                                     double* __restrict__ Wg, double* __restrict__ Qg,
+                                                     const double* __restrict__ scale,
+                                                     int32_t* __restrict__ rotated) {
+    constexpr int B = kSvdBlock, B2 = 2 * B, NP = B2 / 2;
+    constexpr int XC = 4096 / B2;              // chunk entries: 16 loads per thread
+    constexpr int NB4 = B2 / 4;                // 4 x 4 blocks of G per row
+    constexpr int LPB = 256 / (NB4 * NB4);     // lanes that share one block of G
+    constexpr int JW = B2 / 4;                 // new vectors per wave in the update
+    static_assert((B2 == 16 || B2 == 32) && LPB >= 1 && (LPB & (LPB - 1)) == 0 && XC % LPB == 0 && XC % 64 == 0,
+                  "thread roles below assume 16 or 32 vectors per block pair");
+    __shared__ double T[B2][XC + 1];
+    __shared__ double G[B2][B2 + 1];
+    __shared__ double V[B2][B2 + 1];
+    __shared__ double cs[NP][2];
+    __shared__ int s_rot, s_any;
+    const int tid = static_cast<int>(threadIdx.x);
+    const int pid = static_cast<int>(blockIdx.x);
     if (pid >= pair_start[n_probs]) return;
-    int lo = 0, hi = n_probs - 1;   // sector of this pair
+    int lo = 0, hi = n_probs - 1;   // sector of this block pair
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (pair_start[mid] <= pid) lo = mid;
         else hi = mid - 1;
     }
     const SvdProb p = probs[lo];
-    const int k = p.k, L = p.L, kp = k + (k & 1);
-    if (k < 2 || r >= kp - 1) return;
+    const int k = p.k, L = p.L;
+    const int nb = (k + B - 1) / B, nbp = nb + (nb & 1);
+    if (k < 2 || r >= nbp - 1) return;
     const int pi = pid - pair_start[lo];
-    const int a = rr_player(pi, r, kp), b = rr_player(kp - 1 - pi, r, kp);
-    if (a >= k || b >= k) return;
-    const int pp = a < b ? a : b, qq = a < b ? b : a;
-    double* wp = Wg + p.w_off + static_cast<int64_t>(pp) * L;
-    double* wq = Wg + p.w_off + static_cast<int64_t>(qq) * L;
-    // vectors of up to 64 * kRegs elements stay in registers between the
-    // dot products and the rotation (one read and one write of each)
-    constexpr int kRegs = 32;
-    double ub[kRegs], vb[kRegs];
-    const bool in_regs = L <= 64 * kRegs;
-    double al = 0.0, be = 0.0, ga = 0.0;
-    if (in_regs) {
+    const int P = rr_player(pi, r, nbp), Qb = rr_player(nbp - 1 - pi, r, nbp);
+    auto col = [&](int i) { return i < B ? P * B + i : Qb * B + (i - B); };
+    double* W = Wg + p.w_off;
+    double* Qm = Qg + p.q_off;
+    // pairs whose inner product is below 1e-30 of the sector's squared norm
+    // are left alone: rotating them moves no singular value by more than
+    // 1e-15 of the largest, and vectors that tend to zero (rank deficiency)
+    // would otherwise keep rotating on rounding noise
+    const double floor_abs = 1e-30 * scale[lo];
+
+    // 1. Gram matrix: thread (blk, xl) sums a 4 x 4 block of G over the chunk
+    //    entries xl, xl + LPB, xl + 2 LPB, ...; the LPB partial sums of a block
+    //    sit in LPB consecutive lanes
+    const int blk = tid / LPB, xl = tid % LPB, I4 = (blk / NB4) * 4, J4 = (blk % NB4) * 4;
+    double acc[4][4];
 #pragma unroll
-        for (int i = 0; i < kRegs; ++i) {
-            const int x = lane + 64 * i;
-            ub[i] = x < L ? wp[x] : 0.0;
-            vb[i] = x < L ? wq[x] : 0.0;
-            al = fma(ub[i], ub[i], al);
-            be = fma(vb[i], vb[i], be);
-            ga = fma(ub[i], vb[i], ga);
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    // a chunk: NL loads per thread, all issued before the first LDS write
+    constexpr int NL = B2 * XC / 256;
+    auto stage = [&](const double* base, int Lx, int x0) {
+        double v[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int idx = tid + 256 * u, i = idx / XC, xx = idx - i * XC;
+            const int c = col(i), x = x0 + xx;
+            v[u] = (c < k && x < Lx) ? base[static_cast<int64_t>(c) * Lx + x] : 0.0;
         }
-    } else {
-        for (int x = lane; x < L; x += 64) {
-            const double u = wp[x], v = wq[x];
-            al = fma(u, u, al);
-            be = fma(v, v, be);
-            ga = fma(u, v, ga);
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int idx = tid + 256 * u, i = idx / XC, xx = idx - i * XC;
+            T[i][xx] = v[u];
         }
+    };
+    for (int x0 = 0; x0 < L; x0 += XC) {
+        stage(W, L, x0);
+        __syncthreads();
+#pragma unroll 4
+        for (int u = 0; u < XC / LPB; ++u) {
+            const int xx = xl + LPB * u;
+            double va[4], vb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) va[a] = T[I4 + a][xx];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vb[b] = T[J4 + b][xx];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(va[a], vb[b], acc[a][b]);
+        }
+        __syncthreads();
     }
-    al = wave_sum(al);
-    be = wave_sum(be);
-    ga = wave_sum(ga);
-    if (fabs(ga) <= 1e-15 * sqrt(al * be)) return;
-    const double zeta = (be - al) / (2.0 * ga);
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-    if (in_regs) {
 #pragma unroll
-        for (int i = 0; i < kRegs; ++i) {
-            const int x = lane + 64 * i;
-            if (x < L) {
-                wp[x] = c * ub[i] - sn * vb[i];
-                wq[x] = sn * ub[i] + c * vb[i];
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            double v = acc[a][b];
+#pragma unroll
+            for (int o = LPB / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            acc[a][b] = v;
+        }
+    if (xl == 0)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) G[I4 + a][J4 + b] = acc[a][b];
+    for (int idx = tid; idx < B2 * B2; idx += 256) V[idx / B2][idx % B2] = (idx / B2 == idx % B2) ? 1.0 : 0.0;
+    if (tid == 0) s_any = 0;
+    __syncthreads();
+
+    // 2. cyclic Jacobi on G: step r2 rotates the NP disjoint pairs of the
+    //    circle schedule over the 16 indices.  With the rotations R_m of the
+    //    pairs, every 2 x 2 block (m1, m2) of G becomes R_m1^T G R_m2 and the
+    //    columns of V of pair m become V R_m: one phase, disjoint entries.
+    //    At most kInner sweeps: the outer sweeps finish the job.
+    constexpr int kInner = 3;
+    for (int sweep = 0; sweep < kInner; ++sweep) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int r2 = 0; r2 < B2 - 1; ++r2) {
+            if (tid < NP) {
+                const int a = rr_player(tid, r2, B2), b = rr_player(B2 - 1 - tid, r2, B2);
+                const int pp = a < b ? a : b, qq = a < b ? b : a;
+                const double al = G[pp][pp], be = G[qq][qq], ga = G[pp][qq];
+                double c = 1.0, sn = 0.0;
+                if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(fabs(al * be)) && fabs(ga) > floor_abs) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    sn = c * t;
+                    s_rot = 1;
+                }
+                cs[tid][0] = c;
+                cs[tid][1] = sn;
             }
+            __syncthreads();
+            for (int it = tid; it < NP * NP + B2 * NP; it += 256) {
+              if (it < NP * NP) {
+                const int m1 = it / NP, m2 = it - m1 * NP;
+                const int a1 = rr_player(m1, r2, B2), b1 = rr_player(B2 - 1 - m1, r2, B2);
+                const int a2 = rr_player(m2, r2, B2), b2 = rr_player(B2 - 1 - m2, r2, B2);
+                const int p1 = a1 < b1 ? a1 : b1, q1 = a1 < b1 ? b1 : a1;
+                const int p2 = a2 < b2 ? a2 : b2, q2 = a2 < b2 ? b2 : a2;
+                const double c1 = cs[m1][0], s1 = cs[m1][1], c2 = cs[m2][0], s2 = cs[m2][1];
+                const double g11 = G[p1][p2], g12 = G[p1][q2], g21 = G[q1][p2], g22 = G[q1][q2];
+                const double t11 = c1 * g11 - s1 * g21, t12 = c1 * g12 - s1 * g22;   // R1^T G
+                const double t21 = s1 * g11 + c1 * g21, t22 = s1 * g12 + c1 * g22;
+                G[p1][p2] = c2 * t11 - s2 * t12;                                      // (R1^T G) R2
+                G[p1][q2] = s2 * t11 + c2 * t12;
+                G[q1][p2] = c2 * t21 - s2 * t22;
+                G[q1][q2] = s2 * t21 + c2 * t22;
+              } else {
+                const int item = it - NP * NP, i = item / NP, m = item - i * NP;
+                const int a = rr_player(m, r2, B2), b = rr_player(B2 - 1 - m, r2, B2);
+                const int pp = a < b ? a : b, qq = a < b ? b : a;
+                const double c = cs[m][0], sn = cs[m][1];
+                const double vp = V[i][pp], vq = V[i][qq];
+                V[i][pp] = c * vp - sn * vq;
+                V[i][qq] = sn * vp + c * vq;
+              }
+            }
+            __syncthreads();
         }
-    } else {
-        for (int x = lane; x < L; x += 64) {
-            const double u = wp[x], v = wq[x];
-            wp[x] = c * u - sn * v;
-            wq[x] = sn * u + c * v;
+        const int rot = s_rot;
+        if (tid == 0 && rot) {
+            s_any = 1;
+            if (sweep == 0) rotated[0] = 1;
+        }
+        __syncthreads();
+        if (!rot) break;
+    }
+    if (!s_any) return;
+
+    // 3. vectors and rows of Q times V: thread (wave w, lane) makes entries
+    //    x0 + lane + 64 v of the new vectors JW w .. JW w + JW - 1
+    const int lane = tid & 63, j0 = (tid >> 6) * JW;
+    for (int pass = 0; pass < 2; ++pass) {
+        double* base = pass == 0 ? W : Qm;
+        const int Lx = pass == 0 ? L : k;
+        for (int x0 = 0; x0 < Lx; x0 += XC) {
+            stage(base, Lx, x0);
+            __syncthreads();
+            for (int v = 0; v < XC / 64; ++v) {
+                const int xx = lane + 64 * v;
+                double y[JW];
+#pragma unroll
+                for (int u = 0; u < JW; ++u) y[u] = 0.0;
+#pragma unroll
+                for (int i = 0; i < B2; ++i) {
+                    const double t = T[i][xx];
+#pragma unroll
+                    for (int u = 0; u < JW; ++u) y[u] = fma(t, V[i][j0 + u], y[u]);
+                }
+                const int x = x0 + xx;
+#pragma unroll
+                for (int u = 0; u < JW; ++u) {
+                    const int c = col(j0 + u);
+                    if (c < k && x < Lx) base[static_cast<int64_t>(c) * Lx + x] = y[u];
+                }
+            }
+            __syncthreads();
         }
     }
-    double* qp = Qg + p.q_off + static_cast<int64_t>(pp) * k;
-    double* qv = Qg + p.q_off + static_cast<int64_t>(qq) * k;
-    for (int x = lane; x < k; x += 64) {
-        const double u = qp[x], v = qv[x];
-        qp[x] = c * u - sn * v;
-        qv[x] = sn * u + c * v;
-    }
-    if (lane == 0) rotated[0] = 1;
 }
 
 // norms, descending order (bitonic sort in LDS) and the outputs; one
@@ -1517,23 +1662,28 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 
 hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
-                      double* Vt, int32_t* flag, int32_t* flag_host, int32_t max_sweeps, int32_t* sweeps_done,
-                      hipStream_t s) {
+                      double* Vt, double* scale, int32_t* flag, int32_t* flag_host, int32_t max_sweeps,
+                      int32_t* sweeps_done, hipStream_t s) {
     if (n_probs <= 0) return hipSuccess;
     dim3 lgrid(256, static_cast<unsigned>(n_probs));
+    hipLaunchKernelGGL(k_fill_i32, dim3(static_cast<unsigned>((2 * n_probs + 63) / 64)), dim3(64), 0, s,
+                       reinterpret_cast<int32_t*>(scale), 2 * n_probs, 0);
     if (src_dtype == 0)
-        hipLaunchKernelGGL((k_svd_load<float>), lgrid, dim3(256), 0, s, static_cast<const float*>(src), probs, W, Q);
+        hipLaunchKernelGGL((k_svd_load<float>), lgrid, dim3(256), 0, s, static_cast<const float*>(src), probs, W, Q,
+                           scale);
     else
         hipLaunchKernelGGL((k_svd_load<uint16_t>), lgrid, dim3(256), 0, s, static_cast<const uint16_t*>(src), probs, W,
-                           Q);
+                           Q, scale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int sweep = 0;
-    const unsigned rgrid = static_cast<unsigned>((n_pairs + 3) / 4);
+    // pair_start counts block pairs; max_kp is the largest (even) block count
+    const unsigned rgrid = static_cast<unsigned>(n_pairs);
     while (sweep < max_sweeps && max_kp > 1 && rgrid > 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flag, 1, 0);
         for (int r = 0; r < max_kp - 1; ++r)
-            hipLaunchKernelGGL(k_svd_round, dim3(rgrid), dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, flag);
+            hipLaunchKernelGGL(k_svd_bround, dim3(rgrid), dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, scale,
+                               flag);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         ++sweep;
