@@ -340,6 +340,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM autotuner (use the default variant)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the per-configuration measurements")
+    ap.add_argument("--secondary-only", action="store_true",
+                    help="only the per-configuration measurements (one JSON line of them; for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -365,6 +367,11 @@ def main():
         log("calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
     ctx = P.Context()
+    if args.secondary_only:
+        stream = torch.cuda.Stream()
+        log("per-configuration measurements only")
+        print(json.dumps({"per_config": secondary(ctx, stream, with_cpu=not args.no_cpu_baseline)}), flush=True)
+        return
     members = W.config3_members(args.members)
     axes = (members[0].axes_a, members[0].axes_b)
     log(f"building batch of {len(members)} members (BF16 inputs, FP32 outputs)")
