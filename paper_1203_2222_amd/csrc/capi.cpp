@@ -95,7 +95,7 @@ struct SvdPlan {
     std::vector<int32_t> pair_start;   // prefix sums of the block pairs per sector
     int32_t max_kp = 0;                // largest (even) block count
     int64_t u_elems = 0, s_elems = 0, vt_elems = 0, w_elems = 0, q_elems = 0;
-    DevMemPtr d_probs, d_pairs, w, q, scale, flag;
+    DevMemPtr d_probs, d_pairs, w, q, scale, gpart, flag;
     int32_t flag_host = 0;
 };
 
@@ -1109,6 +1109,8 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
                 plan->q = alloc(static_cast<size_t>(plan->q_elems) * sizeof(double));
                 plan->flag = alloc(sizeof(int32_t));
                 plan->scale = alloc(plan->probs.size() * sizeof(double));
+                plan->gpart = alloc(static_cast<size_t>(std::max<int32_t>(1, plan->pair_start.back())) * kSvdSlices *
+                                    (4 * kSvdBlock * kSvdBlock) * sizeof(double));
             }
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->svd_plans[key] = plan;
@@ -1119,6 +1121,7 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
                              static_cast<const int32_t*>(plan->d_pairs->ptr), static_cast<int32_t>(plan->probs.size()),
                              plan->pair_start.back(), plan->max_kp, static_cast<double*>(plan->w->ptr),
                              static_cast<double*>(plan->q->ptr), U, S, Vt, static_cast<double*>(plan->scale->ptr),
+                             static_cast<double*>(plan->gpart->ptr),
                              static_cast<int32_t*>(plan->flag->ptr),
                              &plan->flag_host, max_sweeps, &done, static_cast<hipStream_t>(stream)));
         if (sweeps) *sweeps = done;

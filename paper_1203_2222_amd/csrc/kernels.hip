@@ -1386,21 +1386,30 @@ __global__ __launch_bounds__(256) void k_svd_load(const Ti* __restrict__ src, co
 //   1. forms their Gram matrix G (2b x 2b) in FP64, streaming the vectors
 //      through LDS in chunks of 4096 / 2b entries (16 loads in flight per
 //      thread);
-//   2. diagonalises G, or nearly (at most three sweeps), by cyclic two-sided
-//      Jacobi in LDS (b disjoint plane rotations per step, the same rotation
-//      as the one-sided method's, accumulated in V);
+//   2. makes one sweep of cyclic two-sided Jacobi on G in LDS (b disjoint
+//      plane rotations per step, the same rotation as the one-sided
+//      method's, accumulated in V);
 //   3. replaces the 2b vectors, and their 2b rows of Q, by their products
 //      with V.
 // The vectors are read twice and written once per round instead of once per
 // scalar round, and a sweep has nb - 1 rounds instead of k - 1.  The sweep
-// counts as converged for the pair when the first Jacobi sweep on G finds
+// counts as converged for the pair when the Jacobi sweep on G finds
 // every off-diagonal entry below 1e-15 of the geometric mean of its diagonal
 // entries (the one-sided method's test).  Vectors past k are zero and are
 // never written.
+// A round is two launches over (block pair, slice), with kSvdSlices slices of
+// the vector entries per pair: PHASE 0 writes each slice's partial Gram
+// matrix to Gpart; PHASE 1 sums the partials in a fixed order (every slice
+// gets the same G, so results do not depend on scheduling), makes the small
+// Jacobi sweep and updates its slice of the vectors and of Q.  Two launches
+// of one slice each measured faster than one launch doing both phases (and
+// than four slices, or more inner sweeps per round) on the largest SVD
+// workload.
+template <int PHASE>
 __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ probs, int n_probs,
                                                      const int32_t* __restrict__ pair_start, int r,
                                                      double* __restrict__ Wg, double* __restrict__ Qg,
-                                                     const double* __restrict__ scale,
+                                                     const double* __restrict__ scale, double* __restrict__ Gpart,
                                                      int32_t* __restrict__ rotated) {
     constexpr int B = kSvdBlock, B2 = 2 * B, NP = B2 / 2;
     constexpr int XC = 4096 / B2;              // chunk entries: 16 loads per thread
@@ -1415,7 +1424,8 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
     __shared__ double cs[NP][2];
     __shared__ int s_rot, s_any;
     const int tid = static_cast<int>(threadIdx.x);
-    const int pid = static_cast<int>(blockIdx.x);
+    const int pid = static_cast<int>(blockIdx.x), slice = static_cast<int>(blockIdx.y);
+    constexpr int S = kSvdSlices;
     if (pid >= pair_start[n_probs]) return;
     int lo = 0, hi = n_probs - 1;   // sector of this block pair
     while (lo < hi) {
@@ -1437,6 +1447,14 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
     // 1e-15 of the largest, and vectors that tend to zero (rank deficiency)
     // would otherwise keep rotating on rounding noise
     const double floor_abs = 1e-30 * scale[lo];
+    // this slice's entries of the vectors (length L) and of the rows of Q
+    // (length k), whole chunks each
+    auto span = [&](int len, int& a, int& b) {
+        const int per = ((len + S - 1) / S + XC - 1) / XC * XC;
+        a = min(len, slice * per);
+        b = min(len, a + per);
+    };
+    double* Gp = Gpart + static_cast<int64_t>(pid) * S * (B2 * B2);
 
     // 1. Gram matrix: thread (blk, xl) sums a 4 x 4 block of G over the chunk
     //    entries xl, xl + LPB, xl + 2 LPB, ...; the LPB partial sums of a block
@@ -1449,13 +1467,13 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
     // a chunk: NL loads per thread, all issued before the first LDS write
     constexpr int NL = B2 * XC / 256;
-    auto stage = [&](const double* base, int Lx, int x0) {
+    auto stage = [&](const double* base, int Lx, int x0, int xend) {
         double v[NL];
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
             const int idx = tid + 256 * u, i = idx / XC, xx = idx - i * XC;
             const int c = col(i), x = x0 + xx;
-            v[u] = (c < k && x < Lx) ? base[static_cast<int64_t>(c) * Lx + x] : 0.0;
+            v[u] = (c < k && x < xend) ? base[static_cast<int64_t>(c) * Lx + x] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
@@ -1463,8 +1481,10 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
             T[i][xx] = v[u];
         }
     };
-    for (int x0 = 0; x0 < L; x0 += XC) {
-        stage(W, L, x0);
+    int xa, xb;
+    span(L, xa, xb);
+    for (int x0 = xa; x0 < (PHASE == 0 ? xb : xa); x0 += XC) {
+        stage(W, L, x0, xb);
         __syncthreads();
 #pragma unroll 4
         for (int u = 0; u < XC / LPB; ++u) {
@@ -1490,12 +1510,20 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
             for (int o = LPB / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
             acc[a][b] = v;
         }
-    if (xl == 0)
+    if constexpr (PHASE == 0) {
+        if (xl == 0)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) G[I4 + a][J4 + b] = acc[a][b];
-    for (int idx = tid; idx < B2 * B2; idx += 256) V[idx / B2][idx % B2] = (idx / B2 == idx % B2) ? 1.0 : 0.0;
+                for (int b = 0; b < 4; ++b) Gp[slice * (B2 * B2) + (I4 + a) * B2 + J4 + b] = acc[a][b];
+        return;
+    }
+    for (int idx = tid; idx < B2 * B2; idx += 256) {
+        double g = 0.0;
+        for (int sl = 0; sl < S; ++sl) g += Gp[sl * (B2 * B2) + idx];
+        G[idx / B2][idx % B2] = g;
+        V[idx / B2][idx % B2] = (idx / B2 == idx % B2) ? 1.0 : 0.0;
+    }
     if (tid == 0) s_any = 0;
     __syncthreads();
 
@@ -1503,8 +1531,8 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
     //    circle schedule over the 16 indices.  With the rotations R_m of the
     //    pairs, every 2 x 2 block (m1, m2) of G becomes R_m1^T G R_m2 and the
     //    columns of V of pair m become V R_m: one phase, disjoint entries.
-    //    At most kInner sweeps: the outer sweeps finish the job.
-    constexpr int kInner = 3;
+    //    One sweep per round: the outer sweeps finish the job.
+    constexpr int kInner = 1;
     for (int sweep = 0; sweep < kInner; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
@@ -1555,7 +1583,7 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
         const int rot = s_rot;
         if (tid == 0 && rot) {
             s_any = 1;
-            if (sweep == 0) rotated[0] = 1;
+            if (sweep == 0 && slice == 0) rotated[0] = 1;
         }
         __syncthreads();
         if (!rot) break;
@@ -1568,8 +1596,10 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
     for (int pass = 0; pass < 2; ++pass) {
         double* base = pass == 0 ? W : Qm;
         const int Lx = pass == 0 ? L : k;
-        for (int x0 = 0; x0 < Lx; x0 += XC) {
-            stage(base, Lx, x0);
+        int ua, ub;
+        span(Lx, ua, ub);
+        for (int x0 = ua; x0 < ub; x0 += XC) {
+            stage(base, Lx, x0, ub);
             __syncthreads();
             for (int v = 0; v < XC / 64; ++v) {
                 const int xx = lane + 64 * v;
@@ -1586,7 +1616,7 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
 #pragma unroll
                 for (int u = 0; u < JW; ++u) {
                     const int c = col(j0 + u);
-                    if (c < k && x < Lx) base[static_cast<int64_t>(c) * Lx + x] = y[u];
+                    if (c < k && x < ub) base[static_cast<int64_t>(c) * Lx + x] = y[u];
                 }
             }
             __syncthreads();
@@ -1662,8 +1692,8 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 
 hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
-                      double* Vt, double* scale, int32_t* flag, int32_t* flag_host, int32_t max_sweeps,
-                      int32_t* sweeps_done, hipStream_t s) {
+                      double* Vt, double* scale, double* Gpart, int32_t* flag, int32_t* flag_host,
+                      int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s) {
     if (n_probs <= 0) return hipSuccess;
     dim3 lgrid(256, static_cast<unsigned>(n_probs));
     hipLaunchKernelGGL(k_fill_i32, dim3(static_cast<unsigned>((2 * n_probs + 63) / 64)), dim3(64), 0, s,
@@ -1678,12 +1708,15 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
     if (e != hipSuccess) return e;
     int sweep = 0;
     // pair_start counts block pairs; max_kp is the largest (even) block count
-    const unsigned rgrid = static_cast<unsigned>(n_pairs);
-    while (sweep < max_sweeps && max_kp > 1 && rgrid > 0) {
+    const dim3 rgrid(static_cast<unsigned>(n_pairs), kSvdSlices);
+    while (sweep < max_sweeps && max_kp > 1 && n_pairs > 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flag, 1, 0);
-        for (int r = 0; r < max_kp - 1; ++r)
-            hipLaunchKernelGGL(k_svd_bround, dim3(rgrid), dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, scale,
+        for (int r = 0; r < max_kp - 1; ++r) {
+            hipLaunchKernelGGL(k_svd_bround<0>, rgrid, dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, scale, Gpart,
                                flag);
+            hipLaunchKernelGGL(k_svd_bround<1>, rgrid, dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, scale, Gpart,
+                               flag);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         ++sweep;

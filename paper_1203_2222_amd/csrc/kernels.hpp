@@ -166,12 +166,13 @@ struct SvdProb {
 };
 constexpr int kSvdMaxK = 4096;    // k sorted in LDS
 constexpr int kSvdBlock = 8;      // vectors per block of the block-Jacobi rounds
+constexpr int kSvdSlices = 1;     // workgroups per pair of blocks (slices of the vector entries)
 // Jacobi sweeps until one rotates nothing or max_sweeps; synchronises the
 // stream once per sweep (the stopping decision is taken on the host).
 hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
-                      double* Vt, double* scale, int32_t* flag, int32_t* flag_host, int32_t max_sweeps,
-                      int32_t* sweeps_done, hipStream_t s);
+                      double* Vt, double* scale, double* Gpart, int32_t* flag, int32_t* flag_host,
+                      int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s);
 
 // Resident workgroups per CU of a variant (persistent grid sizing).
 int gemm_blocks_per_cu(int compute, int variant);
