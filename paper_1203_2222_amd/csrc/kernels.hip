@@ -382,13 +382,11 @@ template <typename Ti, typename To>
 hipError_t launch_tv(const CopyOp* ops, const TileTask* tasks, int32_t n_tasks, int32_t n_wg, const PtrTable& bufs,
                      hipStream_t s) {
     constexpr size_t lds = TransposeShape<Ti>::lds_bytes;
-    static bool configured = false;
-    if (!configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transpose_vec<Ti, To>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-        configured = true;
-    }
+    // once per process (a thread-safe static initialisation)
+    static const hipError_t configured =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transpose_vec<Ti, To>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (configured != hipSuccess) return configured;
     hipLaunchKernelGGL((k_transpose_vec<Ti, To>), dim3(static_cast<unsigned>(n_wg)), dim3(256), lds, s, ops, tasks,
                        n_tasks, bufs);
     return hipGetLastError();
@@ -928,13 +926,11 @@ template <int MT, int NT, int KT, int WGM, int WGN, int OCC, int SA>
 hipError_t launch_big(const GemmProb* probs, const GemmTile* tiles, int32_t n_tiles, int32_t grid,
                       const EpiRow* rows, const EpiCol* cols, const PtrTable& bufs, hipStream_t s) {
     constexpr size_t lds = 2 * (MT + NT) * (KT / 8) * 16;
-    static bool configured = false;
-    if (!configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, WGM, WGN, OCC, SA>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-        configured = true;
-    }
+    // once per process (a thread-safe static initialisation)
+    static const hipError_t configured =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_big<MT, NT, KT, WGM, WGN, OCC, SA>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (configured != hipSuccess) return configured;
     hipLaunchKernelGGL((k_gemm_bf16_big<MT, NT, KT, WGM, WGN, OCC, SA>), dim3(static_cast<unsigned>(grid)),
                        dim3(64 * WGM * WGN), lds, s, probs, tiles, n_tiles, rows, cols, bufs);
     return hipGetLastError();
@@ -1185,13 +1181,11 @@ template <int MT, int NT, int KT, int WGM, int WGN, int ST, int OPT>
 hipError_t launch_dl(const GemmProb* probs, const GemmTile* tiles, int32_t n_tiles, int32_t grid, const EpiRow* rows,
                      const EpiCol* cols, const PtrTable& bufs, hipStream_t s) {
     constexpr size_t lds = dl_lds_bytes<MT, NT, KT, ST>();
-    static bool configured = false;
-    if (!configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_dl<MT, NT, KT, WGM, WGN, ST, OPT>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-        configured = true;
-    }
+    // once per process (a thread-safe static initialisation)
+    static const hipError_t configured =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_bf16_dl<MT, NT, KT, WGM, WGN, ST, OPT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (configured != hipSuccess) return configured;
     hipLaunchKernelGGL((k_gemm_bf16_dl<MT, NT, KT, WGM, WGN, ST, OPT>), dim3(static_cast<unsigned>(grid)),
                        dim3(64 * WGM * WGN), lds, s, probs, tiles, n_tiles, rows, cols, bufs);
     return hipGetLastError();
@@ -1456,15 +1450,6 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
     };
     double* Gp = Gpart + static_cast<int64_t>(pid) * S * (B2 * B2);
 
-    // 1. Gram matrix: thread (blk, xl) sums a 4 x 4 block of G over the chunk
-    //    entries xl, xl + LPB, xl + 2 LPB, ...; the LPB partial sums of a block
-    //    sit in LPB consecutive lanes
-    const int blk = tid / LPB, xl = tid % LPB, I4 = (blk / NB4) * 4, J4 = (blk % NB4) * 4;
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
     // a chunk: NL loads per thread, all issued before the first LDS write
     constexpr int NL = B2 * XC / 256;
     auto stage = [&](const double* base, int Lx, int x0, int xend) {
@@ -1481,36 +1466,45 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
             T[i][xx] = v[u];
         }
     };
-    int xa, xb;
-    span(L, xa, xb);
-    for (int x0 = xa; x0 < (PHASE == 0 ? xb : xa); x0 += XC) {
-        stage(W, L, x0, xb);
-        __syncthreads();
-#pragma unroll 4
-        for (int u = 0; u < XC / LPB; ++u) {
-            const int xx = xl + LPB * u;
-            double va[4], vb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) va[a] = T[I4 + a][xx];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) vb[b] = T[J4 + b][xx];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(va[a], vb[b], acc[a][b]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            double v = acc[a][b];
-#pragma unroll
-            for (int o = LPB / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-            acc[a][b] = v;
-        }
     if constexpr (PHASE == 0) {
+        // 1. Gram matrix: thread (blk, xl) sums a 4 x 4 block of G over the chunk
+        //    entries xl, xl + LPB, xl + 2 LPB, ...; the LPB partial sums of a block
+        //    sit in LPB consecutive lanes
+        const int blk = tid / LPB, xl = tid % LPB, I4 = (blk / NB4) * 4, J4 = (blk % NB4) * 4;
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        int xa, xb;
+        span(L, xa, xb);
+        for (int x0 = xa; x0 < xb; x0 += XC) {
+            stage(W, L, x0, xb);
+            __syncthreads();
+#pragma unroll 4
+            for (int u = 0; u < XC / LPB; ++u) {
+                const int xx = xl + LPB * u;
+                double va[4], vb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) va[a] = T[I4 + a][xx];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) vb[b] = T[J4 + b][xx];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = fma(va[a], vb[b], acc[a][b]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                double v = acc[a][b];
+#pragma unroll
+                for (int o = LPB / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                acc[a][b] = v;
+            }
         if (xl == 0)
 #pragma unroll
             for (int a = 0; a < 4; ++a)

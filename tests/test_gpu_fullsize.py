@@ -7,7 +7,9 @@ oracle computes one by one:
   launch): sampled entries of sampled members, error against the unrounded
   draws and against the stored BF16 values;
 * config 5 (SU(2), chi=576): sampled reduced blocks of C by the block-wise
-  multiply, and the recoupled blocks of sampled label tuples.
+  multiply, and the recoupled blocks of sampled label tuples;
+* config 4's A as a matrix (17 sectors up to 1976 x 1976): the block SVD's
+  singular values of every sector, and its factors on sampled sectors.
 """
 import numpy as np
 import pytest
@@ -178,3 +180,49 @@ def test_config5_su2_sampled(ctx):
             den += np.sum(ref ** 2)
     say(f"  recoupled blocks rel err {np.sqrt(num / den):.3e}")
     assert np.sqrt(num / den) <= 1e-5
+
+
+def test_config4_block_svd_full_size(ctx):
+    """The block SVD in the launch the benchmark times (config 4's A split
+    after two legs: 17 sectors up to 1976 x 1976): every singular value of
+    every sector against numpy's, and U diag(S) Vt and orthonormality on the
+    largest sector and two sampled ones."""
+    from oracle import svd as SV
+    say("case config4 full size block svd")
+    c = W.config4()
+    g = W.generator(c.seed, "cuda")
+    a = W.gaussian(T.num_elements(c.A), g, "cuda")
+    A = ctx.tensor(c.A, 4, data=a)
+    F = ctx.permute_fuse(A, (0, 1, 2, 3), 2)
+    U, S, Vt, sweeps, shapes = ctx.svd(F)
+    torch.cuda.synchronize()
+    say(f"  {len(shapes)} sectors, {sweeps} sweeps")
+    ref = SV.block_singular_values(c.A, a.double().cpu().numpy(), 2)
+    fused = F.data.double().cpu().numpy()
+    U, S, Vt = U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy()
+    secs = [s for s in F.sectors() if s[1] > 0 and s[2] > 0]
+    assert len(secs) == len(shapes) == len(ref) == 17
+    ks = [k for _, _, _, k in shapes]
+    rng = np.random.default_rng(4)
+    check = {int(np.argmax(ks))} | {int(i) for i in rng.choice(len(ks), 2, replace=False)}
+    uo = so = vo = 0
+    worst = 0.0
+    for idx, ((lab, m, n, off), (_, _, _, k)) in enumerate(zip(secs, shapes)):
+        s, r = S[so:so + k], ref[lab]
+        np.testing.assert_allclose(s, r, rtol=1e-11, atol=1e-12 * r[0], err_msg=str(lab))
+        worst = max(worst, float(np.max(np.abs(s - r)) / r[0]))
+        if idx in check:
+            u = U[uo:uo + m * k].reshape(m, k)
+            vt = Vt[vo:vo + k * n].reshape(k, n)
+            tmat = fused[off:off + m * n].reshape(m, n)
+            # every vector and row of Q takes one 16-term update per round,
+            # sweeps x (nb - 1) = 18 x 246 of them: a random walk of about
+            # sqrt(16 * 4428) eps = 3e-14 per entry of Q's orthogonality error,
+            # sqrt(k) = 44 times that in the relative Frobenius error of
+            # U diag(S) Vt; the bound leaves a factor of about 8
+            assert np.linalg.norm((u * s) @ vt - tmat) <= 1e-11 * np.linalg.norm(tmat), lab
+            assert np.abs(u.T @ u - np.eye(k)).max() <= 1e-11, lab
+            assert np.abs(vt @ vt.T - np.eye(k)).max() <= 1e-11, lab
+        uo, so, vo = uo + m * k, so + k, vo + k * n
+    say(f"  largest singular-value error over s_max {worst:.2e}")
+    assert 1 <= sweeps < 60
