@@ -1324,9 +1324,9 @@ hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const Ge
 // in Q; at convergence the vector norms are the singular values, the
 // normalised vectors one set of singular vectors and Q the other.  A sweep
 // is a sequence of rounds of the round-robin (circle) schedule over blocks of
-// vectors; one launch runs one round of every sector at once (one workgroup
-// per pair of blocks, disjoint pairs), so the launch boundary orders the
-// rounds and the whole GPU works on them.
+// vectors; a round of every sector runs at once (one workgroup per pair of
+// blocks, disjoint pairs, two launches per round), so launch boundaries
+// order the rounds and the whole GPU works on them.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ double as_f64(T x);
