@@ -278,7 +278,8 @@ __device__ __forceinline__ void tile_copy(const CopyOp* __restrict__ ops, const 
 // cache lines.  Each source row of the tile is staged with 16-byte loads
 // from its aligned-down start; row r sits at LDS column rot(r) + off[r],
 // where the rotation rot(r) = VI ((r / 8) mod 8) puts rows 8 apart on
-// different banks.  Destination rows are written in 16-byte aligned chunks,
+// different banks.  All of a thread's source loads are issued before its
+// first LDS write.  Destination rows are written in 16-byte aligned chunks,
 // eight lanes per row on eight consecutive chunks (128 contiguous bytes),
 // each chunk gathered down an LDS column; element stores only at the ends.
 // The source is read through one range-checked buffer resource per tile
@@ -286,7 +287,8 @@ __device__ __forceinline__ void tile_copy(const CopyOp* __restrict__ ops, const 
 template <typename Ti>
 struct TransposeShape {
     static constexpr int VI = 16 / sizeof(Ti);
-    static constexpr int RW = kTile + 2 * VI + 7 * VI;   // staged row width incl. rotation room
+    static constexpr int NV = (kTile + 2 * VI - 2) / VI;   // vectors that cover one source row segment
+    static constexpr int RW = kTile + 2 * VI + 7 * VI;       // staged row width incl. rotation room
     static constexpr int TI = vtile_rows(sizeof(Ti));
     static constexpr size_t lds_bytes = static_cast<size_t>(TI) * RW * sizeof(Ti) + TI * sizeof(int);
 };
@@ -296,11 +298,11 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
                                                        const TileTask* __restrict__ tasks, int n_tasks,
                                                        PtrTable bufs) {
     using Sh = TransposeShape<Ti>;
-    constexpr int VI = Sh::VI, RW = Sh::RW, TI = Sh::TI;
+    constexpr int VI = Sh::VI, NV = Sh::NV, RW = Sh::RW, TI = Sh::TI;
     constexpr int VO = Pack<To>::V;
-    constexpr int NV = (kTile + 2 * VI - 2) / VI;   // vectors that cover one source row segment
     constexpr int NC = (TI + 2 * VO - 2) / VO;      // chunks that cover one destination row segment
     constexpr int NH = (NC + 7) / 8;                // groups of eight chunks
+    constexpr int NLD = (TI * NV + 255) / 256;      // source vectors per thread
     constexpr int I = kMaxCopyDims - 1;
     static_assert((RW * sizeof(Ti)) % 16 == 0, "LDS rows must stay 16-byte aligned");
     extern __shared__ u32x4_t lds_raw[];
@@ -336,18 +338,34 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
         const int e_full = full / static_cast<int>(sizeof(Ti));
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<Ti*>(src + base), static_cast<short>(0), full, 0x00020000);
-        for (int it = threadIdx.x; it < TI * NV; it += 256) {
-            const int r = it / NV, v = it - r * NV;
-            if (r >= ni) continue;
+        // item it = (row r, vector v)
+        auto item = [&](int it, int& r, int& v, int& off, int& e0) {
+            r = it / NV;
+            v = it - r * NV;
+            if (it >= TI * NV || r >= ni) return false;
             const int64_t start = so + (i0 + r) * sI + j0;
             const int64_t a = start & ~static_cast<int64_t>(VI - 1);
-            const int off = static_cast<int>(start - a);
+            off = static_cast<int>(start - a);
+            e0 = static_cast<int>(a - base) + v * VI;   // element index from the resource base
+            return true;
+        };
+        u32x4_t ld[NLD];
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            int r, v, off, e0;
+            ld[u] = u32x4_t{0u, 0u, 0u, 0u};
+            if (item(static_cast<int>(threadIdx.x) + 256 * u, r, v, off, e0) && v * VI < off + nj)
+                ld[u] = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(
+                                                        rs, e0 * static_cast<int>(sizeof(Ti)), 0, 0));
+        }
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            int r, v, off, e0;
+            if (!item(static_cast<int>(threadIdx.x) + 256 * u, r, v, off, e0)) continue;
             if (v == 0) row_off[r] = rot(r) + off;
             if (v * VI >= off + nj) continue;
-            const int e0 = static_cast<int>(a - base) + v * VI;   // element index from the resource base
             Ti* row = tile + r * RW + rot(r);
-            reinterpret_cast<u32x4_t*>(row)[v] =
-                __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, e0 * static_cast<int>(sizeof(Ti)), 0, 0));
+            reinterpret_cast<u32x4_t*>(row)[v] = ld[u];
             for (int e = e0 > e_full ? e0 : e_full; e < e0 + VI && e < lim; ++e) row[v * VI + (e - e0)] = src[base + e];
         }
         __syncthreads();
@@ -364,7 +382,8 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
             if (vec_dst && c_lo >= 0 && c_lo + VO <= ni) {
                 To v[VO];
 #pragma unroll
-                for (int u = 0; u < VO; ++u) v[u] = flip(Conv<Ti, To>::f(tile[(c_lo + u) * RW + row_off[c_lo + u] + j]), op.neg);
+                for (int u = 0; u < VO; ++u)
+                    v[u] = flip(Conv<Ti, To>::f(tile[(c_lo + u) * RW + row_off[c_lo + u] + j]), op.neg);
                 *reinterpret_cast<u32x4_t*>(dst + d0 + c_lo) = Pack<To>::f(v);
             } else {
 #pragma unroll

@@ -45,6 +45,25 @@ def test_u1_permute_fuse_bit_exact(ctx, perm, n_row):
     assert torch.equal(rt.data, a)
 
 
+@pytest.mark.parametrize("perm", [(2, 3, 0, 1), (1, 0, 3, 2), (3, 2, 1, 0)])
+@pytest.mark.parametrize("n_row", [2, 4])
+def test_u1_permute_bf16_bit_exact(ctx, perm, n_row):
+    # BF16 in and out: the transposing copies with 16-byte source vectors,
+    # blocks up to 400 x 400 (several tiles along both dims, ragged tails)
+    say(f"case permute bf16 perm={perm} n_row={n_row}")
+    c = W.config4()
+    g = W.generator(4, "cuda")
+    a = draw(c.A, g).to(torch.bfloat16)
+    A = ctx.tensor(c.A, 4, "bf16", data=a)
+    P = ctx.permute_fuse(A, perm, n_row)
+    back = ctx.permute_fuse(P, tuple(range(4)), 4)
+    _, ref = _oracle_permute(c.A, a.double().cpu().numpy(), perm)
+    assert np.array_equal(host(back), ref)
+    inv = tuple(int(i) for i in np.argsort(perm))
+    rt = ctx.permute_fuse(P, inv, 4)
+    assert torch.equal(rt.data.view(torch.int16), a.view(torch.int16))
+
+
 def test_bf16_conversion_round_to_nearest_even(ctx):
     say("case bf16 conversion")
     c = W.config1()
