@@ -137,7 +137,9 @@ int32_t sym_ctx_clear(sym_ctx* ctx);
  * an Abelian tensor (0 = invariant; must be 0 for SU(2)); dtype: SYM_F32 or
  * SYM_BF16; data: device pointer to
  * numel elements in the layout described above, borrowed (may be NULL and set
- * later with sym_tensor_set_data).  Pure host work. */
+ * later with sym_tensor_set_data).  Compute calls fail with SYM_E_ARG on a
+ * tensor whose buffer is still NULL, unless numel is 0 (no allowed block:
+ * nothing is read or written).  Pure host work. */
 int32_t sym_tensor_create(sym_ctx* ctx, int32_t group, int32_t rank, const sym_leg* legs,
                           int32_t n_row, int32_t tree, int32_t qtot, int32_t dtype,
                           void* data, sym_tensor** out);
@@ -285,7 +287,9 @@ int32_t sym_default_variant(int32_t compute, int32_t* variant);
  * may be NULL) receives the number run.  The call synchronises `stream` once
  * per sweep (the stopping decision is taken on the host).  Singular vectors
  * of zero singular values are returned as zeros.  SYM_E_UNSUPPORTED for a
- * sector with min(M_s, N_s) > 4096.  The caller owns the outputs; the FP64
+ * sector with min(M_s, N_s) > 4096.  A tensor with no sector (all three
+ * sizes 0) returns at once: U, S, Vt may then be NULL, and *sweeps is 0.
+ * The caller owns the outputs; the FP64
  * workspaces belong to the context (cached per structure), so calls on one
  * structure must not overlap. */
 int32_t sym_svd_sizes(const sym_tensor* T, int64_t* u_elems, int64_t* s_elems, int64_t* vt_elems);

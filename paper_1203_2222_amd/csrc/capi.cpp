@@ -163,6 +163,10 @@ struct sym_graph {
 
 namespace {
 
+// A tensor with stored elements needs a buffer; one with none (no allowed
+// block) may have none: no kernel reads or writes it.
+bool has_data(const sym_tensor* t) { return t->data != nullptr || t->d->numel == 0; }
+
 std::vector<Leg> read_legs(int32_t rank, const sym_leg* legs) {
     if (rank < 0 || rank > SYM_MAX_RANK) throw Error(SYM_E_ARG, "rank outside [0, SYM_MAX_RANK]");
     if (rank > 0 && !legs) throw Error(SYM_E_ARG, "legs is NULL");
@@ -381,7 +385,7 @@ void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor*
     t.p[kSlotWsIn] = plan.ws_in ? plan.ws_in->ptr : nullptr;
     t.p[kSlotWsOut] = plan.ws_out ? plan.ws_out->ptr : nullptr;
     for (int i = 0; i < plan.count; ++i) {
-        if (!A[i]->data || !B[i]->data || !C[i]->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        if (!has_data(A[i]) || !has_data(B[i]) || !has_data(C[i])) throw Error(SYM_E_ARG, "tensor has no data pointer");
         t.p[kSlotUser + i] = A[i]->data;
         t.p[kSlotUser + plan.count + i] = B[i]->data;
         t.p[kSlotUser + 2 * plan.count + i] = C[i]->data;
@@ -586,7 +590,7 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
     return guard([&] {
         if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
         PermuteSpec s = check_perm(*in->d, perm);
-        if (!in->data || !out->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        if (!has_data(in) || !has_data(out)) throw Error(SYM_E_ARG, "tensor has no data pointer");
         std::ostringstream k;
         k << "P|" << in->d->key << '|' << out->d->key << '|' << n_row_out << '|';
         for (int32_t p : s.perm) k << p << ',';
@@ -679,7 +683,7 @@ int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
     return guard([&] {
         if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
         const std::vector<int32_t> p = check_tree_perm(*in->d, perm, tree_out);
-        if (!in->data || !out->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        if (!has_data(in) || !has_data(out)) throw Error(SYM_E_ARG, "tensor has no data pointer");
         std::ostringstream k;
         k << "T|" << in->d->key << '|' << out->d->key << '|' << n_row_out << '|' << tree_out << '|';
         for (int32_t v : p) k << v << ',';
@@ -873,7 +877,7 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->backward_plans[k.str()] = plan;
         }
-        if (!A->data || !B->data || !dC->data || (dA && !dA->data) || (dB && !dB->data))
+        if (!has_data(A) || !has_data(B) || !has_data(dC) || (dA && !has_data(dA)) || (dB && !has_data(dB)))
             throw Error(SYM_E_ARG, "tensor has no data pointer");
         PtrTable t{};
         t.p[0] = plan->ws_in ? plan->ws_in->ptr : nullptr;
@@ -1085,8 +1089,8 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
     // one plan per structure; calls with the same structure on one context
     // share its workspaces, so they must not overlap in time
     return guard([&] {
-        if (!ctx || !T || !U || !S || !Vt) throw Error(SYM_E_ARG, "NULL argument");
-        if (!T->data) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        if (!ctx || !T) throw Error(SYM_E_ARG, "NULL argument");
+        if (!has_data(T)) throw Error(SYM_E_ARG, "tensor has no data pointer");
         if (max_sweeps < 1) throw Error(SYM_E_ARG, "max_sweeps must be >= 1");
         const std::string key = "S|" + T->d->key;
         std::shared_ptr<SvdPlan> plan;
@@ -1115,7 +1119,9 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->svd_plans[key] = plan;
         }
-        if (plan->probs.empty()) return;
+        if (sweeps) *sweeps = 0;
+        if (plan->probs.empty()) return;   // no sector: nothing to factorise or write
+        if (!U || !S || !Vt) throw Error(SYM_E_ARG, "NULL argument");
         int32_t done = 0;
         HIP_CHECK(launch_svd(T->d->dtype, T->data, static_cast<const SvdProb*>(plan->d_probs->ptr),
                              static_cast<const int32_t*>(plan->d_pairs->ptr), static_cast<int32_t>(plan->probs.size()),

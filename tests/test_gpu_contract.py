@@ -156,3 +156,33 @@ def test_repeated_calls_bitwise_deterministic(ctx):
     B = ctx.tensor(c.B, 4, data=draw(c.B, g))
     outs = [host(to_canonical(ctx, ctx.contract(A, B, c.axes_a, c.axes_b, comp))) for comp in ("f32", "f32", "bf16", "bf16")]
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[2], outs[3])
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_empty_operands_give_zero_output(ctx, compute):
+    # A (charge 0 in, 1 out) and B (1 in, 0 out) have no allowed block, so
+    # they store nothing and need no buffer; C (0 in, 0 out) has one block,
+    # every entry a sum over no terms
+    say(f"case empty operands {compute}")
+    l0 = W.u1_leg(0, 0, [3], "in")
+    l1 = W.u1_leg(1, 1, [2], "out")
+    Aspec = W.TensorSpec(W.U1, (l0, l1))
+    Bspec = W.TensorSpec(W.U1, (l1.flipped(), l0.flipped()))
+    assert T.num_elements(Aspec) == 0 and T.num_elements(Bspec) == 0
+    dt = "bf16" if compute == "bf16" else "f32"
+    A = ctx.tensor(Aspec, 1, dt)
+    B = ctx.tensor(Bspec, 1, dt)
+    C = ctx.contract_output(A, B, (1,), (0,))
+    assert C.numel() == 9 == T.num_elements(K.result_spec(Aspec, Bspec, (1,), (0,)))
+    C.data.fill_(7.0)
+    ctx.contract(A, B, (1,), (0,), compute, out=C)
+    assert np.all(host(C) == 0.0)
+    # the SVD of a tensor with no sector: nothing to factorise
+    U, S, Vt, sweeps, shapes = ctx.svd(A)
+    assert shapes == [] and S.numel() == 0 and U.numel() == 0 and Vt.numel() == 0 and sweeps == 0
+    if compute == "f32":
+        # the backward of an empty operand pair: dA, dB are empty, nothing fails
+        dC = ctx.tensor(C.spec, C.n_row, data=torch.ones(9, device="cuda"))
+        dA, dB = ctx.contract_backward(A, B, dC, (1,), (0,))
+        torch.cuda.synchronize()
+        assert dA.numel() == 0 and dB.numel() == 0
