@@ -202,3 +202,28 @@ def test_abelian_label_validation():
                        qtot=(0, 0))
     with pytest.raises(SymError):
         ctx.describe(big, 2)
+
+
+def test_svd_size_limit_and_sizes():
+    # sym_svd_sizes plans on the host: a sector of 4096 x 5000 fits, 4097 x 4097
+    # is refused with SYM_E_UNSUPPORTED; the sizes are those of U, S, Vt
+    from ctypes import byref, c_int64
+    L = _lib_or_skip()
+    ctx = _ctx()
+
+    def sizes(m, n):
+        spec = W.TensorSpec(W.U1, (W.u1_leg(0, 0, [m], "in"), W.u1_leg(0, 0, [n], "out")))
+        t = ctx.describe(spec, 1)
+        u, s, v = c_int64(), c_int64(), c_int64()
+        st = L.lib().sym_svd_sizes(t.handle, byref(u), byref(s), byref(v))
+        return st, (u.value, s.value, v.value)
+
+    assert sizes(4096, 5000) == (0, (4096 * 4096, 4096, 4096 * 5000))
+    assert sizes(5000, 4096) == (0, (5000 * 4096, 4096, 4096 * 4096))
+    assert sizes(4097, 4097)[0] == 8
+    # no allowed block: every size is 0
+    spec = W.TensorSpec(W.U1, (W.u1_leg(0, 0, [3], "in"), W.u1_leg(1, 1, [2], "out")))
+    t = ctx.describe(spec, 1)
+    u, s, v = c_int64(7), c_int64(7), c_int64(7)
+    assert L.lib().sym_svd_sizes(t.handle, byref(u), byref(s), byref(v)) == 0
+    assert (u.value, s.value, v.value) == (0, 0, 0)
