@@ -497,6 +497,13 @@ def main():
         ctx.clear()
         torch.cuda.empty_cache()
         result["per_config"] = secondary(ctx, stream, with_cpu=not args.no_cpu_baseline)
+        # the second reference point for the GEMM's fraction: a large square
+        # BF16 product by the vendor library on the same GPU (context only)
+        ceil = result["per_config"].get("hipblaslt_8192cube_bf16_TFLOPs")
+        if ceil:
+            result["roofline"]["measured_ceiling"] = {
+                "what": "hipBLASLt 8192^3 BF16 (torch.matmul) on this GPU", "TFLOPs": ceil,
+                "frac": round(gemm_tf / ceil, 4)}
 
     print(json.dumps(result), flush=True)
 
