@@ -39,6 +39,9 @@ int32_t guard(F&& f) {
     } catch (const std::exception& e) {
         set_error(e.what());
         return SYM_E_ARG;
+    } catch (...) {   // nothing may cross the C-ABI as an exception
+        set_error("unexpected exception");
+        return SYM_E_ARG;
     }
 }
 
