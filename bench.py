@@ -347,7 +347,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this library "
               "(multi-GPU sharding of sectors is a design note, not implemented).", file=sys.stderr)
         sys.exit(2)
 

@@ -1272,12 +1272,12 @@ const GemmVariant kBF16Variants[] = {{256, 256, "k_gemm_bf16_big 256x256 k64 4w"
 int gemm_num_variants(int compute) { return compute == 0 ? 3 : 16; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
 // Defaults from measurements on MI355X.  256x256 tiles (operand re-reads
-// beyond L2 fall with the tile size: 128x128 ran the 64-member batch at 406
+// beyond L2 fall with the tile size: 128x128 ran the 64-member batch at 377
 // TFLOP/s) with 8 waves, two per SIMD, fed by direct loads through a
-// five-stage LDS ring: 917 TFLOP/s on the batch and 1158 on one 8192^3
-// product, against 774-802 and 832 for the register-staged 256x256 kernel
-// on the same GPU.  The ranking moved between GPUs of the pool, which is
-// what the autotuner is for.
+// five-stage LDS ring: 990 to 1024 TFLOP/s on the batch and about 1190 on
+// one 8192^3 product, against 901 on the batch for the register-staged
+// 256x256 kernel on the same GPU.  The ranking of the 256x256 variants
+// moved from one MI355X to another, which is what the autotuner is for.
 int gemm_default_variant(int compute) { return compute == 0 ? 0 : 10; }
 int gemm_default_variant_wide(int compute) { return compute == 0 ? 0 : 5; }
 
