@@ -293,7 +293,7 @@ struct TransposeShape {
     static constexpr size_t lds_bytes = static_cast<size_t>(TI) * RW * sizeof(Ti) + TI * sizeof(int);
 };
 
-template <typename Ti, typename To>
+template <typename Ti, typename To, bool MERGED>
 __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict__ ops,
                                                        const TileTask* __restrict__ tasks, int n_tasks,
                                                        PtrTable bufs) {
@@ -319,18 +319,40 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
         int64_t so = op.src_off, dof = op.dst_off;
         int rem = t.outer;
         for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d) {
-            if (d == J) continue;
+            if (d == J || (MERGED && (d == op.ihi || d == op.jhi))) continue;
             const int q = div_by(rem, op.mag[d], op.shf[d]);
             const int i = rem - q * op.size[d];
             rem = q;
             so += i * op.sstride[d];
             dof += i * op.dstride[d];
         }
+        // tile rows i (destination-contiguous, index i_lo + size[I] i_hi)
+        // and columns j (source-contiguous, j_lo + size[J] j_hi)
+        // (MERGED: ops with ihi or jhi set; the launch of the others never
+        // divides)
+        const int nIlo = op.size[I], nJlo = op.size[J];
+        const int nI = MERGED && op.ihi >= 0 ? nIlo * op.size[op.ihi] : nIlo;
+        const int nJ = MERGED && op.jhi >= 0 ? nJlo * op.size[op.jhi] : nJlo;
+        const int64_t sI = op.sstride[I], sIhi = MERGED && op.ihi >= 0 ? op.sstride[op.ihi] : 0;
+        const int64_t dJ = op.dstride[J], dJhi = MERGED && op.jhi >= 0 ? op.dstride[op.jhi] : 0;
+        auto src_row = [&](int i) -> int64_t {   // source offset of row i
+            if constexpr (!MERGED) return i * sI;
+            const int h = div_by(i, op.mag[I], op.shf[I]);
+            return (i - h * nIlo) * sI + h * sIhi;
+        };
+        auto dst_row = [&](int j) -> int64_t {   // destination offset of column j
+            if constexpr (!MERGED) return j * dJ;
+            const int h = div_by(j, op.mag[J], op.shf[J]);
+            return (j - h * nJlo) * dJ + h * dJhi;
+        };
         const int i0 = t.it * TI, j0 = t.jt * kTile;
-        const int ni = min(TI, op.size[I] - i0), nj = min(kTile, op.size[J] - j0);
-        const int64_t sI = op.sstride[I], dJ = op.dstride[J];
-        // row r of the tile: source elements [so + (i0 + r) sI + j0, + nj)
-        const int64_t base = (so + i0 * sI + j0) & ~static_cast<int64_t>(VI - 1);
+        const int ni = min(TI, nI - i0), nj = min(kTile, nJ - j0);
+        // row r of the tile: source elements [so + src_row(i0 + r) + j0, + nj);
+        // the lowest row start is that of the first row, or of i_lo = 0 in
+        // the tile's first i_hi when the tile wraps past the end of i_lo
+        const int h0 = MERGED ? div_by(i0, op.mag[I], op.shf[I]) : 0;
+        const int64_t first = (i0 - h0 * nIlo + ni > nIlo ? int64_t{0} : (i0 - h0 * nIlo) * sI) + h0 * sIhi;
+        const int64_t base = (so + first + j0) & ~static_cast<int64_t>(VI - 1);
         const int64_t avail = op.src_len - base;
         const int64_t cap = (int64_t{1} << 30) / static_cast<int64_t>(sizeof(Ti));
         const int lim = static_cast<int>(avail < cap ? avail : cap);
@@ -343,7 +365,7 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
             r = it / NV;
             v = it - r * NV;
             if (it >= TI * NV || r >= ni) return false;
-            const int64_t start = so + (i0 + r) * sI + j0;
+            const int64_t start = so + src_row(i0 + r) + j0;
             const int64_t a = start & ~static_cast<int64_t>(VI - 1);
             off = static_cast<int>(start - a);
             e0 = static_cast<int>(a - base) + v * VI;   // element index from the resource base
@@ -375,7 +397,7 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
             const int g = wi / NH, h = wi - g * NH;
             const int j = 8 * g + (lane >> 3), c = 8 * h + (lane & 7);
             if (j >= nj || c >= NC) continue;
-            const int64_t d0 = dof + (j0 + j) * dJ + i0;
+            const int64_t d0 = dof + dst_row(j0 + j) + i0;
             const int delta = vec_dst ? static_cast<int>(d0 & (VO - 1)) : 0;
             const int c_lo = c * VO - delta;
             if (c_lo >= ni || c_lo + VO <= 0) continue;
@@ -397,17 +419,17 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
     }
 }
 
-template <typename Ti, typename To>
+template <typename Ti, typename To, bool MERGED>
 hipError_t launch_tv(const CopyOp* ops, const TileTask* tasks, int32_t n_tasks, int32_t n_wg, const PtrTable& bufs,
                      hipStream_t s) {
     constexpr size_t lds = TransposeShape<Ti>::lds_bytes;
     // once per process (a thread-safe static initialisation)
     static const hipError_t configured =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transpose_vec<Ti, To>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transpose_vec<Ti, To, MERGED>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (configured != hipSuccess) return configured;
-    hipLaunchKernelGGL((k_transpose_vec<Ti, To>), dim3(static_cast<unsigned>(n_wg)), dim3(256), lds, s, ops, tasks,
-                       n_tasks, bufs);
+    hipLaunchKernelGGL((k_transpose_vec<Ti, To, MERGED>), dim3(static_cast<unsigned>(n_wg)), dim3(256), lds, s, ops,
+                       tasks, n_tasks, bufs);
     return hipGetLastError();
 }
 
@@ -422,14 +444,22 @@ __global__ __launch_bounds__(256) void k_permute_tiled(const CopyOp* __restrict_
     }
 }
 
-hipError_t launch_transpose_vec(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
+template <bool MERGED>
+hipError_t launch_tv_types(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks, int32_t n_tasks,
+                           int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
+    if (src_dtype == 0 && dst_dtype == 0) return launch_tv<float, float, MERGED>(ops, tasks, n_tasks, n_wg, bufs, s);
+    if (src_dtype == 0 && dst_dtype == 1) return launch_tv<float, uint16_t, MERGED>(ops, tasks, n_tasks, n_wg, bufs, s);
+    if (src_dtype == 1 && dst_dtype == 1)
+        return launch_tv<uint16_t, uint16_t, MERGED>(ops, tasks, n_tasks, n_wg, bufs, s);
+    return launch_tv<uint16_t, float, MERGED>(ops, tasks, n_tasks, n_wg, bufs, s);
+}
+
+hipError_t launch_transpose_vec(int src_dtype, int dst_dtype, bool merged, const CopyOp* ops, const TileTask* tasks,
                                 int32_t n_tasks, int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
     if (n_tasks <= 0) return hipSuccess;
     if (n_wg <= 0) return hipErrorInvalidValue;
-    if (src_dtype == 0 && dst_dtype == 0) return launch_tv<float, float>(ops, tasks, n_tasks, n_wg, bufs, s);
-    if (src_dtype == 0 && dst_dtype == 1) return launch_tv<float, uint16_t>(ops, tasks, n_tasks, n_wg, bufs, s);
-    if (src_dtype == 1 && dst_dtype == 1) return launch_tv<uint16_t, uint16_t>(ops, tasks, n_tasks, n_wg, bufs, s);
-    return launch_tv<uint16_t, float>(ops, tasks, n_tasks, n_wg, bufs, s);
+    return merged ? launch_tv_types<true>(src_dtype, dst_dtype, ops, tasks, n_tasks, n_wg, bufs, s)
+                  : launch_tv_types<false>(src_dtype, dst_dtype, ops, tasks, n_tasks, n_wg, bufs, s);
 }
 
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks, int32_t n_tasks,

@@ -33,6 +33,11 @@ struct CopyOp {
     int32_t rowcopy;     // rows of a contiguous source run along the destination's rows
     int64_t src_len;     // elements readable from the source buffer's base pointer
     int32_t neg;         // 1: the block changes sign (fermionic swap factors)
+    // vectorized transposes of small blocks: the dim that continues the
+    // destination-contiguous dim (dstride == size of the innermost dim) and
+    // the one that continues the source-contiguous dim tj (sstride ==
+    // size[tj]), merged into them so that a tile spans both; -1 for none
+    int32_t ihi, jhi;
     int32_t pad;
 };
 
@@ -131,7 +136,8 @@ hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
 hipError_t launch_copy_rows(int src_dtype, int dst_dtype, const CopyOp* ops, const RowTask* tasks, int32_t n_tasks,
                             int32_t grid, const PtrTable& bufs, hipStream_t s);
-hipError_t launch_transpose_vec(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,
+// merged: the tasks' ops have ihi or jhi set (all of them, or none)
+hipError_t launch_transpose_vec(int src_dtype, int dst_dtype, bool merged, const CopyOp* ops, const TileTask* tasks,
                                 int32_t n_tasks, int32_t grid, const PtrTable& bufs, hipStream_t s);
 // grid: workgroups, each taking tasks w, w + grid, ...
 hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops, const TileTask* tasks,

@@ -135,6 +135,7 @@ void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_
         op.src_buf = src_buf;
         op.dst_buf = dst_buf;
         op.tj = -1;
+        op.ihi = op.jhi = -1;
         op.src_len = src_base + src.numel;
         // rows of one contiguous source run, written along contiguous destination rows
         constexpr int II = kMaxCopyDims - 1;
@@ -161,22 +162,38 @@ void CopyProgram::finalize() {
     wg_begin.clear();
     tile_tasks.clear();
     vtile_tasks.clear();
+    mtile_tasks.clear();
     row_tasks.clear();
     for (size_t i = 0; i < ops.size(); ++i) {
-        const CopyOp& op = ops[i];
+        CopyOp& op = ops[i];
         if (op.tj >= 0) {
             constexpr int I = kMaxCopyDims - 1;
-            int64_t outer = 1;
-            for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d)
-                if (d != op.tj) outer *= op.size[d];
             // destination rows of unit stride take the vectorized kernel, as
             // long as one tile's source rows span less than 2^29 bytes
             const int esz = src_dtype == SYM_BF16 ? 2 : 4;
             const int ti = vtile_rows(esz);
             const bool vec = op.dstride[I] == 1 && op.sstride[I] > 0 && op.sstride[I] * ti * esz < (int64_t{1} << 29);
-            const int nj = (op.size[op.tj] + kTile - 1) / kTile;
-            const int ni = (op.size[I] + (vec ? ti : kTile) - 1) / (vec ? ti : kTile);
-            std::vector<TileTask>& list = vec ? vtile_tasks : tile_tasks;
+            op.ihi = op.jhi = -1;
+            if (vec && static_cast<int64_t>(op.count) * esz < (int64_t{1} << 29)) {
+                // small blocks: continue a short row dim with the dim that
+                // follows it in the destination, a short column dim with the
+                // one that follows it in the source, so tiles fill up (the
+                // block spans less than 2^29 bytes, so any tile does too)
+                for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d) {
+                    if (d == op.tj) continue;
+                    if (op.ihi < 0 && op.size[I] < ti && op.dstride[d] == op.size[I]) op.ihi = d;
+                    else if (op.jhi < 0 && op.size[op.tj] < kTile && op.sstride[d] == op.size[op.tj]) op.jhi = d;
+                }
+            }
+            int64_t outer = 1;
+            for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d)
+                if (d != op.tj && d != op.ihi && d != op.jhi) outer *= op.size[d];
+            const int64_t nI = static_cast<int64_t>(op.size[I]) * (op.ihi >= 0 ? op.size[op.ihi] : 1);
+            const int64_t nJ = static_cast<int64_t>(op.size[op.tj]) * (op.jhi >= 0 ? op.size[op.jhi] : 1);
+            const int nj = static_cast<int>((nJ + kTile - 1) / kTile);
+            const int ni = static_cast<int>((nI + (vec ? ti : kTile) - 1) / (vec ? ti : kTile));
+            std::vector<TileTask>& list =
+                !vec ? tile_tasks : (op.ihi >= 0 || op.jhi >= 0) ? mtile_tasks : vtile_tasks;
             // tiles adjacent along the source's contiguous dim share the
             // cache lines at their boundary: keep them next to each other
             for (int64_t o = 0; o < outer; ++o)
@@ -221,6 +238,7 @@ void CopyProgram::finalize() {
     // sharing boundary lines meet in the same L2.
     tile_grid = xcd_order(tile_tasks);
     vtile_grid = xcd_order(vtile_tasks);
+    mtile_grid = xcd_order(mtile_tasks);
 }
 
 int32_t CopyProgram::xcd_order(std::vector<TileTask>& list) {
@@ -244,6 +262,7 @@ void CopyProgram::upload(const Allocator& alloc) {
     d_tile_tasks = upload_vec(alloc, tile_tasks);
     d_row_tasks = upload_vec(alloc, row_tasks);
     d_vtile_tasks = upload_vec(alloc, vtile_tasks);
+    d_mtile_tasks = upload_vec(alloc, mtile_tasks);
 }
 
 hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
@@ -262,9 +281,15 @@ hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
         if (e != hipSuccess) return e;
     }
     if (!vtile_tasks.empty()) {
-        hipError_t e = launch_transpose_vec(src_dtype, dst_dtype, static_cast<const CopyOp*>(d_ops->ptr),
+        hipError_t e = launch_transpose_vec(src_dtype, dst_dtype, false, static_cast<const CopyOp*>(d_ops->ptr),
                                             static_cast<const TileTask*>(d_vtile_tasks->ptr),
                                             static_cast<int32_t>(vtile_tasks.size()), vtile_grid, bufs, s);
+        if (e != hipSuccess) return e;
+    }
+    if (!mtile_tasks.empty()) {
+        hipError_t e = launch_transpose_vec(src_dtype, dst_dtype, true, static_cast<const CopyOp*>(d_ops->ptr),
+                                            static_cast<const TileTask*>(d_mtile_tasks->ptr),
+                                            static_cast<int32_t>(mtile_tasks.size()), mtile_grid, bufs, s);
         if (e != hipSuccess) return e;
     }
     if (!tile_tasks.empty())

@@ -35,12 +35,13 @@ struct CopyProgram {
     std::vector<TileTask> tile_tasks;
     std::vector<RowTask> row_tasks;
     std::vector<TileTask> vtile_tasks;   // transposes with unit-stride destination rows
+    std::vector<TileTask> mtile_tasks;   // the same, for ops with merged row or column dims
     int32_t tile_grid = 0;   // workgroups of the tiled kernels (a multiple of 8 once there are 8 tasks)
-    int32_t vtile_grid = 0;
+    int32_t vtile_grid = 0, mtile_grid = 0;
     static constexpr int32_t kTileGridMax = 8192;
     int src_dtype = SYM_F32, dst_dtype = SYM_F32;
     // device copies
-    DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks, d_row_tasks, d_vtile_tasks;
+    DevMemPtr d_ops, d_tasks, d_wg, d_tile_tasks, d_row_tasks, d_vtile_tasks, d_mtile_tasks;
 
     // dst block j <- src block with labels dst.labels permuted back by perm
     void add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
