@@ -453,7 +453,8 @@ def main():
             "peak": PEAK_TFLOPS["bf16"],
             "unit": "TFLOP/s",
             "frac": round(gemm_tf / PEAK_TFLOPS["bf16"], 4),
-            "traffic": measured_traffic(kernel),
+            "traffic": (measured_traffic(kernel) or {}).get("bytes_per_launch"),
+            "traffic_detail": measured_traffic(kernel),
             "gemm_ms": round(phases[1], 4),
             "timing": "average GEMM launch time from HIP events recorded by the library on the launch stream",
         },
