@@ -480,6 +480,10 @@ def main():
         A32, B32 = build_inputs(ctx, members, device, "f32")
     if not args.no_fp32:
         log("FP32 graph timing (same batch, FP32 inputs)")
+        variant32 = P.default_variant("f32")
+        if not args.no_tune:
+            with torch.cuda.stream(stream):
+                variant32 = ctx.tune_batched(A32, B32, axes[0], axes[1], "f32", Cs, stream)
         steps32 = max(2, args.steps // 3)
         _, ev32 = time_graph(ctx, A32, B32, Cs, axes, "f32", steps32, 1, stream)
         ph32 = time_phases(ctx, A32, B32, Cs, axes, "f32", 2, stream)
@@ -488,6 +492,7 @@ def main():
             "value": round(flops / (ev32 * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "ms_per_step": round(ev32, 3),
             "gemm_achieved": round(gemm32, 3), "peak": PEAK_TFLOPS["f32"],
             "frac": round(gemm32 / PEAK_TFLOPS["f32"], 4), "gemm_ms": round(ph32[1], 3),
+            "gemm_variant": {"index": variant32, "name": P.variant_name("f32", variant32), "autotuned": not args.no_tune},
         }
         result["bf16_speedup_vs_fp32"] = round(ev32 / ev_ms, 3)
 
