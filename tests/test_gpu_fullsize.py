@@ -74,7 +74,23 @@ def test_config2_fp32_sampled(ctx):
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     say(f"  sampled rel err {err:.3e}")
     assert err <= 1e-5
-    del A, B, C, a, b
+    del B, C, b
+    # the permutes the benchmark times, on the same tensor: sampled blocks of
+    # the sector-major results equal the transposed input blocks bit for bit
+    # (the axis reversal runs tiles that span several small blocks)
+    inb = {bl.labels: bl for bl in A.blocks()}
+    for perm in ((3, 2, 1, 0), (0, 2, 1, 3), (1, 0, 3, 2)):
+        say(f"  permute {perm}")
+        R = ctx.permute_fuse(A, perm, 2)
+        torch.cuda.synchronize()
+        outb = R.blocks()
+        for i in rng.choice(len(outb), 40, replace=False):
+            ob = outb[int(i)]
+            src = inb[tuple(ob.labels[perm.index(k)] for k in range(4))]
+            want = A.block_view(src).permute(*perm)
+            assert torch.equal(R.block_view(ob), want), (perm, ob.labels)
+        del R
+    del A, a
     torch.cuda.empty_cache()
 
 
