@@ -227,3 +227,17 @@ def test_svd_size_limit_and_sizes():
     u, s, v = c_int64(7), c_int64(7), c_int64(7)
     assert L.lib().sym_svd_sizes(t.handle, byref(u), byref(s), byref(v)) == 0
     assert (u.value, s.value, v.value) == (0, 0, 0)
+
+
+def test_missing_library_fails_loudly():
+    # no CPU fallback: without libsymtensor.so the first library call raises
+    import subprocess
+    import sys
+    code = ("import paper_1203_2222_amd._lib as L\n"
+            "L.LIB_PATH = '/nonexistent/libsymtensor.so'\n"
+            "import paper_1203_2222_amd as P\n"
+            "P.Context(use_torch_allocator=False)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=300)
+    assert r.returncode != 0
+    assert "libsymtensor.so is missing" in r.stderr
