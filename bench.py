@@ -188,6 +188,23 @@ def secondary(ctx, stream, with_cpu=True):
         replay = _timed(lambda: graph.launch(stream), 200, stream)
         out["u1_chi20_latency_us"] = {"eager": round(eager * 1e3, 2), "graph": round(replay * 1e3, 2),
                                       "useful_flops": ctx.flops(A, B, c.axes_a, c.axes_b)}
+        if with_cpu:
+            # the oracle on the same inputs: naive dense einsum (NumPy's C
+            # loops, one thread) and the FP64 pairwise block contraction
+            import os
+            from oracle import contract as K
+            from oracle import tensors as T
+            fa, fb = A.data.double().cpu().numpy(), B.data.double().cpu().numpy()
+            t0 = time.perf_counter()
+            K.contract_dense(T.to_dense(c.A, fa), T.to_dense(c.B, fb), c.axes_a, c.axes_b)
+            t_dense = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            K.contract_pairs(c.A, fa, c.B, fb, c.axes_a, c.axes_b)
+            t_pairs = time.perf_counter() - t0
+            out["u1_chi20_latency_us"]["cpu_baseline"] = {
+                "dense_einsum_us": round(t_dense * 1e6, 1), "blocks_fp64_us": round(t_pairs * 1e6, 1),
+                "unit": "us", "kind": "oracle", "cores": len(os.sched_getaffinity(0)),
+                "sample": "the whole contraction; the dense einsum runs on one thread"}
         del graph, A, B, C
 
         # config 2: one FP32 contraction, chi = 256
