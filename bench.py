@@ -321,6 +321,36 @@ def secondary(ctx, stream, with_cpu=True):
                               "reverse_leg2_ms": round(msv, 3),
                               "reverse_leg2_GBps": round(A.numel() * 8 / msv / 1e6, 1),
                               "fuse_ms": round(msf, 3), "fuse_GBps": round(A.numel() * 8 / msf / 1e6, 1)}
+        if with_cpu:
+            # the oracle's recoupling (F-move then swap of legs 2, 3, in FP64)
+            # on the blocks of 64 sampled label tuples of the same C
+            import os
+            import numpy as np
+            from oracle import su2
+            from oracle import tensors as T
+            blocks = {}
+            for bl in C.blocks():
+                blocks.setdefault(bl.labels, {})[bl.internal] = bl
+            torch.cuda.synchronize()
+            tuples = sorted(blocks)
+            pick = np.random.default_rng(5).choice(len(tuples), min(64, len(tuples)), replace=False)
+            host = {}
+            for k in pick:
+                lab = tuples[int(k)]
+                host[lab] = {e: C.block_view(bl).double().cpu().numpy() for e, bl in blocks[lab].items()}
+            t0 = time.perf_counter()
+            n_el = 0
+            for (j1, j2, j3, j4), ce in host.items():
+                es = T.su2_internals(T.TREE_LEFT, (j1, j2, j3, j4))
+                for f in T.su2_internals(T.TREE_RIGHT, (j1, j2, j3, j4)):
+                    y = sum(su2.fmove(j1, j2, j3, j4, e, f) * ce[e] for e in es)
+                    y = su2.swap_phase(j2, j3, f) * np.ascontiguousarray(np.transpose(y, (0, 2, 1, 3)))
+                    n_el += y.size
+            t_rc = time.perf_counter() - t0
+            out["su2_j4_fp32"]["cpu_baseline"] = {
+                "recouple_GBps": round(n_el * 8 / t_rc / 1e9, 3), "unit": "GB/s", "kind": "oracle",
+                "cores": len(os.sched_getaffinity(0)),
+                "sample": f"{len(host)} label tuples ({n_el} output elements) of the same C, FP64 NumPy"}
         del A, B, C, R, F, T1, T2
     ctx.clear()
     torch.cuda.empty_cache()
