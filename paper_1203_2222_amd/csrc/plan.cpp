@@ -192,9 +192,13 @@ void CopyProgram::finalize() {
             const int64_t nJ = static_cast<int64_t>(op.size[op.tj]) * (op.jhi >= 0 ? op.size[op.jhi] : 1);
             const int nj = static_cast<int>((nJ + kTile - 1) / kTile);
             const int ni = static_cast<int>((nI + (vec ? ti : kTile) - 1) / (vec ? ti : kTile));
-            if (vec && op.ihi < 0 && op.jhi < 0 && 4 * nI * nJ < static_cast<int64_t>(ti) * kTile) {
+            if (vec && op.ihi < 0 && op.jhi < 0 && op.count >= kChunk &&
+                4 * nI * nJ < static_cast<int64_t>(ti) * kTile) {
                 // a small transpose that fills under a quarter of a tile and
-                // has no dim to merge: element-wise (the rows sit in L2)
+                // has no dim to merge: element-wise (the rows sit in L2).
+                // Blocks below one element-wise task stay tiled: the
+                // element-wise kernel runs a workgroup's tasks one after the
+                // other, which a contraction of tiny blocks would wait for.
                 for (int32_t s0 = 0; s0 < op.count; s0 += kChunk)
                     tasks.push_back({static_cast<int32_t>(i), s0, std::min(kChunk, op.count - s0), 0});
                 continue;
