@@ -60,7 +60,17 @@
  *
  * Streams.  Kernels are launched on the hipStream_t passed as `stream` (NULL =
  * the null stream).  The library never synchronises a stream except in
- * sym_graph_* calls and sym_sync.
+ * sym_graph_create_batched, sym_svd and the first call on a new structure
+ * (which builds its plan).
+ *
+ * Overlapping calls.  A plan is cached per structure (the tensors' leg
+ * descriptions, the axes and the compute type) and owns that structure's
+ * workspaces.  Calls that use the same plan (sym_contract, sym_contract_batched,
+ * sym_contract_backward, sym_svd on equal structures, and replays of a graph
+ * built from that plan) write the same workspaces: they must not run at the
+ * same time, whether on different streams, from different threads, or beside
+ * a graph replay.  Calls on different structures, or on different contexts,
+ * may overlap.
  */
 #ifndef SYMTENSOR_H
 #define SYMTENSOR_H
@@ -124,11 +134,31 @@ typedef void* (*sym_alloc_fn)(size_t bytes, void* user);
 typedef void (*sym_free_fn)(void* ptr, void* user);
 
 /* Context: allocator bridge and plan cache.  alloc/free may be NULL (then
- * hipMalloc/hipFree).  Creating a context touches no GPU. */
+ * hipMalloc/hipFree).  Creating a context touches no GPU.  Plan caches are
+ * guarded by a lock, so one context may be used from several threads (subject
+ * to the overlap rule above). */
 int32_t sym_ctx_create(sym_alloc_fn alloc, sym_free_fn free_fn, void* user, sym_ctx** out);
 void sym_ctx_destroy(sym_ctx* ctx);
-/* Drop every cached plan and its workspace. */
+/* Drop every cached plan; a plan's workspaces are freed when nothing else
+ * (a sym_graph, a sym_hold) still refers to it. */
 int32_t sym_ctx_clear(sym_ctx* ctx);
+
+/* Holds: keep plans alive for a graph captured outside the library (the
+ * thesis' "precompute once, reuse every iteration" structure replayed from a
+ * captured iteration).  Between sym_hold_begin and sym_hold_end every plan a
+ * compute call on ctx uses (contraction, backward, permute, recoupling, SVD)
+ * is added to the hold, and stays allocated, device tables and workspaces
+ * included, until sym_hold_destroy, whatever happens to the context's caches
+ * meanwhile (sym_ctx_clear, sym_tune_batched, a plan rebuilt for another tile
+ * variant).  One hold collects at a time per context (SYM_E_ARG otherwise).
+ * sym_hold_count gives the number of plans held.  Destroying a hold frees
+ * nothing the caches still use; a hold must be destroyed while the
+ * context's allocator callbacks can still be called.  Pure host work. */
+typedef struct sym_hold sym_hold;
+int32_t sym_hold_begin(sym_ctx* ctx, sym_hold** out);
+int32_t sym_hold_end(sym_ctx* ctx);
+int32_t sym_hold_count(const sym_hold* h, int64_t* n);
+void sym_hold_destroy(sym_hold* h);
 
 /* Describe a symmetric tensor (section "Block structure"; eq:datak).
  * group: one of the groups above; rank <= SYM_MAX_RANK (SU(2): 4); n_row in
@@ -231,7 +261,8 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
 
 /* count independent contractions C[i] = A[i] . B[i] with the same axes: all
  * fuses in one launch, every sector GEMM of every member in one persistent
- * grouped-GEMM launch, all splits in one launch. */
+ * grouped-GEMM launch, all splits in one launch (in chunks of 64 members; every
+ * chunk is validated before the first launch). */
 int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
                              const sym_tensor* const* B, int32_t n, const int32_t* axesA,
                              const int32_t* axesB, int32_t compute, sym_tensor* const* C,

@@ -6,7 +6,8 @@ in include/symtensor.h); this package only marshals arguments.  Build the
 library with ``python -m paper_1203_2222_amd.build``.
 """
 from ._lib import SymError, lib  # noqa: F401
-from .tensor import Context, Graph, SymTensor, default_variant, fmove_coeff, num_variants, su2_gamma, variant_name  # noqa: F401
+from .tensor import (Context, Graph, Hold, SymTensor, default_variant, fmove_coeff,  # noqa: F401
+                     num_variants, su2_gamma, variant_name)
 
 
 def __getattr__(name):

@@ -39,6 +39,10 @@ SIGNATURES = {
     "sym_ctx_create": (c_int32, [ALLOC_FN, FREE_FN, c_void_p, PP]),
     "sym_ctx_destroy": (None, [P]),
     "sym_ctx_clear": (c_int32, [P]),
+    "sym_hold_begin": (c_int32, [P, PP]),
+    "sym_hold_end": (c_int32, [P]),
+    "sym_hold_count": (c_int32, [P, I64P]),
+    "sym_hold_destroy": (None, [P]),
     "sym_tensor_create": (c_int32, [P, c_int32, c_int32, POINTER(SymLeg), c_int32, c_int32, c_int32, c_int32, P, PP]),
     "sym_tensor_destroy": (None, [P]),
     "sym_tensor_set_data": (c_int32, [P, P]),

@@ -77,11 +77,16 @@ class Chain:
     def capture(self, g: torch.Tensor) -> "torch.cuda.CUDAGraph":
         """A HIP graph of one iteration.  Runs one iteration first, so every
         plan and workspace exists before capture; replaying the graph reuses
-        the handles' buffers, so g and the tensors' data must stay in place."""
+        the handles' buffers, so g and the tensors' data must stay in place.
+        The plans the captured kernels use are held by the graph
+        (``graph.sym_hold``), so clearing or retuning the context cannot free
+        what a replay reads and writes."""
         self.gs[-1].data.copy_(g)
         self.iteration(self.gs[-1].data)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            self.iteration(self.gs[-1].data)
+        with self.ctx.hold() as hold:
+            with torch.cuda.graph(graph):
+                self.iteration(self.gs[-1].data)
+        graph.sym_hold = hold
         return graph

@@ -65,6 +65,7 @@ struct ContractPlan {
     GemmProgram gemm;
     CopyProgram split;     // FP32 -> FP32
     DevMemPtr ws_in, ws_out;
+    int64_t in_elems = 0, out_elems = 0;   // workspace sizes (compute dtype, FP32)
     int grid = 1;
     int64_t flops = 0;
     int requested_variant = -1;   // the variant asked for (the GEMM may run a fallback)
@@ -102,21 +103,56 @@ struct SvdPlan {
     int32_t flag_host = 0;
 };
 
+// Plans kept alive for as long as a caller needs them (sym_hold_*): a graph
+// captured outside the library replays kernels that read a plan's device
+// tables and write its workspaces, so those must outlive any change to the
+// context's caches.
+struct HoldSet {
+    std::mutex mu;
+    std::vector<std::shared_ptr<const void>> plans;
+    void add(const std::shared_ptr<const void>& p) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const auto& q : plans)
+            if (q == p) return;
+        plans.push_back(p);
+    }
+};
+
+struct sym_hold {
+    std::shared_ptr<HoldSet> set;
+};
+
 struct sym_ctx {
     sym_alloc_fn alloc = nullptr;
     sym_free_fn free_fn = nullptr;
     void* user = nullptr;
-    std::mutex mu;
+    std::mutex mu;   // plan caches and the active hold set
     std::unordered_map<std::string, std::shared_ptr<ContractPlan>> contract_plans;
     std::unordered_map<std::string, std::shared_ptr<BackwardPlan>> backward_plans;
     std::unordered_map<std::string, std::shared_ptr<PermutePlan>> permute_plans;
     std::unordered_map<std::string, std::shared_ptr<SvdPlan>> svd_plans;
+    std::shared_ptr<HoldSet> hold;
+    std::mutex tmu;   // tile choice, tuner results and timing events
     int variant[2] = {-1, -1};
     int n_cu = 0;
     bool timing = false;
     bool events_ready = false;
     hipEvent_t ev[4] = {};
     std::unordered_map<std::string, int> tuned;   // plan key hash -> variant
+
+    // record a plan in the active hold set, if any
+    void note(const std::shared_ptr<const void>& plan) {
+        std::shared_ptr<HoldSet> h;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            h = hold;
+        }
+        if (h) h->add(plan);
+    }
+    bool timing_on() {
+        std::lock_guard<std::mutex> lk(tmu);
+        return timing;
+    }
 
     Allocator allocator() {
         return [this](size_t bytes) -> DevMemPtr {
@@ -152,6 +188,7 @@ struct sym_ctx {
     }
 
     void ensure_events() {
+        std::lock_guard<std::mutex> lk(tmu);
         if (events_ready) return;
         for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
         events_ready = true;
@@ -296,35 +333,34 @@ std::string axes_key(int32_t n, const int32_t* a, const int32_t* b) {
 }
 
 int pick_variant(sym_ctx* ctx, int compute, const std::string& key) {
+    std::lock_guard<std::mutex> lk(ctx->tmu);
     if (ctx->variant[compute] >= 0) return ctx->variant[compute];
     auto it = ctx->tuned.find(std::to_string(compute) + ":" + std::to_string(std::hash<std::string>{}(key)));
     if (it != ctx->tuned.end()) return it->second;
     return gemm_default_variant(compute);
 }
 
-std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
-                                                  const sym_tensor* const* B, int32_t n, const int32_t* axA,
-                                                  const int32_t* axB, int32_t compute, sym_tensor* const* C,
-                                                  std::string* key_out, int variant_override) {
+std::string contract_key(int32_t count, const sym_tensor* const* A, const sym_tensor* const* B, int32_t n,
+                         const int32_t* axA, const int32_t* axB, int32_t compute, sym_tensor* const* C,
+                         std::vector<PairInfo>* infos) {
     if (compute != SYM_F32 && compute != SYM_BF16) throw Error(SYM_E_DTYPE, "compute must be F32 or BF16");
     if (count < 1 || count > kMaxBatch) throw Error(SYM_E_ARG, "batch size outside [1, 84]");
     std::ostringstream k;
     k << "C|" << compute << '|' << axes_key(n, axA, axB);
-    std::vector<PairInfo> infos;
     for (int i = 0; i < count; ++i) {
         if (!A[i] || !B[i] || !C[i]) throw Error(SYM_E_ARG, "tensor handle is NULL");
-        infos.push_back(check_pair(*A[i]->d, *B[i]->d, n, axA, axB));
+        PairInfo p = check_pair(*A[i]->d, *B[i]->d, n, axA, axB);
+        if (infos) infos->push_back(std::move(p));
         k << '#' << A[i]->d->key << '#' << B[i]->d->key << '#' << C[i]->d->key;
     }
-    const std::string key = k.str();
-    if (key_out) *key_out = key;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto it = ctx->contract_plans.find(key);
-        if (it != ctx->contract_plans.end() && variant_override < 0 &&
-            it->second->requested_variant == pick_variant(ctx, compute, key))
-            return it->second;
-    }
+    return k.str();
+}
+
+// Host part of a contraction plan: block copies, sector GEMMs, tile list and
+// workspace sizes; no device memory is touched.
+std::shared_ptr<ContractPlan> plan_contract_host(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
+                                                 const sym_tensor* const* B, const std::vector<PairInfo>& infos,
+                                                 int32_t compute, sym_tensor* const* C, int var) {
     auto plan = std::make_shared<ContractPlan>();
     plan->count = count;
     plan->compute = compute;
@@ -364,16 +400,36 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
             plan->split.add(*want_c, c, identity(c.rank), kSlotWsOut, kSlotUser + 2 * count + i, c_base, 0);
         }
     }
-    const int var = variant_override >= 0 ? variant_override : pick_variant(ctx, compute, key);
     plan->requested_variant = var;
     plan->grid = ctx->cus() * gemm_blocks_per_cu(compute, var);
     plan->gemm.finalize(var, plan->grid);
     plan->flops = plan->gemm.flops;
     for (auto& f : plan->fuse) f.finalize();
     plan->split.finalize();
+    plan->in_elems = in_off;
+    plan->out_elems = out_off;
+    return plan;
+}
+
+std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
+                                                  const sym_tensor* const* B, int32_t n, const int32_t* axA,
+                                                  const int32_t* axB, int32_t compute, sym_tensor* const* C,
+                                                  std::string* key_out, int variant_override) {
+    std::vector<PairInfo> infos;
+    const std::string key = contract_key(count, A, B, n, axA, axB, compute, C, &infos);
+    if (key_out) *key_out = key;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->contract_plans.find(key);
+        if (it != ctx->contract_plans.end() && variant_override < 0 &&
+            it->second->requested_variant == pick_variant(ctx, compute, key))
+            return it->second;
+    }
+    const int var = variant_override >= 0 ? variant_override : pick_variant(ctx, compute, key);
+    auto plan = plan_contract_host(ctx, count, A, B, infos, compute, C, var);
     Allocator alloc = ctx->allocator();
-    if (in_off) plan->ws_in = zeroed(alloc, static_cast<size_t>(in_off) * dtype_size(compute));
-    if (out_off) plan->ws_out = alloc(static_cast<size_t>(out_off) * sizeof(float));
+    if (plan->in_elems) plan->ws_in = zeroed(alloc, static_cast<size_t>(plan->in_elems) * dtype_size(compute));
+    if (plan->out_elems) plan->ws_out = alloc(static_cast<size_t>(plan->out_elems) * sizeof(float));
     for (auto& f : plan->fuse) f.upload(alloc);
     plan->gemm.upload(alloc);
     plan->split.upload(alloc);
@@ -381,6 +437,7 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
     ctx->contract_plans[key] = plan;
     return plan;
 }
+
 
 void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor* const* A, const sym_tensor* const* B,
                        sym_tensor* const* C, hipStream_t s, bool allow_timing) {
@@ -393,7 +450,7 @@ void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor*
         t.p[kSlotUser + plan.count + i] = B[i]->data;
         t.p[kSlotUser + 2 * plan.count + i] = C[i]->data;
     }
-    const bool timing = allow_timing && ctx->timing;
+    const bool timing = allow_timing && ctx->timing_on();
     if (timing) {
         ctx->ensure_events();
         HIP_CHECK(hipEventRecord(ctx->ev[0], s));
@@ -452,6 +509,36 @@ int32_t sym_ctx_clear(sym_ctx* ctx) {
         ctx->svd_plans.clear();
     });
 }
+
+int32_t sym_hold_begin(sym_ctx* ctx, sym_hold** out) {
+    return guard([&] {
+        if (!ctx || !out) throw Error(SYM_E_ARG, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->hold) throw Error(SYM_E_ARG, "a hold is already collecting on this context");
+        auto* h = new sym_hold();
+        h->set = std::make_shared<HoldSet>();
+        ctx->hold = h->set;
+        *out = h;
+    });
+}
+
+int32_t sym_hold_end(sym_ctx* ctx) {
+    return guard([&] {
+        if (!ctx) throw Error(SYM_E_ARG, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->hold.reset();
+    });
+}
+
+int32_t sym_hold_count(const sym_hold* h, int64_t* n) {
+    return guard([&] {
+        if (!h || !n) throw Error(SYM_E_ARG, "NULL argument");
+        std::lock_guard<std::mutex> lk(h->set->mu);
+        *n = static_cast<int64_t>(h->set->plans.size());
+    });
+}
+
+void sym_hold_destroy(sym_hold* h) { delete h; }
 
 int32_t sym_tensor_create(sym_ctx* ctx, int32_t group, int32_t rank, const sym_leg* legs, int32_t n_row, int32_t tree,
                           int32_t qtot, int32_t dtype, void* data, sym_tensor** out) {
@@ -623,6 +710,7 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->permute_plans[k.str()] = plan;
         }
+        ctx->note(plan);
         PtrTable t{};
         t.p[0] = in->data;
         t.p[1] = out->data;
@@ -706,6 +794,7 @@ int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->permute_plans[k.str()] = plan;
         }
+        ctx->note(plan);
         PtrTable t{};
         t.p[0] = in->data;
         t.p[1] = out->data;
@@ -774,12 +863,27 @@ int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* cons
                              sym_tensor* const* C, void* stream) {
     return guard([&] {
         if (!ctx || !A || !B || !C) throw Error(SYM_E_ARG, "NULL argument");
+        if (count < 1) throw Error(SYM_E_ARG, "count must be >= 1");
+        // every member is checked, and every chunk planned, before the first
+        // launch, so a bad member leaves all outputs untouched
+        for (int32_t first = 0; first < count; first += 64)
+            (void)contract_key(std::min<int32_t>(64, count - first), A + first, B + first, n, axesA, axesB, compute,
+                               C + first, nullptr);
+        std::vector<std::shared_ptr<ContractPlan>> plans;
         for (int32_t first = 0; first < count; first += 64) {
             const int32_t m = std::min<int32_t>(64, count - first);
-            auto plan = build_contract_plan(ctx, m, A + first, B + first, n, axesA, axesB, compute, C + first, nullptr, -1);
-            run_contract_plan(ctx, *plan, A + first, B + first, C + first, static_cast<hipStream_t>(stream), count <= 64);
+            plans.push_back(build_contract_plan(ctx, m, A + first, B + first, n, axesA, axesB, compute, C + first,
+                                                nullptr, -1));
+            for (int32_t i = first; i < first + m; ++i)
+                if (!has_data(A[i]) || !has_data(B[i]) || !has_data(C[i]))
+                    throw Error(SYM_E_ARG, "tensor has no data pointer");
         }
-        if (count < 1) throw Error(SYM_E_ARG, "count must be >= 1");
+        for (size_t c = 0; c < plans.size(); ++c) {
+            const int32_t first = static_cast<int32_t>(c) * 64;
+            ctx->note(plans[c]);
+            run_contract_plan(ctx, *plans[c], A + first, B + first, C + first, static_cast<hipStream_t>(stream),
+                              count <= 64);
+        }
     });
 }
 
@@ -882,6 +986,7 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
         }
         if (!has_data(A) || !has_data(B) || !has_data(dC) || (dA && !has_data(dA)) || (dB && !has_data(dB)))
             throw Error(SYM_E_ARG, "tensor has no data pointer");
+        ctx->note(plan);
         PtrTable t{};
         t.p[0] = plan->ws_in ? plan->ws_in->ptr : nullptr;
         t.p[1] = plan->ws_out ? plan->ws_out->ptr : nullptr;
@@ -948,6 +1053,7 @@ void sym_graph_destroy(sym_graph* g) {
 int32_t sym_ctx_set_timing(sym_ctx* ctx, int32_t enable) {
     return guard([&] {
         if (!ctx) throw Error(SYM_E_ARG, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->tmu);
         ctx->timing = enable != 0;
     });
 }
@@ -956,7 +1062,10 @@ int32_t sym_ctx_phase_ms(sym_ctx* ctx, int32_t phase, float* ms) {
     return guard([&] {
         if (!ctx || !ms) throw Error(SYM_E_ARG, "NULL argument");
         if (phase < 0 || phase > 2) throw Error(SYM_E_ARG, "phase must be 0, 1 or 2");
-        if (!ctx->events_ready) throw Error(SYM_E_ARG, "timing was not enabled for a contraction");
+        {
+            std::lock_guard<std::mutex> lk(ctx->tmu);
+            if (!ctx->events_ready) throw Error(SYM_E_ARG, "timing was not enabled for a contraction");
+        }
         HIP_CHECK(hipEventElapsedTime(ms, ctx->ev[phase], ctx->ev[phase + 1]));
     });
 }
@@ -987,6 +1096,7 @@ int32_t sym_ctx_set_variant(sym_ctx* ctx, int32_t compute, int32_t variant) {
     return guard([&] {
         if (!ctx || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");
         if (variant >= gemm_num_variants(compute)) throw Error(SYM_E_ARG, "no such variant");
+        std::lock_guard<std::mutex> lk(ctx->tmu);
         ctx->variant[compute] = variant < 0 ? -1 : variant;
     });
 }
@@ -999,8 +1109,12 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
         if (count > 64) throw Error(SYM_E_UNSUPPORTED, "tuning takes at most 64 contractions");
         hipStream_t s = static_cast<hipStream_t>(stream);
         ctx->ensure_events();
-        const bool was_timing = ctx->timing;
-        ctx->timing = true;
+        bool was_timing;
+        {
+            std::lock_guard<std::mutex> lk(ctx->tmu);
+            was_timing = ctx->timing;
+            ctx->timing = true;
+        }
         std::string key;
         float best_ms = 0.f;
         int best = -1;
@@ -1019,9 +1133,12 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
                 best = v;
             }
         }
-        ctx->timing = was_timing;
         const std::string tk = std::to_string(compute) + ":" + std::to_string(std::hash<std::string>{}(key));
-        ctx->tuned[tk] = best;
+        {
+            std::lock_guard<std::mutex> lk(ctx->tmu);
+            ctx->timing = was_timing;
+            ctx->tuned[tk] = best;
+        }
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->contract_plans.erase(key);
@@ -1125,6 +1242,7 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
         if (sweeps) *sweeps = 0;
         if (plan->probs.empty()) return;   // no sector: nothing to factorise or write
         if (!U || !S || !Vt) throw Error(SYM_E_ARG, "NULL argument");
+        ctx->note(plan);
         int32_t done = 0;
         HIP_CHECK(launch_svd(T->d->dtype, T->data, static_cast<const SvdProb*>(plan->d_probs->ptr),
                              static_cast<const int32_t*>(plan->d_pairs->ptr), static_cast<int32_t>(plan->probs.size()),

@@ -21,9 +21,13 @@ LayoutOpts workspace_opts(int32_t dtype, bool trans) {
 namespace {
 
 template <typename T>
-DevMemPtr upload_vec(const Allocator& alloc, const std::vector<T>& v) {
+DevMemPtr upload_vec(const Allocator& alloc, const std::vector<T>& v, Deferred* deferred = nullptr) {
     if (v.empty()) return nullptr;
     DevMemPtr m = alloc(v.size() * sizeof(T));
+    if (deferred) {
+        deferred->push_back({m->ptr, v.data(), v.size() * sizeof(T)});
+        return m;
+    }
     hipError_t e = hipMemcpy(m->ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
     if (e != hipSuccess) throw Error(SYM_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
     return m;
@@ -266,14 +270,14 @@ int32_t CopyProgram::xcd_order(std::vector<TileTask>& list) {
     return grid;
 }
 
-void CopyProgram::upload(const Allocator& alloc) {
-    d_ops = upload_vec(alloc, ops);
-    d_tasks = upload_vec(alloc, tasks);
-    d_wg = upload_vec(alloc, wg_begin);
-    d_tile_tasks = upload_vec(alloc, tile_tasks);
-    d_row_tasks = upload_vec(alloc, row_tasks);
-    d_vtile_tasks = upload_vec(alloc, vtile_tasks);
-    d_mtile_tasks = upload_vec(alloc, mtile_tasks);
+void CopyProgram::upload(const Allocator& alloc, Deferred* deferred) {
+    d_ops = upload_vec(alloc, ops, deferred);
+    d_tasks = upload_vec(alloc, tasks, deferred);
+    d_wg = upload_vec(alloc, wg_begin, deferred);
+    d_tile_tasks = upload_vec(alloc, tile_tasks, deferred);
+    d_row_tasks = upload_vec(alloc, row_tasks, deferred);
+    d_vtile_tasks = upload_vec(alloc, vtile_tasks, deferred);
+    d_mtile_tasks = upload_vec(alloc, mtile_tasks, deferred);
 }
 
 hipError_t CopyProgram::launch(const PtrTable& bufs, hipStream_t s) const {
@@ -512,11 +516,11 @@ void GemmProgram::finalize(int v, int grid) {
     }
 }
 
-void GemmProgram::upload(const Allocator& alloc) {
-    d_probs = upload_vec(alloc, probs);
-    d_tiles = upload_vec(alloc, tiles);
-    d_rows = upload_vec(alloc, erows);
-    d_cols = upload_vec(alloc, ecols);
+void GemmProgram::upload(const Allocator& alloc, Deferred* deferred) {
+    d_probs = upload_vec(alloc, probs, deferred);
+    d_tiles = upload_vec(alloc, tiles, deferred);
+    d_rows = upload_vec(alloc, erows, deferred);
+    d_cols = upload_vec(alloc, ecols, deferred);
 }
 
 hipError_t GemmProgram::launch(const PtrTable& bufs, int grid, hipStream_t s) const {

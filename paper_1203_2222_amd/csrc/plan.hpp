@@ -27,6 +27,18 @@ struct DevMem {
 using DevMemPtr = std::shared_ptr<DevMem>;
 using Allocator = std::function<DevMemPtr(size_t)>;
 
+// A host-to-device copy of a plan table.  Plans whose tables live in memory
+// that other calls reuse (the entry point that allocates nothing) record
+// their uploads instead of performing them, and repeat them before each
+// launch; the host vectors they read belong to the plan and never change
+// after it is built.
+struct HostCopy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+using Deferred = std::vector<HostCopy>;
+
 // A batch of block copies launched together.
 struct CopyProgram {
     std::vector<CopyOp> ops;
@@ -47,7 +59,7 @@ struct CopyProgram {
     void add(const Desc& src, const Desc& dst, const std::vector<int32_t>& perm, int src_buf, int dst_buf,
              int64_t src_base = 0, int64_t dst_base = 0);
     void finalize();
-    void upload(const Allocator& alloc);
+    void upload(const Allocator& alloc, Deferred* deferred = nullptr);
     bool empty() const { return ops.empty(); }
     // XCD-aware order of a tile list for a persistent grid; returns the grid
     static int32_t xcd_order(std::vector<TileTask>& list);
@@ -73,7 +85,7 @@ struct GemmProgram {
     bool add_indirect(const Desc& Z, const Desc& out, const Desc& X, const Desc& Y, int z_buf, int x_buf, int y_buf,
                       int64_t x_base, int64_t y_base);
     void finalize(int variant, int grid);
-    void upload(const Allocator& alloc);
+    void upload(const Allocator& alloc, Deferred* deferred = nullptr);
     hipError_t launch(const PtrTable& bufs, int grid, hipStream_t s) const;
 };
 

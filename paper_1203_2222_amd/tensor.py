@@ -194,8 +194,18 @@ class Context:
             pass
 
     def clear(self):
-        """Drop every cached plan and its workspace."""
+        """Drop every cached plan (workspaces a Hold or Graph still needs stay)."""
         L.check(L.lib().sym_ctx_clear(self.handle))
+
+    def hold(self) -> "Hold":
+        """Collect, until the returned Hold's ``end()`` (or the end of its
+        ``with`` block), every plan the calls on this context use, and keep
+        them allocated for the Hold's lifetime: attach it to a graph captured
+        outside the library so that its replays find their tables and
+        workspaces whatever happens to the context's caches."""
+        h = c_void_p()
+        L.check(L.lib().sym_hold_begin(self.handle, byref(h)))
+        return Hold(self, h)
 
     def close(self):
         h = getattr(self, "handle", None)
@@ -392,6 +402,44 @@ class Context:
                                          _dtype_code(compute), L.ptr_array(c.handle.value for c in Cs),
                                          _stream(stream), byref(best)))
         return best.value
+
+
+class Hold:
+    """Plans kept alive for a graph captured outside the library (sym_hold_*)."""
+
+    def __init__(self, ctx: Context, handle: c_void_p):
+        self._ctx = ctx   # its allocator callbacks free the held workspaces
+        self.handle = handle
+        self._open = True
+
+    def end(self) -> None:
+        if self._open:
+            self._open = False
+            L.check(L.lib().sym_hold_end(self._ctx.handle))
+
+    def __enter__(self) -> "Hold":
+        return self
+
+    def __exit__(self, *exc) -> None:
+        self.end()
+
+    def count(self) -> int:
+        n = c_int64()
+        L.check(L.lib().sym_hold_count(self.handle, byref(n)))
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                self.end()
+            except Exception:
+                pass
+            self.handle = None
+            try:
+                L.lib().sym_hold_destroy(h)
+            except Exception:   # interpreter shutdown
+                pass
 
 
 class Graph:

@@ -154,6 +154,42 @@ def test_error_paths():
     assert "NULL" in L.lib().sym_last_error().decode()
 
 
+def test_hold_api():
+    import paper_1203_2222_amd as P
+    ctx = _ctx()
+    h = ctx.hold()
+    assert h.count() == 0
+    with pytest.raises(P.SymError) as e:   # one collecting hold per context
+        ctx.hold()
+    assert e.value.status == 1
+    h.end()
+    h2 = ctx.hold()   # the next hold may start once the first stopped collecting
+    h2.end()
+    assert h.count() == 0 and h2.count() == 0
+    del h, h2
+    ctx.clear()
+
+
+def test_batched_checks_every_member_before_device_work():
+    # A spectrum mismatch in member 70 (the second chunk of 64) is reported as
+    # such.  Without a GPU any device call fails with SYM_E_HIP, so getting
+    # SYM_E_SPECTRUM shows the check ran before any plan or launch.
+    from paper_1203_2222_amd import _lib as L
+    ctx = _ctx()
+    c = W.config1()
+    a = ctx.describe(c.A, 4)
+    cc = ctx.describe(K.result_spec(c.A, c.B, c.axes_a, c.axes_b), 4)
+    lj = W.u1_leg(-2, 2, [4, 4, 4, 4, 3], "out")
+    odd = ctx.describe(W.TensorSpec(W.U1, (lj, lj, lj.flipped(), lj.flipped())), 4)
+    As = [a] * 71
+    Bs = [a] * 70 + [odd]
+    Cs = [cc] * 71
+    st = L.lib().sym_contract_batched(ctx.handle, 71, L.ptr_array(x.handle.value for x in As),
+                                      L.ptr_array(x.handle.value for x in Bs), 2, L.i32_array((2, 3)),
+                                      L.i32_array((0, 1)), L.SYM_F32, L.ptr_array(x.handle.value for x in Cs), None)
+    assert st == 2, L.lib().sym_last_error()
+
+
 def test_variant_names_and_default():
     import paper_1203_2222_amd as P
     for compute in ("f32", "bf16"):

@@ -172,3 +172,28 @@ def test_bf16_variants_bitwise_equal(ctx):
     for v, o in outs.items():
         for m, a, b in zip(members, outs[0], o):
             assert np.array_equal(a, b), (v, m.name)
+
+
+def test_batch_beyond_one_chunk_and_bad_member_leaves_outputs_untouched(ctx):
+    # 71 members run as chunks of 64 and 7; a C that does not describe member
+    # 70's result is rejected before the first chunk launches
+    import paper_1203_2222_amd as P
+    say("case batch of 71 with a bad last member")
+    base = _members()
+    members = [base[i % len(base)] for i in range(71)]
+    As, Bs, Cs, host_in = _build(ctx, members)
+    bad = ctx.tensor(W.TensorSpec(W.U1, tuple(members[70].A.legs), qtot=1), 4)   # wrong total charge
+    for C in Cs:
+        C.data.fill_(float("nan"))
+    torch.cuda.synchronize()
+    with pytest.raises(P.SymError) as e:
+        ctx.contract_batched(As, Bs, (2, 3), (0, 1), "f32", outs=Cs[:70] + [bad])
+    assert e.value.status == 9
+    torch.cuda.synchronize()
+    for C in Cs:
+        assert bool(torch.isnan(C.data).all())
+    ctx.contract_batched(As, Bs, (2, 3), (0, 1), "f32", outs=Cs)
+    for i in (0, 63, 64, 70):
+        m = members[i]
+        _, ref = K.contract_pairs(m.A, host_in[i][0], m.B, host_in[i][1], m.axes_a, m.axes_b)
+        assert rel_err(host(Cs[i]), ref) <= 1e-5, i

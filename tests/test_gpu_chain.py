@@ -119,3 +119,33 @@ def test_chain_graph_replay_matches_eager(ctx):
             assert np.array_equal(a, b), rep
         ch.iteration(ch.gs[-1].data)   # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_chain_graph_holds_its_plans_through_context_clear(ctx):
+    # the captured kernels read plan tables and write plan workspaces: a hold
+    # attached to the graph keeps them allocated when the context drops its
+    # caches, and new eager plans then get memory of their own
+    say("case chain graph replay after ctx.clear()")
+    from paper_1203_2222_amd.chain import Chain
+    specs = _specs(4)
+    xs, gen = _build(ctx, specs, 14)
+    ch = Chain(ctx, xs, [AX] * 3)
+    g = W.gaussian(ch.output.numel(), gen, "cuda")
+    ch.iteration(g)
+    torch.cuda.synchronize()
+    eager = [host(d).copy() for d in ch.grads] + [host(ch.output).copy()]
+    graph = ch.capture(g)
+    assert graph.sym_hold.count() >= 2   # the forward and the backward plans (links of equal structure share one)
+    for rep in range(3):
+        ctx.clear()
+        junk = torch.full((1 << 24,), float("nan"), device="cuda")   # recycled memory gets overwritten
+        ch.iteration(ch.gs[-1].data)   # eager plans rebuilt in fresh memory
+        for t in ch.grads[1:] + [ch.output]:
+            t.data.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [host(d) for d in ch.grads] + [host(ch.output)]
+        for a, b in zip(eager, got):
+            assert np.array_equal(a, b), rep
+        del junk
