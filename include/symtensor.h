@@ -250,6 +250,28 @@ int32_t sym_contract(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int
                      const int32_t* axesA, const int32_t* axesB, int32_t compute, sym_tensor* C,
                      void* stream);
 
+/* sym_contract for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bit for bit) as sym_contract; the
+ * difference is where the library's own device memory lives.  Instead of
+ * workspaces from the context's allocator, the fused operands, any split
+ * workspace and the plan's tables are placed in a fixed array of
+ * sym_noalloc_capacity() bytes (64 MiB) that the library holds on every
+ * device it runs on until the process ends.  No call allocates or frees
+ * device memory (the host plan is built on the first call per structure and
+ * cached in the context, host memory only).
+ * Limit: a contraction whose fused operands, split workspace and tables need
+ * more than the array holds fails with SYM_E_UNSUPPORTED before any launch.
+ * All calls on one device share the array and find it as the last call left
+ * it: each call first re-uploads its tables (asynchronous copies on
+ * `stream`) and clears the fused-operand workspace with a kernel.  Calls that
+ * overlap in time on one device (any context, any stream) race on the array
+ * and must not be made. */
+int32_t sym_contract_noalloc(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
+                             const int32_t* axesA, const int32_t* axesB, int32_t compute, sym_tensor* C,
+                             void* stream);
+int32_t sym_noalloc_capacity(int64_t* bytes);
+
 /* Backward of C = A . B for a cotangent dC (same description as C): per
  * sector dA_s = dC_s B_s^T and dB_s = A_s^T dC_s, split back into A's and B's
  * layouts (the adjoint of eq:blockmult).  dA or dB may be NULL to skip it;

@@ -58,6 +58,8 @@ SIGNATURES = {
     "sym_su2_gamma": (c_int32, [c_int32, I32P, c_int32, I32P, c_int32, I32P, I32P, I32P, POINTER(c_double)]),
     "sym_contract_output": (c_int32, [P, P, P, c_int32, I32P, I32P, P, PP]),
     "sym_contract": (c_int32, [P, P, P, c_int32, I32P, I32P, c_int32, P, P]),
+    "sym_contract_noalloc": (c_int32, [P, P, P, c_int32, I32P, I32P, c_int32, P, P]),
+    "sym_noalloc_capacity": (c_int32, [I64P]),
     "sym_contract_backward": (c_int32, [P, P, P, P, c_int32, I32P, I32P, c_int32, P, P, P]),
     "sym_contract_batched": (c_int32, [P, c_int32, PP, PP, c_int32, I32P, I32P, c_int32, PP, P]),
     "sym_contract_flops": (c_int32, [P, P, P, c_int32, I32P, I32P, I64P]),

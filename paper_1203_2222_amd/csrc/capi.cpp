@@ -69,6 +69,11 @@ struct ContractPlan {
     int grid = 1;
     int64_t flops = 0;
     int requested_variant = -1;   // the variant asked for (the GEMM may run a fallback)
+    // Plans of the no-alloc entry point: tables and workspaces live in the
+    // fixed scratch array, which every such call reuses, so each launch first
+    // repeats the table uploads and clears the fused-operand workspace.
+    bool noalloc = false;
+    Deferred staged;
 };
 
 struct BackwardPlan {
@@ -128,6 +133,7 @@ struct sym_ctx {
     void* user = nullptr;
     std::mutex mu;   // plan caches and the active hold set
     std::unordered_map<std::string, std::shared_ptr<ContractPlan>> contract_plans;
+    std::unordered_map<std::string, std::shared_ptr<ContractPlan>> noalloc_plans;
     std::unordered_map<std::string, std::shared_ptr<BackwardPlan>> backward_plans;
     std::unordered_map<std::string, std::shared_ptr<PermutePlan>> permute_plans;
     std::unordered_map<std::string, std::shared_ptr<SvdPlan>> svd_plans;
@@ -438,6 +444,50 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
     return plan;
 }
 
+// Plan of the no-alloc entry point on the current device: the workspaces
+// and every table are laid out back to back in that device's scratch array
+// (256-byte aligned ranges); the uploads are recorded, to be repeated before
+// each launch.  No device memory is allocated.
+std::shared_ptr<ContractPlan> build_noalloc_plan(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
+                                                 const int32_t* axA, const int32_t* axB, int32_t compute,
+                                                 sym_tensor* C) {
+    std::vector<PairInfo> infos;
+    const std::string key = contract_key(1, &A, &B, n, axA, axB, compute, &C, &infos);
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    void* base = nullptr;
+    HIP_CHECK(noalloc_scratch(&base));
+    const std::string nkey = "N|" + std::to_string(dev) + '|' + key;
+    const int var = pick_variant(ctx, compute, key);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->noalloc_plans.find(nkey);
+        if (it != ctx->noalloc_plans.end() && it->second->requested_variant == var) return it->second;
+    }
+    auto plan = plan_contract_host(ctx, 1, &A, &B, infos, compute, &C, var);
+    plan->noalloc = true;
+    size_t used = 0;
+    char* const b = static_cast<char*>(base);
+    Allocator arena = [b, &used](size_t bytes) -> DevMemPtr {
+        auto m = std::make_shared<DevMem>();   // no release: the array is never freed
+        m->bytes = static_cast<size_t>(align_up(static_cast<int64_t>(std::max<size_t>(bytes, 256)), 256));
+        m->ptr = b + used;
+        used += m->bytes;
+        return m;
+    };
+    if (plan->in_elems) plan->ws_in = arena(static_cast<size_t>(plan->in_elems) * dtype_size(compute));
+    if (plan->out_elems) plan->ws_out = arena(static_cast<size_t>(plan->out_elems) * sizeof(float));
+    for (auto& f : plan->fuse) f.upload(arena, &plan->staged);
+    plan->gemm.upload(arena, &plan->staged);
+    plan->split.upload(arena, &plan->staged);
+    if (used > kNoAllocScratchBytes)
+        throw Error(SYM_E_UNSUPPORTED, "contraction needs " + std::to_string(used) +
+                                           " bytes of workspace and tables; the no-alloc scratch holds " +
+                                           std::to_string(kNoAllocScratchBytes));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->noalloc_plans[nkey] = plan;
+    return plan;
+}
 
 void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor* const* A, const sym_tensor* const* B,
                        sym_tensor* const* C, hipStream_t s, bool allow_timing) {
@@ -449,6 +499,12 @@ void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor*
         t.p[kSlotUser + i] = A[i]->data;
         t.p[kSlotUser + plan.count + i] = B[i]->data;
         t.p[kSlotUser + 2 * plan.count + i] = C[i]->data;
+    }
+    if (plan.noalloc) {
+        // the scratch array holds whatever the last call on this device left
+        for (const HostCopy& c : plan.staged)
+            HIP_CHECK(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, s));
+        if (plan.ws_in) HIP_CHECK(launch_zero16(plan.ws_in->ptr, plan.ws_in->bytes, s));
     }
     const bool timing = allow_timing && ctx->timing_on();
     if (timing) {
@@ -504,6 +560,7 @@ int32_t sym_ctx_clear(sym_ctx* ctx) {
         if (!ctx) throw Error(SYM_E_ARG, "ctx is NULL");
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->contract_plans.clear();
+        ctx->noalloc_plans.clear();
         ctx->backward_plans.clear();
         ctx->permute_plans.clear();
         ctx->svd_plans.clear();
@@ -890,6 +947,23 @@ int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* cons
 int32_t sym_contract(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n, const int32_t* axesA,
                      const int32_t* axesB, int32_t compute, sym_tensor* C, void* stream) {
     return sym_contract_batched(ctx, 1, &A, &B, n, axesA, axesB, compute, &C, stream);
+}
+
+int32_t sym_contract_noalloc(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n, const int32_t* axesA,
+                             const int32_t* axesB, int32_t compute, sym_tensor* C, void* stream) {
+    return guard([&] {
+        if (!ctx || !A || !B || !C) throw Error(SYM_E_ARG, "NULL argument");
+        auto plan = build_noalloc_plan(ctx, A, B, n, axesA, axesB, compute, C);
+        if (!has_data(A) || !has_data(B) || !has_data(C)) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        run_contract_plan(ctx, *plan, &A, &B, &C, static_cast<hipStream_t>(stream), false);
+    });
+}
+
+int32_t sym_noalloc_capacity(int64_t* bytes) {
+    return guard([&] {
+        if (!bytes) throw Error(SYM_E_ARG, "NULL argument");
+        *bytes = static_cast<int64_t>(kNoAllocScratchBytes);
+    });
 }
 
 // ----- backward -----------------------------------------------------------------

@@ -3,7 +3,9 @@
 // recoupling of reduced blocks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -1836,6 +1838,54 @@ hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const Fm
     if (n_tasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_recouple, dim3(static_cast<unsigned>(n_tasks)), dim3(256), 0, s, groups, in_blks, out_blks, coef,
                        tasks, bufs, in_buf, out_buf);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device memory of the entry point that allocates nothing.  The array
+// is a module variable: every GPU the library runs on holds its own copy for
+// the life of the process.  On the host its name is only a stand-in for the
+// symbol; the device address comes from hipGetSymbolAddress, looked up once
+// per device with that device current, and only that address is ever handed
+// to kernels or copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+// Zero fill by a kernel (also inside captured graphs, where a memset node is
+// avoided); n16 16-byte words from a 16-byte aligned address.
+__global__ __launch_bounds__(256) void k_zero16(u32x4* __restrict__ p, int64_t n16) {
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n16;
+         i += static_cast<int64_t>(gridDim.x) * 256)
+        p[i] = z;
+}
+
+hipError_t launch_zero16(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if ((bytes & 15u) != 0 || (reinterpret_cast<uintptr_t>(p) & 15u) != 0) return hipErrorInvalidValue;
+    const int64_t n16 = static_cast<int64_t>(bytes / 16);
+    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero16, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, static_cast<u32x4*>(p), n16);
     return hipGetLastError();
 }
 

@@ -185,4 +185,12 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
 // Resident workgroups per CU of a variant (persistent grid sizing).
 int gemm_blocks_per_cu(int compute, int variant);
 
+// Device memory of the entry point that allocates nothing: a fixed array of
+// kNoAllocScratchBytes on every device, its address for the current device
+// (looked up on the first call on that device).
+constexpr size_t kNoAllocScratchBytes = size_t{64} << 20;
+hipError_t noalloc_scratch(void** ptr);
+// Zero `bytes` (a multiple of 16) from a 16-byte aligned device address.
+hipError_t launch_zero16(void* p, size_t bytes, hipStream_t s);
+
 }  // namespace sym

@@ -316,6 +316,16 @@ class Context:
                                      C.handle, _stream(stream)))
         return C
 
+    def contract_noalloc(self, A: SymTensor, B: SymTensor, axes_a, axes_b, compute="f32", out: SymTensor = None,
+                         stream=None) -> SymTensor:
+        """sym_contract_noalloc: the library allocates no device memory (its
+        workspaces and tables sit in a fixed per-device array)."""
+        C = out if out is not None else self.contract_output(A, B, axes_a, axes_b)
+        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
+        L.check(L.lib().sym_contract_noalloc(self.handle, A.handle, B.handle, len(axes_a), aa, ab,
+                                             _dtype_code(compute), C.handle, _stream(stream)))
+        return C
+
     def contract_batched(self, As, Bs, axes_a, axes_b, compute="bf16", outs=None, stream=None):
         Cs = outs if outs is not None else [self.contract_output(a, b, axes_a, axes_b) for a, b in zip(As, Bs)]
         aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
@@ -440,6 +450,12 @@ class Hold:
                 L.lib().sym_hold_destroy(h)
             except Exception:   # interpreter shutdown
                 pass
+
+
+def noalloc_capacity() -> int:
+    n = c_int64()
+    L.check(L.lib().sym_noalloc_capacity(byref(n)))
+    return n.value
 
 
 class Graph:

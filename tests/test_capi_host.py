@@ -154,7 +154,7 @@ def test_error_paths():
     assert "NULL" in L.lib().sym_last_error().decode()
 
 
-def test_hold_api():
+def test_hold_api_and_noalloc_capacity():
     import paper_1203_2222_amd as P
     ctx = _ctx()
     h = ctx.hold()
@@ -168,6 +168,7 @@ def test_hold_api():
     assert h.count() == 0 and h2.count() == 0
     del h, h2
     ctx.clear()
+    assert P.noalloc_capacity() == 64 << 20
 
 
 def test_batched_checks_every_member_before_device_work():
