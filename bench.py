@@ -70,35 +70,42 @@ def build_batch(ctx, members, device, dtype="f32"):
 
 
 def time_graph(ctx, As, Bs, Cs, axes, compute, steps, warmup, stream):
+    """Replays of the batch's HIP graph: `warmup` untimed, then exactly
+    `steps` timed, each between two HIP events on the launch stream, with a
+    device synchronisation before and after.  Returns (wall ms per step,
+    median ms per replay, mean ms per replay)."""
+    import statistics
     import torch
     graph = ctx.graph_batched(As, Bs, axes[0], axes[1], compute, Cs, stream)
     for _ in range(warmup):
         graph.launch(stream)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):
+    evs[0].record(stream)
+    for i in range(steps):
         graph.launch(stream)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    return wall, ev0.elapsed_time(ev1) / steps
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return wall, statistics.median(per), sum(per) / steps
 
 
 def time_phases(ctx, As, Bs, Cs, axes, compute, reps, stream):
-    """Average per-phase kernel time (ms) from the library's HIP events,
-    recorded on the stream the kernels run on."""
+    """Median per-phase kernel time (ms) over `reps` calls, from the
+    library's HIP events recorded on the stream the kernels run on."""
+    import statistics
     import torch
     ctx.set_timing(True)
-    acc = [0.0, 0.0, 0.0]
+    acc = [[], [], []]
     for _ in range(reps):
         ctx.contract_batched(As, Bs, axes[0], axes[1], compute, Cs, stream)
         torch.cuda.synchronize()
         for p in range(3):
-            acc[p] += ctx.phase_ms(p)
+            acc[p].append(ctx.phase_ms(p))
     ctx.set_timing(False)
-    return [a / reps for a in acc]
+    return [statistics.median(a) for a in acc]
 
 
 def cpu_baseline(members, As, Bs, budget_s):
@@ -130,16 +137,27 @@ def cpu_baseline(members, As, Bs, budget_s):
 
 
 def _timed(fn, reps, stream):
+    """Median ms of `reps` calls of fn, each between HIP events on `stream`."""
+    import statistics
     import torch
     fn()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record(stream)
+    for i in range(reps):
         fn()
-    e1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    return statistics.median(evs[i].elapsed_time(evs[i + 1]) for i in range(reps))
+
+
+def _rel(got, ref):
+    import numpy as np
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def _oracle_info(t_s, sample):
+    return {"seconds": round(t_s, 4), "kind": "oracle", "cores": len(os.sched_getaffinity(0)), "sample": sample}
 
 
 def cpu_baseline_svd(spec, flat_dev):
@@ -198,6 +216,8 @@ def secondary(ctx, stream, with_cpu=True):
             t0 = time.perf_counter()
             K.contract_dense(T.to_dense(c.A, fa), T.to_dense(c.B, fb), c.axes_a, c.axes_b)
             t_dense = time.perf_counter() - t0
+            dense_c = K.contract_dense(T.to_dense(c.A, fa), T.to_dense(c.B, fb), c.axes_a, c.axes_b)
+            t_dense = time.perf_counter() - t0
             t0 = time.perf_counter()
             K.contract_pairs(c.A, fa, c.B, fb, c.axes_a, c.axes_b)
             t_pairs = time.perf_counter() - t0
@@ -205,6 +225,13 @@ def secondary(ctx, stream, with_cpu=True):
                 "dense_einsum_us": round(t_dense * 1e6, 1), "blocks_fp64_us": round(t_pairs * 1e6, 1),
                 "unit": "us", "kind": "oracle", "cores": len(os.sched_getaffinity(0)),
                 "sample": "the whole contraction; the dense einsum runs on one thread"}
+            sc = K.result_spec(c.A, c.B, c.axes_a, c.axes_b)
+            Cc = ctx.tensor(C.spec, 4)
+            ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=Cc, stream=stream)
+            torch.cuda.synchronize()
+            out["u1_chi20_latency_us"]["rel_err_fp32_vs_dense_oracle"] = _rel(
+                Cc.data.double().cpu().numpy(), T.from_dense(sc, dense_c))
+            del Cc
         del graph, A, B, C
 
         # config 2: one FP32 contraction, chi = 256
@@ -217,6 +244,17 @@ def secondary(ctx, stream, with_cpu=True):
         out["u1_chi256_fp32"] = {"TFLOPs": round(fl / ms / 1e9, 2), "ms": round(ms, 3),
                                  "gemm_TFLOPs": round(fl / ph[1] / 1e9, 2),
                                  "gemm_frac_fp32_peak": round(fl / ph[1] / 1e9 / PEAK_TFLOPS["f32"], 4)}
+        if with_cpu:
+            from oracle import contract as K
+            fa, fb = A.data.double().cpu().numpy(), B.data.double().cpu().numpy()
+            t0 = time.perf_counter()
+            _, ref = K.contract_sectors(c.A, fa, c.B, fb, c.axes_a, c.axes_b)
+            t_or = time.perf_counter() - t0
+            out["u1_chi256_fp32"]["cpu_baseline"] = {
+                "value": round(fl / t_or / 1e12, 4), "unit": "TFLOP/s", **_oracle_info(
+                    t_or, "the whole contraction by per-sector FP64 numpy matmul")}
+            out["u1_chi256_fp32"]["rel_err_fp32_vs_fp64_oracle"] = _rel(Cs[0].data.double().cpu().numpy(), ref)
+            del fa, fb, ref
         # permute bandwidth on the same tensor (the E2-style permute benchmark)
         for perm in ((0, 2, 1, 3), (3, 2, 1, 0)):
             P0 = ctx.permute_fuse(A, perm, 2)
@@ -239,6 +277,30 @@ def secondary(ctx, stream, with_cpu=True):
         out["u1_chi128_grad_fp32"] = {"forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
                                       "forward_TFLOPs": round(fl / fwd / 1e9, 2),
                                       "backward_TFLOPs": round(2 * fl / bwd / 1e9, 2)}
+        if with_cpu:
+            # the oracle's forward (per-sector FP64) and gradients of
+            # <contract(A,B), G> on the same draws; G as a canonical block list
+            from oracle import contract as K
+            from oracle import grad as GR
+            G = ctx.tensor(C.spec, 4, data=W.gaussian(C.numel(), g, "cuda"))
+            Cc = ctx.tensor(C.spec, 4)
+            ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=Cc, stream=stream)
+            ctx.contract_backward(A, B, G, c.axes_a, c.axes_b, "f32", dA=dA, dB=dB, stream=stream)
+            torch.cuda.synchronize()
+            fa, fb, fg = (x.data.double().cpu().numpy() for x in (A, B, G))
+            t0 = time.perf_counter()
+            _, ref = K.contract_sectors(c.A, fa, c.B, fb, c.axes_a, c.axes_b)
+            t_f = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            ga, gb = GR.grads(c.A, fa, c.B, fb, fg, c.axes_a, c.axes_b)
+            t_b = time.perf_counter() - t0
+            out["u1_chi128_grad_fp32"]["cpu_baseline"] = {
+                "forward_TFLOPs": round(fl / t_f / 1e12, 4), "backward_TFLOPs": round(2 * fl / t_b / 1e12, 4),
+                "unit": "TFLOP/s", **_oracle_info(t_f + t_b, "the whole forward and backward, FP64 numpy")}
+            out["u1_chi128_grad_fp32"]["rel_err_fp32_vs_fp64_oracle"] = {
+                "C": _rel(Cc.data.double().cpu().numpy(), ref), "dA": _rel(dA.data.double().cpu().numpy(), ga),
+                "dB": _rel(dB.data.double().cpu().numpy(), gb)}
+            del G, Cc, fa, fb, fg, ref, ga, gb
         del A, B, C, dC, dA, dB
 
         # a network-update step at config 4's shapes: chain X0.X1.X2.X3 with the
@@ -351,10 +413,124 @@ def secondary(ctx, stream, with_cpu=True):
                 "recouple_GBps": round(n_el * 8 / t_rc / 1e9, 3), "unit": "GB/s", "kind": "oracle",
                 "cores": len(os.sched_getaffinity(0)),
                 "sample": f"{len(host)} label tuples ({n_el} output elements) of the same C, FP64 NumPy"}
+            # the whole contraction by the oracle's pairwise block route, and
+            # the errors of C and of the recoupled R against it
+            from oracle import contract as K
+            from oracle import recouple as RC
+            fa, fb = A.data.double().cpu().numpy(), B.data.double().cpu().numpy()
+            t0 = time.perf_counter()
+            sc, ref = K.contract_pairs(c.A, fa, c.B, fb, c.axes_a, c.axes_b)
+            t_c = time.perf_counter() - t0
+            out["su2_j4_fp32"]["cpu_baseline"]["contract_TFLOPs"] = round(fl / t_c / 1e12, 4)
+            out["su2_j4_fp32"]["cpu_baseline"]["contract_seconds"] = round(t_c, 3)
+            Cc = ctx.permute_fuse(C, (0, 1, 2, 3), 4)
+            torch.cuda.synchronize()
+            out["su2_j4_fp32"]["rel_err_fp32_vs_fp64_oracle"] = {"C": _rel(Cc.data.double().cpu().numpy(), ref)}
+            _, rref = RC.fmove_swap(sc, ref)
+            out["su2_j4_fp32"]["rel_err_fp32_vs_fp64_oracle"]["recoupled"] = _rel(R.data.double().cpu().numpy(), rref)
+            del fa, fb, ref, rref, Cc
         del A, B, C, R, F, T1, T2
+
+        # tiny SU(2) instances (d_j = 1; spins up to 2 and up to 4, chi = 15
+        # and 45): device latency, and the oracle's naive dense einsum (one
+        # thread) of the same contraction, whose result pins the device's
+        if with_cpu:
+            import numpy as np
+            from oracle import contract as K
+            from oracle import tensors as T
+            for max2j in (4, 8):
+                c = W.config5_tiny(max2j)
+                A, B, _ = make(c)
+                C = ctx.contract_output(A, B, c.axes_a, c.axes_b)
+                us = _timed(lambda: ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=C, stream=stream), 50,
+                            stream) * 1e3
+                Cc = ctx.permute_fuse(C, (0, 1, 2, 3), 4)
+                torch.cuda.synchronize()
+                fa, fb = A.data.double().cpu().numpy(), B.data.double().cpu().numpy()
+                da, db = T.to_dense(c.A, fa), T.to_dense(c.B, fb)
+                t0 = time.perf_counter()
+                dc = K.contract_dense(da, db, c.axes_a, c.axes_b)
+                t_d = time.perf_counter() - t0
+                sc = K.result_spec(c.A, c.B, c.axes_a, c.axes_b)
+                chi = sum(d * (l + 1) for l, d in zip(c.A.legs[0].labels, c.A.legs[0].degs))
+                out[f"su2_tiny_chi{chi}"] = {
+                    "gpu_us": round(us, 2), "useful_flops": ctx.flops(A, B, c.axes_a, c.axes_b),
+                    "dense_naive_macs": int(np.prod(da.shape) * db.shape[2] * db.shape[3]),
+                    "cpu_baseline": {"dense_einsum_ms": round(t_d * 1e3, 2), **_oracle_info(
+                        t_d, "the whole contraction by NumPy einsum without path optimisation, one thread")},
+                    "rel_err_fp32_vs_dense_oracle": _rel(Cc.data.double().cpu().numpy(), T.from_dense(sc, dc))}
+                del A, B, C, Cc
     ctx.clear()
     torch.cuda.empty_cache()
     return out
+
+
+def literal_prefix(ctx, stream, variant, margin_bytes=8 << 30):
+    """The batched workload with its drawn per-index dimensions taken
+    literally ({64,128,256,512}, no halving): the longest prefix of the
+    members, in draw order, whose operands, fused operands, outputs and split
+    workspaces fit the free device memory.  One BF16 step of that prefix
+    (plan built and graph captured first), the GEMM's share and fraction."""
+    import torch
+    import paper_1203_2222_amd as P
+    import workloads as W
+    members = W.config3_literal_members(64)
+    free, total = torch.cuda.mem_get_info()
+    budget = free - margin_bytes
+    chosen, need = [], 0
+    for m in members:
+        n = ctx.describe(m.A, 4).numel()
+        # BF16 A and B, their fused BF16 copies (rows padded: 3 % allowed),
+        # FP32 C, and the FP32 split workspace of outputs past 2^29 entries
+        b = n * (2 + 2) + int(n * (2 + 2) * 1.03) + n * 4 + (n * 4 if n >= (1 << 29) else 0)
+        if need + b > budget:
+            break
+        need += b
+        chosen.append(m)
+    log(f"literal-chi prefix: {len(chosen)} members, about {need / 1e9:.1f} GB of {free / 1e9:.1f} GB free")
+    As, Bs, Cs = [], [], []
+    for m in chosen:
+        g = W.generator(m.seed, "cuda")
+        for spec, dst in ((m.A, As), (m.B, Bs)):
+            n = ctx.describe(spec, 4).numel()
+            buf = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+            step = 1 << 28   # draws in slices: no full-size FP32 temporary
+            for i in range(0, n, step):
+                buf[i:i + step] = torch.randn(min(step, n - i), generator=g, device="cuda").to(torch.bfloat16)
+            dst.append(ctx.tensor(spec, 4, "bf16", data=buf))
+    Cs = build_outputs(ctx, chosen, As, Bs)
+    axes = (chosen[0].axes_a, chosen[0].axes_b)
+    flops = sum(ctx.flops(a, b, *axes) for a, b in zip(As, Bs))
+    ctx.set_variant("bf16", variant)
+    try:
+        with torch.cuda.stream(stream):
+            t0 = time.perf_counter()
+            ctx.contract_batched(As, Bs, axes[0], axes[1], "bf16", Cs, stream)
+            torch.cuda.synchronize()
+            first_s = time.perf_counter() - t0
+            _, med, mean = time_graph(ctx, As, Bs, Cs, axes, "bf16", 3, 1, stream)
+            ph = time_phases(ctx, As, Bs, Cs, axes, "bf16", 3, stream)
+    finally:
+        ctx.set_variant("bf16", -1)
+    used = torch.cuda.max_memory_allocated()
+    res = {
+        "members": len(chosen), "chi": [m.extra["chi"] for m in chosen],
+        "stored_elements_per_operand": int(sum(a.numel() for a in As)),
+        "useful_flops": int(flops), "ms_per_step": round(med, 3),
+        "TFLOPs": round(flops / med / 1e9, 2),
+        "phases_ms": {"fuse": round(ph[0], 3), "gemm": round(ph[1], 3), "split": round(ph[2], 3)},
+        "gemm_TFLOPs": round(flops / ph[1] / 1e9, 2),
+        "gemm_frac_bf16_peak": round(flops / ph[1] / 1e9 / PEAK_TFLOPS["bf16"], 4),
+        "first_call_s": round(first_s, 2), "peak_device_bytes": int(used),
+        "gemm_variant": {"index": variant, "name": P.variant_name("bf16", variant)},
+        "what": "longest draw-order prefix of the batch with chi in {64,128,256,512} that fits the device; "
+                "outputs of 2^29 entries or more take the separate split pass; inputs are BF16 draws made in "
+                "slices (not the unsliced stream of the tests)",
+    }
+    del As, Bs, Cs
+    ctx.clear()
+    torch.cuda.empty_cache()
+    return res
 
 
 def measured_traffic(kernel):
@@ -379,7 +555,7 @@ def measured_traffic(kernel):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 run of the same batch")
@@ -387,6 +563,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM autotuner (use the default variant)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the per-configuration measurements")
+    ap.add_argument("--no-literal", action="store_true",
+                    help="skip the literal-dimension prefix of the batched workload")
     ap.add_argument("--secondary-only", action="store_true",
                     help="only the per-configuration measurements (one JSON line of them; for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -429,11 +607,9 @@ def main():
 
     # the plan (block lists, sector matching, LPT tile list, device tables)
     # is built once per structure on the host and cached: its build time is
-    # the first call minus a later one, after a one-member call has loaded
-    # the kernels
+    # the first call minus a later one (the first also loads the kernels;
+    # every GEMM launch of the run covers the whole batch)
     with torch.cuda.stream(stream):
-        ctx.contract_batched(As[:1], Bs[:1], axes[0], axes[1], "bf16", Cs[:1], stream)
-        torch.cuda.synchronize()
         calls = []
         for _ in range(2):
             t0 = time.perf_counter()
@@ -456,9 +632,10 @@ def main():
     kernel = P.variant_name("bf16", variant)
 
     log("BF16 graph timing")
-    wall_ms, ev_ms = time_graph(ctx, As, Bs, Cs, axes, "bf16", args.steps, args.warmup, stream)
-    phases = time_phases(ctx, As, Bs, Cs, axes, "bf16", max(3, min(args.steps, 5)), stream)
-    log(f"bf16 step {ev_ms:.3f} ms (wall {wall_ms:.3f}); phases fuse/gemm/split = {phases}")
+    wall_ms, ev_ms, mean_ms = time_graph(ctx, As, Bs, Cs, axes, "bf16", args.steps, args.warmup, stream)
+    phases = time_phases(ctx, As, Bs, Cs, axes, "bf16", max(5, min(args.steps, 9)), stream)
+    log(f"bf16 step median {ev_ms:.3f} ms, mean {mean_ms:.3f} (wall {wall_ms:.3f}); "
+        f"phases fuse/gemm/split = {phases}")
     value = flops / (ev_ms * 1e-3) / 1e12
     gemm_tf = flops / (phases[1] * 1e-3) / 1e12
 
@@ -476,6 +653,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ev_ms, 4),
+        "ms_per_step_mean": round(mean_ms, 4),
+        "timing": f"median over {args.steps} graph replays of the step, each between HIP events on the "
+                  f"launch stream, after {args.warmup} untimed replays",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -503,7 +683,7 @@ def main():
             "traffic": (measured_traffic(kernel) or {}).get("bytes_per_launch"),
             "traffic_detail": measured_traffic(kernel),
             "gemm_ms": round(phases[1], 4),
-            "timing": "average GEMM launch time from HIP events recorded by the library on the launch stream",
+            "timing": "median GEMM launch time from HIP events recorded by the library on the launch stream",
         },
         "phases_ms": {"fuse": round(phases[0], 4), "gemm": round(phases[1], 4), "split": round(phases[2], 4)},
         "plan": {"build_ms": round(plan_ms, 1),
@@ -531,9 +711,9 @@ def main():
         if not args.no_tune:
             with torch.cuda.stream(stream):
                 variant32 = ctx.tune_batched(A32, B32, axes[0], axes[1], "f32", Cs, stream)
-        steps32 = max(2, args.steps // 3)
-        _, ev32 = time_graph(ctx, A32, B32, Cs, axes, "f32", steps32, 1, stream)
-        ph32 = time_phases(ctx, A32, B32, Cs, axes, "f32", 2, stream)
+        steps32 = max(3, args.steps // 4)
+        _, ev32, _ = time_graph(ctx, A32, B32, Cs, axes, "f32", steps32, 1, stream)
+        ph32 = time_phases(ctx, A32, B32, Cs, axes, "f32", 3, stream)
         gemm32 = flops / (ph32[1] * 1e-3) / 1e12
         result["fp32_same_batch"] = {
             "value": round(flops / (ev32 * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "ms_per_step": round(ev32, 3),
@@ -564,11 +744,21 @@ def main():
             "max": max(errs), "members": len(errs), "tolerance": 3e-3,
             "reference": "FP64 oracle on the unrounded FP32 draws (includes BF16 input rounding)"}
 
+    del As, Bs, Cs, A32, B32
+    ctx.clear()
+    torch.cuda.empty_cache()
+    if not args.no_literal:
+        log("literal-dimension prefix of the batch")
+        try:
+            result["literal_chi_prefix"] = literal_prefix(ctx, stream, variant)
+        except (RuntimeError, torch.cuda.OutOfMemoryError) as e:   # reported, not fatal
+            result["literal_chi_prefix"] = {"error": str(e)[:300]}
+            ctx.clear()
+            torch.cuda.empty_cache()
+        log(f"literal prefix: {result['literal_chi_prefix']}")
+
     if not args.no_secondary:
         log("per-configuration measurements")
-        del As, Bs, Cs, A32, B32
-        ctx.clear()
-        torch.cuda.empty_cache()
         result["per_config"] = secondary(ctx, stream, with_cpu=not args.no_cpu_baseline)
         # the second reference point for the GEMM's fraction: a large square
         # BF16 product by the vendor library on the same GPU (context only)

@@ -208,15 +208,37 @@ def contract_sectors(spec_a, flat_a, spec_b, flat_b, axes_a, axes_b, matmul=None
 
 def sample_u1(spec_a, flat_a, spec_b, flat_b, axes_a, axes_b, points) -> np.ndarray:
     """Entries C[p] for dense output positions ``points`` (list of index tuples),
-    each summed straight from the definition: the needed dense slices of A and B
-    are materialised from their blocks (zero outside allowed blocks)."""
-    da = T.split_flat(spec_a, np.asarray(flat_a, dtype=np.float64))
-    db = T.split_flat(spec_b, np.asarray(flat_b, dtype=np.float64))
+    each summed straight from the definition (eq:tensormult): the needed dense
+    slices of A and B are materialised from their blocks (zero outside allowed
+    blocks)."""
+    fa = np.asarray(flat_a, dtype=np.float64)
+    fb = np.asarray(flat_b, dtype=np.float64)
+    if fa.size != T.num_elements(spec_a) or fb.size != T.num_elements(spec_b):
+        raise ValueError("buffer sizes do not match the tensors")
+    return sample_u1_blocks(spec_a, lambda o, n: fa[o:o + n], spec_b, lambda o, n: fb[o:o + n],
+                            axes_a, axes_b, points)
+
+
+def sample_u1_blocks(spec_a, read_a, spec_b, read_b, axes_a, axes_b, points) -> np.ndarray:
+    """sample_u1 for tensors too large to hold on the host: ``read_x(offset,
+    count)`` returns ``count`` stored entries of X from flat offset ``offset``
+    of its canonical block list, and only the blocks that share a sample's
+    free-leg labels are read (each once per call)."""
+    blocks_a = T.blocks(spec_a)
+    blocks_b = T.blocks(spec_b)
     fa = [i for i in range(len(spec_a.legs)) if i not in axes_a]
     fb = [i for i in range(len(spec_b.legs)) if i not in axes_b]
     offs_a = [T.leg_offsets(T.U1, l)[0] for l in spec_a.legs]
     offs_b = [T.leg_offsets(T.U1, l)[0] for l in spec_b.legs]
     dims_x = [T.leg_offsets(T.U1, spec_a.legs[i])[1] for i in axes_a]
+    cache = {}
+
+    def block(side, b):
+        key = (side, b.key)
+        if key not in cache:
+            read = read_a if side == 0 else read_b
+            cache[key] = np.asarray(read(b.offset, b.size), dtype=np.float64).reshape(b.shape)
+        return cache[key]
 
     def locate(leg, offs, idx):
         for lab, d in zip(leg.labels, leg.degs):
@@ -224,31 +246,28 @@ def sample_u1(spec_a, flat_a, spec_b, flat_b, axes_a, axes_b, points) -> np.ndar
                 return lab, idx - offs[lab]
         raise IndexError(idx)
 
+    def gather(side, spec, bl, free, axes, offs, fixed):
+        # the dense slice of one operand along the contracted legs, for fixed free indices
+        out = np.zeros(dims_x)
+        for b in bl:
+            if all(b.labels[i] == lab for i, (lab, _) in zip(free, fixed)):
+                idx = [slice(None)] * len(b.labels)
+                for i, (_, t) in zip(free, fixed):
+                    idx[i] = t
+                sub = block(side, b)[tuple(idx)]
+                sl = tuple(slice(offs[i][b.labels[i]],
+                                 offs[i][b.labels[i]] + spec.legs[i].degs[spec.legs[i].labels.index(b.labels[i])])
+                           for i in axes)
+                out[sl] = np.transpose(sub, np.argsort(np.argsort(list(axes))))
+        return out
+
     vals = []
     for p in points:
         pa, pb = p[:len(fa)], p[len(fa):]
         fixed_a = [locate(spec_a.legs[i], offs_a[i], x) for i, x in zip(fa, pa)]
         fixed_b = [locate(spec_b.legs[i], offs_b[i], x) for i, x in zip(fb, pb)]
-        row_a = np.zeros(dims_x)
-        col_b = np.zeros(dims_x)
-        for (la, _), blk in da.items():
-            if all(la[i] == lab for i, (lab, _) in zip(fa, fixed_a)):
-                idx = [slice(None)] * len(la)
-                for i, (_, t) in zip(fa, fixed_a):
-                    idx[i] = t
-                sub = blk[tuple(idx)]
-                sl = tuple(slice(offs_a[i][la[i]], offs_a[i][la[i]] + spec_a.legs[i].degs[spec_a.legs[i].labels.index(la[i])])
-                           for i in axes_a)
-                row_a[sl] = np.transpose(sub, np.argsort(np.argsort(list(axes_a))))
-        for (lb, _), blk in db.items():
-            if all(lb[i] == lab for i, (lab, _) in zip(fb, fixed_b)):
-                idx = [slice(None)] * len(lb)
-                for i, (_, t) in zip(fb, fixed_b):
-                    idx[i] = t
-                sub = blk[tuple(idx)]
-                sl = tuple(slice(offs_b[i][lb[i]], offs_b[i][lb[i]] + spec_b.legs[i].degs[spec_b.legs[i].labels.index(lb[i])])
-                           for i in axes_b)
-                col_b[sl] = np.transpose(sub, np.argsort(np.argsort(list(axes_b))))
+        row_a = gather(0, spec_a, blocks_a, fa, axes_a, offs_a, fixed_a)
+        col_b = gather(1, spec_b, blocks_b, fb, axes_b, offs_b, fixed_b)
         vals.append(float(np.sum(row_a * col_b)))
     return np.array(vals)
 

@@ -922,10 +922,12 @@ int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* cons
         if (!ctx || !A || !B || !C) throw Error(SYM_E_ARG, "NULL argument");
         if (count < 1) throw Error(SYM_E_ARG, "count must be >= 1");
         // every member is checked, and every chunk planned, before the first
-        // launch, so a bad member leaves all outputs untouched
-        for (int32_t first = 0; first < count; first += 64)
-            (void)contract_key(std::min<int32_t>(64, count - first), A + first, B + first, n, axesA, axesB, compute,
-                               C + first, nullptr);
+        // launch, so a bad member leaves all outputs untouched (one chunk is
+        // checked by its own plan lookup)
+        if (count > 64)
+            for (int32_t first = 0; first < count; first += 64)
+                (void)contract_key(std::min<int32_t>(64, count - first), A + first, B + first, n, axesA, axesB,
+                                   compute, C + first, nullptr);
         std::vector<std::shared_ptr<ContractPlan>> plans;
         for (int32_t first = 0; first < count; first += 64) {
             const int32_t m = std::min<int32_t>(64, count - first);

@@ -76,6 +76,38 @@ def test_sector_layout_u1():
         assert b.shape == ob[b.labels].shape
 
 
+def test_literal_chi512_member_layout_and_flops_match_oracle():
+    # member 0 of the batched workload with the drawn dimension taken
+    # literally: chi = 512 per index, 4.91 G stored entries per operand, so
+    # block offsets run past 2^32 and the output is far above the 2^29
+    # entries the GEMM epilogue addresses directly (it takes the split pass)
+    m = W.config3_literal_members(1)[0]
+    assert m.extra["chi"] == 512
+    ctx = _ctx()
+    a = ctx.describe(m.A, 4)
+    ob = T.blocks(m.A)
+    n = T.num_elements(m.A)
+    assert a.numel() == n == 4910582018 and n > 2 ** 32
+    lb = a.blocks()
+    assert len(lb) == len(ob) == 1469
+    assert [b.offset for b in lb] == [b.offset for b in ob]
+    assert [b.shape for b in lb] == [b.shape for b in ob]
+    assert max(b.offset for b in lb) > 2 ** 32
+    # sector matrices of the fused operand: rows and columns are the
+    # convolution of the leg degeneracies (the charge of two fused legs)
+    d = np.array(m.A.legs[0].degs, dtype=np.int64)
+    ms = np.convolve(d, d)
+    secs = ctx.describe(m.A, 2).sectors()
+    assert [s[0] for s in secs] == list(range(-12, 13))
+    assert [s[1] for s in secs] == list(ms) and [s[2] for s in secs] == list(ms)
+    assert secs[-1][3] + ms[-1] * ms[-1] == n
+    b = ctx.describe(m.B, 4)
+    f = ctx.flops(a, b, m.axes_a, m.axes_b)
+    assert f == K.sector_flops(m.A, m.B, m.axes_a, m.axes_b) == int(np.sum(2 * ms ** 3))
+    c = ctx.describe(K.result_spec(m.A, m.B, m.axes_a, m.axes_b), 4)
+    assert c.numel() == n and n >= 2 ** 29
+
+
 def test_su2_layouts_match_oracle():
     c = W.config5(4, [2, 1, 1, 1, 1])
     ctx = _ctx()

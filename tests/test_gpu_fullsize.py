@@ -4,8 +4,12 @@ oracle computes one by one:
 * config 2 (U(1), chi=256, FP32): sampled dense output entries summed from the
   definition (dense slices of A and B materialised from their blocks);
 * config 3 (64-member batch, BF16-stored inputs, the benchmark's graph-replayed
-  launch): sampled entries of sampled members, error against the unrounded
-  draws and against the stored BF16 values;
+  launch): every output entry of every chi=256 member against the unrounded
+  draws, sampled entries of members of every size against the unrounded draws
+  and the stored BF16 values;
+* config 3's member 0 with its drawn dimension taken literally (chi=512,
+  4.91 G entries per operand, 209.8 TFLOP): sampled entries of four output
+  blocks, read block by block from the device, and every output entry written;
 * config 5 (SU(2), chi=576): sampled reduced blocks of C by the block-wise
   multiply, and the recoupled blocks of sampled label tuples;
 * config 4's A as a matrix (17 sectors up to 1976 x 1976): the block SVD's
@@ -135,7 +139,79 @@ def test_config3_batched_bf16_graph_sampled(ctx):
     say(f"  sampled rel errs {['%.2e' % e for e in errs]} (stored values: {['%.2e' % e for e in errs16]})")
     assert max(errs) <= 3e-3
     assert max(errs16) <= 1e-5
+    # every entry of every chi=256 member (85 % of the batch's FLOPs) against
+    # the oracle's per-sector FP64 products on the unrounded draws
+    full = []
+    for i, m in enumerate(members):
+        if m.extra["chi"] != 256:
+            continue
+        g = W.generator(m.seed, "cuda")
+        fa = W.gaussian(T.num_elements(m.A), g, "cuda").double().cpu().numpy()
+        fb = W.gaussian(T.num_elements(m.B), g, "cuda").double().cpu().numpy()
+        _, ref = K.contract_sectors(m.A, fa, m.B, fb, m.axes_a, m.axes_b)
+        del fa, fb
+        got = Cs[i].data.double().cpu().numpy()
+        full.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+        del got, ref
+    say(f"  whole-output rel errs of the {len(full)} chi=256 members: max {max(full):.3e}")
+    assert len(full) == 16
+    assert max(full) <= 3e-3
     del graph, As, Bs, Cs
+    torch.cuda.empty_cache()
+
+
+def test_config3_literal_chi512_member_bf16_sampled(ctx):
+    # Member 0 of the batched workload with the drawn dimension 512 taken
+    # literally: 4.91 G stored entries per operand (offsets past 2^32), an
+    # output of 4.91 G entries (past the 2^29 the GEMM epilogue addresses, so
+    # the GEMM writes a sector-major workspace and the split pass scatters
+    # it into the canonical blocks) and 209.8 TFLOP in one launch.
+    import paper_1203_2222_amd as P
+    say("case config3 literal member 0 (chi=512) bf16")
+    ctx.clear()
+    torch.cuda.empty_cache()
+    m = W.config3_literal_members(1)[0]
+    n = T.num_elements(m.A)
+    # raw FP32 draws, BF16 operands, fused BF16 operands, C and its split workspace
+    need = n * (4 + 4 + 2 + 2 + 2 + 2 + 4 + 4)
+    free, _ = torch.cuda.mem_get_info()
+    assert free > 1.05 * need, (free, need)
+    c2 = P.Context()
+    g = W.generator(m.seed, "cuda")
+    a = W.gaussian(n, g, "cuda")
+    b = W.gaussian(n, g, "cuda")
+    A = c2.tensor(m.A, 4, "bf16", data=a.to(torch.bfloat16))
+    B = c2.tensor(m.B, 4, "bf16", data=b.to(torch.bfloat16))
+    sc = K.result_spec(m.A, m.B, m.axes_a, m.axes_b)
+    C = c2.tensor(sc, 4)
+    C.data.fill_(float("nan"))
+    c2.contract(A, B, m.axes_a, m.axes_b, "bf16", out=C)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(C.data).all()), "an output entry was not written"
+    # four output blocks: the largest contraction (charge 0) with the smallest
+    # and the largest row tuples, the smallest sector, and a general one
+    oblocks = {bl.labels: bl for bl in T.blocks(sc)}
+    rng = np.random.default_rng(7)
+    pts, offs = [], []
+    for labels in ((-6, 6, -6, 6), (0, 0, 6, -6), (6, 6, 6, 6), (2, -1, 0, 1)):
+        bl = oblocks[labels]
+        for _ in range(10):
+            t = tuple(int(rng.integers(0, d)) for d in bl.shape)
+            pts.append(_dense_index(sc, labels, t))
+            offs.append(bl.offset + int(np.ravel_multi_index(t, bl.shape)))
+    got = C.data[torch.tensor(offs, device="cuda")].double().cpu().numpy()
+
+    def reader(x):
+        return lambda o, k: x[o:o + k].double().cpu().numpy()
+
+    ref = K.sample_u1_blocks(m.A, reader(a), m.B, reader(b), m.axes_a, m.axes_b, pts)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    ref16 = K.sample_u1_blocks(m.A, reader(A.data), m.B, reader(B.data), m.axes_a, m.axes_b, pts)
+    err16 = float(np.linalg.norm(got - ref16) / np.linalg.norm(ref16))
+    say(f"  sampled rel err {err:.3e} (stored values: {err16:.3e})")
+    assert err <= 3e-3
+    assert err16 <= 1e-5
+    del A, B, C, a, b, c2
     torch.cuda.empty_cache()
 
 

@@ -115,6 +115,42 @@ def test_sampled_entries_match_dense():
     np.testing.assert_allclose(vals, [dc[p] for p in pts], atol=1e-12)
 
 
+def test_sampled_entries_from_block_reads_match_dense():
+    # the block-reader form reads each needed block once and nothing else:
+    # every block read shares the free-leg labels of some sample
+    li = W.u1_leg(-2, 2, [2, 3, 4, 3, 2], "in")
+    spec = W.TensorSpec(W.U1, (li, li, li.flipped(), li.flipped()))
+    c = W.Contraction("u1_chi14", spec, spec, (2, 3), (0, 1), seed=0)
+    rng = np.random.default_rng(3)
+    fa, fb = _draw(c.A, rng), _draw(c.B, rng)
+    sc, dc = _dense_route(c.A, fa, c.B, fb, c.axes_a, c.axes_b)
+    nz = np.argwhere(T.dense_mask(sc))
+    pts = [tuple(p) for p in nz[rng.choice(len(nz), 12, replace=False)]]
+    reads = {0: [], 1: []}
+
+    def reader(side, flat):
+        def read(o, n):
+            reads[side].append((o, n))
+            return flat[o:o + n]
+        return read
+
+    vals = K.sample_u1_blocks(c.A, reader(0, fa), c.B, reader(1, fb), c.axes_a, c.axes_b, pts)
+    np.testing.assert_allclose(vals, [dc[p] for p in pts], rtol=1e-12, atol=1e-12)
+    for side, spec, free in ((0, c.A, (0, 1)), (1, c.B, (2, 3))):
+        assert len(set(reads[side])) == len(reads[side])
+        by_off = {b.offset: b for b in T.blocks(spec)}
+        wanted = set()
+        for p in pts:
+            labs = []
+            for leg_i, x in zip(free, p[:2] if side == 0 else p[2:]):
+                offs, _ = T.leg_offsets(T.U1, spec.legs[leg_i])
+                labs.append(max(l for l in spec.legs[leg_i].labels if offs[l] <= x))
+            wanted.add(tuple(labs))
+        for o, n in reads[side]:
+            b = by_off[o]
+            assert b.size == n and tuple(b.labels[i] for i in free) in wanted
+
+
 def test_sector_flops_su2_config5_by_characters():
     # The sector of coupled spin e holds every copy of e in V (x) V.  Count the
     # copies from the J_z spectrum alone (states with 2M = 2e minus states with

@@ -170,6 +170,24 @@ def config3_members(count: int = 64) -> List[Contraction]:
     return out
 
 
+def config3_literal_members(count: int = 64) -> List[Contraction]:
+    """The batched workload's members with the drawn per-index dimension
+    {64,128,256,512} taken literally (no halving), in draw order; the same
+    seeds as config3_members.  The whole batch needs about 0.7 TB, so only a
+    prefix of it fits one device."""
+    import numpy as np
+    draws = np.random.default_rng(0).choice([64, 128, 256, 512], 64)
+    out = []
+    for i in range(count):
+        chi = int(draws[i])
+        d = gaussian_profile_degs(range(-6, 7), chi)
+        li = u1_leg(-6, 6, d, IN)
+        A, B = _u1_operator_pair(li, li.flipped())
+        out.append(Contraction(f"u1_batch_literal_m{i}_chi{chi}", A, B, (2, 3), (0, 1),
+                               seed=1000 + i, compute="bf16", extra={"chi": chi}))
+    return out
+
+
 def config4() -> Contraction:
     """U(1), charges -4..4, degeneracies [8,12,16,18,20,18,16,12,8] (dim 128);
     loss <contract(A,B), G>, operands drawn in the order A, B, G."""
