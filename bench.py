@@ -375,6 +375,9 @@ def secondary(ctx, stream, with_cpu=True):
         mst = _timed(lambda: ctx.permute_tree_into(C, (1, 2, 0, 3), W.TREE_LEFT, 2, T1, stream=stream), 5, stream)
         T2 = ctx.permute_tree(A, (0, 1, 2, 3), W.TREE_LEFT, 4)
         msv = _timed(lambda: ctx.permute_tree_into(A, (0, 1, 2, 3), W.TREE_LEFT, 4, T2, stream=stream), 5, stream)
+        # a permutation that moves the contiguous last leg (the LDS-tiled kernel)
+        T3 = ctx.permute_tree(C, (3, 2, 1, 0), W.TREE_LEFT, 4)
+        msx = _timed(lambda: ctx.permute_tree_into(C, (3, 2, 1, 0), W.TREE_LEFT, 4, T3, stream=stream), 5, stream)
         out["su2_j4_fp32"] = {"contract_TFLOPs": round(fl / ms / 1e9, 2), "contract_ms": round(ms, 3),
                               "recouple_ms": round(msr, 3),
                               "recouple_GBps": round(C.numel() * 8 / msr / 1e6, 1),
@@ -382,6 +385,8 @@ def secondary(ctx, stream, with_cpu=True):
                               "permute_120_left_GBps": round(C.numel() * 8 / mst / 1e6, 1),
                               "reverse_leg2_ms": round(msv, 3),
                               "reverse_leg2_GBps": round(A.numel() * 8 / msv / 1e6, 1),
+                              "permute_3210_left_ms": round(msx, 3),
+                              "permute_3210_left_GBps": round(C.numel() * 8 / msx / 1e6, 1),
                               "fuse_ms": round(msf, 3), "fuse_GBps": round(A.numel() * 8 / msf / 1e6, 1)}
         if with_cpu:
             # the oracle's recoupling (F-move then swap of legs 2, 3, in FP64)
@@ -429,7 +434,7 @@ def secondary(ctx, stream, with_cpu=True):
             _, rref = RC.fmove_swap(sc, ref)
             out["su2_j4_fp32"]["rel_err_fp32_vs_fp64_oracle"]["recoupled"] = _rel(R.data.double().cpu().numpy(), rref)
             del fa, fb, ref, rref, Cc
-        del A, B, C, R, F, T1, T2
+        del A, B, C, R, F, T1, T2, T3
 
         # tiny SU(2) instances (d_j = 1; spins up to 2 and up to 4, chi = 15
         # and 45): device latency, and the oracle's naive dense einsum (one

@@ -1793,43 +1793,213 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
 // kRecoupleChunk elements of one tuple, several per thread, so that the
 // tuple's metadata is read once for many elements.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks,
-                                                  const FmBlk* __restrict__ out_blks, const double* __restrict__ coef,
-                                                  const FmTask* __restrict__ tasks, PtrTable bufs, int in_buf,
-                                                  int out_buf) {
-    const FmTask t = tasks[blockIdx.x];
-    const FmGroup g = groups[t.group];
-    const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
-    float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
-    const FmBlk* __restrict__ ib = in_blks + g.in_first;
-    const FmBlk* __restrict__ ob = out_blks + g.out_first;
-    const double* __restrict__ c = coef + g.coef_first;
+// U output positions per thread per pass (256 apart, so lanes stay on
+// consecutive positions); all their n loads are issued before any use
+template <int NB>
+__device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __restrict__ ib,
+                                               const FmBlk* __restrict__ ob, const double* __restrict__ cf,
+                                               const float* __restrict__ src, float* __restrict__ dst, int start,
+                                               int end) {
+    constexpr int U = NB <= 2 ? 8 : NB <= 4 ? 4 : NB <= 8 ? 2 : 1;
     const int n = g.n;
     const int d1 = g.d[1], d2 = g.d[2], d3 = g.d[3];
     auto rel = [](const FmBlk& b, int t0, int t1, int t2, int t3) {
         return static_cast<uint32_t>(t0 * b.stride[0] + t1 * b.stride[1] + t2 * b.stride[2] + t3 * b.stride[3]);
     };
-    const int end = t.start + t.count;
-    for (int e = t.start + static_cast<int>(threadIdx.x); e < end; e += 256) {
-        const int r = div_by(e, g.mag[3], g.shf[3]);
-        const int t3 = e - r * d3;
-        const int q = div_by(r, g.mag[2], g.shf[2]);
-        const int t2 = r - q * d2;
-        const int t0 = div_by(q, g.mag[1], g.shf[1]);
-        const int t1 = q - t0 * d1;
-        const uint32_t ri0 = rel(ib[0], t0, t1, t2, t3), ro0 = rel(ob[0], t0, t1, t2, t3);
-        double x[kMaxRecouple];
+    for (int e0 = start + static_cast<int>(threadIdx.x); e0 < end; e0 += 256 * U) {
+        float xs[U][NB];
+        uint32_t ro[U];
+        bool ok[U];
 #pragma unroll
-        for (int i = 0; i < kMaxRecouple; ++i)
-            if (i < n) x[i] = static_cast<double>(src[ib[i].off + (g.same_in ? ri0 : rel(ib[i], t0, t1, t2, t3))]);
-        for (int f = 0; f < n; ++f) {
-            double y = 0.0;
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + 256 * u;
+            ok[u] = e < end;
+            const int ee = ok[u] ? e : start;
+            const int r = div_by(ee, g.mag[3], g.shf[3]);
+            const int t3 = ee - r * d3;
+            const int q = div_by(r, g.mag[2], g.shf[2]);
+            const int t2 = r - q * d2;
+            const int t0 = div_by(q, g.mag[1], g.shf[1]);
+            const int t1 = q - t0 * d1;
+            const uint32_t ri0 = rel(ib[0], t0, t1, t2, t3);
+            ro[u] = g.same_out ? rel(ob[0], t0, t1, t2, t3) : static_cast<uint32_t>(ee);   // ee: decoded again below
 #pragma unroll
-            for (int i = 0; i < kMaxRecouple; ++i)
-                if (i < n) y = fma(c[f * n + i], x[i], y);
-            dst[ob[f].off + (g.same_out ? ro0 : rel(ob[f], t0, t1, t2, t3))] = static_cast<float>(y);
+            for (int i = 0; i < NB; ++i)
+                xs[u][i] = i < n ? src[ib[i].off + (g.same_in ? ri0 : rel(ib[i], t0, t1, t2, t3))] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            int t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+            if (!g.same_out) {
+                const int ee = static_cast<int>(ro[u]);
+                const int r = div_by(ee, g.mag[3], g.shf[3]);
+                t3 = ee - r * d3;
+                const int q = div_by(r, g.mag[2], g.shf[2]);
+                t2 = r - q * d2;
+                t0 = div_by(q, g.mag[1], g.shf[1]);
+                t1 = q - t0 * d1;
+            }
+#pragma unroll
+            for (int f = 0; f < NB; ++f) {
+                if (f >= n) break;
+                double y = 0.0;
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    if (i < n) y = fma(cf[f * n + i], static_cast<double>(xs[u][i]), y);
+                dst[ob[f].off + (g.same_out ? ro[u] : rel(ob[f], t0, t1, t2, t3))] = static_cast<float>(y);
+            }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks,
+                                                  const FmBlk* __restrict__ out_blks, const double* __restrict__ coef,
+                                                  const FmTask* __restrict__ tasks, PtrTable bufs, int in_buf,
+                                                  int out_buf) {
+    __shared__ double cf[kMaxRecouple * kMaxRecouple];
+    const FmTask t = tasks[blockIdx.x];
+    const FmGroup& g = groups[t.group];
+    for (int k = threadIdx.x; k < g.n * g.n; k += 256) cf[k] = coef[g.coef_first + k];
+    __syncthreads();
+    const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
+    float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
+    const FmBlk* __restrict__ ib = in_blks + g.in_first;
+    const FmBlk* __restrict__ ob = out_blks + g.out_first;
+    const int end = t.start + t.count;
+    const int n = g.n;
+    if (n <= 1) recouple_elems<1>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 2) recouple_elems<2>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 4) recouple_elems<4>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 8) recouple_elems<8>(g, ib, ob, cf, src, dst, t.start, end);
+    else recouple_elems<kMaxRecouple>(g, ib, ob, cf, src, dst, t.start, end);
+}
+
+// LDS-tiled K9 (see FtGroup): a workgroup moves one box of all n input
+// blocks of a label tuple into LDS, issuing every load of the box before it
+// stores any of them (16 per thread in flight), in the order that makes
+// consecutive lanes read consecutive input addresses; it then combines the
+// n values of each box position with the FP64 coefficients (staged in LDS)
+// and writes the n output blocks in output order.  Per-block offsets and
+// strides are decoded once per task into LDS.  The combination is unrolled
+// for n up to NB (the smallest power of two >= n).
+template <int NB>
+__device__ __forceinline__ void recouple_combine(const float* __restrict__ tile, const double* __restrict__ cf,
+                                                 const int64_t* __restrict__ obase, const int32_t (*ostr)[3],
+                                                 float* __restrict__ dst, int n, int E, int T2, int T3, int v1, int v2,
+                                                 int v3, uint32_t m0, int s0, uint32_t m1, int s1) {
+    for (int q = threadIdx.x; q < E; q += 256) {
+        const int r = div_by(q, m0, s0);
+        const int l3 = q - r * T3;
+        const int l1 = div_by(r, m1, s1);
+        const int l2 = r - l1 * T2;
+        if (l1 >= v1 || l2 >= v2 || l3 >= v3) continue;
+        double x[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) x[i] = i < n ? static_cast<double>(tile[i * E + q]) : 0.0;
+#pragma unroll
+        for (int f = 0; f < NB; ++f) {
+            if (f >= n) break;
+            double y = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (i < n) y = fma(cf[f * n + i], x[i], y);
+            dst[obase[f] + (l1 * ostr[f][0] + l2 * ostr[f][1] + l3 * ostr[f][2])] = static_cast<float>(y);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recouple_tiled(const FtGroup* __restrict__ groups,
+                                                        const FmBlk* __restrict__ in_blks,
+                                                        const FmBlk* __restrict__ out_blks,
+                                                        const double* __restrict__ coef,
+                                                        const FtTask* __restrict__ tasks, PtrTable bufs, int in_buf,
+                                                        int out_buf) {
+    constexpr int U = 16;
+    __shared__ float tile[kFtElems];
+    __shared__ double cf[kMaxRecouple * kMaxRecouple];
+    __shared__ int64_t ibase[kMaxRecouple], obase[kMaxRecouple];
+    __shared__ int32_t istr[kMaxRecouple][3], ostr[kMaxRecouple][3];
+    const FtTask t = tasks[blockIdx.x];
+    const FtGroup& g = groups[t.group];
+    const int n = g.n;
+    const int a0 = g.ax[0], a1 = g.ax[1], a2 = g.ax[2], a3 = g.ax[3];
+    const int T1 = g.t[1], T2 = g.t[2], T3 = g.t[3], E = g.esz;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < n * n; k += 256) cf[k] = coef[g.coef_first + k];
+    if (tid < 2 * n) {
+        const bool in = tid < n;
+        const int i = in ? tid : tid - n;
+        const FmBlk b = in ? in_blks[g.in_first + i] : out_blks[g.out_first + i];
+        const int64_t base = b.off + static_cast<int64_t>(t.o[0]) * b.stride[a0] +
+                             static_cast<int64_t>(t.o[1]) * b.stride[a1] + static_cast<int64_t>(t.o[2]) * b.stride[a2] +
+                             static_cast<int64_t>(t.o[3]) * b.stride[a3];
+        (in ? ibase : obase)[i] = base;
+        int32_t* st = in ? istr[i] : ostr[i];
+        st[0] = b.stride[a1];
+        st[1] = b.stride[a2];
+        st[2] = b.stride[a3];
+    }
+    __syncthreads();
+    // extents of the box inside the blocks (edge tiles are clipped)
+    const int v1 = min(T1, g.dim[a1] - t.o[1]), v2 = min(T2, g.dim[a2] - t.o[2]), v3 = min(T3, g.dim[a3] - t.o[3]);
+    const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
+    float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
+    const int lf = g.ld[0], lm = g.ld[1];
+    const int tf = g.t[lf], tm = g.t[lm];
+    const int total = n * E;
+    for (int b0 = 0; b0 < total; b0 += 256 * U) {
+        float v[U];
+        int pos[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = b0 + u * 256 + tid;
+            pos[u] = -1;
+            v[u] = 0.f;
+            if (idx < total) {
+                const int i = div_by(idx, g.mag[4], g.shf[4]);
+                const int q = idx - i * E;
+                const int r = div_by(q, g.mag[2], g.shf[2]);
+                const int uf = q - r * tf;
+                const int us = div_by(r, g.mag[3], g.shf[3]);
+                const int um = r - us * tm;
+                // box coordinates (slots 1..3) from the load-order ones
+                const int l1 = lf == 1 ? uf : (lm == 1 ? um : us);
+                const int l2 = lf == 2 ? uf : (lm == 2 ? um : us);
+                const int l3 = lf == 3 ? uf : (lm == 3 ? um : us);
+                if (l1 < v1 && l2 < v2 && l3 < v3) {
+                    const int rel = l1 * istr[i][0] + l2 * istr[i][1] + l3 * istr[i][2];
+                    v[u] = src[ibase[i] + rel];
+                    pos[u] = i * E + (l1 * T2 + l2) * T3 + l3;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (pos[u] >= 0) tile[pos[u]] = v[u];
+    }
+    __syncthreads();
+    const uint32_t m0 = g.mag[0], m1 = g.mag[1];
+    const int s0 = g.shf[0], s1 = g.shf[1];
+    if (n <= 1)
+        recouple_combine<1>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+    else if (n <= 2)
+        recouple_combine<2>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+    else if (n <= 4)
+        recouple_combine<4>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+    else if (n <= 8)
+        recouple_combine<8>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+    else
+        recouple_combine<kMaxRecouple>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+}
+
+hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
+                                 const FtTask* tasks, int32_t n_tasks, const PtrTable& bufs, int32_t in_buf,
+                                 int32_t out_buf, hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recouple_tiled, dim3(static_cast<unsigned>(n_tasks)), dim3(256), 0, s, groups, in_blks,
+                       out_blks, coef, tasks, bufs, in_buf, out_buf);
+    return hipGetLastError();
 }
 
 hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,

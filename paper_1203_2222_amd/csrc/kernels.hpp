@@ -10,7 +10,7 @@ namespace sym {
 constexpr int kMaxBufs = 256;       // distinct base pointers one launch may address
 constexpr int kMaxCopyDims = 6;     // dims of a coalesced block copy
 constexpr int kMaxRecouple = 16;    // intermediate spins of one label tuple
-constexpr int kRecoupleChunk = 2048;   // elements of one label tuple per workgroup task
+constexpr int kRecoupleChunk = 4096;   // elements of one label tuple per workgroup task
 
 // Base pointers of one launch, passed by value as a kernel argument.
 struct PtrTable {
@@ -131,6 +131,34 @@ struct FmTask {
     int32_t group, start, count, pad;
 };
 
+// LDS-tiled recoupling: a task is a tile of one label tuple, the same box of
+// every one of its n input and n output blocks.  The box fixes the index
+// along output axis ax[0] and spans t[1] x t[2] x t[3] indices along output
+// axes ax[1], ax[2], ax[3] (ascending, so ax[3] is the output's innermost
+// axis).  Loads walk the box fastest along the tile axis of smallest input
+// stride (ld[0], then ld[1], then ld[2]: slots 1..3), so that consecutive
+// lanes read consecutive input addresses; the combination and the stores
+// walk it in output order.
+constexpr int kFtElems = 8192;   // floats of one tile over all n blocks (32 KB of LDS)
+struct FtGroup {
+    int32_t n;
+    int32_t dim[4];      // output block dims, output-axis order
+    int32_t ax[4];       // ax[0]: axis fixed per task; ax[1..3]: tile axes
+    int32_t t[4];        // nominal tile extents along ax[1..3] (t[0] = 1)
+    int32_t ld[3];       // load order: tile slots (1..3), fastest first
+    int32_t esz;         // t[1] t[2] t[3]
+    // floor(x / d) by multiplier and shift for d = t[3], t[2], t[ld[0]],
+    // t[ld[1]] and esz (x < 2^31)
+    uint32_t mag[5];
+    int32_t shf[5];
+    int32_t in_first, out_first, coef_first;
+};
+struct FtTask {
+    int32_t group;
+    int32_t o[4];        // index along ax[0]; tile origin along ax[1..3]
+    int32_t pad[3];
+};
+
 // Launchers (kernels.hip).  Every launcher returns the hipError_t of the launch.
 hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
@@ -145,6 +173,9 @@ hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops,
 hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles,
                        int32_t n_tiles, int32_t grid, const EpiRow* rows, const EpiCol* cols,
                        const PtrTable& bufs, hipStream_t s);
+hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
+                                 const double* coef, const FtTask* tasks, int32_t n_tasks, const PtrTable& bufs,
+                                 int32_t in_buf, int32_t out_buf, hipStream_t s);
 hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
                            const double* coef, const FmTask* tasks, int32_t n_tasks,
                            const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);

@@ -1,6 +1,8 @@
 // Plan builders: block copies (permute / fuse / split), sector GEMM lists and
 // SU(2) recoupling tables.
 #include <algorithm>
+#include <climits>
+#include <cstdlib>
 #include <numeric>
 
 #include "plan.hpp"
@@ -536,10 +538,83 @@ hipError_t GemmProgram::launch(const PtrTable& bufs, int grid, hipStream_t s) co
 // RecoupleProgram: LEFT tree (legs 1,2,3,4) -> RIGHT tree on legs (1,3,2,4)
 // ---------------------------------------------------------------------------
 
+namespace {
+
+int64_t isqrt64(int64_t x) {
+    int64_t r = 0;
+    while ((r + 1) * (r + 1) <= x) ++r;
+    return r;
+}
+
+// Box of the tiled recoupling kernel for one label tuple (see FtGroup): the
+// axis fixed per task is output axis 0, or axis 1 when the input is
+// contiguous along output axis 0; the box holds kFtElems / n entries of each
+// block, shaped so that both the input runs (along the tile axis of smallest
+// input stride) and the output runs (along the innermost axes) are long.
+void choose_box(FtGroup& g, const FmBlk& in0) {
+    int fastest = -1;
+    for (int k = 0; k < 4; ++k)
+        if (g.dim[k] > 1 && (fastest < 0 || in0.stride[k] < in0.stride[fastest] ||
+                             (in0.stride[k] == in0.stride[fastest] && k > fastest)))
+            fastest = k;
+    g.ax[0] = fastest == 0 ? 1 : 0;
+    for (int k = 0, s = 1; k < 4; ++k)
+        if (k != g.ax[0]) g.ax[s++] = k;
+    int64_t D[4] = {1, g.dim[g.ax[1]], g.dim[g.ax[2]], g.dim[g.ax[3]]};
+    // load order: tile slots by input stride (size-1 axes last, ties to the inner slot)
+    int slot[3] = {1, 2, 3};
+    std::sort(slot, slot + 3, [&](int x, int y) {
+        const int64_t sx = D[x] == 1 ? INT64_MAX : in0.stride[g.ax[x]];
+        const int64_t sy = D[y] == 1 ? INT64_MAX : in0.stride[g.ax[y]];
+        if (sx != sy) return sx < sy;
+        return x > y;
+    });
+    for (int k = 0; k < 3; ++k) g.ld[k] = slot[k];
+    const int64_t E = std::max<int64_t>(1, kFtElems / g.n);
+    int64_t T[4] = {1, 1, 1, 1};
+    const int f = slot[0], m = slot[1];
+    if (f == 3) {
+        // the input keeps the output's innermost axis: runs along slot 3, then
+        // along the slot whose input stride comes next
+        T[3] = std::min(D[3], E);
+        const int64_t rem = std::max<int64_t>(1, E / T[3]);
+        if (m == 2) {
+            T[2] = std::min(D[2], rem);
+            T[1] = std::min(D[1], std::max<int64_t>(1, rem / T[2]));
+        } else {
+            T[2] = std::min(D[2], std::max<int64_t>(1, isqrt64(rem)));
+            T[1] = std::min(D[1], std::max<int64_t>(1, rem / T[2]));
+            if (T[1] == D[1]) T[2] = std::min(D[2], std::max<int64_t>(1, rem / T[1]));
+        }
+    } else {
+        // a transpose between the input's contiguous slot f and slot 3
+        T[3] = std::min(D[3], std::max<int64_t>(16, isqrt64(E)));
+        const int64_t rem = std::max<int64_t>(1, E / T[3]);
+        T[f] = std::min(D[f], rem);
+        const int o = 6 - 3 - f;   // the remaining slot
+        T[o] = std::min(D[o], std::max<int64_t>(1, rem / T[f]));
+    }
+    g.t[0] = 1;
+    for (int k = 1; k < 4; ++k) g.t[k] = static_cast<int32_t>(T[k]);
+    g.esz = g.t[1] * g.t[2] * g.t[3];
+    if (static_cast<int64_t>(g.esz) * g.n > kFtElems) throw Error(SYM_E_UNSUPPORTED, "recoupling box too large");
+    const int32_t divs[5] = {g.t[3], g.t[2], g.t[g.ld[0]], g.t[g.ld[1]], g.esz};
+    for (int k = 0; k < 5; ++k) magic_divisor(divs[k], g.mag[k], g.shf[k]);
+}
+
+}  // namespace
+
 void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm) {
     if (in.group != SYM_SU2 || out.group != SYM_SU2 || in.rank != 4 || out.rank != 4 || perm.size() != 4)
         throw Error(SYM_E_UNSUPPORTED, "recoupling acts on rank-4 SU(2) tensors");
     const TreeMoves mv = tree_moves(in.tree, perm.data(), out.tree);
+    // Inputs are row-major over their legs in every layout, so the input is
+    // contiguous along its last leg.  When that leg stays last the
+    // element-wise kernel reads and writes along the same runs (measured
+    // 2.7-3.0 TB/s on config 5, slightly ahead of the tiled kernel); when it
+    // moves, the tiled kernel transposes through LDS (full reversal: 2.5
+    // against 0.73 TB/s).
+    tiled = perm[3] != 3;
     size_t i = 0;
     std::vector<int32_t> es, fs;
     std::vector<double> gamma;
@@ -594,6 +669,20 @@ void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<i
             for (int l = 0; l < 4; ++l) g.same_out &= out_blks.back().stride[l] == out_blks[static_cast<size_t>(g.out_first)].stride[l];
         }
         coef.insert(coef.end(), gamma.begin(), gamma.end());
+        FtGroup tg{};
+        tg.n = n;
+        for (int k = 0; k < 4; ++k) tg.dim[k] = g.d[k];
+        tg.in_first = g.in_first;
+        tg.out_first = g.out_first;
+        tg.coef_first = g.coef_first;
+        choose_box(tg, in_blks[static_cast<size_t>(g.in_first)]);
+        const int32_t tgi = static_cast<int32_t>(tgroups.size());
+        for (int32_t o0 = 0; o0 < tg.dim[tg.ax[0]]; ++o0)
+            for (int32_t o1 = 0; o1 < tg.dim[tg.ax[1]]; o1 += tg.t[1])
+                for (int32_t o2 = 0; o2 < tg.dim[tg.ax[2]]; o2 += tg.t[2])
+                    for (int32_t o3 = 0; o3 < tg.dim[tg.ax[3]]; o3 += tg.t[3])
+                        ttasks.push_back({tgi, {o0, o1, o2, o3}, {0, 0, 0}});
+        tgroups.push_back(tg);
         const int64_t elems = b0.size;
         if (elems >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block too large to recouple");
         for (int64_t s = 0; s < elems; s += kRecoupleChunk)
@@ -610,10 +699,17 @@ void RecoupleProgram::upload(const Allocator& alloc) {
     d_out = upload_vec(alloc, out_blks);
     d_coef = upload_vec(alloc, coef);
     d_tasks = upload_vec(alloc, tasks);
+    d_tgroups = upload_vec(alloc, tgroups);
+    d_ttasks = upload_vec(alloc, ttasks);
 }
 
 hipError_t RecoupleProgram::launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const {
     if (tasks.empty()) return hipSuccess;
+    if (tiled)
+        return launch_recouple_tiled(static_cast<const FtGroup*>(d_tgroups->ptr), static_cast<const FmBlk*>(d_in->ptr),
+                                     static_cast<const FmBlk*>(d_out->ptr), static_cast<const double*>(d_coef->ptr),
+                                     static_cast<const FtTask*>(d_ttasks->ptr), static_cast<int32_t>(ttasks.size()),
+                                     bufs, in_buf, out_buf, s);
     return launch_recouple(static_cast<const FmGroup*>(d_groups->ptr), static_cast<const FmBlk*>(d_in->ptr),
                            static_cast<const FmBlk*>(d_out->ptr), static_cast<const double*>(d_coef->ptr),
                            static_cast<const FmTask*>(d_tasks->ptr), static_cast<int32_t>(tasks.size()), bufs, in_buf,

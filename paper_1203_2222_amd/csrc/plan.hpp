@@ -94,7 +94,10 @@ struct RecoupleProgram {
     std::vector<FmBlk> in_blks, out_blks;
     std::vector<double> coef;
     std::vector<FmTask> tasks;
-    DevMemPtr d_groups, d_in, d_out, d_coef, d_tasks;
+    std::vector<FtGroup> tgroups;   // the same label tuples, for the LDS-tiled kernel
+    std::vector<FtTask> ttasks;
+    bool tiled = false;             // the permutation moves the input's contiguous (last) leg
+    DevMemPtr d_groups, d_in, d_out, d_coef, d_tasks, d_tgroups, d_ttasks;
     // Gamma(tree, perm, tree') of every label tuple; out's leg k is in's leg perm[k]
     void build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm);
     void upload(const Allocator& alloc);
