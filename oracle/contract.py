@@ -55,10 +55,19 @@ def result_spec(spec_a, spec_b, axes_a, axes_b):
     legs = [spec_a.legs[i] for i in fa] + [spec_b.legs[i] for i in fb]
     if spec_a.group in T.ABELIAN:
         return _Spec(spec_a.group, legs, qtot=T.combine_qtot(spec_a.group, spec_a.qtot, spec_b.qtot))
-    if not (spec_a.tree == T.TREE_OPERATOR and tuple(axes_a) == (2, 3) and tuple(axes_b) == (0, 1)
+    if (spec_a.tree == T.TREE_OPERATOR and tuple(axes_a) == (2, 3) and tuple(axes_b) == (0, 1)
             and spec_b.tree in (T.TREE_OPERATOR, T.TREE_LEFT)):
-        raise ValueError("SU(2) contraction supported: operator A legs 3,4 with B legs 1,2")
-    return _Spec(T.SU2, legs, tree=spec_b.tree)
+        return _Spec(T.SU2, legs, tree=spec_b.tree)
+    # any other SU(2) contraction: the result on the CHAIN tree of its arrows
+    return _Spec(T.SU2, legs, tree=T.TREE_CHAIN)
+
+
+def contract_su2_dense(spec_a, flat_a, spec_b, flat_b, axes_a, axes_b):
+    """SU(2) contraction by the definition (eq:tensormult): both dense
+    tensors, contracted, projected on the result's tree.  Returns (spec, flat)."""
+    sc = result_spec(spec_a, spec_b, axes_a, axes_b)
+    dc = contract_dense(T.to_dense(spec_a, flat_a), T.to_dense(spec_b, flat_b), axes_a, axes_b)
+    return sc, T.from_dense(sc, dc)
 
 
 def contract_dense(dense_a: np.ndarray, dense_b: np.ndarray, axes_a, axes_b) -> np.ndarray:

@@ -120,3 +120,105 @@ def permute_tree(spec, flat, perm, tree_out):
         if spec.legs[p].arrow != out_spec.legs[i].arrow:
             dense = reverse_leg_dense(spec.legs[p], dense, i)
     return out_spec, T.from_dense(out_spec, dense), dense
+
+
+def chain_spec(spec, perm, arrows_out):
+    """Description of the CHAIN tensor with legs permuted (leg i is the
+    input's leg perm[i], same spectrum) and the given arrows."""
+    legs = [_Leg(tuple(spec.legs[p].labels), tuple(spec.legs[p].degs), a) for p, a in zip(perm, arrows_out)]
+    return _Spec(T.SU2, legs, T.TREE_CHAIN)
+
+
+def permute_chain(spec, flat, perm, arrows_out):
+    """Blocks of an SU(2) tensor (any tree) with legs permuted by perm, the
+    legs whose arrow changes reversed, on the CHAIN tree of arrows_out: the
+    6j-free route (dense tensor, transposed, reversed, projected).  Returns
+    (out_spec, flat blocks)."""
+    out_spec = chain_spec(spec, perm, arrows_out)
+    dense = np.transpose(T.to_dense(spec, flat), perm)
+    for i, p in enumerate(perm):
+        if spec.legs[p].arrow != out_spec.legs[i].arrow:
+            dense = reverse_leg_dense(spec.legs[p], dense, i)
+    return out_spec, T.from_dense(out_spec, dense)
+
+
+def fused_leg(leg_a, leg_b):
+    """Spectrum of the leg fused from two SU(2) legs of one arrow (eq:decoV,
+    eq:su2fusecanon): every spin c of j_a (x) j_b, its degeneracy the sum of
+    d_a d_b over the pairs (j_a, j_b) that reach it; inside c the pairs run
+    lexicographically, each over its d_a x d_b degeneracy indices row-major.
+    Returns (leg, {c: [(j_a, j_b, offset of the pair inside c)]})."""
+    deg_c, parts = {}, {}
+    for ja, da in zip(leg_a.labels, leg_a.degs):
+        for jb, db in zip(leg_b.labels, leg_b.degs):
+            for c in range(abs(ja - jb), ja + jb + 1, 2):
+                parts.setdefault(c, []).append((ja, jb, deg_c.get(c, 0)))
+                deg_c[c] = deg_c.get(c, 0) + da * db
+    labels = tuple(sorted(deg_c))
+    return _Leg(labels, tuple(deg_c[c] for c in labels), leg_a.arrow), parts
+
+
+def fuse_dense(spec, dense, i):
+    """Dense tensor with legs i and i + 1 fused (reshape of eq:fuse): the pair
+    basis (j_a t_a m_a, j_b t_b m_b) goes to (c, t_c, m_c) by the
+    Clebsch-Gordan change of basis C_{j_a m_a, j_b m_b -> c m_c} (eq:cg),
+    t_c enumerating the pairs as in fused_leg."""
+    la, lb = spec.legs[i], spec.legs[i + 1]
+    fl, parts = fused_leg(la, lb)
+    offa, _ = T.leg_offsets(T.SU2, la)
+    offb, _ = T.leg_offsets(T.SU2, lb)
+    offc, dimc = T.leg_offsets(T.SU2, fl)
+    dega, degb = dict(zip(la.labels, la.degs)), dict(zip(lb.labels, lb.degs))
+    x = np.moveaxis(np.moveaxis(np.asarray(dense, dtype=np.float64), i + 1, 0), i + 1, 0)   # [a, b, rest]
+    out = np.zeros((dimc,) + x.shape[2:])
+    for c, plist in parts.items():
+        for ja, jb, o in plist:
+            da, db = dega[ja], degb[jb]
+            cgt = su2.cg_tensor(ja, jb, c)   # [m_a, m_b, m_c]
+            for ta in range(da):
+                for tb in range(db):
+                    sa = offa[ja] + ta * (ja + 1)
+                    sb = offb[jb] + tb * (jb + 1)
+                    blk = x[sa:sa + ja + 1, sb:sb + jb + 1]   # [m_a, m_b, rest]
+                    tc = o + ta * db + tb
+                    sc = offc[c] + tc * (c + 1)
+                    out[sc:sc + c + 1] += np.tensordot(cgt, blk, axes=([0, 1], [0, 1]))
+    return np.moveaxis(out, 0, i)
+
+
+def fuse_chain(spec, flat, i):
+    """Blocks of the CHAIN tensor with legs i, i + 1 (one arrow) fused, by the
+    6j-free route: dense tensor, fused legs, projected on the CHAIN tree of
+    the result.  Returns (out_spec, flat blocks)."""
+    if spec.legs[i].arrow != spec.legs[i + 1].arrow:
+        raise ValueError("fused legs must share their arrow")
+    fl, _ = fused_leg(spec.legs[i], spec.legs[i + 1])
+    legs = list(spec.legs[:i]) + [fl] + list(spec.legs[i + 2:])
+    out_spec = _Spec(T.SU2, legs, T.TREE_CHAIN)
+    return out_spec, T.from_dense(out_spec, fuse_dense(spec, T.to_dense(spec, flat), i))
+
+
+def split_chain(spec, flat, i, leg_a, leg_b):
+    """Inverse of fuse_chain: leg i of the CHAIN tensor (the fusion of leg_a and
+    leg_b) split back into them.  The Clebsch-Gordan change of basis is
+    orthogonal, so the dense split is its transpose.  Returns (out_spec, flat)."""
+    fl, parts = fused_leg(leg_a, leg_b)
+    leg = spec.legs[i]
+    if tuple(fl.labels) != tuple(leg.labels) or tuple(fl.degs) != tuple(leg.degs):
+        raise ValueError("leg i is not the fusion of the two legs")
+    legs = list(spec.legs[:i]) + [_Leg(leg_a.labels, leg_a.degs, leg.arrow),
+                                  _Leg(leg_b.labels, leg_b.degs, leg.arrow)] + list(spec.legs[i + 1:])
+    out_spec = _Spec(T.SU2, legs, T.TREE_CHAIN)
+    dense = T.to_dense(spec, flat)
+    # dense fuse is linear and orthogonal on the pair space: apply its transpose
+    shape = list(dense.shape)
+    dima, dimb = T.leg_offsets(T.SU2, leg_a)[1], T.leg_offsets(T.SU2, leg_b)[1]
+    basis = np.eye(dima * dimb).reshape(dima * dimb, dima, dimb)
+    fmat = np.stack([fuse_dense(_Spec(T.SU2, [out_spec.legs[i], out_spec.legs[i + 1]], T.TREE_CHAIN), e, 0)
+                     for e in basis])   # [pair, fused]
+    x = np.moveaxis(dense, i, 0).reshape(shape[i], -1)
+    y = fmat @ x   # [pair, rest]
+    y = y.reshape([dima, dimb] + [s for k, s in enumerate(shape) if k != i])
+    y = np.moveaxis(np.moveaxis(y, 1, i + 1), 0, i)
+    return out_spec, T.from_dense(out_spec, y)
+

@@ -32,6 +32,17 @@ SU(2) rule.  Rank-4 tensors on three trees, each node obeying the fusion rule
   LEFT     (in,in,in,out):  Q^e = sum_me C_{j1 j2->e} C_{e j3->j4}   (eq:cob1)
   RIGHT    (in,in,in,out):  Q^f = sum_mf C_{j2 j3->f} C_{j1 f->j4}   (eq:cob2)
 The dense tensor is T = sum_e P^e (x) Q^e (eq:deco41, eq:deco42).
+
+Tensors of any rank use the CHAIN tree (section "Tree decompositions of
+SU(2)-invariant tensors", eq:datastruct, with the fusion tree taken
+left-associative): the incoming legs, in leg order c_0, c_1, ..., are fused
+one after the other, (c_0, c_1 -> a_1), (a_1, c_2 -> a_2), ..., to a total
+spin J; the outgoing legs d_0, d_1, ... likewise (b_1, b_2, ...) to the same
+J; Q = sum_M [in chain](m_in -> J M) [out chain](m_out -> J M).  An empty
+chain has total spin 0.  A block is a label tuple with the free intermediate
+spins (a_1 .. a_{n-2}, J, b_1 .. b_{m-2}), J listed only when both chains
+have two legs or more (otherwise a leg's spin, or 0, fixes it).  With arrows
+(in,in,out,out) this is the OPERATOR tree, with (in,in,in,out) the LEFT tree.
 """
 from __future__ import annotations
 
@@ -47,7 +58,8 @@ IN, OUT = "in", "out"
 U1, SU2 = "U1", "SU2"
 Z2, U1xU1, Z2F = "Z2", "U1xU1", "Z2F"
 ABELIAN = (U1, Z2, U1xU1, Z2F)
-TREE_NONE, TREE_OPERATOR, TREE_LEFT, TREE_RIGHT = 0, 1, 2, 3
+TREE_NONE, TREE_OPERATOR, TREE_LEFT, TREE_RIGHT, TREE_CHAIN = 0, 1, 2, 3, 4
+MAX_RANK = 8
 
 _SU2_ARROWS = {
     TREE_OPERATOR: (IN, IN, OUT, OUT),
@@ -59,7 +71,7 @@ _SU2_ARROWS = {
 @dataclass(frozen=True)
 class Block:
     labels: Tuple[int, ...]
-    internal: Optional[int]   # SU(2) intermediate spin (doubled); None for U(1)
+    internal: Optional[object]   # SU(2): intermediate spin (rank-4 trees) or tuple of them (CHAIN); None for U(1)
     shape: Tuple[int, ...]
     offset: int               # start of the block in the flat storage
 
@@ -161,6 +173,71 @@ def permute_dense(spec, dense: np.ndarray, perm: Sequence[int]) -> np.ndarray:
     return np.transpose(dense, perm)
 
 
+def chain_sequences(tjs: Sequence[int]) -> List[Tuple[int, ...]]:
+    """Every sequence of coupled spins (a_0 = j_0, a_1, ..., a_{n-1}) of a
+    left-associative fusion chain of the given spins; [()] for no spin."""
+    if not tjs:
+        return [()]
+    seqs = [(tjs[0],)]
+    for tj in tjs[1:]:
+        seqs = [s + (a,) for s in seqs for a in range(abs(s[-1] - tj), s[-1] + tj + 1, 2)]
+    return seqs
+
+
+def chain_total(seq) -> int:
+    return seq[-1] if seq else 0
+
+
+def chain_sides(arrows) -> Tuple[List[int], List[int]]:
+    """Leg positions of the incoming and of the outgoing chain, in leg order."""
+    return [i for i, a in enumerate(arrows) if a == IN], [i for i, a in enumerate(arrows) if a == OUT]
+
+
+def chain_key(a, b) -> Tuple[int, ...]:
+    """Free intermediate spins of a CHAIN block from its two coupled sequences."""
+    n, m = len(a), len(b)
+    return tuple(a[1:n - 1]) + ((a[-1],) if n >= 2 and m >= 2 else ()) + tuple(b[1:m - 1])
+
+
+def chain_internals(arrows, tj: Sequence[int]) -> List[Tuple[int, ...]]:
+    """Free intermediate spins of every CHAIN block of a label tuple, ascending."""
+    ins, outs = chain_sides(arrows)
+    seq_a = chain_sequences([tj[i] for i in ins])
+    seq_b = chain_sequences([tj[i] for i in outs])
+    return sorted(chain_key(a, b) for a in seq_a for b in seq_b if chain_total(a) == chain_total(b))
+
+
+def chain_split(arrows, tj: Sequence[int], key) -> Tuple[Tuple[int, ...], Tuple[int, ...]]:
+    """The two coupled sequences (in chain, out chain) of a CHAIN block."""
+    ins, outs = chain_sides(arrows)
+    for a in chain_sequences([tj[i] for i in ins]):
+        for b in chain_sequences([tj[i] for i in outs]):
+            if chain_total(a) == chain_total(b) and chain_key(a, b) == tuple(key):
+                return a, b
+    raise ValueError("no such CHAIN block")
+
+
+def chain_tensor(tjs: Sequence[int], seq) -> np.ndarray:
+    """The fusion chain as a tensor [m_0, ..., m_{n-1}, M]: the product of the
+    Clebsch-Gordan tensors of its nodes (eq:cg), summed over the inner m."""
+    if not tjs:
+        return np.ones((1,))
+    t = np.eye(tjs[0] + 1)
+    for k in range(1, len(tjs)):
+        t = np.tensordot(t, su2.cg_tensor(seq[k - 1], tjs[k], seq[k]), axes=([t.ndim - 1], [0]))
+    return t
+
+
+def chain_structural(arrows, tj: Sequence[int], key) -> np.ndarray:
+    """Structural tensor Q[m_1, .., m_k] (legs in leg order) of a CHAIN block."""
+    ins, outs = chain_sides(arrows)
+    a, b = chain_split(arrows, tj, key)
+    tin = chain_tensor([tj[i] for i in ins], a)
+    tout = chain_tensor([tj[i] for i in outs], b)
+    q = np.tensordot(tin, tout, axes=([tin.ndim - 1], [tout.ndim - 1]))
+    return np.transpose(q, np.argsort(ins + outs))
+
+
 def su2_internals(tree: int, tj: Sequence[int]) -> List[int]:
     """Intermediate spins (doubled, ascending) compatible with the tree."""
     j1, j2, j3, j4 = tj
@@ -180,7 +257,12 @@ def su2_internals(tree: int, tj: Sequence[int]) -> List[int]:
 
 
 def validate(spec) -> None:
-    if spec.group == SU2:
+    if spec.group == SU2 and spec.tree == TREE_CHAIN:
+        if not 1 <= len(spec.legs) <= MAX_RANK:
+            raise ValueError("CHAIN tensors have rank 1..8")
+        if any(lab < 0 for l in spec.legs for lab in l.labels):
+            raise ValueError("negative spin")
+    elif spec.group == SU2:
         if len(spec.legs) != 4 or spec.tree not in _SU2_ARROWS:
             raise ValueError("SU(2) tensors here are rank 4 on a known tree")
         if tuple(l.arrow for l in spec.legs) != _SU2_ARROWS[spec.tree]:
@@ -209,6 +291,8 @@ def blocks(spec) -> List[Block]:
             if not allowed_abelian(spec.group, labels, arrows, spec.qtot):
                 continue
             internals = [None]
+        elif spec.tree == TREE_CHAIN:
+            internals = chain_internals(arrows, labels)
         else:
             internals = su2_internals(spec.tree, labels)
         for e in internals:
@@ -242,6 +326,13 @@ def join_blocks(spec, data: Dict[tuple, np.ndarray], dtype=np.float64) -> np.nda
     return flat
 
 
+def block_structural(spec, labels, internal) -> np.ndarray:
+    """Structural tensor of one SU(2) block of a tensor (any tree)."""
+    if spec.tree == TREE_CHAIN:
+        return chain_structural([l.arrow for l in spec.legs], labels, internal)
+    return structural(spec.tree, labels, internal)
+
+
 def structural(tree: int, tj: Sequence[int], te: int) -> np.ndarray:
     """Structural tensor Q^e[m1,m2,m3,m4] of the given tree."""
     j1, j2, j3, j4 = tj
@@ -273,8 +364,10 @@ def to_dense(spec, flat: np.ndarray) -> np.ndarray:
         if spec.group in ABELIAN:
             dense[sl] = p
         else:
-            q = structural(spec.tree, labels, e)
-            sub = np.einsum("abcd,wxyz->awbxcydz", p, q)
+            q = block_structural(spec, labels, e)
+            k = p.ndim
+            sub = np.multiply.outer(p, q)   # [t_1..t_k, m_1..m_k] -> [t_1, m_1, t_2, m_2, ...]
+            sub = np.transpose(sub, [x for i in range(k) for x in (i, k + i)])
             dense[sl] += sub.reshape(dense[sl].shape)
     return dense
 
@@ -291,11 +384,12 @@ def from_dense(spec, dense: np.ndarray) -> np.ndarray:
         if spec.group in ABELIAN:
             out[b.key] = np.array(sub)
         else:
-            q = structural(spec.tree, b.labels, b.internal)
+            q = block_structural(spec, b.labels, b.internal)
             dims = [irrep_dim(SU2, lab) for lab in b.labels]
-            s4 = sub.reshape(b.shape[0], dims[0], b.shape[1], dims[1],
-                             b.shape[2], dims[2], b.shape[3], dims[3])
-            out[b.key] = np.einsum("awbxcydz,wxyz->abcd", s4, q) / np.sum(q * q)
+            k = len(dims)
+            sk = sub.reshape([x for i in range(k) for x in (b.shape[i], dims[i])])
+            sk = np.transpose(sk, [2 * i for i in range(k)] + [2 * i + 1 for i in range(k)])
+            out[b.key] = np.tensordot(sk, q, axes=(list(range(k, 2 * k)), list(range(k)))) / np.sum(q * q)
     return join_blocks(spec, out)
 
 
