@@ -19,9 +19,19 @@
  *    sum(q, in legs) equals the tensor's total charge (0 for an invariant
  *    tensor).  This is the invariance condition eq:Tinv with exp(i r q) on
  *    every leg.
- *  - SU(2) tensors here have rank 4 and one of three trees (eq:cob1, eq:cob2,
+ *  - SU(2) tensors of rank 4 may use one of three trees (eq:cob1, eq:cob2,
  *    eq:deco41): OPERATOR (in,in,out,out), (1,2)->e->(3,4); LEFT
  *    (in,in,in,out), {1,2->e; e,3->4}; RIGHT (in,in,in,out), {2,3->f; 1,f->4}.
+ *    SU(2) tensors of any rank (1..8) and any arrows use the CHAIN tree (a
+ *    tree decomposition, eq:datastruct, with left-associative fusion trees):
+ *    the incoming legs, in leg order c_0, c_1, .., are fused as
+ *    (c_0, c_1 -> a_1), (a_1, c_2 -> a_2), .. to a total spin J, the outgoing
+ *    legs d_0, d_1, .. likewise (b_1, b_2, ..) to the same J (an empty chain
+ *    has total 0).  A block is a label tuple with its free intermediate
+ *    spins (a_1 .. a_{n-2}, J when both chains have two legs or more,
+ *    b_1 .. b_{m-2}), blocks of one label tuple ordered by that key.  With
+ *    arrows (in,in,out,out) it is the OPERATOR tree, with (in,in,in,out) the
+ *    LEFT tree, with the same blocks.
  *    Every node obeys the fusion rule eq:fusionrules.
  *
  * Data layout ("sector-major for a bipartition").  A tensor declares n_row:
@@ -33,6 +43,11 @@
  *    tuple belongs to s = sum(q, out col legs) - sum(q, in col legs) - qtot.
  *  - SU(2) (n_row = 2, OPERATOR or LEFT tree): the sector is the intermediate
  *    spin e; a row pair (j1,j2) appears in every sector e it can fuse to.
+ *  - SU(2) CHAIN tree (0 < n_row < rank, the first n_row legs incoming): the
+ *    sector is the coupled spin a_{n_row-1} of the row legs; a row tuple is
+ *    the row labels with a_1 .. a_{n_row-2}, a column tuple the other labels
+ *    with the remaining intermediate spins; tuples are ordered labels first,
+ *    then spins.
  *  - Inside a sector, rows run over row-label tuples in lexicographic order,
  *    each spanning the row-major product of its row-leg degeneracies; columns
  *    likewise over column-label tuples.  This is the fuse of eq:fuse with the
@@ -113,7 +128,7 @@ enum { SYM_U1 = 0, SYM_SU2 = 1, SYM_Z2 = 2, SYM_U1U1 = 3, SYM_Z2F = 4 };   /* gr
 enum { SYM_F32 = 0, SYM_BF16 = 1 };                /* element type                */
 enum { SYM_IN = 0, SYM_OUT = 1 };                  /* leg direction               */
 enum { SYM_TREE_NONE = 0, SYM_TREE_OPERATOR = 1,   /* SU(2) coupling tree         */
-       SYM_TREE_LEFT = 2, SYM_TREE_RIGHT = 3 };
+       SYM_TREE_LEFT = 2, SYM_TREE_RIGHT = 3, SYM_TREE_CHAIN = 4 };
 
 #define SYM_MAX_RANK 8
 
@@ -161,9 +176,11 @@ int32_t sym_hold_count(const sym_hold* h, int64_t* n);
 void sym_hold_destroy(sym_hold* h);
 
 /* Describe a symmetric tensor (section "Block structure"; eq:datak).
- * group: one of the groups above; rank <= SYM_MAX_RANK (SU(2): 4); n_row in
- * [0, rank] (SU(2): 0, 2 or 4, and 2 only on the OPERATOR or LEFT tree); tree:
- * SU(2) tree id (SYM_TREE_NONE for the Abelian groups); qtot: total charge of
+ * group: one of the groups above; rank <= SYM_MAX_RANK (SU(2) rank-4 trees:
+ * 4); n_row in [0, rank] (rank-4 SU(2) trees: 0, 2 or 4, and 2 only on the
+ * OPERATOR or LEFT tree; CHAIN: 0 or rank, or a bipartition whose row legs
+ * are incoming); tree: SU(2) tree id (SYM_TREE_NONE for the Abelian groups);
+ * qtot: total charge of
  * an Abelian tensor (0 = invariant; must be 0 for SU(2)); dtype: SYM_F32 or
  * SYM_BF16; data: device pointer to
  * numel elements in the layout described above, borrowed (may be NULL and set
@@ -183,6 +200,11 @@ int32_t sym_tensor_num_sectors(const sym_tensor* t, int64_t* n_sectors);
  * element stride of each leg inside the data (any output may be NULL). */
 int32_t sym_tensor_block_info(const sym_tensor* t, int64_t i, int32_t* labels, int32_t* internal,
                               int64_t* offset, int64_t* shape, int64_t* strides);
+/* SU(2) CHAIN tree: the free intermediate spins (doubled) of block i, its
+ * key within its label tuple: (a_1 .. a_{n-2}, J when both chains have two
+ * legs or more, b_1 .. b_{m-2}) (see sym_tensor_create); *n_inner receives
+ * their number (0 for other trees and groups); inner may be NULL. */
+int32_t sym_tensor_block_inner(const sym_tensor* t, int64_t i, int32_t* inner, int32_t* n_inner);
 /* Sector i: its label (U(1) charge or SU(2) 2e), rows, cols, element offset. */
 int32_t sym_tensor_sector_info(const sym_tensor* t, int64_t i, int32_t* label, int64_t* rows,
                                int64_t* cols, int64_t* offset);
@@ -236,6 +258,22 @@ int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
  * fs (gamma holds cap * cap); SYM_E_ARG when *n would exceed it.  No GPU. */
 int32_t sym_su2_gamma(int32_t tree_in, const int32_t* perm, int32_t tree_out, const int32_t* spins, int32_t cap,
                       int32_t* n, int32_t* es, int32_t* fs, double* gamma);
+
+/* The Gamma of a PERMUTE with REVERSE between CHAIN trees for one label
+ * tuple, on the host (eq:Gamma, eq:permsu2; section "Reversal of indices"):
+ * input legs with arrows_in and doubled spins spins[rank]; output leg i is
+ * input leg perm[i] with arrow arrows_out[i].  On return *n is the number of
+ * blocks of the tuple (the same on both sides), keys_in[n * key_len_in] and
+ * keys_out[n * key_len_out] their keys in block order (see
+ * sym_tensor_block_inner), gamma[f * n + e] the coefficient from input block e
+ * to output block f.  Composed in FP64 from exchanges at a node (eq:braid3),
+ * F-moves (eq:fmove2, 6j by Racah's formula) and bends (eq:cupj, eq:capj; the
+ * leg's m index summed against the cup's or cap's row index).  cap bounds n
+ * (keys hold cap * rank entries, gamma cap * cap); SYM_E_ARG when n exceeds
+ * it.  No GPU. */
+int32_t sym_su2_chain_gamma(int32_t rank, const int32_t* arrows_in, const int32_t* perm, const int32_t* arrows_out,
+                            const int32_t* spins, int32_t cap, int32_t* n, int32_t* key_len_in, int32_t* key_len_out,
+                            int32_t* keys_in, int32_t* keys_out, double* gamma);
 
 /* Contraction C = A . B (see above).  compute: SYM_F32 (FP32 MFMA, FP32
  * accumulate) or SYM_BF16 (operands rounded to BF16 on the device, BF16 MFMA,

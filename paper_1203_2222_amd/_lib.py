@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "SYM_OK", 1: "SYM_E_ARG", 2: "SYM_E_SPECTRUM", 3: "SYM_E_ARRO
 SYM_U1, SYM_SU2, SYM_Z2, SYM_U1U1, SYM_Z2F = 0, 1, 2, 3, 4
 SYM_F32, SYM_BF16 = 0, 1
 SYM_IN, SYM_OUT = 0, 1
-SYM_TREE_NONE, SYM_TREE_OPERATOR, SYM_TREE_LEFT, SYM_TREE_RIGHT = 0, 1, 2, 3
+SYM_TREE_NONE, SYM_TREE_OPERATOR, SYM_TREE_LEFT, SYM_TREE_RIGHT, SYM_TREE_CHAIN = 0, 1, 2, 3, 4
 MAX_RANK = 8
 
 
@@ -51,11 +51,14 @@ SIGNATURES = {
     "sym_tensor_num_sectors": (c_int32, [P, I64P]),
     "sym_tensor_block_info": (c_int32, [P, c_int64, I32P, I32P, I64P, I64P, I64P]),
     "sym_tensor_sector_info": (c_int32, [P, c_int64, I32P, I64P, I64P, I64P]),
+    "sym_tensor_block_inner": (c_int32, [P, c_int64, I32P, I32P]),
     "sym_permute_fuse_output": (c_int32, [P, P, I32P, c_int32, c_int32, P, PP]),
     "sym_permute_fuse": (c_int32, [P, P, I32P, c_int32, P, P]),
     "sym_permute_tree_output": (c_int32, [P, P, I32P, c_int32, c_int32, P, PP]),
     "sym_permute_tree": (c_int32, [P, P, I32P, c_int32, c_int32, P, P]),
     "sym_su2_gamma": (c_int32, [c_int32, I32P, c_int32, I32P, c_int32, I32P, I32P, I32P, POINTER(c_double)]),
+    "sym_su2_chain_gamma": (c_int32, [c_int32, I32P, I32P, I32P, I32P, c_int32, I32P, I32P, I32P, I32P, I32P,
+                                      POINTER(c_double)]),
     "sym_contract_output": (c_int32, [P, P, P, c_int32, I32P, I32P, P, PP]),
     "sym_contract": (c_int32, [P, P, P, c_int32, I32P, I32P, c_int32, P, P]),
     "sym_contract_noalloc": (c_int32, [P, P, P, c_int32, I32P, I32P, c_int32, P, P]),

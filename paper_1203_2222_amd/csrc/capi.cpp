@@ -660,6 +660,17 @@ int32_t sym_tensor_block_info(const sym_tensor* t, int64_t i, int32_t* labels, i
     });
 }
 
+int32_t sym_tensor_block_inner(const sym_tensor* t, int64_t i, int32_t* inner, int32_t* n_inner) {
+    return guard([&] {
+        if (!t || !n_inner) throw Error(SYM_E_ARG, "NULL argument");
+        if (i < 0 || i >= static_cast<int64_t>(t->d->blocks.size())) throw Error(SYM_E_ARG, "block index out of range");
+        const Block& b = t->d->blocks[static_cast<size_t>(i)];
+        *n_inner = b.n_inner;
+        if (inner)
+            for (int k = 0; k < b.n_inner; ++k) inner[k] = b.inner[static_cast<size_t>(k)];
+    });
+}
+
 int32_t sym_tensor_sector_info(const sym_tensor* t, int64_t i, int32_t* label, int64_t* rows, int64_t* cols,
                                int64_t* offset) {
     return guard([&] {
@@ -878,6 +889,38 @@ int32_t sym_su2_gamma(int32_t tree_in, const int32_t* perm, int32_t tree_out, co
         *n = m;
         std::copy(e.begin(), e.end(), es);
         std::copy(f.begin(), f.end(), fs);
+        std::copy(g.begin(), g.end(), gamma);
+    });
+}
+
+int32_t sym_su2_chain_gamma(int32_t rank, const int32_t* arrows_in, const int32_t* perm, const int32_t* arrows_out,
+                            const int32_t* spins, int32_t cap, int32_t* n, int32_t* key_len_in, int32_t* key_len_out,
+                            int32_t* keys_in, int32_t* keys_out, double* gamma) {
+    return guard([&] {
+        if (!arrows_in || !perm || !arrows_out || !spins || !n || !key_len_in || !key_len_out || !keys_in || !keys_out ||
+            !gamma)
+            throw Error(SYM_E_ARG, "NULL argument");
+        if (rank < 1 || rank > SYM_MAX_RANK) throw Error(SYM_E_ARG, "rank outside [1, SYM_MAX_RANK]");
+        std::vector<bool> seen(static_cast<size_t>(rank), false);
+        for (int i = 0; i < rank; ++i) {
+            if (perm[i] < 0 || perm[i] >= rank || seen[static_cast<size_t>(perm[i])]) throw Error(SYM_E_ARG, "not a permutation");
+            seen[static_cast<size_t>(perm[i])] = true;
+            if (spins[i] < 0) throw Error(SYM_E_ARG, "negative spin");
+            if ((arrows_in[i] != SYM_IN && arrows_in[i] != SYM_OUT) || (arrows_out[i] != SYM_IN && arrows_out[i] != SYM_OUT))
+                throw Error(SYM_E_ARG, "arrow must be SYM_IN or SYM_OUT");
+        }
+        std::vector<std::vector<int32_t>> ki, ko;
+        std::vector<double> g;
+        chain_gamma(rank, arrows_in, perm, arrows_out, spins, ki, ko, g);
+        const int32_t m = static_cast<int32_t>(ki.size());
+        if (m > cap) throw Error(SYM_E_ARG, "capacity too small for the blocks of this label tuple");
+        *n = m;
+        *key_len_in = m ? static_cast<int32_t>(ki[0].size()) : 0;
+        *key_len_out = m ? static_cast<int32_t>(ko[0].size()) : 0;
+        for (int32_t r = 0; r < m; ++r) {
+            std::copy(ki[static_cast<size_t>(r)].begin(), ki[static_cast<size_t>(r)].end(), keys_in + r * *key_len_in);
+            std::copy(ko[static_cast<size_t>(r)].begin(), ko[static_cast<size_t>(r)].end(), keys_out + r * *key_len_out);
+        }
         std::copy(g.begin(), g.end(), gamma);
     });
 }

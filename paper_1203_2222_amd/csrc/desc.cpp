@@ -7,6 +7,7 @@
 // the fusion rule eq:fusionrules.  Blocks are the degeneracy tensors of the
 // canonical form (eq:datak).
 #include <algorithm>
+#include <map>
 #include <set>
 #include <sstream>
 
@@ -23,9 +24,71 @@ std::string label_key(const int32_t* labels, int n, int32_t internal) {
     return s;
 }
 
+std::string inner_key(const int32_t* labels, int n, const int32_t* inner, int n_inner) {
+    std::string s(static_cast<size_t>(n + n_inner + 1) * sizeof(int32_t), '\0');
+    if (n) std::memcpy(&s[0], labels, static_cast<size_t>(n) * sizeof(int32_t));
+    if (n_inner) std::memcpy(&s[static_cast<size_t>(n) * sizeof(int32_t)], inner, static_cast<size_t>(n_inner) * sizeof(int32_t));
+    const int32_t tag = -2 - n_inner;   // distinct from any rank-4 internal spin
+    std::memcpy(&s[static_cast<size_t>(n + n_inner) * sizeof(int32_t)], &tag, sizeof(int32_t));
+    return s;
+}
+
 int32_t Desc::find_block(const int32_t* labels, int32_t internal) const {
     auto it = block_index.find(label_key(labels, rank, internal));
     return it == block_index.end() ? -1 : it->second;
+}
+
+int32_t Desc::find_block_inner(const int32_t* labels, const int32_t* inner, int32_t n_inner) const {
+    auto it = block_index.find(inner_key(labels, rank, inner, n_inner));
+    return it == block_index.end() ? -1 : it->second;
+}
+
+int32_t Desc::find_block(const int32_t* labels, const Block& like) const {
+    if (tree == SYM_TREE_CHAIN) return find_block_inner(labels, like.inner.data(), like.n_inner);
+    return find_block(labels, like.internal);
+}
+
+std::vector<Seq> chain_sequences(const std::vector<int32_t>& spins) {
+    std::vector<Seq> out;
+    if (spins.empty()) {
+        out.emplace_back();
+        return out;
+    }
+    out.push_back(Seq{spins[0]});
+    for (size_t k = 1; k < spins.size(); ++k) {
+        std::vector<Seq> next;
+        for (const Seq& q : out) {
+            const int32_t a = q.back(), j = spins[k];
+            for (int32_t c = a > j ? a - j : j - a; c <= a + j; c += 2) {
+                Seq r = q;
+                r.push_back(c);
+                next.push_back(std::move(r));
+            }
+        }
+        out.swap(next);
+    }
+    return out;
+}
+
+std::vector<int32_t> chain_key(const Seq& a, const Seq& b) {
+    const size_t n = a.size(), m = b.size();
+    std::vector<int32_t> k;
+    for (size_t i = 1; i + 1 < n; ++i) k.push_back(a[i]);
+    if (n >= 2 && m >= 2) k.push_back(a.back());
+    for (size_t i = 1; i + 1 < m; ++i) k.push_back(b[i]);
+    return k;
+}
+
+std::vector<ChainBlock> chain_blocks(const std::vector<int32_t>& arrows, const int32_t* labels, int rank) {
+    std::vector<int32_t> sin, sout;
+    for (int l = 0; l < rank; ++l) (arrows[static_cast<size_t>(l)] == SYM_IN ? sin : sout).push_back(labels[l]);
+    const std::vector<Seq> A = chain_sequences(sin), B = chain_sequences(sout);
+    std::vector<ChainBlock> out;
+    for (const Seq& a : A)
+        for (const Seq& b : B)
+            if (chain_total(a) == chain_total(b)) out.push_back(ChainBlock{a, b, chain_key(a, b)});
+    std::sort(out.begin(), out.end(), [](const ChainBlock& x, const ChainBlock& y) { return x.key < y.key; });
+    return out;
 }
 
 int32_t Desc::find_sector(int32_t label) const {
@@ -112,19 +175,29 @@ void validate(int32_t group, const std::vector<Leg>& legs, int32_t n_row, int32_
         }
         return;
     }
-    if (rank != 4) throw Error(SYM_E_UNSUPPORTED, "SU(2) tensors here have rank 4");
     if (qtot != 0) throw Error(SYM_E_ARG, "SU(2) tensors are invariant (qtot = 0)");
+    for (const Leg& l : legs)
+        for (int32_t lab : l.label)
+            if (lab < 0) throw Error(SYM_E_CHARGE, "SU(2) labels are 2j >= 0");
+    if (tree == SYM_TREE_CHAIN) {
+        if (rank < 1) throw Error(SYM_E_ARG, "CHAIN tensors have rank 1..SYM_MAX_RANK");
+        // sector-major layouts: the first n_row legs are the first incoming
+        // legs of the chain (rows), the sector their coupled spin
+        if (n_row > 0 && n_row < rank)
+            for (int i = 0; i < n_row; ++i)
+                if (legs[static_cast<size_t>(i)].arrow != SYM_IN)
+                    throw Error(SYM_E_UNSUPPORTED, "a CHAIN sector layout needs its row legs incoming");
+        return;
+    }
+    if (rank != 4) throw Error(SYM_E_UNSUPPORTED, "OPERATOR, LEFT and RIGHT trees have rank 4 (use the CHAIN tree)");
     static const int32_t op_arrows[4] = {SYM_IN, SYM_IN, SYM_OUT, SYM_OUT};
     static const int32_t fuse_arrows[4] = {SYM_IN, SYM_IN, SYM_IN, SYM_OUT};
     const int32_t* want = nullptr;
     if (tree == SYM_TREE_OPERATOR) want = op_arrows;
     else if (tree == SYM_TREE_LEFT || tree == SYM_TREE_RIGHT) want = fuse_arrows;
-    else throw Error(SYM_E_ARG, "SU(2) tensors need the OPERATOR, LEFT or RIGHT tree");
+    else throw Error(SYM_E_ARG, "SU(2) tensors need the OPERATOR, LEFT, RIGHT or CHAIN tree");
     for (int i = 0; i < 4; ++i)
         if (legs[static_cast<size_t>(i)].arrow != want[i]) throw Error(SYM_E_ARROW, "arrows do not match the SU(2) tree");
-    for (const Leg& l : legs)
-        for (int32_t lab : l.label)
-            if (lab < 0) throw Error(SYM_E_CHARGE, "SU(2) labels are 2j >= 0");
     if (!(n_row == 0 || n_row == 4 || n_row == 2)) throw Error(SYM_E_UNSUPPORTED, "SU(2) n_row must be 0, 2 or 4");
     if (n_row == 2 && tree == SYM_TREE_RIGHT)
         throw Error(SYM_E_UNSUPPORTED, "the RIGHT tree has no 2|2 sector layout");
@@ -222,7 +295,7 @@ void build_u1(Desc& d) {
         auto c = cpos.find(label_key(t.lab.data() + nr, rank - nr, 0));
         if (r == rpos.end() || c == cpos.end() || r->second.first != c->second.first) continue;
         Block b;
-        b.labels = t.lab;
+        std::copy(t.lab.begin(), t.lab.begin() + SYM_MAX_RANK, b.labels.begin());
         b.internal = -1;
         for (int i = 0; i < rank; ++i) b.shape[static_cast<size_t>(i)] = deg_of(d.legs[static_cast<size_t>(i)], t.lab[static_cast<size_t>(i)]);
         b.size = t.dim;
@@ -267,7 +340,7 @@ void build_su2(Desc& d) {
         for (const Tuple& t : all) {
             for (int32_t e : su2_internals(d.tree, t.lab.data())) {
                 Block b;
-                b.labels = t.lab;
+                std::copy(t.lab.begin(), t.lab.begin() + SYM_MAX_RANK, b.labels.begin());
                 b.internal = e;
                 for (int i = 0; i < 4; ++i) b.shape[static_cast<size_t>(i)] = deg_of(d.legs[static_cast<size_t>(i)], t.lab[static_cast<size_t>(i)]);
                 b.size = t.dim;
@@ -287,7 +360,7 @@ void build_su2(Desc& d) {
     for (const Tuple& t : all) {
         for (int32_t e : su2_internals(d.tree, t.lab.data())) {
             Block b;
-            b.labels = t.lab;
+            std::copy(t.lab.begin(), t.lab.begin() + SYM_MAX_RANK, b.labels.begin());
             b.internal = e;
             for (int i = 0; i < 4; ++i) b.shape[static_cast<size_t>(i)] = deg_of(d.legs[static_cast<size_t>(i)], t.lab[static_cast<size_t>(i)]);
             b.size = t.dim;
@@ -305,6 +378,117 @@ void build_su2(Desc& d) {
     d.numel = off;
 }
 
+// CHAIN tree (any rank).  Canonical block list for n_row = 0 or rank;
+// otherwise sector-major for the bipartition after the first n_row
+// (incoming) legs: the sector of a block is the coupled spin a_{n_row-1} of
+// its row legs, a row tuple is (row labels, a_1 .. a_{n_row-2}) and a column
+// tuple the remaining labels with the remaining intermediate spins
+// (a_{n_row} .. a_{n-1}, b_1 .. b_{m-2}).  Row and column tuples are
+// ordered lexicographically, labels first.
+void build_chain(Desc& d) {
+    const int rank = d.rank, k = d.n_row;
+    std::vector<int32_t> arrows;
+    int n_in = 0;
+    for (const Leg& l : d.legs) {
+        arrows.push_back(l.arrow);
+        n_in += l.arrow == SYM_IN;
+    }
+    std::vector<Tuple> all = enumerate(d.legs, 0, rank);
+    auto shape_of = [&](Block& b, const Tuple& t) {
+        for (int i = 0; i < rank; ++i) b.shape[static_cast<size_t>(i)] = deg_of(d.legs[static_cast<size_t>(i)], t.lab[static_cast<size_t>(i)]);
+        b.size = t.dim;
+    };
+    auto set_key = [](Block& b, const std::vector<int32_t>& key) {
+        if (key.size() > static_cast<size_t>(SYM_MAX_RANK)) throw Error(SYM_E_UNSUPPORTED, "too many intermediate spins");
+        b.n_inner = static_cast<int32_t>(key.size());
+        for (size_t i = 0; i < key.size(); ++i) b.inner[i] = key[i];
+    };
+    if (k == 0 || k == rank) {
+        Sector s;
+        s.label = 0;
+        d.sectors.push_back(s);
+        int64_t off = 0;
+        for (const Tuple& t : all) {
+            for (const ChainBlock& cb : chain_blocks(arrows, t.lab.data(), rank)) {
+                Block b;
+                b.labels = {};
+                for (int i = 0; i < rank; ++i) b.labels[static_cast<size_t>(i)] = t.lab[static_cast<size_t>(i)];
+                set_key(b, cb.key);
+                shape_of(b, t);
+                b.sector = 0;
+                b.offset = off;
+                int64_t acc = 1;
+                for (int l = rank - 1; l >= 0; --l) { b.stride[static_cast<size_t>(l)] = acc; acc *= b.shape[static_cast<size_t>(l)]; }
+                off += b.size;
+                d.blocks.push_back(b);
+            }
+        }
+        Sector& s0 = d.sectors[0];
+        if (k == rank) { s0.rows = off; s0.cols = 1; s0.ld = 1; }
+        else { s0.rows = 1; s0.cols = off; s0.ld = off; }
+        d.numel = off;
+        return;
+    }
+    // row / column tuples of every block, grouped by sector
+    struct Item { Tuple t; Tuple row, col; int32_t sector; ChainBlock cb; };
+    std::vector<Item> items;
+    std::map<int32_t, std::set<std::vector<int32_t>>> rset, cset;
+    std::map<std::vector<int32_t>, Tuple> tuple_of;
+    auto make_tuple = [&](const int32_t* labs, int nl, int first_leg, const std::vector<int32_t>& ints) {
+        Tuple u;
+        u.n = nl + static_cast<int32_t>(ints.size());
+        if (u.n > 2 * SYM_MAX_RANK) throw Error(SYM_E_UNSUPPORTED, "tuple too long");
+        for (int i = 0; i < nl; ++i) {
+            u.lab[static_cast<size_t>(i)] = labs[i];
+            u.dim *= deg_of(d.legs[static_cast<size_t>(first_leg + i)], labs[i]);
+        }
+        for (size_t i = 0; i < ints.size(); ++i) u.lab[static_cast<size_t>(nl) + i] = ints[i];
+        return u;
+    };
+    auto vec_of = [](const Tuple& u) { return std::vector<int32_t>(u.lab.begin(), u.lab.begin() + u.n); };
+    for (const Tuple& t : all) {
+        for (const ChainBlock& cb : chain_blocks(arrows, t.lab.data(), rank)) {
+            // the first k legs are the first k incoming ones: a_0 .. a_{k-1}
+            std::vector<int32_t> rint(cb.a.begin() + 1, cb.a.begin() + (k >= 2 ? k - 1 : 1));
+            if (k < 2) rint.clear();
+            std::vector<int32_t> cint(cb.a.begin() + k, cb.a.end());
+            for (size_t i = 1; i + 1 < cb.b.size(); ++i) cint.push_back(cb.b[i]);
+            Item it{t, make_tuple(t.lab.data(), k, 0, rint), make_tuple(t.lab.data() + k, rank - k, k, cint),
+                    cb.a[static_cast<size_t>(k - 1)], cb};
+            rset[it.sector].insert(vec_of(it.row));
+            cset[it.sector].insert(vec_of(it.col));
+            tuple_of[vec_of(it.row)] = it.row;
+            items.push_back(std::move(it));
+        }
+    }
+    std::map<std::pair<int32_t, std::vector<int32_t>>, Tuple> ctuple;
+    for (const Item& it : items) ctuple[{it.sector, vec_of(it.col)}] = it.col;
+    for (auto& kv : rset) {
+        Sector s;
+        s.label = kv.first;
+        for (const auto& v : kv.second) s.row_tuples.push_back(tuple_of.at(v));
+        for (const auto& v : cset.at(kv.first)) s.col_tuples.push_back(ctuple.at({kv.first, v}));
+        d.sectors.push_back(std::move(s));
+    }
+    finish_sectors(d);
+    std::map<std::pair<int32_t, std::vector<int32_t>>, int64_t> rpos, cpos;
+    for (const Sector& s : d.sectors) {
+        for (size_t i = 0; i < s.row_tuples.size(); ++i) rpos[{s.label, vec_of(s.row_tuples[i])}] = s.row_off[i];
+        for (size_t i = 0; i < s.col_tuples.size(); ++i) cpos[{s.label, vec_of(s.col_tuples[i])}] = s.col_off[i];
+    }
+    for (const Item& it : items) {
+        Block b;
+        for (int i = 0; i < rank; ++i) b.labels[static_cast<size_t>(i)] = it.t.lab[static_cast<size_t>(i)];
+        set_key(b, it.cb.key);
+        shape_of(b, it.t);
+        b.sector = d.find_sector(it.sector);
+        place_block(d, b, d.sectors[static_cast<size_t>(b.sector)], rpos.at({it.sector, vec_of(it.row)}),
+                    cpos.at({it.sector, vec_of(it.col)}));
+        d.blocks.push_back(b);
+    }
+    (void)n_in;
+}
+
 }  // namespace
 
 DescPtr make_desc(int32_t group, const std::vector<Leg>& legs, int32_t n_row, int32_t tree, int32_t qtot,
@@ -319,12 +503,18 @@ DescPtr make_desc(int32_t group, const std::vector<Leg>& legs, int32_t n_row, in
     d->dtype = dtype;
     d->opts = opts;
     d->legs = legs;
-    if (group == SYM_SU2 && opts.trans && n_row != 2)
+    if (group == SYM_SU2 && tree != SYM_TREE_CHAIN && opts.trans && n_row != 2)
         throw Error(SYM_E_UNSUPPORTED, "transposed SU(2) layout needs n_row = 2");
+    if (group == SYM_SU2 && tree == SYM_TREE_CHAIN && opts.trans && (n_row == 0 || n_row == d->rank))
+        throw Error(SYM_E_UNSUPPORTED, "transposed CHAIN layout needs a sector bipartition");
     if (is_abelian(group)) build_u1(*d);
+    else if (tree == SYM_TREE_CHAIN) build_chain(*d);
     else build_su2(*d);
-    for (size_t i = 0; i < d->blocks.size(); ++i)
-        d->block_index[label_key(d->blocks[i].labels.data(), d->rank, d->blocks[i].internal)] = static_cast<int32_t>(i);
+    for (size_t i = 0; i < d->blocks.size(); ++i) {
+        const Block& b = d->blocks[i];
+        d->block_index[tree == SYM_TREE_CHAIN ? inner_key(b.labels.data(), d->rank, b.inner.data(), b.n_inner)
+                                              : label_key(b.labels.data(), d->rank, b.internal)] = static_cast<int32_t>(i);
+    }
     std::ostringstream k;
     k << group << '|' << d->rank << '|' << n_row << '|' << tree << '|' << qtot << '|' << dtype << '|'
       << opts.trans << '|' << opts.ld_align << '|' << opts.base_align;

@@ -39,9 +39,11 @@ struct Leg {
     bool same_spectrum(const Leg& o) const { return label == o.label && deg == o.deg; }
 };
 
-// A tuple of labels on a subset of legs, with its degeneracy product.
+// A tuple of labels on a subset of legs (for SU(2) CHAIN trees followed by
+// the intermediate spins that belong to that side), with its degeneracy
+// product.
 struct Tuple {
-    std::array<int32_t, SYM_MAX_RANK> lab{};
+    std::array<int32_t, 2 * SYM_MAX_RANK> lab{};
     int32_t n = 0;
     int64_t dim = 1;
     bool operator==(const Tuple& o) const {
@@ -54,7 +56,10 @@ struct Tuple {
 
 struct Block {
     std::array<int32_t, SYM_MAX_RANK> labels{};
-    int32_t internal = -1;   // SU(2) intermediate spin (doubled); -1 for U(1)
+    int32_t internal = -1;   // SU(2) intermediate spin (doubled) of a rank-4 tree; -1 otherwise
+    // SU(2) CHAIN tree: the block's free intermediate spins (see chain_key)
+    std::array<int32_t, SYM_MAX_RANK> inner{};
+    int32_t n_inner = 0;
     std::array<int64_t, SYM_MAX_RANK> shape{};
     std::array<int64_t, SYM_MAX_RANK> stride{};
     int64_t offset = 0;      // element offset of entry (0,..,0)
@@ -90,12 +95,17 @@ struct Desc {
     std::unordered_map<std::string, int32_t> block_index;  // label tuple (+internal) -> block
 
     int32_t find_block(const int32_t* labels, int32_t internal) const;
+    // block with these labels and the intermediate spins of `like` (its
+    // internal, or its CHAIN key)
+    int32_t find_block(const int32_t* labels, const Block& like) const;
+    int32_t find_block_inner(const int32_t* labels, const int32_t* inner, int32_t n_inner) const;
     int32_t find_sector(int32_t label) const;
 };
 
 using DescPtr = std::shared_ptr<const Desc>;
 
 std::string label_key(const int32_t* labels, int n, int32_t internal);
+std::string inner_key(const int32_t* labels, int n, const int32_t* inner, int n_inner);
 DescPtr make_desc(int32_t group, const std::vector<Leg>& legs, int32_t n_row, int32_t tree,
                   int32_t qtot, int32_t dtype, const LayoutOpts& opts = LayoutOpts());
 std::vector<Leg> permute_legs(const std::vector<Leg>& legs, const std::vector<int32_t>& perm);
@@ -105,6 +115,25 @@ size_t dtype_size(int32_t dtype);
 inline bool triangle(int a, int b, int c) {
     return (a + b + c) % 2 == 0 && c >= (a > b ? a - b : b - a) && c <= a + b;
 }
+
+// SU(2) CHAIN tree (tensors of any rank; section "Tree decompositions of
+// SU(2)-invariant tensors", eq:datastruct, with left-associative fusion
+// trees): the incoming legs, in leg order c_0, c_1, ..., are fused as
+// (c_0, c_1 -> a_1), (a_1, c_2 -> a_2), ... to a total spin J, the outgoing
+// legs d_0, d_1, ... likewise (b_1, b_2, ...) to the same J.  An empty chain
+// has total 0.  A coupled sequence is (a_0 = j_{c_0}, a_1, .., a_{n-1} = J).
+// The key of a block lists its free intermediate spins:
+// (a_1 .. a_{n-2}, J if both chains have two legs or more, b_1 .. b_{m-2}).
+using Seq = std::vector<int32_t>;
+std::vector<Seq> chain_sequences(const std::vector<int32_t>& spins);
+inline int32_t chain_total(const Seq& s) { return s.empty() ? 0 : s.back(); }
+std::vector<int32_t> chain_key(const Seq& a, const Seq& b);
+struct ChainBlock {
+    Seq a, b;                     // coupled sequences of the incoming and outgoing chains
+    std::vector<int32_t> key;
+};
+// every CHAIN block of one label tuple (labels in leg order), sorted by key
+std::vector<ChainBlock> chain_blocks(const std::vector<int32_t>& arrows, const int32_t* labels, int rank);
 // Recoupling coefficient F^{D E}_{A B C J} (eq:sixj), doubled spins.
 double fmove_coeff(int tA, int tB, int tC, int tJ, int tD, int tE);
 double sixj(int a, int b, int c, int d, int e, int f);
@@ -127,5 +156,13 @@ TreeMoves tree_moves(int32_t tree_in, const int32_t* perm, int32_t tree_out);
 // are the input's and output's intermediate spins, coef[f][e] row-major.
 void tree_gamma(const TreeMoves& mv, const int32_t* j, std::vector<int32_t>& es, std::vector<int32_t>& fs,
                 std::vector<double>& coef);
+
+// Gamma of a PERMUTE with REVERSE between CHAIN trees (newtree.cpp): input
+// legs with arrows_in and doubled spins j; output leg i is input leg perm[i]
+// with arrow arrows_out[i].  keys_in / keys_out: the blocks' keys in block
+// order; coef[f * n + e] maps input block e to output block f.
+void chain_gamma(int rank, const int32_t* arrows_in, const int32_t* perm, const int32_t* arrows_out,
+                 const int32_t* j, std::vector<std::vector<int32_t>>& keys_in,
+                 std::vector<std::vector<int32_t>>& keys_out, std::vector<double>& coef);
 
 }  // namespace sym

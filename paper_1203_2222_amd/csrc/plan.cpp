@@ -73,7 +73,8 @@ void CopyProgram::add(const Desc& src, const Desc& dst, const std::vector<int32_
     int32_t lab[SYM_MAX_RANK];
     for (const Block& b : dst.blocks) {
         for (int i = 0; i < rank; ++i) lab[perm[static_cast<size_t>(i)]] = b.labels[static_cast<size_t>(i)];
-        const int32_t si = src.find_block(lab, b.internal);
+        if (src.tree != dst.tree) throw Error(SYM_E_ARG, "block copies keep the SU(2) tree");
+        const int32_t si = src.find_block(lab, b);
         if (si < 0) throw Error(SYM_E_MISMATCH, "destination block has no source block");
         const Block& sb = src.blocks[static_cast<size_t>(si)];
         // dims in destination leg order, outermost first

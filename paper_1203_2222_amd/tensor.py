@@ -116,6 +116,16 @@ class SymTensor:
                                  tuple(shape[:r]), tuple(strides[:r])))
         return out
 
+    def block_keys(self):
+        """SU(2) CHAIN tree: the free intermediate spins of every block, in block order."""
+        out = []
+        buf = (c_int32 * L.MAX_RANK)()
+        n = c_int32()
+        for i in range(self.num_blocks()):
+            L.check(L.lib().sym_tensor_block_inner(self.handle, i, buf, byref(n)))
+            out.append(tuple(buf[:n.value]))
+        return out
+
     def sectors(self):
         n = c_int64()
         L.check(L.lib().sym_tensor_num_sectors(self.handle, byref(n)))
@@ -509,3 +519,22 @@ def su2_gamma(tree_in: int, perm: Sequence[int], tree_out: int, spins: Sequence[
 
 def fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE) -> float:
     return L.lib().sym_fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE)
+
+
+def su2_chain_gamma(arrows_in: Sequence[str], perm: Sequence[int], arrows_out: Sequence[str], spins: Sequence[int]):
+    """(input block keys, output block keys, Gamma[f][e]) of a PERMUTE with
+    REVERSE between CHAIN trees for one label tuple of doubled spins (host only)."""
+    rank = len(spins)
+    cap = 4096
+    n, ki, ko = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    kin = (ctypes.c_int32 * (cap * rank))()
+    kout = (ctypes.c_int32 * (cap * rank))()
+    g = (ctypes.c_double * (cap * cap))()
+    L.check(L.lib().sym_su2_chain_gamma(rank, L.i32_array(_ARROWS[a] for a in arrows_in), L.i32_array(perm),
+                                        L.i32_array(_ARROWS[a] for a in arrows_out), L.i32_array(spins), cap,
+                                        byref(n), byref(ki), byref(ko), kin, kout, g))
+    k = n.value
+    keys_in = [tuple(kin[r * ki.value:(r + 1) * ki.value]) for r in range(k)]
+    keys_out = [tuple(kout[r * ko.value:(r + 1) * ko.value]) for r in range(k)]
+    return keys_in, keys_out, [[g[f * k + e] for e in range(k)] for f in range(k)]
+
