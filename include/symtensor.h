@@ -251,6 +251,55 @@ int32_t sym_permute_tree_output(sym_ctx* ctx, const sym_tensor* in, const int32_
                                 int32_t n_row_out, void* data, sym_tensor** out);
 int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t tree_out,
                          int32_t n_row_out, sym_tensor* out, void* stream);
+/* General SU(2) PERMUTE with REVERSE onto the CHAIN tree, at any rank (the
+ * routine PERMUTE with Gamma(tree, p, tree') of eq:permsu2 and eq:Gamma,
+ * section "Tree decompositions of SU(2)-invariant tensors", and REVERSE of
+ * section "Reversal of indices").  out's leg i is in's leg perm[i] (same
+ * spectrum) with arrow arrows_out[i]; every leg whose arrow changes is
+ * reversed (an outgoing leg by the cup of eq:cupj, an incoming one by the cap
+ * of eq:capj, the leg's m index summed against the matrix's row index).  For
+ * each label tuple the output blocks are y_f = sum_e Gamma[f][e] x_e (legs
+ * permuted), Gamma composed on the host in FP64 (see sym_su2_chain_gamma),
+ * the combination on the device in FP64 on FP32 data.  in: SU(2), FP32, on
+ * the CHAIN, OPERATOR or LEFT tree, any layout; n_row_out: any layout the
+ * CHAIN tree allows.  Limits: rank <= 8, at most 32 blocks per label tuple
+ * (SYM_E_UNSUPPORTED otherwise).  sym_su2_permute_output creates the result's
+ * handle (data may be NULL); sym_su2_permute writes into out, which must
+ * describe exactly that result; in and out must not overlap.  The plan is
+ * built on the first call and cached. */
+int32_t sym_su2_permute_output(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, const int32_t* arrows_out,
+                               int32_t n_row_out, void* data, sym_tensor** out);
+int32_t sym_su2_permute(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, const int32_t* arrows_out,
+                        int32_t n_row_out, sym_tensor* out, void* stream);
+/* FUSE and SPLIT of two adjacent legs of an SU(2) tensor (section "Reshape
+ * of indices" of the tree-decomposition chapter; eq:fuse, eq:su2fusecanon).
+ * FUSE: legs leg and leg + 1 of in (one arrow) become one leg whose labels
+ * are every spin c of j_a (x) j_b, with degeneracy the sum of d_a d_b over the
+ * pairs (j_a, j_b) that reach c; inside c the pairs run lexicographically
+ * (j_a, then j_b), each over its d_a x d_b degeneracy indices row-major.
+ * When the two legs are the first two of their chain, the fusion deletes the
+ * first node and moves no value (the blocks are relabelled); otherwise one
+ * F-move (eq:fmove2, FP64) maps their two nodes to (A, c -> J).  SPLIT is the
+ * inverse: leg `leg` of in, the fusion of legs2[0] and legs2[1] (their
+ * labels and degeneracies; arrows are taken from in's leg, SYM_E_SPECTRUM if
+ * they do not fuse to it), becomes those two legs.  in: SU(2), FP32, CHAIN
+ * tree (FUSE also takes OPERATOR and LEFT), any layout; the result is on the
+ * CHAIN tree with n_row_out.  *_output create the result's handle (data may
+ * be NULL); sym_su2_fuse / sym_su2_split write into out, which must describe
+ * exactly that result; in and out must not overlap.  Plans are cached. */
+int32_t sym_su2_fuse_output(sym_ctx* ctx, const sym_tensor* in, int32_t leg, int32_t n_row_out, void* data,
+                            sym_tensor** out);
+int32_t sym_su2_fuse(sym_ctx* ctx, const sym_tensor* in, int32_t leg, int32_t n_row_out, sym_tensor* out,
+                     void* stream);
+int32_t sym_su2_split_output(sym_ctx* ctx, const sym_tensor* in, int32_t leg, const sym_leg* legs2, int32_t n_row_out,
+                             void* data, sym_tensor** out);
+int32_t sym_su2_split(sym_ctx* ctx, const sym_tensor* in, int32_t leg, sym_tensor* out, void* stream);
+/* Spectrum of leg `leg` of a tensor: *n labels, their degeneracies and the
+ * arrow.  With labels and degs both NULL only *n (and *arrow) are written;
+ * otherwise SYM_E_ARG if *n is above cap. */
+int32_t sym_tensor_leg(const sym_tensor* t, int32_t leg, int32_t cap, int32_t* n, int32_t* labels, int64_t* degs,
+                       int32_t* arrow);
+
 /* The Gamma of sym_permute_tree for one label tuple, on the host: spins[4]
  * are the doubled spins of the input's legs; on return *n is the number of
  * intermediate spins, es[*n] the input tree's (ascending), fs[*n] the output
@@ -277,9 +326,20 @@ int32_t sym_su2_chain_gamma(int32_t rank, const int32_t* arrows_in, const int32_
 
 /* Contraction C = A . B (see above).  compute: SYM_F32 (FP32 MFMA, FP32
  * accumulate) or SYM_BF16 (operands rounded to BF16 on the device, BF16 MFMA,
- * FP32 accumulate, FP32 output).  C must have dtype F32.  SU(2): A must be an
- * OPERATOR tensor contracted on legs (2,3) with legs (0,1) of an OPERATOR or
- * LEFT tensor B; C gets B's tree.  sym_contract_output creates C's handle
+ * FP32 accumulate, FP32 output).  C must have dtype F32.  SU(2): an OPERATOR
+ * tensor A contracted on legs (2,3) with legs (0,1) of an OPERATOR or LEFT
+ * tensor B gives C on B's tree (sector-major, n_row 2), by one GEMM per
+ * intermediate spin (any compute type).  Any other SU(2) contraction of
+ * CHAIN, OPERATOR or LEFT tensors, over any axes (at least one contracted and
+ * one free leg on each side), follows the five steps of the thesis on CHAIN
+ * trees (section "Multiplication of two tensors" of the tree-decomposition
+ * chapter): A is recoupled (PERMUTE with REVERSE, sym_su2_permute) so that its
+ * free legs are incoming rows and its contracted legs outgoing, B so that its
+ * contracted legs (in the order of axesB) are incoming rows, one GEMM runs per
+ * coupled spin of the contracted legs (the Clebsch-Gordan chains of the
+ * contracted legs contract to the identity, eq:cgunitary), and the product is
+ * recoupled into C, a CHAIN tensor (default layout: the canonical block list)
+ * with A's free legs then B's free legs and their arrows.  FP32 only.  sym_contract_output creates C's handle
  * (data may be NULL).  The plan (block matching, offsets, tile list) is built
  * on the first call and cached in the context. */
 int32_t sym_contract_output(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,

@@ -2,6 +2,7 @@
 // the host side of permute / contract / backward / batched / graph calls.
 #include <algorithm>
 #include <cstdio>
+#include <deque>
 #include <cstdlib>
 #include <fstream>
 #include <functional>
@@ -59,11 +60,20 @@ constexpr int kSlotWsOut = 1;   // GEMM outputs that still need a split (FP32)
 constexpr int kSlotUser = 2;    // user tensors from here on
 constexpr int kMaxBatch = (kMaxBufs - kSlotUser) / 3;
 
+// A recoupling launched as part of a contraction (general SU(2) operands).
+struct RcStep {
+    RecoupleProgram prog;
+    int in_slot = 0, out_slot = 0;
+};
+
 struct ContractPlan {
     int count = 0, compute = SYM_F32;
     CopyProgram fuse[2];   // by source dtype (F32, BF16) -> compute dtype
     GemmProgram gemm;
     CopyProgram split;     // FP32 -> FP32
+    // general SU(2) contractions: operands recoupled into their GEMM forms
+    // before the GEMM, results recoupled into C after it
+    std::deque<RcStep> rc_pre, rc_post;
     DevMemPtr ws_in, ws_out;
     int64_t in_elems = 0, out_elems = 0;   // workspace sizes (compute dtype, FP32)
     int grid = 1;
@@ -230,6 +240,7 @@ std::vector<Leg> read_legs(int32_t rank, const sym_leg* legs) {
 struct PairInfo {
     std::vector<int32_t> fa, fb, axa, axb;
     std::vector<int32_t> perm_a, perm_b;   // A: fa ++ axa ; B: axb ++ fb
+    bool su2_general = false;              // SU(2) outside the rank-4 operator form
 };
 
 PairInfo check_pair(const Desc& A, const Desc& B, int32_t n, const int32_t* axesA, const int32_t* axesB) {
@@ -260,12 +271,22 @@ PairInfo check_pair(const Desc& A, const Desc& B, int32_t n, const int32_t* axes
     p.perm_b = p.axb;
     p.perm_b.insert(p.perm_b.end(), p.fb.begin(), p.fb.end());
     if (A.group == SYM_SU2) {
-        const bool ok = A.tree == SYM_TREE_OPERATOR && n == 2 && p.axa == std::vector<int32_t>{2, 3} &&
-                        p.axb == std::vector<int32_t>{0, 1} &&
-                        (B.tree == SYM_TREE_OPERATOR || B.tree == SYM_TREE_LEFT);
-        if (!ok)
-            throw Error(SYM_E_UNSUPPORTED,
-                        "SU(2) contraction: an OPERATOR tensor on legs (2,3) with legs (0,1) of an OPERATOR or LEFT tensor");
+        const bool fast = A.tree == SYM_TREE_OPERATOR && n == 2 && p.axa == std::vector<int32_t>{2, 3} &&
+                          p.axb == std::vector<int32_t>{0, 1} &&
+                          (B.tree == SYM_TREE_OPERATOR || B.tree == SYM_TREE_LEFT);
+        if (!fast) {
+            // the five steps on CHAIN trees: both operands recoupled into
+            // their matrix forms, one GEMM per coupled spin, the product
+            // recoupled into C
+            auto chainlike = [](const Desc& d) {
+                return d.tree == SYM_TREE_CHAIN || d.tree == SYM_TREE_OPERATOR || d.tree == SYM_TREE_LEFT;
+            };
+            if (!chainlike(A) || !chainlike(B))
+                throw Error(SYM_E_UNSUPPORTED, "SU(2) contraction takes CHAIN, OPERATOR or LEFT tensors");
+            if (n < 1 || p.fa.empty() || p.fb.empty())
+                throw Error(SYM_E_UNSUPPORTED, "SU(2) contraction needs a contracted leg and a free leg on each side");
+            p.su2_general = true;
+        }
     }
     return p;
 }
@@ -274,6 +295,8 @@ DescPtr result_desc(const Desc& A, const Desc& B, const PairInfo& p) {
     std::vector<Leg> legs;
     for (int32_t i : p.fa) legs.push_back(A.legs[static_cast<size_t>(i)]);
     for (int32_t i : p.fb) legs.push_back(B.legs[static_cast<size_t>(i)]);
+    if (A.group == SYM_SU2 && p.su2_general)
+        return make_desc(SYM_SU2, legs, static_cast<int32_t>(legs.size()), SYM_TREE_CHAIN, 0, SYM_F32);
     if (A.group == SYM_SU2)
         return make_desc(SYM_SU2, legs, 2, B.tree, 0, SYM_F32);
     return make_desc(A.group, legs, static_cast<int32_t>(p.fa.size()), SYM_TREE_NONE, combine_qtot(A.group, A.qtot, B.qtot),
@@ -290,6 +313,33 @@ DescPtr fused_a(const Desc& A, const PairInfo& p, int32_t dtype, bool trans) {
 DescPtr fused_b(const Desc& B, const PairInfo& p, int32_t dtype, bool trans) {
     return make_desc(B.group, permute_legs(B.legs, p.perm_b), static_cast<int32_t>(p.axb.size()), B.tree, B.qtot, dtype,
                      workspace_opts(dtype, trans));
+}
+
+// GEMM forms of a general SU(2) contraction (CHAIN trees): A' = A's free
+// legs (incoming, rows) then its contracted legs (outgoing); B' = B's
+// contracted legs (incoming, rows, in the order of the axes) then its free
+// legs (arrows kept), stored transposed; C' = A's free legs (incoming, rows)
+// then B's free legs.  The sector of A' and C' is the coupled spin of A's
+// free legs, that of B' the coupled spin of the contracted legs, which the
+// GEMM pairs (the Clebsch-Gordan chains of the contracted legs contract to
+// the identity, eq:cgunitary).
+struct Su2Forms {
+    DescPtr ap, bp, cp;
+};
+
+Su2Forms su2_forms(const Desc& A, const Desc& B, const PairInfo& p, int32_t compute) {
+    Su2Forms f;
+    std::vector<Leg> la = permute_legs(A.legs, p.perm_a), lb = permute_legs(B.legs, p.perm_b), lc;
+    for (size_t i = 0; i < la.size(); ++i) la[i].arrow = i < p.fa.size() ? SYM_IN : SYM_OUT;
+    for (size_t i = 0; i < p.axb.size(); ++i) lb[i].arrow = SYM_IN;
+    for (size_t i = 0; i < p.fa.size(); ++i) lc.push_back(la[i]);
+    for (size_t i = p.axb.size(); i < lb.size(); ++i) lc.push_back(lb[i]);
+    f.ap = make_desc(SYM_SU2, la, static_cast<int32_t>(p.fa.size()), SYM_TREE_CHAIN, 0, compute,
+                     workspace_opts(compute, false));
+    f.bp = make_desc(SYM_SU2, lb, static_cast<int32_t>(p.axb.size()), SYM_TREE_CHAIN, 0, compute,
+                     workspace_opts(compute, true));
+    f.cp = make_desc(SYM_SU2, lc, static_cast<int32_t>(p.fa.size()), SYM_TREE_CHAIN, 0, SYM_F32);
+    return f;
 }
 
 std::vector<int32_t> identity(int n) {
@@ -385,6 +435,38 @@ std::shared_ptr<ContractPlan> plan_contract_host(sym_ctx* ctx, int32_t count, co
         if (c.group != want_c->group || c.legs != want_c->legs || c.qtot != want_c->qtot ||
             (c.group == SYM_SU2 && c.tree != want_c->tree) || c.dtype != SYM_F32)
             throw Error(SYM_E_MISMATCH, "C does not describe the contraction result");
+        if (p.su2_general) {
+            if (compute != SYM_F32 || a.dtype != SYM_F32 || b.dtype != SYM_F32)
+                throw Error(SYM_E_DTYPE, "general SU(2) contractions run in FP32");
+            const Su2Forms f = su2_forms(a, b, p, compute);
+            const int64_t a_base = in_off;
+            in_off = align_up(in_off + f.ap->numel, 64);
+            const int64_t b_base = in_off;
+            in_off = align_up(in_off + f.bp->numel, 64);
+            const int64_t c_base = out_off;
+            out_off = align_up(out_off + f.cp->numel, 64);
+            std::vector<int32_t> cperm = identity(c.rank);
+            plan->rc_pre.emplace_back();
+            plan->rc_pre.back().prog.build(a, *f.ap, p.perm_a, 0, a_base);
+            plan->rc_pre.back().in_slot = kSlotUser + i;
+            plan->rc_pre.back().out_slot = kSlotWsIn;
+            // A contracted pair whose A leg is incoming is reversed on both
+            // sides (cap on A's leg, cup on B's); cap . cup^T = (-1)^(2j)
+            // (eq:capj, eq:cupj), so B's coefficients take that sign back
+            uint32_t sign_legs = 0;
+            for (size_t k = 0; k < p.axb.size(); ++k)
+                if (b.legs[static_cast<size_t>(p.axb[k])].arrow == SYM_OUT) sign_legs |= 1u << p.axb[k];
+            plan->rc_pre.emplace_back();
+            plan->rc_pre.back().prog.build(b, *f.bp, p.perm_b, 0, b_base, sign_legs);
+            plan->rc_pre.back().in_slot = kSlotUser + count + i;
+            plan->rc_pre.back().out_slot = kSlotWsIn;
+            plan->gemm.add(*f.cp, *f.ap, *f.bp, kSlotWsOut, kSlotWsIn, kSlotWsIn, c_base, a_base, b_base);
+            plan->rc_post.emplace_back();
+            plan->rc_post.back().prog.build(*f.cp, c, cperm, c_base, 0);
+            plan->rc_post.back().in_slot = kSlotWsOut;
+            plan->rc_post.back().out_slot = kSlotUser + 2 * count + i;
+            continue;
+        }
         DescPtr af = fused_a(a, p, compute, false);
         DescPtr bf = fused_b(b, p, compute, true);   // stored N x K: K contiguous
         const int64_t a_base = in_off;
@@ -439,6 +521,8 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
     for (auto& f : plan->fuse) f.upload(alloc);
     plan->gemm.upload(alloc);
     plan->split.upload(alloc);
+    for (auto& r : plan->rc_pre) r.prog.upload(alloc);
+    for (auto& r : plan->rc_post) r.prog.upload(alloc);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->contract_plans[key] = plan;
     return plan;
@@ -480,6 +564,8 @@ std::shared_ptr<ContractPlan> build_noalloc_plan(sym_ctx* ctx, const sym_tensor*
     for (auto& f : plan->fuse) f.upload(arena, &plan->staged);
     plan->gemm.upload(arena, &plan->staged);
     plan->split.upload(arena, &plan->staged);
+    for (auto& r : plan->rc_pre) r.prog.upload(arena, &plan->staged);
+    for (auto& r : plan->rc_post) r.prog.upload(arena, &plan->staged);
     if (used > kNoAllocScratchBytes)
         throw Error(SYM_E_UNSUPPORTED, "contraction needs " + std::to_string(used) +
                                            " bytes of workspace and tables; the no-alloc scratch holds " +
@@ -512,10 +598,12 @@ void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor*
         HIP_CHECK(hipEventRecord(ctx->ev[0], s));
     }
     for (const auto& f : plan.fuse) HIP_CHECK(f.launch(t, s));
+    for (const auto& r : plan.rc_pre) HIP_CHECK(r.prog.launch(t, r.in_slot, r.out_slot, s));
     if (timing) HIP_CHECK(hipEventRecord(ctx->ev[1], s));
     HIP_CHECK(plan.gemm.launch(t, plan.grid, s));
     if (timing) HIP_CHECK(hipEventRecord(ctx->ev[2], s));
     HIP_CHECK(plan.split.launch(t, s));
+    for (const auto& r : plan.rc_post) HIP_CHECK(r.prog.launch(t, r.in_slot, r.out_slot, s));
     if (timing) HIP_CHECK(hipEventRecord(ctx->ev[3], s));
 }
 
@@ -870,6 +958,231 @@ int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
     });
 }
 
+// ----- SU(2) PERMUTE / REVERSE onto CHAIN trees (any rank) -------------------------
+
+namespace {
+
+std::vector<int32_t> check_su2_chain_perm(const Desc& in, const int32_t* perm, const int32_t* arrows_out) {
+    if (in.group != SYM_SU2) throw Error(SYM_E_UNSUPPORTED, "sym_su2_permute acts on SU(2) tensors");
+    if (in.tree != SYM_TREE_CHAIN && in.tree != SYM_TREE_OPERATOR && in.tree != SYM_TREE_LEFT)
+        throw Error(SYM_E_UNSUPPORTED, "sym_su2_permute takes CHAIN, OPERATOR or LEFT tensors");
+    if (in.dtype != SYM_F32) throw Error(SYM_E_DTYPE, "recoupling works on FP32 data");
+    if (!perm || !arrows_out) throw Error(SYM_E_ARG, "NULL argument");
+    std::vector<int32_t> p(perm, perm + in.rank);
+    std::vector<bool> seen(static_cast<size_t>(in.rank), false);
+    for (int i = 0; i < in.rank; ++i) {
+        if (p[static_cast<size_t>(i)] < 0 || p[static_cast<size_t>(i)] >= in.rank || seen[static_cast<size_t>(p[static_cast<size_t>(i)])])
+            throw Error(SYM_E_ARG, "not a permutation");
+        seen[static_cast<size_t>(p[static_cast<size_t>(i)])] = true;
+        if (arrows_out[i] != SYM_IN && arrows_out[i] != SYM_OUT) throw Error(SYM_E_ARG, "arrow must be SYM_IN or SYM_OUT");
+    }
+    return p;
+}
+
+DescPtr su2_chain_result(const Desc& in, const std::vector<int32_t>& perm, const int32_t* arrows_out, int32_t n_row_out) {
+    std::vector<Leg> legs = permute_legs(in.legs, perm);
+    for (size_t i = 0; i < legs.size(); ++i) legs[i].arrow = arrows_out[i];
+    return make_desc(SYM_SU2, legs, n_row_out, SYM_TREE_CHAIN, 0, SYM_F32);
+}
+
+}  // namespace
+
+int32_t sym_su2_permute_output(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, const int32_t* arrows_out,
+                               int32_t n_row_out, void* data, sym_tensor** out) {
+    (void)ctx;
+    return guard([&] {
+        if (!in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        const std::vector<int32_t> p = check_su2_chain_perm(*in->d, perm, arrows_out);
+        auto* t = new sym_tensor();
+        try {
+            t->d = su2_chain_result(*in->d, p, arrows_out, n_row_out);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        t->data = data;
+        *out = t;
+    });
+}
+
+int32_t sym_su2_permute(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, const int32_t* arrows_out,
+                        int32_t n_row_out, sym_tensor* out, void* stream) {
+    return guard([&] {
+        if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        const std::vector<int32_t> p = check_su2_chain_perm(*in->d, perm, arrows_out);
+        if (!has_data(in) || !has_data(out)) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        std::ostringstream k;
+        k << "U|" << in->d->key << '|' << out->d->key << '|';
+        for (int32_t v : p) k << v << ',';
+        std::shared_ptr<PermutePlan> plan;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->permute_plans.find(k.str());
+            if (it != ctx->permute_plans.end()) plan = it->second;
+        }
+        if (!plan) {
+            DescPtr want = su2_chain_result(*in->d, p, arrows_out, n_row_out);
+            if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
+            plan = std::make_shared<PermutePlan>();
+            plan->is_recouple = true;
+            plan->recouple.build(*in->d, *out->d, p);
+            plan->recouple.upload(ctx->allocator());
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->permute_plans[k.str()] = plan;
+        }
+        ctx->note(plan);
+        PtrTable t{};
+        t.p[0] = in->data;
+        t.p[1] = out->data;
+        HIP_CHECK(plan->recouple.launch(t, 0, 1, static_cast<hipStream_t>(stream)));
+    });
+}
+
+// ----- SU(2) FUSE / SPLIT of two adjacent legs (CHAIN trees) --------------------------
+
+namespace {
+
+void check_fuse_legs(const Desc& d, int32_t leg) {
+    if (d.group != SYM_SU2 || (d.tree != SYM_TREE_CHAIN && d.tree != SYM_TREE_OPERATOR && d.tree != SYM_TREE_LEFT))
+        throw Error(SYM_E_UNSUPPORTED, "FUSE and SPLIT act on SU(2) CHAIN, OPERATOR or LEFT tensors");
+    if (d.dtype != SYM_F32) throw Error(SYM_E_DTYPE, "FUSE and SPLIT work on FP32 data");
+    if (leg < 0 || leg + 1 >= d.rank) throw Error(SYM_E_ARG, "leg and leg + 1 must be legs of the tensor");
+}
+
+DescPtr fused_desc(const Desc& in, int32_t leg, int32_t n_row_out) {
+    check_fuse_legs(in, leg);
+    const Leg& a = in.legs[static_cast<size_t>(leg)];
+    const Leg& b = in.legs[static_cast<size_t>(leg + 1)];
+    if (a.arrow != b.arrow) throw Error(SYM_E_ARROW, "fused legs must share their arrow");
+    std::vector<Leg> legs;
+    for (int l = 0; l < in.rank; ++l) {
+        if (l == leg + 1) continue;
+        legs.push_back(l == leg ? fuse_legs(a, b).leg : in.legs[static_cast<size_t>(l)]);
+    }
+    return make_desc(SYM_SU2, legs, n_row_out, SYM_TREE_CHAIN, 0, SYM_F32);
+}
+
+DescPtr split_desc(const Desc& in, int32_t leg, const Leg& a, const Leg& b, int32_t n_row_out) {
+    if (in.group != SYM_SU2 || in.tree != SYM_TREE_CHAIN) throw Error(SYM_E_UNSUPPORTED, "SPLIT acts on CHAIN tensors");
+    if (in.dtype != SYM_F32) throw Error(SYM_E_DTYPE, "FUSE and SPLIT work on FP32 data");
+    if (leg < 0 || leg >= in.rank || in.rank + 1 > SYM_MAX_RANK) throw Error(SYM_E_ARG, "bad leg or rank");
+    const Leg& f = in.legs[static_cast<size_t>(leg)];
+    Leg la = a, lb = b;
+    la.arrow = lb.arrow = f.arrow;
+    const Leg fl = fuse_legs(la, lb).leg;
+    if (fl.label != f.label || fl.deg != f.deg) throw Error(SYM_E_SPECTRUM, "the leg is not the fusion of the two legs");
+    std::vector<Leg> legs;
+    for (int l = 0; l < in.rank; ++l) {
+        if (l == leg) {
+            legs.push_back(la);
+            legs.push_back(lb);
+        } else {
+            legs.push_back(in.legs[static_cast<size_t>(l)]);
+        }
+    }
+    return make_desc(SYM_SU2, legs, n_row_out, SYM_TREE_CHAIN, 0, SYM_F32);
+}
+
+void run_fuse(sym_ctx* ctx, const sym_tensor* in, sym_tensor* out, int32_t leg, bool to_fused, const std::string& key,
+              hipStream_t stream) {
+    if (!has_data(in) || !has_data(out)) throw Error(SYM_E_ARG, "tensor has no data pointer");
+    std::shared_ptr<PermutePlan> plan;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->permute_plans.find(key);
+        if (it != ctx->permute_plans.end()) plan = it->second;
+    }
+    if (!plan) {
+        plan = std::make_shared<PermutePlan>();
+        plan->is_recouple = true;
+        if (to_fused) plan->recouple.build_fuse(*in->d, *out->d, leg, true);
+        else plan->recouple.build_fuse(*out->d, *in->d, leg, false);
+        plan->recouple.upload(ctx->allocator());
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->permute_plans[key] = plan;
+    }
+    ctx->note(plan);
+    PtrTable t{};
+    t.p[0] = in->data;
+    t.p[1] = out->data;
+    HIP_CHECK(plan->recouple.launch(t, 0, 1, stream));
+}
+
+}  // namespace
+
+int32_t sym_su2_fuse_output(sym_ctx* ctx, const sym_tensor* in, int32_t leg, int32_t n_row_out, void* data,
+                            sym_tensor** out) {
+    (void)ctx;
+    return guard([&] {
+        if (!in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        auto* t = new sym_tensor();
+        try {
+            t->d = fused_desc(*in->d, leg, n_row_out);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        t->data = data;
+        *out = t;
+    });
+}
+
+int32_t sym_su2_fuse(sym_ctx* ctx, const sym_tensor* in, int32_t leg, int32_t n_row_out, sym_tensor* out,
+                     void* stream) {
+    return guard([&] {
+        if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        DescPtr want = fused_desc(*in->d, leg, n_row_out);
+        if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the fused tensor");
+        run_fuse(ctx, in, out, leg, true, "F|" + in->d->key + '|' + out->d->key + '|' + std::to_string(leg),
+                 static_cast<hipStream_t>(stream));
+    });
+}
+
+int32_t sym_su2_split_output(sym_ctx* ctx, const sym_tensor* in, int32_t leg, const sym_leg* legs2, int32_t n_row_out,
+                             void* data, sym_tensor** out) {
+    (void)ctx;
+    return guard([&] {
+        if (!in || !out || !legs2) throw Error(SYM_E_ARG, "NULL argument");
+        const std::vector<Leg> two = read_legs(2, legs2);
+        auto* t = new sym_tensor();
+        try {
+            t->d = split_desc(*in->d, leg, two[0], two[1], n_row_out);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        t->data = data;
+        *out = t;
+    });
+}
+
+int32_t sym_su2_split(sym_ctx* ctx, const sym_tensor* in, int32_t leg, sym_tensor* out, void* stream) {
+    return guard([&] {
+        if (!ctx || !in || !out) throw Error(SYM_E_ARG, "NULL argument");
+        if (out->d->rank != in->d->rank + 1 || leg < 0 || leg >= in->d->rank) throw Error(SYM_E_ARG, "bad leg or rank");
+        DescPtr want = split_desc(*in->d, leg, out->d->legs[static_cast<size_t>(leg)],
+                                  out->d->legs[static_cast<size_t>(leg + 1)], out->d->n_row);
+        if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the split tensor");
+        run_fuse(ctx, in, out, leg, false, "S|" + in->d->key + '|' + out->d->key + '|' + std::to_string(leg),
+                 static_cast<hipStream_t>(stream));
+    });
+}
+
+int32_t sym_tensor_leg(const sym_tensor* t, int32_t leg, int32_t cap, int32_t* n, int32_t* labels, int64_t* degs,
+                       int32_t* arrow) {
+    return guard([&] {
+        if (!t || !n) throw Error(SYM_E_ARG, "NULL argument");
+        if (leg < 0 || leg >= t->d->rank) throw Error(SYM_E_ARG, "leg out of range");
+        const Leg& l = t->d->legs[static_cast<size_t>(leg)];
+        *n = static_cast<int32_t>(l.label.size());
+        if (arrow) *arrow = l.arrow;
+        if (!labels && !degs) return;   // a query of *n
+        if (*n > cap) throw Error(SYM_E_ARG, "capacity too small for the leg's labels");
+        if (labels) std::copy(l.label.begin(), l.label.end(), labels);
+        if (degs) std::copy(l.deg.begin(), l.deg.end(), degs);
+    });
+}
+
 int32_t sym_su2_gamma(int32_t tree_in, const int32_t* perm, int32_t tree_out, const int32_t* spins, int32_t cap,
                       int32_t* n, int32_t* es, int32_t* fs, double* gamma) {
     return guard([&] {
@@ -951,9 +1264,14 @@ int32_t sym_contract_flops(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* 
     return guard([&] {
         if (!A || !B || !flops) throw Error(SYM_E_ARG, "NULL argument");
         PairInfo p = check_pair(*A->d, *B->d, n, axesA, axesB);
-        DescPtr c = result_desc(*A->d, *B->d, p);
         GemmProgram g;
-        g.add(*c, *fused_a(*A->d, p, SYM_F32, false), *fused_b(*B->d, p, SYM_F32, true), 0, 0, 0);
+        if (p.su2_general) {
+            const Su2Forms f = su2_forms(*A->d, *B->d, p, SYM_F32);
+            g.add(*f.cp, *f.ap, *f.bp, 0, 0, 0);
+        } else {
+            DescPtr c = result_desc(*A->d, *B->d, p);
+            g.add(*c, *fused_a(*A->d, p, SYM_F32, false), *fused_b(*B->d, p, SYM_F32, true), 0, 0, 0);
+        }
         *flops = g.flops;
     });
 }
@@ -1020,6 +1338,8 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
         if (!ctx || !A || !B || !dC) throw Error(SYM_E_ARG, "NULL argument");
         if (compute != SYM_F32 && compute != SYM_BF16) throw Error(SYM_E_DTYPE, "compute must be F32 or BF16");
         PairInfo p = check_pair(*A->d, *B->d, n, axesA, axesB);
+        if (p.su2_general)
+            throw Error(SYM_E_UNSUPPORTED, "the backward covers the Abelian groups and the rank-4 SU(2) operator form");
         const Desc& dc = *dC->d;
         if (dA && (dA->d->legs != A->d->legs || dA->d->dtype != SYM_F32 || dA->d->qtot != A->d->qtot || dA->d->tree != A->d->tree))
             throw Error(SYM_E_MISMATCH, "dA does not describe A (FP32)");

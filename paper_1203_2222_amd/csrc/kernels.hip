@@ -1794,52 +1794,60 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
 // tuple's metadata is read once for many elements.
 // ---------------------------------------------------------------------------
 // U output positions per thread per pass (256 apart, so lanes stay on
-// consecutive positions); all their n loads are issued before any use
+// consecutive positions); all their n loads are issued before any use.  A
+// position is decoded once (mixed radix over the output's dims) into its
+// offset inside the first input and the first output block; blocks that
+// share strides reuse it.
 template <int NB>
 __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __restrict__ ib,
                                                const FmBlk* __restrict__ ob, const double* __restrict__ cf,
                                                const float* __restrict__ src, float* __restrict__ dst, int start,
                                                int end) {
     constexpr int U = NB <= 2 ? 8 : NB <= 4 ? 4 : NB <= 8 ? 2 : 1;
-    const int n = g.n;
-    const int d1 = g.d[1], d2 = g.d[2], d3 = g.d[3];
-    auto rel = [](const FmBlk& b, int t0, int t1, int t2, int t3) {
-        return static_cast<uint32_t>(t0 * b.stride[0] + t1 * b.stride[1] + t2 * b.stride[2] + t3 * b.stride[3]);
+    constexpr int R = kMaxRecoupleRank;
+    const int n = g.n, rank = g.rank;
+    // offsets of position e in block b, for all blocks sharing b's strides or not
+    auto decode = [&](int e, int (&t)[R]) {
+        int r = e;
+#pragma unroll
+        for (int k = R - 1; k >= 1; --k) {
+            if (k < rank) {
+                const int q = div_by(r, g.mag[k], g.shf[k]);
+                t[k] = r - q * g.d[k];
+                r = q;
+            } else {
+                t[k] = 0;
+            }
+        }
+        t[0] = r;
+    };
+    auto rel = [&](const FmBlk& b, const int (&t)[R]) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < rank) o += static_cast<uint32_t>(t[k] * b.stride[k]);
+        return o;
     };
     for (int e0 = start + static_cast<int>(threadIdx.x); e0 < end; e0 += 256 * U) {
         float xs[U][NB];
-        uint32_t ro[U];
-        bool ok[U];
+        int pos[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = e0 + 256 * u;
-            ok[u] = e < end;
-            const int ee = ok[u] ? e : start;
-            const int r = div_by(ee, g.mag[3], g.shf[3]);
-            const int t3 = ee - r * d3;
-            const int q = div_by(r, g.mag[2], g.shf[2]);
-            const int t2 = r - q * d2;
-            const int t0 = div_by(q, g.mag[1], g.shf[1]);
-            const int t1 = q - t0 * d1;
-            const uint32_t ri0 = rel(ib[0], t0, t1, t2, t3);
-            ro[u] = g.same_out ? rel(ob[0], t0, t1, t2, t3) : static_cast<uint32_t>(ee);   // ee: decoded again below
+            pos[u] = e < end ? e : -1;
+            int t[R];
+            decode(e < end ? e : start, t);
+            const uint32_t ri0 = rel(ib[0], t);
 #pragma unroll
             for (int i = 0; i < NB; ++i)
-                xs[u][i] = i < n ? src[ib[i].off + (g.same_in ? ri0 : rel(ib[i], t0, t1, t2, t3))] : 0.f;
+                xs[u][i] = i < n ? src[ib[i].off + (g.same_in ? ri0 : rel(ib[i], t))] : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!ok[u]) continue;
-            int t0 = 0, t1 = 0, t2 = 0, t3 = 0;
-            if (!g.same_out) {
-                const int ee = static_cast<int>(ro[u]);
-                const int r = div_by(ee, g.mag[3], g.shf[3]);
-                t3 = ee - r * d3;
-                const int q = div_by(r, g.mag[2], g.shf[2]);
-                t2 = r - q * d2;
-                t0 = div_by(q, g.mag[1], g.shf[1]);
-                t1 = q - t0 * d1;
-            }
+            if (pos[u] < 0) continue;
+            int t[R];
+            decode(pos[u], t);
+            const uint32_t ro0 = rel(ob[0], t);
 #pragma unroll
             for (int f = 0; f < NB; ++f) {
                 if (f >= n) break;
@@ -1847,7 +1855,7 @@ __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __
 #pragma unroll
                 for (int i = 0; i < NB; ++i)
                     if (i < n) y = fma(cf[f * n + i], static_cast<double>(xs[u][i]), y);
-                dst[ob[f].off + (g.same_out ? ro[u] : rel(ob[f], t0, t1, t2, t3))] = static_cast<float>(y);
+                dst[ob[f].off + (g.same_out ? ro0 : rel(ob[f], t))] = static_cast<float>(y);
             }
         }
     }
@@ -1872,6 +1880,7 @@ __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ gr
     else if (n <= 2) recouple_elems<2>(g, ib, ob, cf, src, dst, t.start, end);
     else if (n <= 4) recouple_elems<4>(g, ib, ob, cf, src, dst, t.start, end);
     else if (n <= 8) recouple_elems<8>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 16) recouple_elems<16>(g, ib, ob, cf, src, dst, t.start, end);
     else recouple_elems<kMaxRecouple>(g, ib, ob, cf, src, dst, t.start, end);
 }
 
@@ -1989,6 +1998,8 @@ __global__ __launch_bounds__(256) void k_recouple_tiled(const FtGroup* __restric
         recouple_combine<4>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else if (n <= 8)
         recouple_combine<8>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+    else if (n <= 16)
+        recouple_combine<16>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else
         recouple_combine<kMaxRecouple>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
 }

@@ -9,7 +9,8 @@ namespace sym {
 
 constexpr int kMaxBufs = 256;       // distinct base pointers one launch may address
 constexpr int kMaxCopyDims = 6;     // dims of a coalesced block copy
-constexpr int kMaxRecouple = 16;    // intermediate spins of one label tuple
+constexpr int kMaxRecouple = 32;    // blocks of one label tuple on either side of a recoupling
+constexpr int kMaxRecoupleRank = 8;
 constexpr int kRecoupleChunk = 4096;   // elements of one label tuple per workgroup task
 
 // Base pointers of one launch, passed by value as a kernel argument.
@@ -108,9 +109,10 @@ struct GemmTile {
 // the output tree).
 struct FmGroup {
     int32_t n;
-    int32_t d[4];        // block dims in output-axis order
-    uint32_t mag[4];     // division by d[k] for k = 1..3 (multiplier and shift,
-    int32_t shf[4];      // floor(x / d) = (x * mag) >> (31 + shf) for x < 2^31)
+    int32_t rank;        // block rank (dims past it are 1)
+    int32_t d[kMaxRecoupleRank];      // block dims in output-axis order
+    uint32_t mag[kMaxRecoupleRank];   // division by d[k] for k >= 1 (multiplier and shift,
+    int32_t shf[kMaxRecoupleRank];    // floor(x / d) = (x * mag) >> (31 + shf) for x < 2^31)
     int32_t same_in;     // all input blocks share their strides
     int32_t same_out;    // all output blocks share their strides
     int32_t in_first;    // index of its first FmBlk among inputs
@@ -123,8 +125,7 @@ struct FmGroup {
 // lies below 2^31 elements from its first one.
 struct FmBlk {
     int64_t off;
-    int32_t stride[4];
-    int32_t pad[2];
+    int32_t stride[kMaxRecoupleRank];
 };
 
 struct FmTask {

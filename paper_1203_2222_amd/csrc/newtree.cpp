@@ -20,6 +20,7 @@
 // node {e,c->d} (CG symmetry); the inverse bend (cap on the incoming slot-2
 // leg of a LEFT tree) divides by the same factor, since cup_c cap_c = 1
 // (eq:wiggle).
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <deque>

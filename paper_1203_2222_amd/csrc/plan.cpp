@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <map>
 #include <numeric>
 
 #include "plan.hpp"
@@ -605,20 +606,158 @@ void choose_box(FtGroup& g, const FmBlk& in0) {
 
 }  // namespace
 
-void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm) {
-    if (in.group != SYM_SU2 || out.group != SYM_SU2 || in.rank != 4 || out.rank != 4 || perm.size() != 4)
-        throw Error(SYM_E_UNSUPPORTED, "recoupling acts on rank-4 SU(2) tensors");
-    const TreeMoves mv = tree_moves(in.tree, perm.data(), out.tree);
+FmBlk RecoupleProgram::view(const Block& b, const int32_t* axis, int rank) {
+    FmBlk fb{};
+    fb.off = b.offset;
+    int64_t span = 0;
+    for (int l = 0; l < rank; ++l) {
+        const int64_t st = b.stride[static_cast<size_t>(axis[l])];
+        span += (b.shape[static_cast<size_t>(axis[l])] - 1) * st;
+        if (st < 0 || st >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block stride beyond 32 bits");
+        fb.stride[l] = static_cast<int32_t>(st);
+    }
+    if (span >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block span beyond 32 bits");
+    return fb;
+}
+
+void RecoupleProgram::add_group(int rank, const int64_t* dims, const std::vector<FmBlk>& ins,
+                                const std::vector<FmBlk>& outs, const std::vector<double>& gamma) {
+    const int n = static_cast<int>(ins.size());
+    if (static_cast<int>(outs.size()) != n || gamma.size() != static_cast<size_t>(n) * n)
+        throw Error(SYM_E_MISMATCH, "recoupling group is not square");
+    if (n > kMaxRecouple) throw Error(SYM_E_UNSUPPORTED, "too many blocks in one label tuple (above 32)");
+    if (rank > kMaxRecoupleRank) throw Error(SYM_E_UNSUPPORTED, "rank above 8");
+    FmGroup g{};
+    g.n = n;
+    g.rank = rank;
+    int64_t elems = 1;
+    for (int k = 0; k < kMaxRecoupleRank; ++k) {
+        g.d[k] = k < rank ? static_cast<int32_t>(dims[k]) : 1;
+        magic_divisor(g.d[k], g.mag[k], g.shf[k]);
+        elems *= g.d[k];
+    }
+    if (elems >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block too large to recouple");
+    g.in_first = static_cast<int32_t>(in_blks.size());
+    g.out_first = static_cast<int32_t>(out_blks.size());
+    g.coef_first = static_cast<int32_t>(coef.size());
+    g.same_in = g.same_out = 1;
+    for (int i = 0; i < n; ++i)
+        for (int l = 0; l < rank; ++l) {
+            g.same_in &= ins[static_cast<size_t>(i)].stride[l] == ins[0].stride[l];
+            g.same_out &= outs[static_cast<size_t>(i)].stride[l] == outs[0].stride[l];
+        }
+    in_blks.insert(in_blks.end(), ins.begin(), ins.end());
+    out_blks.insert(out_blks.end(), outs.begin(), outs.end());
+    coef.insert(coef.end(), gamma.begin(), gamma.end());
+    if (rank == 4) {
+        FtGroup tg{};
+        tg.n = n;
+        for (int k = 0; k < 4; ++k) tg.dim[k] = g.d[k];
+        tg.in_first = g.in_first;
+        tg.out_first = g.out_first;
+        tg.coef_first = g.coef_first;
+        choose_box(tg, ins[0]);
+        const int32_t tgi = static_cast<int32_t>(tgroups.size());
+        for (int32_t o0 = 0; o0 < tg.dim[tg.ax[0]]; ++o0)
+            for (int32_t o1 = 0; o1 < tg.dim[tg.ax[1]]; o1 += tg.t[1])
+                for (int32_t o2 = 0; o2 < tg.dim[tg.ax[2]]; o2 += tg.t[2])
+                    for (int32_t o3 = 0; o3 < tg.dim[tg.ax[3]]; o3 += tg.t[3])
+                        ttasks.push_back({tgi, {o0, o1, o2, o3}, {0, 0, 0}});
+        tgroups.push_back(tg);
+    }
+    for (int64_t st = 0; st < elems; st += kRecoupleChunk)
+        tasks.push_back({static_cast<int32_t>(groups.size()), static_cast<int32_t>(st),
+                         static_cast<int32_t>(std::min<int64_t>(kRecoupleChunk, elems - st)), 0});
+    groups.push_back(g);
+}
+
+namespace {
+
+// the CHAIN key of a block of a CHAIN, OPERATOR or LEFT tensor (the rank-4
+// trees list their one intermediate spin, which is the CHAIN key there)
+std::vector<int32_t> key_of(const Desc& d, const Block& b) {
+    if (d.tree == SYM_TREE_CHAIN) return std::vector<int32_t>(b.inner.begin(), b.inner.begin() + b.n_inner);
+    return std::vector<int32_t>{b.internal};
+}
+
+int32_t find_keyed(const Desc& d, const int32_t* labels, const std::vector<int32_t>& key) {
+    if (d.tree == SYM_TREE_CHAIN) return d.find_block_inner(labels, key.data(), static_cast<int32_t>(key.size()));
+    if (key.size() != 1) return -1;
+    return d.find_block(labels, key[0]);
+}
+
+bool chain_like(const Desc& d) {
+    return d.tree == SYM_TREE_CHAIN || d.tree == SYM_TREE_OPERATOR || d.tree == SYM_TREE_LEFT;
+}
+
+}  // namespace
+
+void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm, int64_t in_base,
+                            int64_t out_base, uint32_t sign_legs) {
+    // (-1)^(2j) summed over the marked legs of a label tuple (doubled spins)
+    auto tuple_sign = [&](const int32_t* labels, std::vector<double>& gamma) {
+        int32_t s = 0;
+        for (int l = 0; l < in.rank; ++l)
+            if (sign_legs >> l & 1u) s += labels[l];
+        if (s & 1)
+            for (double& g : gamma) g = -g;
+    };
+    if (in.group != SYM_SU2 || out.group != SYM_SU2 || in.rank != out.rank || static_cast<int>(perm.size()) != in.rank)
+        throw Error(SYM_E_UNSUPPORTED, "recoupling acts on SU(2) tensors of equal rank");
+    const int rank = in.rank;
     // Inputs are row-major over their legs in every layout, so the input is
     // contiguous along its last leg.  When that leg stays last the
     // element-wise kernel reads and writes along the same runs (measured
     // 2.7-3.0 TB/s on config 5, slightly ahead of the tiled kernel); when it
-    // moves, the tiled kernel transposes through LDS (full reversal: 2.5
-    // against 0.73 TB/s).
-    tiled = perm[3] != 3;
+    // moves, the tiled kernel (rank 4) transposes through LDS (full reversal:
+    // 2.5 against 0.73 TB/s).
+    tiled = rank == 4 && perm[static_cast<size_t>(rank - 1)] != rank - 1;
+    int64_t dims[kMaxRecoupleRank];
+    if (in.tree == SYM_TREE_CHAIN || out.tree == SYM_TREE_CHAIN) {
+        if (!chain_like(in) || !chain_like(out))
+            throw Error(SYM_E_UNSUPPORTED, "CHAIN recoupling takes CHAIN, OPERATOR or LEFT tensors");
+        std::vector<int32_t> ain, aout;
+        for (const Leg& l : in.legs) ain.push_back(l.arrow);
+        for (const Leg& l : out.legs) aout.push_back(l.arrow);
+        std::vector<std::vector<int32_t>> ki, ko;
+        std::vector<double> gamma;
+        size_t i = 0;
+        while (i < in.blocks.size()) {
+            const Block& b0 = in.blocks[i];
+            size_t jend = i;
+            while (jend < in.blocks.size() &&
+                   std::equal(in.blocks[jend].labels.begin(), in.blocks[jend].labels.begin() + rank, b0.labels.begin()))
+                ++jend;
+            chain_gamma(rank, ain.data(), perm.data(), aout.data(), b0.labels.data(), ki, ko, gamma);
+            tuple_sign(b0.labels.data(), gamma);
+            if (ki.size() != jend - i) throw Error(SYM_E_MISMATCH, "input blocks do not match the tree");
+            for (int k = 0; k < rank; ++k) dims[k] = b0.shape[static_cast<size_t>(perm[static_cast<size_t>(k)])];
+            std::vector<FmBlk> ins, outs;
+            for (size_t k = i; k < jend; ++k) {
+                if (key_of(in, in.blocks[k]) != ki[k - i]) throw Error(SYM_E_MISMATCH, "input blocks out of key order");
+                ins.push_back(view(in.blocks[k], perm.data(), rank));
+                ins.back().off += in_base;
+            }
+            int32_t olab[SYM_MAX_RANK];
+            for (int l = 0; l < rank; ++l) olab[l] = b0.labels[static_cast<size_t>(perm[static_cast<size_t>(l)])];
+            static const int32_t ident[kMaxRecoupleRank] = {0, 1, 2, 3, 4, 5, 6, 7};
+            for (const auto& k : ko) {
+                const int32_t oi = find_keyed(out, olab, k);
+                if (oi < 0) throw Error(SYM_E_MISMATCH, "recoupled block missing from the output");
+                outs.push_back(view(out.blocks[static_cast<size_t>(oi)], ident, rank));
+                outs.back().off += out_base;
+            }
+            add_group(rank, dims, ins, outs, gamma);
+            i = jend;
+        }
+        return;
+    }
+    if (rank != 4) throw Error(SYM_E_UNSUPPORTED, "rank-4 trees only");
+    const TreeMoves mv = tree_moves(in.tree, perm.data(), out.tree);
     size_t i = 0;
     std::vector<int32_t> es, fs;
     std::vector<double> gamma;
+    static const int32_t ident4[4] = {0, 1, 2, 3};
     while (i < in.blocks.size()) {
         const Block& b0 = in.blocks[i];
         size_t j = i;
@@ -627,81 +766,174 @@ void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<i
                std::equal(in.blocks[j].labels.begin(), in.blocks[j].labels.begin() + 4, b0.labels.begin()))
             ++j;
         tree_gamma(mv, b0.labels.data(), es, fs, gamma);
+        tuple_sign(b0.labels.data(), gamma);
         const int n = static_cast<int>(es.size());
         if (static_cast<size_t>(n) != j - i) throw Error(SYM_E_MISMATCH, "input blocks do not match the tree");
-        if (n > kMaxRecouple) throw Error(SYM_E_UNSUPPORTED, "too many intermediate spins");
-        FmGroup g{};
-        g.n = n;
         // output axis k is input axis perm[k]
-        for (int k = 0; k < 4; ++k) {
-            g.d[k] = static_cast<int32_t>(b0.shape[static_cast<size_t>(perm[k])]);
-            magic_divisor(g.d[k], g.mag[k], g.shf[k]);
-        }
-        g.in_first = static_cast<int32_t>(in_blks.size());
-        g.out_first = static_cast<int32_t>(out_blks.size());
-        g.coef_first = static_cast<int32_t>(coef.size());
-        // 32-bit element offsets inside a block
-        auto narrow = [&](const Block& b, const int32_t* axis) {
-            FmBlk fb{};
-            fb.off = b.offset;
-            int64_t span = 0;
-            for (int l = 0; l < 4; ++l) {
-                const int64_t st = b.stride[static_cast<size_t>(axis[l])];
-                span += (b.shape[static_cast<size_t>(axis[l])] - 1) * st;
-                if (st < 0 || st >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block stride beyond 32 bits");
-                fb.stride[l] = static_cast<int32_t>(st);
-            }
-            if (span >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block span beyond 32 bits");
-            return fb;
-        };
-        static const int32_t ident[4] = {0, 1, 2, 3};
-        g.same_in = g.same_out = 1;
+        for (int k = 0; k < 4; ++k) dims[k] = b0.shape[static_cast<size_t>(perm[static_cast<size_t>(k)])];
+        std::vector<FmBlk> ins, outs;
         for (size_t k = i; k < j; ++k) {
             if (in.blocks[k].internal != es[k - i]) throw Error(SYM_E_MISMATCH, "input intermediate spins out of order");
-            in_blks.push_back(narrow(in.blocks[k], perm.data()));
-            for (int l = 0; l < 4; ++l) g.same_in &= in_blks.back().stride[l] == in_blks[static_cast<size_t>(g.in_first)].stride[l];
+            ins.push_back(view(in.blocks[k], perm.data(), 4));
+            ins.back().off += in_base;
         }
         int32_t olab[4];
-        for (int l = 0; l < 4; ++l) olab[l] = b0.labels[static_cast<size_t>(perm[l])];
+        for (int l = 0; l < 4; ++l) olab[l] = b0.labels[static_cast<size_t>(perm[static_cast<size_t>(l)])];
         for (int32_t f : fs) {
             const int32_t oi = out.find_block(olab, f);
             if (oi < 0) throw Error(SYM_E_MISMATCH, "recoupled block missing from the output");
-            out_blks.push_back(narrow(out.blocks[static_cast<size_t>(oi)], ident));
-            for (int l = 0; l < 4; ++l) g.same_out &= out_blks.back().stride[l] == out_blks[static_cast<size_t>(g.out_first)].stride[l];
+            outs.push_back(view(out.blocks[static_cast<size_t>(oi)], ident4, 4));
+            outs.back().off += out_base;
         }
-        coef.insert(coef.end(), gamma.begin(), gamma.end());
-        FtGroup tg{};
-        tg.n = n;
-        for (int k = 0; k < 4; ++k) tg.dim[k] = g.d[k];
-        tg.in_first = g.in_first;
-        tg.out_first = g.out_first;
-        tg.coef_first = g.coef_first;
-        choose_box(tg, in_blks[static_cast<size_t>(g.in_first)]);
-        const int32_t tgi = static_cast<int32_t>(tgroups.size());
-        for (int32_t o0 = 0; o0 < tg.dim[tg.ax[0]]; ++o0)
-            for (int32_t o1 = 0; o1 < tg.dim[tg.ax[1]]; o1 += tg.t[1])
-                for (int32_t o2 = 0; o2 < tg.dim[tg.ax[2]]; o2 += tg.t[2])
-                    for (int32_t o3 = 0; o3 < tg.dim[tg.ax[3]]; o3 += tg.t[3])
-                        ttasks.push_back({tgi, {o0, o1, o2, o3}, {0, 0, 0}});
-        tgroups.push_back(tg);
-        const int64_t elems = b0.size;
-        if (elems >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block too large to recouple");
-        for (int64_t s = 0; s < elems; s += kRecoupleChunk)
-            tasks.push_back({static_cast<int32_t>(groups.size()), static_cast<int32_t>(s),
-                             static_cast<int32_t>(std::min<int64_t>(kRecoupleChunk, elems - s)), 0});
-        groups.push_back(g);
+        add_group(4, dims, ins, outs, gamma);
         i = j;
     }
 }
 
-void RecoupleProgram::upload(const Allocator& alloc) {
-    d_groups = upload_vec(alloc, groups);
-    d_in = upload_vec(alloc, in_blks);
-    d_out = upload_vec(alloc, out_blks);
-    d_coef = upload_vec(alloc, coef);
-    d_tasks = upload_vec(alloc, tasks);
-    d_tgroups = upload_vec(alloc, tgroups);
-    d_ttasks = upload_vec(alloc, ttasks);
+FusedLeg fuse_legs(const Leg& a, const Leg& b) {
+    FusedLeg f;
+    std::map<int32_t, int64_t> deg;
+    for (size_t ia = 0; ia < a.label.size(); ++ia)
+        for (size_t ib = 0; ib < b.label.size(); ++ib) {
+            const int32_t ja = a.label[ia], jb = b.label[ib];
+            for (int32_t c = ja > jb ? ja - jb : jb - ja; c <= ja + jb; c += 2) {
+                f.offset[{ja, jb, c}] = deg[c];
+                deg[c] += a.deg[ia] * b.deg[ib];
+            }
+        }
+    for (const auto& kv : deg) {
+        f.leg.label.push_back(kv.first);
+        f.leg.deg.push_back(kv.second);
+    }
+    f.leg.arrow = a.arrow;
+    return f;
+}
+
+void RecoupleProgram::build_fuse(const Desc& unf, const Desc& fus, int leg, bool to_fused) {
+    if (unf.tree != SYM_TREE_CHAIN && unf.tree != SYM_TREE_OPERATOR && unf.tree != SYM_TREE_LEFT)
+        throw Error(SYM_E_UNSUPPORTED, "FUSE and SPLIT take CHAIN, OPERATOR or LEFT tensors");
+    const int rank = unf.rank;
+    const Leg& la = unf.legs[static_cast<size_t>(leg)];
+    const Leg& lb = unf.legs[static_cast<size_t>(leg + 1)];
+    const FusedLeg fl = fuse_legs(la, lb);
+    const int side = la.arrow;
+    int p = 0;   // position of the first fused leg in its chain
+    for (int l = 0; l < leg; ++l) p += unf.legs[static_cast<size_t>(l)].arrow == side;
+    std::vector<int32_t> arrows;
+    for (const Leg& l : unf.legs) arrows.push_back(l.arrow);
+    tiled = false;
+    // views of the unfused shape inside a fused block: the fused axis as two
+    // axes (t_a, t_b) at the offset of the pair
+    auto fused_view = [&](const Block& fb, int64_t pair_off, const int64_t* dims) {
+        FmBlk v{};
+        const int64_t sf = fb.stride[static_cast<size_t>(leg)];
+        v.off = fb.offset + pair_off * sf;
+        int64_t span = 0;
+        for (int k = 0; k < rank; ++k) {
+            int64_t st;
+            if (k < leg) st = fb.stride[static_cast<size_t>(k)];
+            else if (k == leg) st = sf * dims[leg + 1];
+            else if (k == leg + 1) st = sf;
+            else st = fb.stride[static_cast<size_t>(k - 1)];
+            if (st < 0 || st >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block stride beyond 32 bits");
+            span += (dims[k] - 1) * st;
+            v.stride[k] = static_cast<int32_t>(st);
+        }
+        if (span >= (int64_t{1} << 31)) throw Error(SYM_E_UNSUPPORTED, "block span beyond 32 bits");
+        return v;
+    };
+    static const int32_t ident[kMaxRecoupleRank] = {0, 1, 2, 3, 4, 5, 6, 7};
+    size_t i = 0;
+    while (i < unf.blocks.size()) {
+        const Block& b0 = unf.blocks[i];
+        size_t jend = i;
+        while (jend < unf.blocks.size() &&
+               std::equal(unf.blocks[jend].labels.begin(), unf.blocks[jend].labels.begin() + rank, b0.labels.begin()))
+            ++jend;
+        const std::vector<ChainBlock> cbs = chain_blocks(arrows, b0.labels.data(), rank);
+        if (cbs.size() != jend - i) throw Error(SYM_E_MISMATCH, "blocks do not match the tree");
+        const int32_t ja = b0.labels[static_cast<size_t>(leg)], jb = b0.labels[static_cast<size_t>(leg + 1)];
+        int64_t dims[kMaxRecoupleRank];
+        for (int k = 0; k < rank; ++k) dims[k] = b0.shape[static_cast<size_t>(k)];
+        // fused labels: the pair replaced by the fused spin
+        auto fused_labels = [&](int32_t c, int32_t* out) {
+            int o = 0;
+            for (int k = 0; k < rank; ++k) {
+                if (k == leg + 1) continue;
+                out[o++] = k == leg ? c : b0.labels[static_cast<size_t>(k)];
+            }
+        };
+        // groups: blocks of this label tuple that agree on everything but s[p]
+        std::map<std::pair<Seq, Seq>, std::vector<size_t>> groups;
+        for (size_t k = 0; k < cbs.size(); ++k) {
+            Seq a = cbs[k].a, b = cbs[k].b;
+            Seq& sq = side == SYM_IN ? a : b;
+            if (p >= 1) sq.erase(sq.begin() + p);   // p = 0: each block alone (its fused spin is s[1])
+            groups[{a, b}].push_back(k);
+        }
+        for (const auto& kv : groups) {
+            std::vector<FmBlk> ub, fbv;
+            std::vector<double> g;
+            const std::vector<size_t>& members = kv.second;
+            const size_t n = members.size();
+            std::vector<int32_t> fspins;
+            if (p == 0) {
+                const ChainBlock& cb = cbs[members[0]];
+                fspins.push_back((side == SYM_IN ? cb.a : cb.b)[1]);
+                g.assign(1, 1.0);
+            } else {
+                const ChainBlock& cb = cbs[members[0]];
+                const Seq& sq = side == SYM_IN ? cb.a : cb.b;
+                const int A = sq[static_cast<size_t>(p - 1)], J = sq[static_cast<size_t>(p + 1)];
+                for (int32_t f = ja > jb ? ja - jb : jb - ja; f <= ja + jb; f += 2)
+                    if (triangle(A, f, J)) fspins.push_back(f);
+                if (fspins.size() != n) throw Error(SYM_E_MISMATCH, "fusion changes the multiplicity");
+                g.assign(n * n, 0.0);
+                for (size_t r = 0; r < n; ++r)
+                    for (size_t c = 0; c < n; ++c) {
+                        const Seq& sc = side == SYM_IN ? cbs[members[c]].a : cbs[members[c]].b;
+                        const double v = fmove_coeff(A, ja, jb, J, sc[static_cast<size_t>(p)], fspins[r]);
+                        // fuse: rows are fused spins; split: rows are the unfused blocks
+                        if (to_fused) g[r * n + c] = v;
+                        else g[c * n + r] = v;
+                    }
+            }
+            for (size_t r = 0; r < n; ++r) {
+                const Block& ublk = unf.blocks[i + members[r]];
+                if (key_of(unf, ublk) != cbs[members[r]].key) throw Error(SYM_E_MISMATCH, "blocks out of key order");
+                ub.push_back(view(ublk, ident, rank));
+                // the fused block: fused labels, its chain with s[p] dropped (p >= 1) or s[0] = c (p = 0)
+                const ChainBlock& cb = cbs[members[r]];
+                Seq a = cb.a, b = cb.b;
+                Seq& sq = side == SYM_IN ? a : b;
+                const int32_t c = fspins[r];
+                // the fused chain: s[p] dropped (p >= 1), or s[0] dropped so that
+                // the fused spin s[1] = c leads (p = 0)
+                sq.erase(sq.begin() + p);
+                int32_t flab[SYM_MAX_RANK];
+                fused_labels(c, flab);
+                const std::vector<int32_t> key = chain_key(a, b);
+                const int32_t fi = fus.tree == SYM_TREE_CHAIN
+                                       ? fus.find_block_inner(flab, key.data(), static_cast<int32_t>(key.size()))
+                                       : -1;
+                if (fi < 0) throw Error(SYM_E_MISMATCH, "fused block missing");
+                fbv.push_back(fused_view(fus.blocks[static_cast<size_t>(fi)], fl.offset.at({ja, jb, c}), dims));
+            }
+            if (to_fused) add_group(rank, dims, ub, fbv, g);
+            else add_group(rank, dims, fbv, ub, g);
+        }
+        i = jend;
+    }
+}
+
+void RecoupleProgram::upload(const Allocator& alloc, Deferred* deferred) {
+    d_groups = upload_vec(alloc, groups, deferred);
+    d_in = upload_vec(alloc, in_blks, deferred);
+    d_out = upload_vec(alloc, out_blks, deferred);
+    d_coef = upload_vec(alloc, coef, deferred);
+    d_tasks = upload_vec(alloc, tasks, deferred);
+    d_tgroups = upload_vec(alloc, tgroups, deferred);
+    d_ttasks = upload_vec(alloc, ttasks, deferred);
 }
 
 hipError_t RecoupleProgram::launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const {

@@ -98,13 +98,35 @@ struct RecoupleProgram {
     std::vector<FtTask> ttasks;
     bool tiled = false;             // the permutation moves the input's contiguous (last) leg
     DevMemPtr d_groups, d_in, d_out, d_coef, d_tasks, d_tgroups, d_ttasks;
-    // Gamma(tree, perm, tree') of every label tuple; out's leg k is in's leg perm[k]
-    void build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm);
-    void upload(const Allocator& alloc);
+    // Gamma(tree, perm, tree') of every label tuple; out's leg k is in's leg
+    // perm[k]; the tensors start at element in_base / out_base of their
+    // buffers.  sign_legs: input legs whose (-1)^(2j) also multiplies the
+    // label tuple's coefficients (bit l for leg l)
+    void build(const Desc& in, const Desc& out, const std::vector<int32_t>& perm, int64_t in_base = 0,
+               int64_t out_base = 0, uint32_t sign_legs = 0);
+    // one label tuple: n input and n output block views over dims (output-axis
+    // order), gamma[f * n + e]
+    void add_group(int rank, const int64_t* dims, const std::vector<FmBlk>& ins, const std::vector<FmBlk>& outs,
+                   const std::vector<double>& gamma);
+    // a block's view with its strides along the given axes (32-bit checked)
+    static FmBlk view(const Block& b, const int32_t* axis, int rank);
+    // FUSE of legs leg, leg + 1 of the CHAIN tensor unf into fus (to_fused),
+    // or SPLIT of fus back into unf (section "Reshape of indices")
+    void build_fuse(const Desc& unf, const Desc& fus, int leg, bool to_fused);
+    void upload(const Allocator& alloc, Deferred* deferred = nullptr);
     hipError_t launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const;
 };
 
 // Layout the library uses for its own fused operands.
 LayoutOpts workspace_opts(int32_t dtype, bool trans);
+
+// The leg fused from two SU(2) legs of one arrow: every spin c of ja (x) jb,
+// degeneracy the sum of da db over the pairs reaching it; inside c the pairs
+// run lexicographically (ja, then jb), each over da x db indices row-major.
+struct FusedLeg {
+    Leg leg;
+    std::map<std::array<int32_t, 3>, int64_t> offset;   // (ja, jb, c) -> offset inside c
+};
+FusedLeg fuse_legs(const Leg& a, const Leg& b);
 
 }  // namespace sym

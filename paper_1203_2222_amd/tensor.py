@@ -116,6 +116,15 @@ class SymTensor:
                                  tuple(shape[:r]), tuple(strides[:r])))
         return out
 
+    def leg(self, i: int):
+        """(labels, degeneracies, arrow) of leg i, read from the library."""
+        n, arrow = c_int32(), c_int32()
+        L.check(L.lib().sym_tensor_leg(self.handle, i, 0, byref(n), None, None, byref(arrow)))
+        lab = (c_int32 * max(1, n.value))()
+        deg = (c_int64 * max(1, n.value))()
+        L.check(L.lib().sym_tensor_leg(self.handle, i, n.value, byref(n), lab, deg, byref(arrow)))
+        return tuple(lab[:n.value]), tuple(deg[:n.value]), "in" if arrow.value == L.SYM_IN else "out"
+
     def block_keys(self):
         """SU(2) CHAIN tree: the free intermediate spins of every block, in block order."""
         out = []
@@ -298,6 +307,48 @@ class Context:
         L.check(L.lib().sym_permute_tree(self.handle, t.handle, p, tree, n_row, res.handle, _stream(stream)))
         return res
 
+    def su2_permute(self, t: SymTensor, perm: Sequence[int], arrows, n_row: int = 0, out=None,
+                    stream=None) -> SymTensor:
+        """General SU(2) PERMUTE with REVERSE onto the CHAIN tree (any rank):
+        leg i of the result is t's leg perm[i] with arrow arrows[i]
+        (sym_su2_permute)."""
+        p = L.i32_array(perm)
+        a = L.i32_array(_ARROWS[x] for x in arrows)
+        h = c_void_p()
+        L.check(L.lib().sym_su2_permute_output(self.handle, t.handle, p, a, n_row, None, byref(h)))
+        legs = [_Leg(t.spec.legs[j].labels, t.spec.legs[j].degs, arrows[i]) for i, j in enumerate(perm)]
+        res = self._wrap_output(h, _Spec(t.spec.group, legs, L.SYM_TREE_CHAIN, 0), n_row, L.SYM_F32, out, t.data.device)
+        L.check(L.lib().sym_su2_permute(self.handle, t.handle, p, a, n_row, res.handle, _stream(stream)))
+        return res
+
+    def su2_fuse(self, t: SymTensor, leg: int, n_row: int = 0, out=None, stream=None) -> SymTensor:
+        """FUSE of legs leg, leg + 1 (one arrow) of an SU(2) tensor (sym_su2_fuse)."""
+        h = c_void_p()
+        L.check(L.lib().sym_su2_fuse_output(self.handle, t.handle, leg, n_row, None, byref(h)))
+        probe = SymTensor(self, h.value, None, None, n_row, L.SYM_F32)
+        legs = []
+        for i in range(t.rank - 1):
+            legs.append(_Leg(*probe.leg(i)))
+        probe.spec = _Spec("SU2", legs, L.SYM_TREE_CHAIN, 0)
+        if out is None:
+            out = torch.empty(probe.numel(), dtype=torch.float32, device=t.data.device)
+        probe.set_data(out)
+        L.check(L.lib().sym_su2_fuse(self.handle, t.handle, leg, n_row, probe.handle, _stream(stream)))
+        return probe
+
+    def su2_split(self, t: SymTensor, leg: int, leg_a, leg_b, n_row: int = 0, out=None, stream=None) -> SymTensor:
+        """SPLIT of leg `leg` of a CHAIN tensor into leg_a, leg_b ((labels,
+        degeneracies) pairs whose fusion it is; sym_su2_split)."""
+        arrow = t.spec.legs[leg].arrow
+        two = _Spec("SU2", [_Leg(leg_a[0], leg_a[1], arrow), _Leg(leg_b[0], leg_b[1], arrow)])
+        arr, keep = _legs_struct(two)
+        h = c_void_p()
+        L.check(L.lib().sym_su2_split_output(self.handle, t.handle, leg, arr, n_row, None, byref(h)))
+        legs = list(t.spec.legs[:leg]) + list(two.legs) + list(t.spec.legs[leg + 1:])
+        res = self._wrap_output(h, _Spec("SU2", legs, L.SYM_TREE_CHAIN, 0), n_row, L.SYM_F32, out, t.data.device)
+        L.check(L.lib().sym_su2_split(self.handle, t.handle, leg, res.handle, _stream(stream)))
+        return res
+
     def permute_tree_into(self, t: SymTensor, perm: Sequence[int], tree: int, n_row: int, out: SymTensor,
                           stream=None) -> SymTensor:
         """permute_tree into an existing handle (no host-side output creation)."""
@@ -316,6 +367,10 @@ class Context:
         tree = getattr(B.spec, "tree", 0) if A.spec.group == "SU2" else 0
         qtot = _qtot_sum(A.spec.group, getattr(A.spec, "qtot", 0), getattr(B.spec, "qtot", 0))
         n_row = 2 if A.spec.group == "SU2" else len(fa)
+        if A.spec.group == "SU2" and not (getattr(A.spec, "tree", 0) == L.SYM_TREE_OPERATOR
+                                          and tuple(axes_a) == (2, 3) and tuple(axes_b) == (0, 1)
+                                          and tree in (L.SYM_TREE_OPERATOR, L.SYM_TREE_LEFT)):
+            tree, n_row = L.SYM_TREE_CHAIN, len(legs)   # the general route: a CHAIN canonical block list
         return self._wrap_output(h, _Spec(A.spec.group, legs, tree, qtot), n_row, L.SYM_F32, data, A.data.device)
 
     def contract(self, A: SymTensor, B: SymTensor, axes_a, axes_b, compute="f32", out: SymTensor = None,

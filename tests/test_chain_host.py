@@ -117,3 +117,75 @@ def test_chain_gamma_orthogonal_and_planted_bend_fails():
     _, _, og = _oracle_gamma(ai, [0, 1, 2, 4, 3], ao, spins)
     np.testing.assert_allclose(np.array(gb), og, atol=1e-12)
     assert np.max(np.abs(-np.array(gb) - og)) > 1e-3
+
+
+def _handle(ctx, spec, n_row):
+    return ctx.describe(spec, n_row)
+
+
+def _wrap(ctx, h, n_row):
+    from paper_1203_2222_amd.tensor import SymTensor
+    from paper_1203_2222_amd import _lib as L
+    return SymTensor(ctx, h.value, None, None, n_row, L.SYM_F32)
+
+
+@pytest.mark.parametrize("arrows,leg", [(("in", "in", "in", "out"), 0), (("in", "in", "in", "out"), 1),
+                                        (("in", "out", "out", "out", "in"), 2)])
+def test_fuse_output_matches_oracle_spectrum_and_blocks(arrows, leg):
+    from ctypes import byref, c_void_p
+    ctx = _ctx()
+    from paper_1203_2222_amd import _lib as L
+    legs = [L5, ((1, 3), (2, 1)), L5, ((0, 2), (1, 2)), ((1,), (3,))][:len(arrows)]
+    spec = _spec(legs, arrows)
+    t = _handle(ctx, spec, len(arrows))
+    h = c_void_p()
+    L.check(L.lib().sym_su2_fuse_output(ctx.handle, t.handle, leg, 0, None, byref(h)))
+    f = _wrap(ctx, h, 0)
+    fl, _ = RC.fused_leg(spec.legs[leg], spec.legs[leg + 1])
+    got = [f.leg(i) for i in range(len(arrows) - 1)]
+    want = [(tuple(l.labels), tuple(l.degs), l.arrow) for l in spec.legs[:leg]] + \
+        [(tuple(fl.labels), tuple(fl.degs), fl.arrow)] + \
+        [(tuple(l.labels), tuple(l.degs), l.arrow) for l in spec.legs[leg + 2:]]
+    assert got == want
+    ospec = W.TensorSpec(W.SU2, tuple(W.Leg(*g) for g in got), tree=T.TREE_CHAIN)
+    assert f.numel() == T.num_elements(ospec)
+    # SPLIT back: the handle of the unfused tensor; a wrong spectrum is rejected
+    from paper_1203_2222_amd.tensor import _Leg, _Spec, _legs_struct
+    two = _Spec("SU2", [_Leg(*legs[leg], arrows[leg]), _Leg(*legs[leg + 1], arrows[leg])])
+    arr, keep = _legs_struct(two)
+    h2 = c_void_p()
+    L.check(L.lib().sym_su2_split_output(ctx.handle, f.handle, leg, arr, len(arrows), None, byref(h2)))
+    s = _wrap(ctx, h2, len(arrows))
+    assert s.numel() == T.num_elements(spec)
+    bad = _Spec("SU2", [_Leg(legs[leg][0], tuple(d + 1 for d in legs[leg][1]), arrows[leg]),
+                        _Leg(*legs[leg + 1], arrows[leg])])
+    arr, keep = _legs_struct(bad)
+    assert L.lib().sym_su2_split_output(ctx.handle, f.handle, leg, arr, len(arrows), None, byref(h2)) != 0
+    # legs of different arrows do not fuse
+    mixed = [i for i in range(len(arrows) - 1) if arrows[i] != arrows[i + 1]]
+    for i in mixed:
+        assert L.lib().sym_su2_fuse_output(ctx.handle, t.handle, i, 0, None, byref(h2)) != 0
+
+
+def test_general_contraction_output_is_chain():
+    from ctypes import byref, c_void_p
+    from oracle import contract as K
+    from paper_1203_2222_amd import _lib as L
+    ctx = _ctx()
+    INT = ((0, 1, 2), (2, 1, 1))
+    sa = _spec([INT, INT, INT, INT], ("in", "in", "out", "out"))
+    sa = W.TensorSpec(W.SU2, sa.legs, tree=T.TREE_OPERATOR)
+    sb = W.TensorSpec(W.SU2, _spec([INT, INT, INT, ((0, 2), (2, 1))], ("in", "in", "in", "out")).legs,
+                      tree=T.TREE_LEFT)
+    A, B = ctx.describe(sa, 4), ctx.describe(sb, 4)
+    for axa, axb in [((2, 3), (1, 2)), ((2,), (0,)), ((3, 2), (2, 1))]:
+        h = c_void_p()
+        L.check(L.lib().sym_contract_output(ctx.handle, A.handle, B.handle, len(axa), L.i32_array(axa),
+                                            L.i32_array(axb), None, byref(h)))
+        sc = K.result_spec(sa, sb, axa, axb)
+        assert sc.tree == T.TREE_CHAIN
+        c = _wrap(ctx, h, len(sc.legs))
+        c.spec = sc
+        assert c.numel() == T.num_elements(sc)
+        assert [(b.labels, k) for b, k in zip(c.blocks(), c.block_keys())] == \
+            [(b.labels, b.internal) for b in T.blocks(sc)]

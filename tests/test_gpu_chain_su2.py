@@ -1,0 +1,152 @@
+"""GPU parity of SU(2) tensors of any rank on CHAIN trees, against the
+oracle's 6j-free routes (dense tensor, transposed / fused / contracted,
+projected on the result's structural tensors): PERMUTE with REVERSE at
+ranks 5 and 6 with half-integer spins, FUSE and SPLIT of adjacent legs at
+the front and inside a chain, and contractions over axes other than the
+rank-4 pattern, a MERA-shaped one (an isometry with three incoming legs and
+one outgoing against a two-site operator) among them."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import contract as K
+from oracle import recouple as RC
+from oracle import tensors as T
+from tests.gpu_util import draw, host, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+HALF = ((1, 3), (2, 1))          # spins 1/2 (two copies) and 3/2
+INT = ((0, 1, 2), (2, 1, 1))     # spins 0, 1/2, 1
+WHOLE = ((0, 2), (2, 1))         # spins 0 and 1
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1203_2222_amd as P
+    return P.Context()
+
+
+def _spec(legs, arrows, tree=T.TREE_CHAIN):
+    return W.TensorSpec(W.SU2, tuple(W.Leg(lab, deg, a) for (lab, deg), a in zip(legs, arrows)), tree=tree)
+
+
+def _tensor(ctx, spec, seed, n_row=None):
+    g = W.generator(seed, "cuda")
+    d = draw(spec, g)
+    t = ctx.tensor(spec, len(spec.legs), data=d)
+    flat = d.double().cpu().numpy()
+    if n_row is not None and n_row != len(spec.legs):
+        t = ctx.su2_permute(t, tuple(range(len(spec.legs))), [l.arrow for l in spec.legs], n_row)
+    return t, flat
+
+
+def _canonical(ctx, t):
+    return host(ctx.su2_permute(t, tuple(range(t.rank)), [l.arrow for l in t.spec.legs], t.rank))
+
+
+PERMUTES = [
+    # rank 5: half-integer legs in pairs, arrows of every leg may change
+    ([HALF, INT, HALF, WHOLE, INT], ("in", "in", "out", "in", "out"), (3, 0, 4, 1, 2),
+     ("in", "out", "out", "in", "in"), 2, 0),
+    ([INT, HALF, HALF, INT, WHOLE], ("in", "out", "in", "out", "out"), (4, 3, 2, 1, 0),
+     ("in", "out", "in", "out", "in"), 0, 1),
+    # rank 6
+    ([HALF, WHOLE, HALF, INT, INT, WHOLE], ("in", "in", "in", "out", "out", "out"), (1, 3, 5, 0, 2, 4),
+     ("in", "in", "out", "out", "in", "out"), 3, 2),
+    ([INT, INT, HALF, HALF, WHOLE, INT], ("out", "in", "in", "out", "in", "out"), (5, 0, 1, 2, 3, 4),
+     ("in", "in", "in", "in", "out", "out"), 0, 4),
+]
+
+
+@pytest.mark.parametrize("legs,arrows,perm,arrows_out,n_row_in,n_row_out", PERMUTES)
+def test_su2_permute_rank5_6_matches_projection(ctx, legs, arrows, perm, arrows_out, n_row_in, n_row_out):
+    say(f"case su2_permute rank {len(legs)} perm {perm} arrows {arrows}->{arrows_out}")
+    spec = _spec(legs, arrows)
+    t, flat = _tensor(ctx, spec, 11, n_row_in or None)
+    out = ctx.su2_permute(t, perm, list(arrows_out), n_row_out)
+    _, ref = RC.permute_chain(spec, flat, list(perm), list(arrows_out))
+    assert rel_err(_canonical(ctx, out), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("legs,arrows,leg,n_row", [
+    ([HALF, INT, HALF, WHOLE], ("in", "in", "in", "out"), 0, 0),      # first two of the chain: relabelling
+    ([HALF, INT, HALF, WHOLE], ("in", "in", "in", "out"), 1, 0),      # inside the chain: one F-move
+    ([INT, HALF, WHOLE, INT, HALF], ("in", "out", "out", "out", "in"), 2, 0),
+    ([INT, HALF, WHOLE, INT, HALF], ("in", "out", "out", "out", "in"), 1, 1),
+    ([INT, WHOLE, HALF, INT, HALF], ("in", "in", "in", "out", "out"), 3, 2),
+])
+def test_su2_fuse_split_match_projection(ctx, legs, arrows, leg, n_row):
+    say(f"case su2 fuse/split leg {leg} arrows {arrows}")
+    spec = _spec(legs, arrows)
+    t, flat = _tensor(ctx, spec, 5)
+    ospec, ref = RC.fuse_chain(spec, flat, leg)
+    F = ctx.su2_fuse(t, leg, n_row)
+    assert [(tuple(l.labels), tuple(l.degs), l.arrow) for l in ospec.legs] == \
+        [(tuple(l.labels), tuple(l.degs), l.arrow) for l in F.spec.legs]
+    assert rel_err(_canonical(ctx, F), ref) <= 1e-6
+    S = ctx.su2_split(F, leg, legs[leg], legs[leg + 1])
+    assert rel_err(_canonical(ctx, S), flat) <= 1e-6
+    # split of the oracle's fused tensor
+    Fo = ctx.tensor(ospec, len(ospec.legs), data=torch.tensor(ref, dtype=torch.float32, device="cuda"))
+    _, sref = RC.split_chain(ospec, ref, leg, spec.legs[leg], spec.legs[leg + 1])
+    assert rel_err(_canonical(ctx, ctx.su2_split(Fo, leg, legs[leg], legs[leg + 1])), sref) <= 1e-6
+
+
+CONTRACTIONS = [
+    # MERA ascending step: a two-site operator (two incoming, two outgoing
+    # legs) on the middle two incoming legs of an isometry (three incoming,
+    # one outgoing)
+    ("mera_op_on_isometry", [INT, INT, INT, INT], ("in", "in", "out", "out"), T.TREE_OPERATOR,
+     [INT, INT, INT, WHOLE], ("in", "in", "in", "out"), T.TREE_LEFT, (2, 3), (1, 2)),
+    ("mera_isometry_on_op", [INT, INT, INT, WHOLE], ("in", "in", "in", "out"), T.TREE_CHAIN,
+     [INT, INT, WHOLE, WHOLE], ("out", "out", "in", "in"), T.TREE_CHAIN, (1, 2), (0, 1)),
+    ("rank5_two_axes", [HALF, INT, WHOLE, HALF, INT], ("in", "out", "in", "out", "in"), T.TREE_CHAIN,
+     [WHOLE, HALF, INT, INT], ("out", "in", "out", "in"), T.TREE_CHAIN, (2, 3), (0, 1)),
+    ("rank4_one_axis", [HALF, INT, INT, HALF], ("in", "in", "out", "out"), T.TREE_OPERATOR,
+     [INT, WHOLE, INT, WHOLE], ("in", "in", "out", "out"), T.TREE_OPERATOR, (2,), (0,)),
+    # incoming contracted legs of A with half-integer spins: the reversal of
+    # both sides of such a pair carries (-1)^(2j)
+    ("rank5_incoming_half", [HALF, INT, INT, HALF, WHOLE], ("in", "in", "out", "out", "in"), T.TREE_CHAIN,
+     [HALF, INT, INT, WHOLE], ("out", "out", "in", "out"), T.TREE_CHAIN, (0, 1), (0, 1)),
+    ("rank6_three_axes", [INT, WHOLE, INT, HALF, HALF, WHOLE], ("in", "in", "out", "out", "in", "out"), T.TREE_CHAIN,
+     [WHOLE, INT, HALF, INT], ("out", "in", "in", "out"), T.TREE_CHAIN, (1, 3, 0), (0, 2, 3)),
+]
+
+
+@pytest.mark.parametrize("name,la,aa,ta,lb,ab,tb,axes_a,axes_b", CONTRACTIONS, ids=[c[0] for c in CONTRACTIONS])
+def test_su2_general_contraction_matches_dense(ctx, name, la, aa, ta, lb, ab, tb, axes_a, axes_b):
+    say(f"case su2 general contraction {name}")
+    sa, sb = _spec(la, aa, ta), _spec(lb, ab, tb)
+    A, fa = _tensor(ctx, sa, 21)
+    B, fb = _tensor(ctx, sb, 22)
+    sc, ref = K.contract_su2_dense(sa, fa, sb, fb, axes_a, axes_b)
+    assert sc.tree == T.TREE_CHAIN
+    C = ctx.contract(A, B, axes_a, axes_b, "f32")
+    assert C.numel() == T.num_elements(sc)
+    assert rel_err(host(C), ref) <= 1e-5
+    # again through the cached plan, into the same output
+    C.data.zero_()
+    ctx.contract(A, B, axes_a, axes_b, "f32", out=C)
+    assert rel_err(host(C), ref) <= 1e-5
+
+
+def test_su2_general_contraction_sector_layout_inputs(ctx):
+    say("case su2 general contraction, sector-layout operands")
+    sa = _spec([INT, INT, INT, WHOLE], ("in", "in", "in", "out"))
+    sb = _spec([WHOLE, INT, INT, INT], ("in", "in", "out", "out"))
+    A, fa = _tensor(ctx, sa, 31, 2)
+    B, fb = _tensor(ctx, sb, 32, 1)
+    sc, ref = K.contract_su2_dense(sb, fb, sa, fa, (2, 3), (1, 2))
+    C = ctx.contract(B, A, (2, 3), (1, 2), "f32")
+    assert rel_err(host(C), ref) <= 1e-5
+
+
+def test_su2_general_contraction_rejects_bf16(ctx):
+    sa = _spec([INT, INT, INT, WHOLE], ("in", "in", "in", "out"))
+    sb = _spec([WHOLE, INT, INT, INT], ("in", "in", "out", "out"))
+    A, _ = _tensor(ctx, sa, 1)
+    B, _ = _tensor(ctx, sb, 2)
+    with pytest.raises(Exception):
+        ctx.contract(B, A, (2, 3), (1, 2), "bf16")
