@@ -459,7 +459,9 @@ int32_t sym_svd_truncate(const sym_tensor* T, const double* S, int64_t chi_max, 
                          double* discarded);
 
 /* SU(2) recoupling coefficient F^{jD jE}_{jA jB jC jJ} (eq:sixj), doubled
- * spins, from the library's own FP64 tables.  Host only. */
+ * spins, from the library's own tables: Racah's sum taken exactly, then
+ * rounded to FP64.  Spins up to 60 (doubled 120); above that the result is
+ * NaN and sym_last_error says why.  Host only. */
 double sym_fmove_coeff(int32_t tjA, int32_t tjB, int32_t tjC, int32_t tjJ, int32_t tjD, int32_t tjE);
 
 const char* sym_last_error(void);

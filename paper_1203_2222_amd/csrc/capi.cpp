@@ -1,6 +1,7 @@
 // C-ABI of the symtensor library: contexts, tensor handles, plan caches and
 // the host side of permute / contract / backward / batched / graph calls.
 #include <algorithm>
+#include <limits>
 #include <cstdio>
 #include <deque>
 #include <cstdlib>
@@ -1732,7 +1733,9 @@ int32_t sym_svd_truncate(const sym_tensor* T, const double* S, int64_t chi_max, 
 }
 
 double sym_fmove_coeff(int32_t tjA, int32_t tjB, int32_t tjC, int32_t tjJ, int32_t tjD, int32_t tjE) {
-    return fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE);
+    double v = std::numeric_limits<double>::quiet_NaN();
+    (void)guard([&] { v = fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE); });
+    return v;
 }
 
 }  // extern "C"

@@ -573,7 +573,10 @@ def su2_gamma(tree_in: int, perm: Sequence[int], tree_out: int, spins: Sequence[
 
 
 def fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE) -> float:
-    return L.lib().sym_fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE)
+    v = L.lib().sym_fmove_coeff(tjA, tjB, tjC, tjJ, tjD, tjE)
+    if v != v:
+        raise L.SymError(8, L.lib().sym_last_error().decode())
+    return v
 
 
 def su2_chain_gamma(arrows_in: Sequence[str], perm: Sequence[int], arrows_out: Sequence[str], spins: Sequence[int]):

@@ -146,6 +146,28 @@ def test_library_fmove_table_matches_oracle():
         assert fmove_coeff(*t) == pytest.approx(su2.fmove(*t), abs=1e-13)
 
 
+def test_library_fmove_large_spins_to_rounding():
+    # The library sums Racah's alternating series exactly (big integers over a
+    # common denominator); its coefficients equal the oracle's exact rationals
+    # to FP64 rounding up to spin 60, where a floating-point sum of the same
+    # series cancels away most of its digits.
+    from paper_1203_2222_amd import fmove_coeff
+    rng = np.random.default_rng(7)
+    done = 0
+    worst = 0.0
+    while done < 60:
+        t = [int(x) for x in rng.integers(40, 121, size=6)]
+        ref = su2.fmove(*t)
+        if ref == 0.0:
+            continue
+        worst = max(worst, abs(fmove_coeff(*t) - ref) / abs(ref))
+        done += 1
+    assert worst < 4e-15
+    from paper_1203_2222_amd import SymError
+    with pytest.raises(SymError):
+        fmove_coeff(122, 2, 122, 2, 122, 122)
+
+
 def test_error_paths():
     from paper_1203_2222_amd import SymError
     L = _lib_or_skip()
