@@ -626,6 +626,7 @@ def main():
 
     variant = P.default_variant("bf16")
     tuned = False
+    tune_s = None
     if not args.no_tune:
         # the in-house autotuner times every compiled tile variant on this
         # plan (outside the timed region) and keeps the fastest
@@ -633,7 +634,8 @@ def main():
         with torch.cuda.stream(stream):
             variant = ctx.tune_batched(As, Bs, axes[0], axes[1], "bf16", Cs, stream)
         tuned = True
-        log(f"autotuner picked BF16 variant {variant} in {time.perf_counter() - t0:.1f} s")
+        tune_s = round(time.perf_counter() - t0, 2)
+        log(f"autotuner picked BF16 variant {variant} in {tune_s:.1f} s")
     kernel = P.variant_name("bf16", variant)
 
     log("BF16 graph timing")
@@ -676,7 +678,7 @@ def main():
                       "C written as an FP32 canonical block list",
             "step": "fuse(A,B -> BF16 sector matrices) + persistent grouped GEMM whose epilogue splits C "
                     "into its blocks, one hipGraph replay",
-            "gemm_variant": {"index": variant, "name": kernel, "autotuned": tuned},
+            "gemm_variant": {"index": variant, "name": kernel, "autotuned": tuned, "tune_s": tune_s},
         },
         "roofline": {
             "bound": "mfma",

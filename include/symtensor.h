@@ -151,7 +151,14 @@ typedef void (*sym_free_fn)(void* ptr, void* user);
 /* Context: allocator bridge and plan cache.  alloc/free may be NULL (then
  * hipMalloc/hipFree).  Creating a context touches no GPU.  Plan caches are
  * guarded by a lock, so one context may be used from several threads (subject
- * to the overlap rule above). */
+ * to the overlap rule above).
+ * Plans are built on the first call with a new structure: their device
+ * tables are copied, and their fused-operand workspaces cleared, on that
+ * call's stream, and the call then waits for that stream (never for the whole
+ * device) before it caches the plan, which is from then on ready for calls
+ * on any stream.  Memory alloc returns during such a call must therefore be
+ * free for use in the order of the call's stream (a stream-ordered pool for
+ * that stream, or memory with no pending work). */
 int32_t sym_ctx_create(sym_alloc_fn alloc, sym_free_fn free_fn, void* user, sym_ctx** out);
 void sym_ctx_destroy(sym_ctx* ctx);
 /* Drop every cached plan; a plan's workspaces are freed when nothing else
@@ -379,10 +386,12 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
                               const int32_t* axesB, int32_t compute, sym_tensor* dA, sym_tensor* dB,
                               void* stream);
 
-/* count independent contractions C[i] = A[i] . B[i] with the same axes: all
- * fuses in one launch, every sector GEMM of every member in one persistent
- * grouped-GEMM launch, all splits in one launch (in chunks of 64 members; every
- * chunk is validated before the first launch). */
+/* count (any number >= 1) independent contractions C[i] = A[i] . B[i] with
+ * the same axes: all fuses in one launch, every sector GEMM of every member in
+ * one persistent grouped-GEMM launch, all splits in one launch, per chunk of
+ * 64 members (device pointers travel as kernel arguments, 3 per member); every
+ * chunk is validated before the first launch, so a bad member anywhere
+ * leaves every output untouched. */
 int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
                              const sym_tensor* const* B, int32_t n, const int32_t* axesA,
                              const int32_t* axesB, int32_t compute, sym_tensor* const* C,
@@ -392,9 +401,10 @@ int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* cons
 int32_t sym_contract_flops(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
                            const int32_t* axesA, const int32_t* axesB, int64_t* flops);
 
-/* HIP graph of a batched contraction: captured once on `stream` (the plan is
- * built first, outside the capture), replayed with sym_graph_launch.  The
- * tensors' data pointers must stay valid and unchanged while the graph lives. */
+/* HIP graph of a batched contraction of any count: captured once on `stream`
+ * (the plans, one per chunk of 64 members, are built first, outside the
+ * capture), replayed with sym_graph_launch.  The tensors' data pointers must
+ * stay valid and unchanged while the graph lives. */
 int32_t sym_graph_create_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
                                  const sym_tensor* const* B, int32_t n, const int32_t* axesA,
                                  const int32_t* axesB, int32_t compute, sym_tensor* const* C,
@@ -410,9 +420,12 @@ int32_t sym_ctx_set_timing(sym_ctx* ctx, int32_t enable);
 int32_t sym_ctx_phase_ms(sym_ctx* ctx, int32_t phase, float* ms);
 
 /* Tile configuration the grouped GEMM uses for a compute type, and the
- * autotuner's entry point: time every compiled tile variant on the plan of
- * this contraction and keep the fastest (also written to the file named by
- * SYM_TUNE_CACHE, when set). */
+ * autotuner's entry point (at most 64 contractions): the plan of this
+ * contraction is built once and run once (its fused operands written); each
+ * compiled tile variant then gets its own tile list over the same plan and
+ * one timed GEMM launch, those within 8 % of the fastest three more, and
+ * the smallest sum wins.  The winner becomes the cached plan of the structure
+ * (also written to the file named by SYM_TUNE_CACHE, when set).  Writes C. */
 int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
                          const sym_tensor* const* B, int32_t n, const int32_t* axesA,
                          const int32_t* axesB, int32_t compute, sym_tensor* const* C, void* stream,

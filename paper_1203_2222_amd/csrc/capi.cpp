@@ -215,7 +215,7 @@ struct sym_ctx {
 struct sym_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::shared_ptr<ContractPlan> plan;
+    std::vector<std::shared_ptr<ContractPlan>> plans;   // one per chunk of 64 members
 };
 
 namespace {
@@ -370,18 +370,28 @@ bool split_env_forced() {
     return v && std::string(v) == "separate";
 }
 
-// Fused-operand workspace: the GEMM kernels read whole 16-byte chunks past the
-// last column of a row and rely on that padding being zero; nothing ever
-// writes it after this clear.  Plans are built outside stream capture, so the
-// device-wide synchronisation here orders the clear after any earlier use of
-// recycled memory.
-DevMemPtr zeroed(const Allocator& alloc, size_t bytes) {
-    DevMemPtr m = alloc(bytes);
-    HIP_CHECK(hipDeviceSynchronize());
-    HIP_CHECK(hipMemset(m->ptr, 0, m->bytes));
-    HIP_CHECK(hipDeviceSynchronize());
-    return m;
-}
+// Device side of a plan build: the table uploads (recorded by the programs'
+// upload calls) and the clears of fused-operand workspaces (the GEMM kernels
+// read whole 16-byte chunks past the last column of a row and rely on that
+// padding being zero; nothing ever writes it after this clear) run in the
+// order of the caller's stream, which is the order in which the context's
+// allocator hands out memory; the build then waits for that stream alone,
+// so a cached plan is ready for calls on any stream.  Plans are built outside
+// stream capture.
+struct BuildUploads {
+    Deferred copies;
+    std::vector<DevMemPtr> clears;
+    DevMemPtr zeroed(const Allocator& alloc, size_t bytes) {
+        DevMemPtr m = alloc(bytes);
+        clears.push_back(m);
+        return m;
+    }
+    void finish(hipStream_t s) {
+        for (const DevMemPtr& m : clears) HIP_CHECK(launch_zero16(m->ptr, m->bytes, s));
+        for (const HostCopy& c : copies) HIP_CHECK(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+};
 
 std::string axes_key(int32_t n, const int32_t* a, const int32_t* b) {
     std::ostringstream k;
@@ -503,7 +513,7 @@ std::shared_ptr<ContractPlan> plan_contract_host(sym_ctx* ctx, int32_t count, co
 std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
                                                   const sym_tensor* const* B, int32_t n, const int32_t* axA,
                                                   const int32_t* axB, int32_t compute, sym_tensor* const* C,
-                                                  std::string* key_out, int variant_override) {
+                                                  std::string* key_out, int variant_override, hipStream_t stream) {
     std::vector<PairInfo> infos;
     const std::string key = contract_key(count, A, B, n, axA, axB, compute, C, &infos);
     if (key_out) *key_out = key;
@@ -517,13 +527,15 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
     const int var = variant_override >= 0 ? variant_override : pick_variant(ctx, compute, key);
     auto plan = plan_contract_host(ctx, count, A, B, infos, compute, C, var);
     Allocator alloc = ctx->allocator();
-    if (plan->in_elems) plan->ws_in = zeroed(alloc, static_cast<size_t>(plan->in_elems) * dtype_size(compute));
+    BuildUploads up;
+    if (plan->in_elems) plan->ws_in = up.zeroed(alloc, static_cast<size_t>(plan->in_elems) * dtype_size(compute));
     if (plan->out_elems) plan->ws_out = alloc(static_cast<size_t>(plan->out_elems) * sizeof(float));
-    for (auto& f : plan->fuse) f.upload(alloc);
-    plan->gemm.upload(alloc);
-    plan->split.upload(alloc);
-    for (auto& r : plan->rc_pre) r.prog.upload(alloc);
-    for (auto& r : plan->rc_post) r.prog.upload(alloc);
+    for (auto& f : plan->fuse) f.upload(alloc, &up.copies);
+    plan->gemm.upload(alloc, &up.copies);
+    plan->split.upload(alloc, &up.copies);
+    for (auto& r : plan->rc_pre) r.prog.upload(alloc, &up.copies);
+    for (auto& r : plan->rc_post) r.prog.upload(alloc, &up.copies);
+    up.finish(stream);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->contract_plans[key] = plan;
     return plan;
@@ -576,8 +588,8 @@ std::shared_ptr<ContractPlan> build_noalloc_plan(sym_ctx* ctx, const sym_tensor*
     return plan;
 }
 
-void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor* const* A, const sym_tensor* const* B,
-                       sym_tensor* const* C, hipStream_t s, bool allow_timing) {
+PtrTable contract_table(const ContractPlan& plan, const sym_tensor* const* A, const sym_tensor* const* B,
+                        sym_tensor* const* C) {
     PtrTable t{};
     t.p[kSlotWsIn] = plan.ws_in ? plan.ws_in->ptr : nullptr;
     t.p[kSlotWsOut] = plan.ws_out ? plan.ws_out->ptr : nullptr;
@@ -587,6 +599,12 @@ void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor*
         t.p[kSlotUser + plan.count + i] = B[i]->data;
         t.p[kSlotUser + 2 * plan.count + i] = C[i]->data;
     }
+    return t;
+}
+
+void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor* const* A, const sym_tensor* const* B,
+                       sym_tensor* const* C, hipStream_t s, bool allow_timing) {
+    const PtrTable t = contract_table(plan, A, B, C);
     if (plan.noalloc) {
         // the scratch array holds whatever the last call on this device left
         for (const HostCopy& c : plan.staged)
@@ -853,17 +871,19 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
             if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
             plan = std::make_shared<PermutePlan>();
             Allocator alloc = ctx->allocator();
+            BuildUploads up;
             if (s.recouple) {
                 plan->is_recouple = true;
                 plan->recouple.build(*in->d, *out->d, s.perm);
-                plan->recouple.upload(alloc);
+                plan->recouple.upload(alloc, &up.copies);
             } else {
                 plan->copy.src_dtype = in->d->dtype;
                 plan->copy.dst_dtype = out->d->dtype;
                 plan->copy.add(*in->d, *out->d, s.perm, 0, 1);
                 plan->copy.finalize();
-                plan->copy.upload(alloc);
+                plan->copy.upload(alloc, &up.copies);
             }
+            up.finish(static_cast<hipStream_t>(stream));
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->permute_plans[k.str()] = plan;
         }
@@ -947,7 +967,9 @@ int32_t sym_permute_tree(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
             plan = std::make_shared<PermutePlan>();
             plan->is_recouple = true;
             plan->recouple.build(*in->d, *out->d, p);
-            plan->recouple.upload(ctx->allocator());
+            BuildUploads up;
+            plan->recouple.upload(ctx->allocator(), &up.copies);
+            up.finish(static_cast<hipStream_t>(stream));
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->permute_plans[k.str()] = plan;
         }
@@ -1027,7 +1049,9 @@ int32_t sym_su2_permute(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm,
             plan = std::make_shared<PermutePlan>();
             plan->is_recouple = true;
             plan->recouple.build(*in->d, *out->d, p);
-            plan->recouple.upload(ctx->allocator());
+            BuildUploads up;
+            plan->recouple.upload(ctx->allocator(), &up.copies);
+            up.finish(static_cast<hipStream_t>(stream));
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->permute_plans[k.str()] = plan;
         }
@@ -1098,7 +1122,9 @@ void run_fuse(sym_ctx* ctx, const sym_tensor* in, sym_tensor* out, int32_t leg, 
         plan->is_recouple = true;
         if (to_fused) plan->recouple.build_fuse(*in->d, *out->d, leg, true);
         else plan->recouple.build_fuse(*out->d, *in->d, leg, false);
-        plan->recouple.upload(ctx->allocator());
+        BuildUploads up;
+        plan->recouple.upload(ctx->allocator(), &up.copies);
+        up.finish(stream);
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->permute_plans[key] = plan;
     }
@@ -1294,7 +1320,7 @@ int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* cons
         for (int32_t first = 0; first < count; first += 64) {
             const int32_t m = std::min<int32_t>(64, count - first);
             plans.push_back(build_contract_plan(ctx, m, A + first, B + first, n, axesA, axesB, compute, C + first,
-                                                nullptr, -1));
+                                                nullptr, -1, static_cast<hipStream_t>(stream)));
             for (int32_t i = first; i < first + m; ++i)
                 if (!has_data(A[i]) || !has_data(B[i]) || !has_data(C[i]))
                     throw Error(SYM_E_ARG, "tensor has no data pointer");
@@ -1416,11 +1442,13 @@ int32_t sym_contract_backward(sym_ctx* ctx, const sym_tensor* A, const sym_tenso
             for (auto& c : plan->copy_in) c.finalize();
             plan->split.finalize();
             Allocator alloc = ctx->allocator();
-            if (in_off) plan->ws_in = zeroed(alloc, static_cast<size_t>(in_off) * dtype_size(compute));
+            BuildUploads up;
+            if (in_off) plan->ws_in = up.zeroed(alloc, static_cast<size_t>(in_off) * dtype_size(compute));
             if (out_off) plan->ws_out = alloc(static_cast<size_t>(out_off) * sizeof(float));
-            for (auto& c : plan->copy_in) c.upload(alloc);
-            plan->gemm.upload(alloc);
-            plan->split.upload(alloc);
+            for (auto& c : plan->copy_in) c.upload(alloc, &up.copies);
+            plan->gemm.upload(alloc, &up.copies);
+            plan->split.upload(alloc, &up.copies);
+            up.finish(static_cast<hipStream_t>(stream));
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->backward_plans[k.str()] = plan;
         }
@@ -1449,15 +1477,31 @@ int32_t sym_graph_create_batched(sym_ctx* ctx, int32_t count, const sym_tensor* 
                                  sym_tensor* const* C, void* stream, sym_graph** out) {
     return guard([&] {
         if (!ctx || !out || !stream) throw Error(SYM_E_ARG, "ctx, out and a non-null stream are required");
-        if (count > 64) throw Error(SYM_E_UNSUPPORTED, "graphs take at most 64 contractions");
-        auto plan = build_contract_plan(ctx, count, A, B, n, axesA, axesB, compute, C, nullptr, -1);
+        if (count < 1 || !A || !B || !C) throw Error(SYM_E_ARG, "bad batch");
         hipStream_t s = static_cast<hipStream_t>(stream);
+        // chunks of 64 members, as in sym_contract_batched, all captured into
+        // one graph; every chunk is checked and planned before the capture
+        if (count > 64)
+            for (int32_t first = 0; first < count; first += 64)
+                (void)contract_key(std::min<int32_t>(64, count - first), A + first, B + first, n, axesA, axesB,
+                                   compute, C + first, nullptr);
         auto* g = new sym_graph();
-        g->plan = plan;
+        try {
+            for (int32_t first = 0; first < count; first += 64)
+                g->plans.push_back(build_contract_plan(ctx, std::min<int32_t>(64, count - first), A + first,
+                                                       B + first, n, axesA, axesB, compute, C + first, nullptr, -1,
+                                                       s));
+        } catch (...) {
+            delete g;
+            throw;
+        }
         try {
             HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {
-                run_contract_plan(ctx, *plan, A, B, C, s, false);
+                for (size_t c = 0; c < g->plans.size(); ++c) {
+                    const int32_t first = static_cast<int32_t>(c) * 64;
+                    run_contract_plan(ctx, *g->plans[c], A + first, B + first, C + first, s, false);
+                }
             } catch (...) {
                 hipGraph_t dummy = nullptr;
                 (void)hipStreamEndCapture(s, &dummy);
@@ -1556,18 +1600,49 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             ctx->timing = true;
         }
         std::string key;
+        // One host plan for every variant: only the GEMM's tile list depends
+        // on the variant, so each candidate is a copy of the plan (sharing its
+        // workspaces and device tables) with its own tiles.  The fused
+        // operands are written once; then only GEMM launches are timed.
+        auto base = build_contract_plan(ctx, count, A, B, n, axesA, axesB, compute, C, &key, -1, s);
+        run_contract_plan(ctx, *base, A, B, C, s, false);
+        const PtrTable t = contract_table(*base, A, B, C);
+        const int nv = gemm_num_variants(compute);
+        std::vector<std::shared_ptr<ContractPlan>> cand(static_cast<size_t>(nv));
+        Allocator alloc = ctx->allocator();
+        for (int v = 0; v < nv; ++v) {
+            auto c = std::make_shared<ContractPlan>(*base);
+            c->requested_variant = v;
+            c->grid = ctx->cus() * gemm_blocks_per_cu(compute, v);
+            c->gemm.finalize(v, c->grid);
+            BuildUploads up;
+            c->gemm.d_tiles = upload_table(alloc, c->gemm.tiles, &up.copies);
+            up.finish(s);
+            cand[static_cast<size_t>(v)] = c;
+        }
+        auto time_gemm = [&](const ContractPlan& c) {
+            HIP_CHECK(hipEventRecord(ctx->ev[1], s));
+            HIP_CHECK(c.gemm.launch(t, c.grid, s));
+            HIP_CHECK(hipEventRecord(ctx->ev[2], s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            float ms = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+            return ms;
+        };
+        // round 1: one launch each; round 2: three more for the variants
+        // within 8 % of the fastest; the smallest sum of round-2 times wins
+        std::vector<float> first(static_cast<size_t>(nv));
+        float fastest = 0.f;
+        for (int v = 0; v < nv; ++v) {
+            first[static_cast<size_t>(v)] = time_gemm(*cand[static_cast<size_t>(v)]);
+            if (v == 0 || first[static_cast<size_t>(v)] < fastest) fastest = first[static_cast<size_t>(v)];
+        }
         float best_ms = 0.f;
         int best = -1;
-        for (int v = 0; v < gemm_num_variants(compute); ++v) {
-            auto plan = build_contract_plan(ctx, count, A, B, n, axesA, axesB, compute, C, &key, v);
+        for (int v = 0; v < nv; ++v) {
+            if (first[static_cast<size_t>(v)] > 1.08f * fastest) continue;
             float total = 0.f;
-            for (int rep = 0; rep < 4; ++rep) {
-                run_contract_plan(ctx, *plan, A, B, C, s, true);
-                HIP_CHECK(hipStreamSynchronize(s));
-                float ms = 0.f;
-                HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
-                if (rep > 0) total += ms;   // first run warms caches
-            }
+            for (int rep = 0; rep < 3; ++rep) total += time_gemm(*cand[static_cast<size_t>(v)]);
             if (best < 0 || total < best_ms) {
                 best_ms = total;
                 best = v;
@@ -1580,8 +1655,9 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             ctx->tuned[tk] = best;
         }
         {
+            // the winner becomes the cached plan of the structure
             std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->contract_plans.erase(key);
+            ctx->contract_plans[key] = cand[static_cast<size_t>(best)];
         }
         if (const char* f = std::getenv("SYM_TUNE_CACHE")) {
             std::ofstream o(f, std::ios::app);
@@ -1663,12 +1739,13 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
             plan = svd_plan_of(*T->d);
             Allocator alloc = ctx->allocator();
             if (!plan->probs.empty()) {
+                BuildUploads up;
                 plan->d_probs = alloc(plan->probs.size() * sizeof(SvdProb));
-                HIP_CHECK(hipMemcpy(plan->d_probs->ptr, plan->probs.data(), plan->probs.size() * sizeof(SvdProb),
-                                    hipMemcpyHostToDevice));
+                up.copies.push_back({plan->d_probs->ptr, plan->probs.data(), plan->probs.size() * sizeof(SvdProb)});
                 plan->d_pairs = alloc(plan->pair_start.size() * sizeof(int32_t));
-                HIP_CHECK(hipMemcpy(plan->d_pairs->ptr, plan->pair_start.data(),
-                                    plan->pair_start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+                up.copies.push_back(
+                    {plan->d_pairs->ptr, plan->pair_start.data(), plan->pair_start.size() * sizeof(int32_t)});
+                up.finish(static_cast<hipStream_t>(stream));
                 plan->w = alloc(static_cast<size_t>(plan->w_elems) * sizeof(double));
                 plan->q = alloc(static_cast<size_t>(plan->q_elems) * sizeof(double));
                 plan->flag = alloc(sizeof(int32_t));

@@ -520,6 +520,10 @@ void GemmProgram::finalize(int v, int grid) {
     }
 }
 
+DevMemPtr upload_table(const Allocator& alloc, const std::vector<GemmTile>& v, Deferred* deferred) {
+    return upload_vec(alloc, v, deferred);
+}
+
 void GemmProgram::upload(const Allocator& alloc, Deferred* deferred) {
     d_probs = upload_vec(alloc, probs, deferred);
     d_tiles = upload_vec(alloc, tiles, deferred);

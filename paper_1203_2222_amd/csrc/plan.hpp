@@ -117,6 +117,10 @@ struct RecoupleProgram {
     hipError_t launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const;
 };
 
+// A device copy of a host table (allocated now; the copy recorded in
+// deferred, to be performed in stream order by the caller).
+DevMemPtr upload_table(const Allocator& alloc, const std::vector<GemmTile>& v, Deferred* deferred);
+
 // Layout the library uses for its own fused operands.
 LayoutOpts workspace_opts(int32_t dtype, bool trans);
 

@@ -7,6 +7,7 @@ memory and the current HIP stream only.
 from __future__ import annotations
 
 import ctypes
+import threading
 from ctypes import byref, c_char_p, c_float, c_int32, c_int64, c_void_p
 from dataclasses import dataclass
 from typing import List, Optional, Sequence, Tuple
@@ -164,9 +165,16 @@ def _legs_struct(spec):
     return arr, keep
 
 
+# The stream of the library call in progress on this thread: workspaces the
+# call allocates come from torch's pool for that stream, so that the library's
+# clears and uploads on that stream are ordered after the memory's earlier use.
+_CALL = threading.local()
+
+
 def _stream(stream=None) -> c_void_p:
     if stream is None:
         stream = torch.cuda.current_stream()
+    _CALL.stream = stream.cuda_stream
     return c_void_p(stream.cuda_stream)
 
 
@@ -201,7 +209,7 @@ class Context:
     @staticmethod
     def _alloc(nbytes, user):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes))
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=getattr(_CALL, "stream", None))
         except Exception:   # out of memory: the library reports SYM_E_NOMEM
             return None
 

@@ -243,6 +243,15 @@ def test_batched_checks_every_member_before_device_work():
                                       L.ptr_array(x.handle.value for x in Bs), 2, L.i32_array((2, 3)),
                                       L.i32_array((0, 1)), L.SYM_F32, L.ptr_array(x.handle.value for x in Cs), None)
     assert st == 2, L.lib().sym_last_error()
+    # 200 members (four chunks), the bad one in the third chunk
+    As = [a] * 200
+    Bs = [a] * 150 + [odd] + [a] * 49
+    Cs = [cc] * 200
+    st = L.lib().sym_contract_batched(ctx.handle, 200, L.ptr_array(x.handle.value for x in As),
+                                      L.ptr_array(x.handle.value for x in Bs), 2, L.i32_array((2, 3)),
+                                      L.i32_array((0, 1)), L.SYM_F32, L.ptr_array(x.handle.value for x in Cs), None)
+    assert st == 2, L.lib().sym_last_error()
+    assert b"spectra" in L.lib().sym_last_error()
 
 
 def test_variant_names_and_default():

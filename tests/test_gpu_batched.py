@@ -197,3 +197,30 @@ def test_batch_beyond_one_chunk_and_bad_member_leaves_outputs_untouched(ctx):
         m = members[i]
         _, ref = K.contract_pairs(m.A, host_in[i][0], m.B, host_in[i][1], m.axes_a, m.axes_b)
         assert rel_err(host(Cs[i]), ref) <= 1e-5, i
+
+
+def test_batch_of_200_eager_and_graph(ctx):
+    # four chunks (64, 64, 64, 8) eagerly and captured into one graph
+    say("case batch of 200, eager and graph")
+    base = _members()
+    members = [base[i % len(base)] for i in range(200)]
+    members = [W.Contraction(f"b{i}", m.A, m.B, m.axes_a, m.axes_b, seed=500 + i) for i, m in enumerate(members)]
+    As, Bs, Cs, host_in = _build(ctx, members)
+    ctx.contract_batched(As, Bs, (2, 3), (0, 1), "f32", outs=Cs)
+    for i in (0, 63, 64, 127, 128, 191, 192, 199):
+        m = members[i]
+        _, ref = K.contract_pairs(m.A, host_in[i][0], m.B, host_in[i][1], m.axes_a, m.axes_b)
+        assert rel_err(host(Cs[i]), ref) <= 1e-5, i
+    eager = [host(C).copy() for C in Cs]
+    stream = torch.cuda.Stream()
+    graph = ctx.graph_batched(As, Bs, (2, 3), (0, 1), "f32", Cs, stream)
+    for rep in range(2):
+        for C in Cs:
+            C.data.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        stream.synchronize()
+        for i, (C, e) in enumerate(zip(Cs, eager)):
+            assert np.array_equal(host(C), e), (rep, i)
+        ctx.contract_batched(As, Bs, (2, 3), (0, 1), "f32", outs=Cs)
+        torch.cuda.synchronize()
