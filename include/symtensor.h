@@ -333,7 +333,14 @@ int32_t sym_su2_chain_gamma(int32_t rank, const int32_t* arrows_in, const int32_
 
 /* Contraction C = A . B (see above).  compute: SYM_F32 (FP32 MFMA, FP32
  * accumulate) or SYM_BF16 (operands rounded to BF16 on the device, BF16 MFMA,
- * FP32 accumulate, FP32 output).  C must have dtype F32.  SU(2): an OPERATOR
+ * FP32 accumulate, FP32 output).  C must have dtype F32.  Small Abelian
+ * contractions (FP32 throughout, no fermionic signs, at most 2^25 useful
+ * FLOPs over the call, every block of A, B and C a strided matrix over its
+ * row and column legs) run as one kernel launch that reads the operand
+ * blocks in place and sums each output block over its block pairs
+ * (eq:tensormult) in FP32 fused multiply-adds; the environment variable
+ * SYM_SMALL=off (read when a plan is built) sends them through the fuse /
+ * grouped GEMM / split path instead.  SU(2): an OPERATOR
  * tensor A contracted on legs (2,3) with legs (0,1) of an OPERATOR or LEFT
  * tensor B gives C on B's tree (sector-major, n_row 2), by one GEMM per
  * intermediate spin (any compute type).  Any other SU(2) contraction of
@@ -403,8 +410,11 @@ int32_t sym_contract_flops(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* 
 
 /* HIP graph of a batched contraction of any count: captured once on `stream`
  * (the plans, one per chunk of 64 members, are built first, outside the
- * capture), replayed with sym_graph_launch.  The tensors' data pointers must
- * stay valid and unchanged while the graph lives. */
+ * capture), replayed with sym_graph_launch.  A contraction small enough to
+ * run as one kernel (see sym_contract) is not captured: its replay launches
+ * that kernel with the arguments fixed here, which costs less than a graph
+ * launch.  The tensors' data pointers must stay valid and unchanged while
+ * the graph lives. */
 int32_t sym_graph_create_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
                                  const sym_tensor* const* B, int32_t n, const int32_t* axesA,
                                  const int32_t* axesB, int32_t compute, sym_tensor* const* C,

@@ -75,6 +75,10 @@ struct ContractPlan {
     // general SU(2) contractions: operands recoupled into their GEMM forms
     // before the GEMM, results recoupled into C after it
     std::deque<RcStep> rc_pre, rc_post;
+    // small Abelian contractions: the whole contraction as one launch
+    // (fuse, GEMM and split programs empty)
+    bool small = false;
+    SmallProgram small_prog;
     DevMemPtr ws_in, ws_out;
     int64_t in_elems = 0, out_elems = 0;   // workspace sizes (compute dtype, FP32)
     int grid = 1;
@@ -156,6 +160,22 @@ struct sym_ctx {
     bool events_ready = false;
     hipEvent_t ev[4] = {};
     std::unordered_map<std::string, int> tuned;   // plan key hash -> variant
+    // The plans of the latest single contractions, found by the identity of
+    // their descriptors (held here, so their addresses stay unique) without
+    // building the structural key; cleared (under mu) whenever a cached
+    // contraction plan may change: a new plan, a tuning, a clear, a forced
+    // tile variant.
+    struct Recent {
+        DescPtr a, b, c;
+        int32_t n = -1, compute = -1;
+        std::array<int32_t, SYM_MAX_RANK> axa{}, axb{};
+        std::shared_ptr<ContractPlan> plan;
+    };
+    std::array<Recent, 8> recent;
+    int recent_next = 0;
+    void forget_recent() {
+        for (auto& r : recent) r = Recent();
+    }
 
     // record a plan in the active hold set, if any
     void note(const std::shared_ptr<const void>& plan) {
@@ -216,6 +236,11 @@ struct sym_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<std::shared_ptr<ContractPlan>> plans;   // one per chunk of 64 members
+    // a contraction that is one launch of the small-contraction kernel is
+    // replayed by launching that kernel with the arguments fixed at creation
+    // (a graph launch costs more than the one kernel it would hold)
+    bool direct = false;
+    PtrTable table{};
 };
 
 namespace {
@@ -423,6 +448,107 @@ std::string contract_key(int32_t count, const sym_tensor* const* A, const sym_te
     return k.str();
 }
 
+// Small Abelian contractions (at most kSmallFlops useful FLOPs over the batch)
+// run as one launch that reads the operands' blocks in place.  SYM_SMALL=off
+// sends them through the fuse / grouped GEMM / split path instead.
+constexpr int64_t kSmallFlops = int64_t{1} << 25;
+
+bool small_env_off() {
+    const char* v = std::getenv("SYM_SMALL");
+    return v && std::string(v) == "off";
+}
+
+// A group of a block's legs as one strided index (legs of extent 1 ignored):
+// each leg's stride must be the next one's times its extent.
+bool merge_legs(const Block& b, const std::vector<int32_t>& legs, int64_t& len, int64_t& stride) {
+    std::vector<int32_t> g;
+    for (int32_t l : legs)
+        if (b.shape[static_cast<size_t>(l)] > 1) g.push_back(l);
+    len = 1;
+    stride = 0;
+    for (size_t i = 0; i + 1 < g.size(); ++i)
+        if (b.stride[static_cast<size_t>(g[i])] !=
+            b.stride[static_cast<size_t>(g[i + 1])] * b.shape[static_cast<size_t>(g[i + 1])])
+            return false;
+    for (int32_t l : g) len *= b.shape[static_cast<size_t>(l)];
+    if (!g.empty()) stride = b.stride[static_cast<size_t>(g.back())];
+    return true;
+}
+
+bool fits32(int64_t x) { return x >= 0 && x < (int64_t{1} << 31); }
+
+// Tasks and block pairs of member i; false when a block is not a strided
+// matrix over its row and column legs or the work exceeds the budget.
+bool add_small(const Desc& a, const Desc& b, const Desc& c, const PairInfo& p, int i, int count, SmallProgram& sp) {
+    const int nfa = static_cast<int>(p.fa.size());
+    std::vector<int32_t> crow, ccol;
+    for (int l = 0; l < c.rank; ++l) (l < nfa ? crow : ccol).push_back(l);
+    // A's blocks by the labels of their free legs
+    std::map<std::vector<int32_t>, std::vector<int32_t>> a_by_free;
+    for (size_t k = 0; k < a.blocks.size(); ++k) {
+        std::vector<int32_t> f;
+        for (int32_t l : p.fa) f.push_back(a.blocks[k].labels[static_cast<size_t>(l)]);
+        a_by_free[f].push_back(static_cast<int32_t>(k));
+    }
+    for (const Block& cb : c.blocks) {
+        int64_t M, N, crs, ccs;
+        if (!merge_legs(cb, crow, M, crs) || !merge_legs(cb, ccol, N, ccs)) return false;
+        if (!fits32(crs) || !fits32(ccs) || !fits32(M * N)) return false;
+        const int32_t first = static_cast<int32_t>(sp.pairs.size());
+        std::vector<int32_t> f(cb.labels.begin(), cb.labels.begin() + nfa);
+        auto it = a_by_free.find(f);
+        if (it != a_by_free.end())
+            for (int32_t ai : it->second) {
+                const Block& ab = a.blocks[static_cast<size_t>(ai)];
+                int32_t bl[SYM_MAX_RANK];
+                for (size_t k = 0; k < p.axb.size(); ++k) bl[p.axb[k]] = ab.labels[static_cast<size_t>(p.axa[k])];
+                for (size_t k = 0; k < p.fb.size(); ++k) bl[p.fb[k]] = cb.labels[static_cast<size_t>(nfa) + k];
+                const int32_t bi = b.find_block(bl, -1);
+                if (bi < 0) continue;
+                const Block& bb = b.blocks[static_cast<size_t>(bi)];
+                int64_t Ma, Ka, ars, acs, Kb, Nb, brs, bcs;
+                if (!merge_legs(ab, p.fa, Ma, ars) || !merge_legs(ab, p.axa, Ka, acs) ||
+                    !merge_legs(bb, p.axb, Kb, brs) || !merge_legs(bb, p.fb, Nb, bcs))
+                    return false;
+                if (Ma != M || Nb != N || Ka != Kb) throw Error(SYM_E_MISMATCH, "block shapes disagree");
+                if (!fits32(ars) || !fits32(acs) || !fits32(brs) || !fits32(bcs) || !fits32(Ka)) return false;
+                SmallPair sp1{};
+                sp1.a_off = ab.offset;
+                sp1.b_off = bb.offset;
+                sp1.a_rs = static_cast<int32_t>(ars);
+                sp1.a_cs = static_cast<int32_t>(acs);
+                sp1.b_rs = static_cast<int32_t>(brs);
+                sp1.b_cs = static_cast<int32_t>(bcs);
+                sp1.K = static_cast<int32_t>(Ka);
+                sp1.a_buf = kSlotUser + i;
+                sp1.b_buf = kSlotUser + count + i;
+                sp.pairs.push_back(sp1);
+                sp.flops += 2 * M * N * Ka;
+                if (sp.flops > kSmallFlops) return false;
+            }
+        for (int64_t e0 = 0; e0 < M * N; e0 += kSmallTaskElems) {
+            const int64_t e1 = std::min<int64_t>(M * N, e0 + kSmallTaskElems);
+            SmallTask t{};
+            t.c_off = cb.offset;
+            t.c_rs = static_cast<int32_t>(crs);
+            t.c_cs = static_cast<int32_t>(ccs);
+            t.N = static_cast<int32_t>(N);
+            t.e0 = static_cast<int32_t>(e0);
+            t.e1 = static_cast<int32_t>(e1);
+            t.pair_first = first;
+            t.pair_count = static_cast<int32_t>(sp.pairs.size()) - first;
+            t.c_buf = kSlotUser + 2 * count + i;
+            sp.tasks.push_back(t);
+        }
+    }
+    return true;
+}
+
+bool small_eligible(const Desc& a, const Desc& b, const Desc& c, int32_t compute) {
+    return is_abelian(a.group) && a.group != SYM_Z2F && compute == SYM_F32 && a.dtype == SYM_F32 &&
+           b.dtype == SYM_F32 && c.dtype == SYM_F32 && !a.opts.trans && !b.opts.trans && !c.opts.trans;
+}
+
 // Host part of a contraction plan: block copies, sector GEMMs, tile list and
 // workspace sizes; no device memory is touched.
 std::shared_ptr<ContractPlan> plan_contract_host(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
@@ -436,6 +562,28 @@ std::shared_ptr<ContractPlan> plan_contract_host(sym_ctx* ctx, int32_t count, co
     plan->fuse[1].src_dtype = SYM_BF16;
     plan->fuse[0].dst_dtype = plan->fuse[1].dst_dtype = compute;
     plan->split.src_dtype = plan->split.dst_dtype = SYM_F32;
+    if (!small_env_off()) {
+        bool ok = true;
+        SmallProgram sp;
+        for (int i = 0; i < count && ok; ++i) {
+            const Desc& a = *A[i]->d;
+            const Desc& b = *B[i]->d;
+            const Desc& c = *C[i]->d;
+            const PairInfo& p = infos[static_cast<size_t>(i)];
+            DescPtr want_c = result_desc(a, b, p);
+            if (c.group != want_c->group || c.legs != want_c->legs || c.qtot != want_c->qtot || c.dtype != SYM_F32)
+                throw Error(SYM_E_MISMATCH, "C does not describe the contraction result");
+            ok = small_eligible(a, b, c, compute) && add_small(a, b, c, p, i, count, sp);
+        }
+        if (ok) {
+            plan->small = true;
+            plan->small_prog = std::move(sp);
+            plan->flops = plan->small_prog.flops;
+            plan->requested_variant = var;
+            plan->grid = 1;
+            return plan;
+        }
+    }
     int64_t in_off = 0, out_off = 0;
     for (int i = 0; i < count; ++i) {
         const Desc& a = *A[i]->d;
@@ -535,9 +683,11 @@ std::shared_ptr<ContractPlan> build_contract_plan(sym_ctx* ctx, int32_t count, c
     plan->split.upload(alloc, &up.copies);
     for (auto& r : plan->rc_pre) r.prog.upload(alloc, &up.copies);
     for (auto& r : plan->rc_post) r.prog.upload(alloc, &up.copies);
+    if (plan->small) plan->small_prog.upload(alloc, &up.copies);
     up.finish(stream);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->contract_plans[key] = plan;
+    ctx->forget_recent();
     return plan;
 }
 
@@ -579,6 +729,7 @@ std::shared_ptr<ContractPlan> build_noalloc_plan(sym_ctx* ctx, const sym_tensor*
     plan->split.upload(arena, &plan->staged);
     for (auto& r : plan->rc_pre) r.prog.upload(arena, &plan->staged);
     for (auto& r : plan->rc_post) r.prog.upload(arena, &plan->staged);
+    if (plan->small) plan->small_prog.upload(arena, &plan->staged);
     if (used > kNoAllocScratchBytes)
         throw Error(SYM_E_UNSUPPORTED, "contraction needs " + std::to_string(used) +
                                            " bytes of workspace and tables; the no-alloc scratch holds " +
@@ -619,6 +770,7 @@ void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor*
     for (const auto& f : plan.fuse) HIP_CHECK(f.launch(t, s));
     for (const auto& r : plan.rc_pre) HIP_CHECK(r.prog.launch(t, r.in_slot, r.out_slot, s));
     if (timing) HIP_CHECK(hipEventRecord(ctx->ev[1], s));
+    if (plan.small) HIP_CHECK(plan.small_prog.launch(t, s));
     HIP_CHECK(plan.gemm.launch(t, plan.grid, s));
     if (timing) HIP_CHECK(hipEventRecord(ctx->ev[2], s));
     HIP_CHECK(plan.split.launch(t, s));
@@ -667,6 +819,7 @@ int32_t sym_ctx_clear(sym_ctx* ctx) {
         if (!ctx) throw Error(SYM_E_ARG, "ctx is NULL");
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->contract_plans.clear();
+        ctx->forget_recent();
         ctx->noalloc_plans.clear();
         ctx->backward_plans.clear();
         ctx->permute_plans.clear();
@@ -1336,7 +1489,42 @@ int32_t sym_contract_batched(sym_ctx* ctx, int32_t count, const sym_tensor* cons
 
 int32_t sym_contract(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n, const int32_t* axesA,
                      const int32_t* axesB, int32_t compute, sym_tensor* C, void* stream) {
-    return sym_contract_batched(ctx, 1, &A, &B, n, axesA, axesB, compute, &C, stream);
+    return guard([&] {
+        if (!ctx || !A || !B || !C) throw Error(SYM_E_ARG, "NULL argument");
+        // a repeated call on the same handles' descriptors finds its plan
+        // without rebuilding the structural key
+        std::shared_ptr<ContractPlan> plan;
+        const bool axes_ok = n >= 0 && n <= SYM_MAX_RANK && (n == 0 || (axesA && axesB));
+        if (axes_ok) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            for (const auto& r : ctx->recent)
+                if (r.plan && r.a == A->d && r.b == B->d && r.c == C->d && r.n == n && r.compute == compute &&
+                    std::equal(axesA, axesA + n, r.axa.begin()) && std::equal(axesB, axesB + n, r.axb.begin())) {
+                    plan = r.plan;
+                    break;
+                }
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (!plan) {
+            plan = build_contract_plan(ctx, 1, &A, &B, n, axesA, axesB, compute, &C, nullptr, -1, s);
+            if (axes_ok) {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                sym_ctx::Recent& r = ctx->recent[static_cast<size_t>(ctx->recent_next)];
+                ctx->recent_next = (ctx->recent_next + 1) % static_cast<int>(ctx->recent.size());
+                r.a = A->d;
+                r.b = B->d;
+                r.c = C->d;
+                r.n = n;
+                r.compute = compute;
+                std::copy(axesA, axesA + n, r.axa.begin());
+                std::copy(axesB, axesB + n, r.axb.begin());
+                r.plan = plan;
+            }
+        }
+        if (!has_data(A) || !has_data(B) || !has_data(C)) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        ctx->note(plan);
+        run_contract_plan(ctx, *plan, &A, &B, &C, s, true);
+    });
 }
 
 int32_t sym_contract_noalloc(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n, const int32_t* axesA,
@@ -1495,6 +1683,17 @@ int32_t sym_graph_create_batched(sym_ctx* ctx, int32_t count, const sym_tensor* 
             delete g;
             throw;
         }
+        if (g->plans.size() == 1 && g->plans[0]->small) {
+            try {
+                g->table = contract_table(*g->plans[0], A, B, C);
+            } catch (...) {
+                delete g;
+                throw;
+            }
+            g->direct = true;
+            *out = g;
+            return;
+        }
         try {
             HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {
@@ -1523,6 +1722,10 @@ int32_t sym_graph_create_batched(sym_ctx* ctx, int32_t count, const sym_tensor* 
 int32_t sym_graph_launch(sym_graph* g, void* stream) {
     return guard([&] {
         if (!g) throw Error(SYM_E_ARG, "graph is NULL");
+        if (g->direct) {
+            HIP_CHECK(g->plans[0]->small_prog.launch(g->table, static_cast<hipStream_t>(stream)));
+            return;
+        }
         HIP_CHECK(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
     });
 }
@@ -1580,8 +1783,12 @@ int32_t sym_ctx_set_variant(sym_ctx* ctx, int32_t compute, int32_t variant) {
     return guard([&] {
         if (!ctx || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");
         if (variant >= gemm_num_variants(compute)) throw Error(SYM_E_ARG, "no such variant");
-        std::lock_guard<std::mutex> lk(ctx->tmu);
-        ctx->variant[compute] = variant < 0 ? -1 : variant;
+        {
+            std::lock_guard<std::mutex> lk(ctx->tmu);
+            ctx->variant[compute] = variant < 0 ? -1 : variant;
+        }
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->forget_recent();
     });
 }
 
@@ -1658,6 +1865,7 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             // the winner becomes the cached plan of the structure
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->contract_plans[key] = cand[static_cast<size_t>(best)];
+            ctx->forget_recent();
         }
         if (const char* f = std::getenv("SYM_TUNE_CACHE")) {
             std::ofstream o(f, std::ios::app);

@@ -2061,6 +2061,42 @@ __global__ __launch_bounds__(256) void k_zero16(u32x4* __restrict__ p, int64_t n
         p[i] = z;
 }
 
+// Small contractions: one workgroup per task, a thread per output entry
+// (two passes of 256), FP32 fused multiply-adds in a fixed order (pairs in
+// plan order, k ascending).  The pair records are uniform across the
+// workgroup, so their fields load into scalar registers; the k loop is
+// unrolled 16 times so that 16 A and 16 B loads are in flight at once.
+// Measured on a contraction of 85 blocks of 16 x 16 (2.66 MFLOP): 7.6 us per
+// call back to back, against 8.1 us unrolled 4 times, 8.0 us with the next
+// pair's record requested ahead, 12.8 us walking all (pair, k) terms as one
+// sequence from LDS, 10.8 us staging the operand blocks in LDS first; a
+// trivial torch kernel takes 6.4 us the same way.
+__global__ __launch_bounds__(256) void k_contract_small(const SmallTask* __restrict__ tasks,
+                                                        const SmallPair* __restrict__ pairs, PtrTable bufs) {
+    const SmallTask t = tasks[blockIdx.x];
+    float* C = static_cast<float*>(const_cast<void*>(bufs.p[t.c_buf])) + t.c_off;
+    for (int e = t.e0 + static_cast<int>(threadIdx.x); e < t.e1; e += 256) {
+        const int m = e / t.N, n = e - m * t.N;
+        float acc = 0.f;
+        for (int q = 0; q < t.pair_count; ++q) {
+            const SmallPair p = pairs[t.pair_first + q];
+            const float* A = static_cast<const float*>(bufs.p[p.a_buf]) + p.a_off + static_cast<int64_t>(m) * p.a_rs;
+            const float* B = static_cast<const float*>(bufs.p[p.b_buf]) + p.b_off + static_cast<int64_t>(n) * p.b_cs;
+#pragma unroll 16
+            for (int k = 0; k < p.K; ++k)
+                acc = __builtin_fmaf(A[static_cast<int64_t>(k) * p.a_cs], B[static_cast<int64_t>(k) * p.b_rs], acc);
+        }
+        C[static_cast<int64_t>(m) * t.c_rs + static_cast<int64_t>(n) * t.c_cs] = acc;
+    }
+}
+
+hipError_t launch_contract_small(const SmallTask* tasks, int32_t n_tasks, const SmallPair* pairs,
+                                 const PtrTable& bufs, hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_contract_small, dim3(static_cast<unsigned>(n_tasks)), dim3(256), 0, s, tasks, pairs, bufs);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero16(void* p, size_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;
     if ((bytes & 15u) != 0 || (reinterpret_cast<uintptr_t>(p) & 15u) != 0) return hipErrorInvalidValue;

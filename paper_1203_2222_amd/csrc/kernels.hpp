@@ -160,6 +160,29 @@ struct FtTask {
     int32_t pad[3];
 };
 
+// Small contractions in one launch (eq:tensormult block by block): a task is
+// a range of entries of one output block, C(m, n) = sum over its block pairs
+// of sum_k A(m, k) B(k, n), each operand block read as a strided matrix
+// straight from the caller's tensors (no fused workspace, no split).
+struct SmallTask {
+    int64_t c_off;
+    int32_t c_rs, c_cs;          // C(m, n) at c_off + m c_rs + n c_cs
+    int32_t N;                   // columns of the block
+    int32_t e0, e1;              // entries [e0, e1) of the block, row-major
+    int32_t pair_first, pair_count;
+    int32_t c_buf;
+    int32_t pad[2];
+};
+struct SmallPair {
+    int64_t a_off, b_off;
+    int32_t a_rs, a_cs;          // A(m, k) at a_off + m a_rs + k a_cs
+    int32_t b_rs, b_cs;          // B(k, n) at b_off + k b_rs + n b_cs
+    int32_t K;
+    int32_t a_buf, b_buf;
+    int32_t pad;
+};
+constexpr int kSmallTaskElems = 512;   // entries of one task (two per thread)
+
 // Launchers (kernels.hip).  Every launcher returns the hipError_t of the launch.
 hipError_t launch_permute(int src_dtype, int dst_dtype, const CopyOp* ops, const CopyTask* tasks,
                           const int32_t* wg_begin, int32_t n_wg, const PtrTable& bufs, hipStream_t s);
@@ -177,6 +200,8 @@ hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const Ge
 hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
                                  const double* coef, const FtTask* tasks, int32_t n_tasks, const PtrTable& bufs,
                                  int32_t in_buf, int32_t out_buf, hipStream_t s);
+hipError_t launch_contract_small(const SmallTask* tasks, int32_t n_tasks, const SmallPair* pairs,
+                                 const PtrTable& bufs, hipStream_t s);
 hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
                            const double* coef, const FmTask* tasks, int32_t n_tasks,
                            const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);

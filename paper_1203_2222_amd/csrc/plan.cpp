@@ -520,6 +520,17 @@ void GemmProgram::finalize(int v, int grid) {
     }
 }
 
+void SmallProgram::upload(const Allocator& alloc, Deferred* deferred) {
+    d_tasks = upload_vec(alloc, tasks, deferred);
+    d_pairs = upload_vec(alloc, pairs, deferred);
+}
+
+hipError_t SmallProgram::launch(const PtrTable& bufs, hipStream_t s) const {
+    if (tasks.empty()) return hipSuccess;
+    return launch_contract_small(static_cast<const SmallTask*>(d_tasks->ptr), static_cast<int32_t>(tasks.size()),
+                                 d_pairs ? static_cast<const SmallPair*>(d_pairs->ptr) : nullptr, bufs, s);
+}
+
 DevMemPtr upload_table(const Allocator& alloc, const std::vector<GemmTile>& v, Deferred* deferred) {
     return upload_vec(alloc, v, deferred);
 }

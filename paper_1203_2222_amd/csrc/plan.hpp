@@ -89,6 +89,16 @@ struct GemmProgram {
     hipError_t launch(const PtrTable& bufs, int grid, hipStream_t s) const;
 };
 
+// A small contraction as one launch of k_contract_small.
+struct SmallProgram {
+    std::vector<SmallTask> tasks;
+    std::vector<SmallPair> pairs;
+    int64_t flops = 0;
+    DevMemPtr d_tasks, d_pairs;
+    void upload(const Allocator& alloc, Deferred* deferred = nullptr);
+    hipError_t launch(const PtrTable& bufs, hipStream_t s) const;
+};
+
 struct RecoupleProgram {
     std::vector<FmGroup> groups;
     std::vector<FmBlk> in_blks, out_blks;

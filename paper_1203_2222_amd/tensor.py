@@ -205,6 +205,8 @@ class Context:
         h = c_void_p()
         L.check(L.lib().sym_ctx_create(self._alloc_cb, self._free_cb, None, byref(h)))
         self.handle = h
+        self._axes_cache = {}
+        self._contract_fn = L.lib().sym_contract
 
     @staticmethod
     def _alloc(nbytes, user):
@@ -381,12 +383,20 @@ class Context:
             tree, n_row = L.SYM_TREE_CHAIN, len(legs)   # the general route: a CHAIN canonical block list
         return self._wrap_output(h, _Spec(A.spec.group, legs, tree, qtot), n_row, L.SYM_F32, data, A.data.device)
 
+    def _axes(self, axes):
+        # ctypes arrays of axis lists, made once per list
+        t = tuple(axes)
+        a = self._axes_cache.get(t)
+        if a is None:
+            a = self._axes_cache[t] = L.i32_array(t)
+        return a
+
     def contract(self, A: SymTensor, B: SymTensor, axes_a, axes_b, compute="f32", out: SymTensor = None,
                  stream=None) -> SymTensor:
         C = out if out is not None else self.contract_output(A, B, axes_a, axes_b)
-        aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
-        L.check(L.lib().sym_contract(self.handle, A.handle, B.handle, len(axes_a), aa, ab, _dtype_code(compute),
-                                     C.handle, _stream(stream)))
+        st = _stream(stream)
+        L.check(self._contract_fn(self.handle, A.handle, B.handle, len(axes_a), self._axes(axes_a),
+                                  self._axes(axes_b), _dtype_code(compute), C.handle, st))
         return C
 
     def contract_noalloc(self, A: SymTensor, B: SymTensor, axes_a, axes_b, compute="f32", out: SymTensor = None,

@@ -209,3 +209,86 @@ def test_allocator_failure_reports_nomem_and_writes_nothing():
     assert e.value.status == 6
     torch.cuda.synchronize()
     assert bool(torch.all(C.data == 7.0))
+
+
+@pytest.mark.parametrize("axes", [((2, 3), (0, 1)), ((0, 1), (2, 3)), ((3,), (0,)), ((1, 3), (2, 1))])
+def test_small_single_launch_matches_oracle_and_gemm_path(axes):
+    # Small Abelian FP32 contractions run as one launch that reads the
+    # operand blocks in place; interleaved free and contracted legs (the last
+    # case) fall back to fuse / GEMM / split.  Both paths against the oracle
+    # and against each other.
+    import os
+    import paper_1203_2222_amd as P
+    axa, axb = axes
+    say(f"case small single launch axes {axa} {axb}")
+    c = W.config1()
+    g = W.generator(21, "cuda")
+    a, b = draw(c.A, g), draw(c.B, g)
+    fa, fb = a.double().cpu().numpy(), b.double().cpu().numpy()
+    _, ref = K.contract_pairs(c.A, fa, c.B, fb, axa, axb)
+    got = {}
+    for mode in ("on", "off"):
+        old = os.environ.get("SYM_SMALL")
+        os.environ["SYM_SMALL"] = mode
+        try:
+            cx = P.Context()
+            A = cx.tensor(c.A, 4, data=a)
+            B = cx.tensor(c.B, 4, data=b)
+            C = cx.contract_output(A, B, axa, axb)
+            C.data.fill_(float("nan"))
+            cx.contract(A, B, axa, axb, "f32", out=C)
+            first = host(C).copy()
+            cx.contract(A, B, axa, axb, "f32", out=C)   # the recent-plan lookup
+            assert np.array_equal(host(C), first)
+            got[mode] = host(to_canonical(cx, C))
+        finally:
+            if old is None:
+                del os.environ["SYM_SMALL"]
+            else:
+                os.environ["SYM_SMALL"] = old
+        assert rel_err(got[mode], ref) <= FP32_TOL, mode
+    assert rel_err(got["on"], got["off"]) <= 1e-6
+
+
+def test_small_batched_members_one_launch(ctx):
+    say("case small batched")
+    members = []
+    for i, d in enumerate(([2] * 5, [3, 1, 3], [1, 2, 3, 2, 1])):
+        h = len(d) // 2
+        li = W.u1_leg(-h, h, d, "in")
+        A = W.TensorSpec(W.U1, (li, li, li.flipped(), li.flipped()))
+        members.append(W.Contraction(f"s{i}", A, A, (2, 3), (0, 1), seed=40 + i))
+    As, Bs, Cs, hin = [], [], [], []
+    for m in members:
+        g = W.generator(m.seed, "cuda")
+        a, b = draw(m.A, g), draw(m.B, g)
+        As.append(ctx.tensor(m.A, 4, data=a))
+        Bs.append(ctx.tensor(m.B, 4, data=b))
+        Cs.append(ctx.contract_output(As[-1], Bs[-1], m.axes_a, m.axes_b))
+        hin.append((a.double().cpu().numpy(), b.double().cpu().numpy()))
+    ctx.contract_batched(As, Bs, (2, 3), (0, 1), "f32", Cs)
+    for m, C, (fa, fb) in zip(members, Cs, hin):
+        _, ref = K.contract_pairs(m.A, fa, m.B, fb, m.axes_a, m.axes_b)
+        assert rel_err(host(to_canonical(ctx, C)), ref) <= FP32_TOL, m.name
+
+
+def test_small_graph_replays_the_one_kernel(ctx):
+    # a graph of a single-kernel contraction replays that kernel directly;
+    # replays with eager work between them give the eager bits
+    say("case small graph replay")
+    c = W.config1()
+    g = W.generator(23, "cuda")
+    A = ctx.tensor(c.A, 4, data=draw(c.A, g))
+    B = ctx.tensor(c.B, 4, data=draw(c.B, g))
+    C = ctx.contract(A, B, c.axes_a, c.axes_b, "f32")
+    eager = host(C).copy()
+    stream = torch.cuda.Stream()
+    graph = ctx.graph_batched([A], [B], c.axes_a, c.axes_b, "f32", [C], stream)
+    for rep in range(3):
+        C.data.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        stream.synchronize()
+        assert np.array_equal(host(C), eager), rep
+        ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=C)
+        torch.cuda.synchronize()
