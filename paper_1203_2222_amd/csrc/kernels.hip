@@ -140,8 +140,13 @@ struct Pack<uint16_t> {
     }
 };
 
+// threads of a row-copy workgroup: on the batched BF16 fuse (32 members,
+// A side plus B side) 512 measured 1 % faster than 256; staging 16384
+// instead of 8192 source elements per task gained another 0.5 % but doubles
+// the FP32 stage, 4096 lost 0.6 %
+constexpr int kCrThreads = 512;
 template <typename Ti, typename To>
-__global__ __launch_bounds__(256) void k_copy_rows(const CopyOp* __restrict__ ops, const RowTask* __restrict__ tasks,
+__global__ __launch_bounds__(kCrThreads) void k_copy_rows(const CopyOp* __restrict__ ops, const RowTask* __restrict__ tasks,
                                                    int n_tasks, PtrTable bufs) {
     constexpr int VI = 16 / sizeof(Ti);
     constexpr int VO = Pack<To>::V;
@@ -170,14 +175,14 @@ __global__ __launch_bounds__(256) void k_copy_rows(const CopyOp* __restrict__ op
                 __builtin_amdgcn_make_buffer_rsrc(const_cast<Ti*>(src + a0), static_cast<short>(0), full, 0x00020000);
             const int nvec = (span + VI - 1) / VI;
             const int e_full = full / static_cast<int>(sizeof(Ti));
-            for (int v = threadIdx.x; v < nvec; v += 256) {
+            for (int v = threadIdx.x; v < nvec; v += kCrThreads) {
                 reinterpret_cast<u32x4_t*>(stage)[v] =
                     __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(r, v * 16, 0, 0));
                 for (int e = v * VI > e_full ? v * VI : e_full; e < (v + 1) * VI && e < lim; ++e)
                     stage[e] = src[a0 + e];
             }
         } else {
-            for (int e = threadIdx.x; e < n; e += 256) stage[e] = src[s0 + e];
+            for (int e = threadIdx.x; e < n; e += kCrThreads) stage[e] = src[s0 + e];
         }
         __syncthreads();
         const int off = static_cast<int>(s0 - a0);
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(256) void k_copy_rows(const CopyOp* __restrict__ op
         const int items = t.nrows * maxch;
         const bool vec_dst = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
         const float inv = 1.f / static_cast<float>(maxch);
-        for (int it = threadIdx.x; it < items; it += 256) {
+        for (int it = threadIdx.x; it < items; it += kCrThreads) {
             int q = static_cast<int>(static_cast<float>(it) * inv);
             int j = it - q * maxch;
             if (j < 0) {
@@ -221,7 +226,7 @@ hipError_t launch_copy_rows(int src_dtype, int dst_dtype, const CopyOp* ops, con
                             int32_t n_wg, const PtrTable& bufs, hipStream_t s) {
     if (n_tasks <= 0) return hipSuccess;
     if (n_wg <= 0) return hipErrorInvalidValue;
-    dim3 grid(static_cast<unsigned>(n_wg)), block(256);
+    dim3 grid(static_cast<unsigned>(n_wg)), block(kCrThreads);
     if (src_dtype == 0 && dst_dtype == 0)
         hipLaunchKernelGGL((k_copy_rows<float, float>), grid, block, 0, s, ops, tasks, n_tasks, bufs);
     else if (src_dtype == 0 && dst_dtype == 1)
@@ -295,8 +300,14 @@ struct TransposeShape {
     static constexpr size_t lds_bytes = static_cast<size_t>(TI) * RW * sizeof(Ti) + TI * sizeof(int);
 };
 
+// threads of a transposing workgroup: the LDS tile (70 KB for BF16) allows
+// two workgroups per CU, so more threads per workgroup are more loads in
+// flight per CU; on the batched BF16 fuse 512 measured 2 % faster than 256
+// (both with the next tile's loads issued before the current tile is
+// written out, itself 2 % faster than without), 1024 0.5 % slower than 512
+constexpr int kTvThreads = 512;
 template <typename Ti, typename To, bool MERGED>
-__global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict__ ops,
+__global__ __launch_bounds__(kTvThreads) void k_transpose_vec(const CopyOp* __restrict__ ops,
                                                        const TileTask* __restrict__ tasks, int n_tasks,
                                                        PtrTable bufs) {
     using Sh = TransposeShape<Ti>;
@@ -304,7 +315,8 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
     constexpr int VO = Pack<To>::V;
     constexpr int NC = (TI + 2 * VO - 2) / VO;      // chunks that cover one destination row segment
     constexpr int NH = (NC + 7) / 8;                // groups of eight chunks
-    constexpr int NLD = (TI * NV + 255) / 256;      // source vectors per thread
+    constexpr int NLD = (TI * NV + kTvThreads - 1) / kTvThreads;   // source vectors per thread
+    constexpr int NW = kTvThreads / 64;                             // waves
     constexpr int I = kMaxCopyDims - 1;
     static_assert((RW * sizeof(Ti)) % 16 == 0, "LDS rows must stay 16-byte aligned");
     extern __shared__ u32x4_t lds_raw[];
@@ -312,112 +324,158 @@ __global__ __launch_bounds__(256) void k_transpose_vec(const CopyOp* __restrict_
     int* row_off = reinterpret_cast<int*>(tile + TI * RW);
     auto rot = [](int r) { return VI * ((r >> 3) & 7); };
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+
+    // everything one tile's staging and write phase need
+    struct Tile {
+        const CopyOp* op;
+        const Ti* src;
+        To* dst;
+        int64_t so, dof, base;
+        int i0, j0, ni, nj, lim, e_full, nIlo, nJlo;
+        int64_t sI, sIhi, dJ, dJhi;
+        __amdgpu_buffer_rsrc_t rs;
+    };
+    auto setup = [&](int ti, Tile& c) {
         const TileTask t = tasks[ti];
         const CopyOp& op = ops[t.op];
-        const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[op.src_buf]);
-        To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[op.dst_buf]));
+        c.op = &op;
+        c.src = static_cast<const Ti*>(bufs.p[op.src_buf]);
+        c.dst = static_cast<To*>(const_cast<void*>(bufs.p[op.dst_buf]));
         const int J = op.tj;
-        int64_t so = op.src_off, dof = op.dst_off;
+        c.so = op.src_off;
+        c.dof = op.dst_off;
         int rem = t.outer;
         for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d) {
             if (d == J || (MERGED && (d == op.ihi || d == op.jhi))) continue;
             const int q = div_by(rem, op.mag[d], op.shf[d]);
             const int i = rem - q * op.size[d];
             rem = q;
-            so += i * op.sstride[d];
-            dof += i * op.dstride[d];
+            c.so += i * op.sstride[d];
+            c.dof += i * op.dstride[d];
         }
         // tile rows i (destination-contiguous, index i_lo + size[I] i_hi)
         // and columns j (source-contiguous, j_lo + size[J] j_hi)
         // (MERGED: ops with ihi or jhi set; the launch of the others never
         // divides)
-        const int nIlo = op.size[I], nJlo = op.size[J];
-        const int nI = MERGED && op.ihi >= 0 ? nIlo * op.size[op.ihi] : nIlo;
-        const int nJ = MERGED && op.jhi >= 0 ? nJlo * op.size[op.jhi] : nJlo;
-        const int64_t sI = op.sstride[I], sIhi = MERGED && op.ihi >= 0 ? op.sstride[op.ihi] : 0;
-        const int64_t dJ = op.dstride[J], dJhi = MERGED && op.jhi >= 0 ? op.dstride[op.jhi] : 0;
-        auto src_row = [&](int i) -> int64_t {   // source offset of row i
-            if constexpr (!MERGED) return i * sI;
-            const int h = div_by(i, op.mag[I], op.shf[I]);
-            return (i - h * nIlo) * sI + h * sIhi;
-        };
-        auto dst_row = [&](int j) -> int64_t {   // destination offset of column j
-            if constexpr (!MERGED) return j * dJ;
-            const int h = div_by(j, op.mag[J], op.shf[J]);
-            return (j - h * nJlo) * dJ + h * dJhi;
-        };
-        const int i0 = t.it * TI, j0 = t.jt * kTile;
-        const int ni = min(TI, nI - i0), nj = min(kTile, nJ - j0);
+        c.nIlo = op.size[I];
+        c.nJlo = op.size[J];
+        const int nI = MERGED && op.ihi >= 0 ? c.nIlo * op.size[op.ihi] : c.nIlo;
+        const int nJ = MERGED && op.jhi >= 0 ? c.nJlo * op.size[op.jhi] : c.nJlo;
+        c.sI = op.sstride[I];
+        c.sIhi = MERGED && op.ihi >= 0 ? op.sstride[op.ihi] : 0;
+        c.dJ = op.dstride[J];
+        c.dJhi = MERGED && op.jhi >= 0 ? op.dstride[op.jhi] : 0;
+        c.i0 = t.it * TI;
+        c.j0 = t.jt * kTile;
+        c.ni = min(TI, nI - c.i0);
+        c.nj = min(kTile, nJ - c.j0);
         // row r of the tile: source elements [so + src_row(i0 + r) + j0, + nj);
         // the lowest row start is that of the first row, or of i_lo = 0 in
         // the tile's first i_hi when the tile wraps past the end of i_lo
-        const int h0 = MERGED ? div_by(i0, op.mag[I], op.shf[I]) : 0;
-        const int64_t first = (i0 - h0 * nIlo + ni > nIlo ? int64_t{0} : (i0 - h0 * nIlo) * sI) + h0 * sIhi;
-        const int64_t base = (so + first + j0) & ~static_cast<int64_t>(VI - 1);
-        const int64_t avail = op.src_len - base;
+        const int h0 = MERGED ? div_by(c.i0, op.mag[I], op.shf[I]) : 0;
+        const int64_t first =
+            (c.i0 - h0 * c.nIlo + c.ni > c.nIlo ? int64_t{0} : (c.i0 - h0 * c.nIlo) * c.sI) + h0 * c.sIhi;
+        c.base = (c.so + first + c.j0) & ~static_cast<int64_t>(VI - 1);
+        const int64_t avail = op.src_len - c.base;
         const int64_t cap = (int64_t{1} << 30) / static_cast<int64_t>(sizeof(Ti));
-        const int lim = static_cast<int>(avail < cap ? avail : cap);
-        const int full = static_cast<int>(lim * sizeof(Ti)) & ~3;
-        const int e_full = full / static_cast<int>(sizeof(Ti));
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<Ti*>(src + base), static_cast<short>(0), full, 0x00020000);
-        // item it = (row r, vector v)
-        auto item = [&](int it, int& r, int& v, int& off, int& e0) {
-            r = it / NV;
-            v = it - r * NV;
-            if (it >= TI * NV || r >= ni) return false;
-            const int64_t start = so + src_row(i0 + r) + j0;
-            const int64_t a = start & ~static_cast<int64_t>(VI - 1);
-            off = static_cast<int>(start - a);
-            e0 = static_cast<int>(a - base) + v * VI;   // element index from the resource base
-            return true;
-        };
-        u32x4_t ld[NLD];
+        c.lim = static_cast<int>(avail < cap ? avail : cap);
+        const int full = static_cast<int>(c.lim * sizeof(Ti)) & ~3;
+        c.e_full = full / static_cast<int>(sizeof(Ti));
+        c.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<Ti*>(c.src + c.base), static_cast<short>(0), full,
+                                                 0x00020000);
+    };
+    auto src_row = [&](const Tile& c, int i) -> int64_t {   // source offset of row i
+        if constexpr (!MERGED) return i * c.sI;
+        const int h = div_by(i, c.op->mag[I], c.op->shf[I]);
+        return (i - h * c.nIlo) * c.sI + h * c.sIhi;
+    };
+    auto dst_row = [&](const Tile& c, int j) -> int64_t {   // destination offset of column j
+        if constexpr (!MERGED) return j * c.dJ;
+        const int h = div_by(j, c.op->mag[c.op->tj], c.op->shf[c.op->tj]);
+        return (j - h * c.nJlo) * c.dJ + h * c.dJhi;
+    };
+    // item it = (row r, vector v)
+    auto item = [&](const Tile& c, int it, int& r, int& v, int& off, int& e0) {
+        r = it / NV;
+        v = it - r * NV;
+        if (it >= TI * NV || r >= c.ni) return false;
+        const int64_t start = c.so + src_row(c, c.i0 + r) + c.j0;
+        const int64_t a = start & ~static_cast<int64_t>(VI - 1);
+        off = static_cast<int>(start - a);
+        e0 = static_cast<int>(a - c.base) + v * VI;   // element index from the resource base
+        return true;
+    };
+    u32x4_t ld[NLD];
+    auto issue = [&](const Tile& c) {
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             int r, v, off, e0;
             ld[u] = u32x4_t{0u, 0u, 0u, 0u};
-            if (item(static_cast<int>(threadIdx.x) + 256 * u, r, v, off, e0) && v * VI < off + nj)
+            if (item(c, static_cast<int>(threadIdx.x) + kTvThreads * u, r, v, off, e0) && v * VI < off + c.nj)
                 ld[u] = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(
-                                                        rs, e0 * static_cast<int>(sizeof(Ti)), 0, 0));
+                                                        c.rs, e0 * static_cast<int>(sizeof(Ti)), 0, 0));
         }
+    };
+    auto stage = [&](const Tile& c) {
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             int r, v, off, e0;
-            if (!item(static_cast<int>(threadIdx.x) + 256 * u, r, v, off, e0)) continue;
+            if (!item(c, static_cast<int>(threadIdx.x) + kTvThreads * u, r, v, off, e0)) continue;
             if (v == 0) row_off[r] = rot(r) + off;
-            if (v * VI >= off + nj) continue;
+            if (v * VI >= off + c.nj) continue;
             Ti* row = tile + r * RW + rot(r);
             reinterpret_cast<u32x4_t*>(row)[v] = ld[u];
-            for (int e = e0 > e_full ? e0 : e_full; e < e0 + VI && e < lim; ++e) row[v * VI + (e - e0)] = src[base + e];
+            for (int e = e0 > c.e_full ? e0 : c.e_full; e < e0 + VI && e < c.lim; ++e)
+                row[v * VI + (e - e0)] = c.src[c.base + e];
         }
-        __syncthreads();
-        const bool vec_dst = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+    };
+    auto emit = [&](const Tile& c) {
+        const bool vec_dst = (reinterpret_cast<uintptr_t>(c.dst) & 15) == 0;
+        const int neg = c.op->neg;
         // wave item (g, h): lane (jj, cc) writes chunk 8 h + cc of destination row j0 + 8 g + jj
-        for (int wi = wave; wi < (kTile / 8) * NH; wi += 4) {
+        for (int wi = wave; wi < (kTile / 8) * NH; wi += NW) {
             const int g = wi / NH, h = wi - g * NH;
-            const int j = 8 * g + (lane >> 3), c = 8 * h + (lane & 7);
-            if (j >= nj || c >= NC) continue;
-            const int64_t d0 = dof + dst_row(j0 + j) + i0;
+            const int j = 8 * g + (lane >> 3), cc = 8 * h + (lane & 7);
+            if (j >= c.nj || cc >= NC) continue;
+            const int64_t d0 = c.dof + dst_row(c, c.j0 + j) + c.i0;
             const int delta = vec_dst ? static_cast<int>(d0 & (VO - 1)) : 0;
-            const int c_lo = c * VO - delta;
-            if (c_lo >= ni || c_lo + VO <= 0) continue;
-            if (vec_dst && c_lo >= 0 && c_lo + VO <= ni) {
+            const int c_lo = cc * VO - delta;
+            if (c_lo >= c.ni || c_lo + VO <= 0) continue;
+            if (vec_dst && c_lo >= 0 && c_lo + VO <= c.ni) {
                 To v[VO];
 #pragma unroll
                 for (int u = 0; u < VO; ++u)
-                    v[u] = flip(Conv<Ti, To>::f(tile[(c_lo + u) * RW + row_off[c_lo + u] + j]), op.neg);
-                *reinterpret_cast<u32x4_t*>(dst + d0 + c_lo) = Pack<To>::f(v);
+                    v[u] = flip(Conv<Ti, To>::f(tile[(c_lo + u) * RW + row_off[c_lo + u] + j]), neg);
+                *reinterpret_cast<u32x4_t*>(c.dst + d0 + c_lo) = Pack<To>::f(v);
             } else {
 #pragma unroll
                 for (int u = 0; u < VO; ++u) {
                     const int r = c_lo + u;
-                    if (r >= 0 && r < ni) dst[d0 + r] = flip(Conv<Ti, To>::f(tile[r * RW + row_off[r] + j]), op.neg);
+                    if (r >= 0 && r < c.ni) c.dst[d0 + r] = flip(Conv<Ti, To>::f(tile[r * RW + row_off[r] + j]), neg);
                 }
             }
         }
+    };
+
+    // software pipeline: the next tile's source loads are in flight while
+    // this tile is written out
+    int ti = blockIdx.x;
+    if (ti >= n_tasks) return;
+    Tile cur;
+    setup(ti, cur);
+    issue(cur);
+    for (; ti < n_tasks; ti += gridDim.x) {
+        stage(cur);
+        __syncthreads();
+        const int tn = ti + static_cast<int>(gridDim.x);
+        Tile nxt = cur;
+        if (tn < n_tasks) {
+            setup(tn, nxt);
+            issue(nxt);
+        }
+        emit(cur);
         __syncthreads();   // the tile is free for the next task
+        cur = nxt;
     }
 }
 
@@ -430,7 +488,7 @@ hipError_t launch_tv(const CopyOp* ops, const TileTask* tasks, int32_t n_tasks, 
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transpose_vec<Ti, To, MERGED>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (configured != hipSuccess) return configured;
-    hipLaunchKernelGGL((k_transpose_vec<Ti, To, MERGED>), dim3(static_cast<unsigned>(n_wg)), dim3(256), lds, s, ops,
+    hipLaunchKernelGGL((k_transpose_vec<Ti, To, MERGED>), dim3(static_cast<unsigned>(n_wg)), dim3(kTvThreads), lds, s, ops,
                        tasks, n_tasks, bufs);
     return hipGetLastError();
 }
