@@ -227,8 +227,11 @@ int32_t sym_tensor_sector_info(const sym_tensor* t, int64_t i, int32_t* label, i
  *    by the swap of legs 2 and 3 with phase (-1)^(j2+j3-f) (eq:perm11); the
  *    output then has n_row_out = 0 or 4 (canonical block list).
  * sym_permute_fuse_output creates the handle of the result (data may be
- * NULL).  sym_permute_fuse writes into out, which must describe exactly that
- * result; in and out must not overlap. */
+ * NULL).  sym_permute_fuse writes into out, which must describe that result,
+ * in the packed layout or in a contraction's operand layout
+ * (sym_contract_operand_output: the same legs, rows and element type, padded
+ * and possibly transposed sector matrices, whose padding it leaves as it
+ * is); in and out must not overlap. */
 int32_t sym_permute_fuse_output(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm,
                                 int32_t n_row_out, int32_t dtype_out, void* data, sym_tensor** out);
 int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm, int32_t n_row_out,
@@ -330,6 +333,24 @@ int32_t sym_su2_gamma(int32_t tree_in, const int32_t* perm, int32_t tree_out, co
 int32_t sym_su2_chain_gamma(int32_t rank, const int32_t* arrows_in, const int32_t* perm, const int32_t* arrows_out,
                             const int32_t* spins, int32_t cap, int32_t* n, int32_t* key_len_in, int32_t* key_len_out,
                             int32_t* keys_in, int32_t* keys_out, double* gamma);
+
+/* Handle of a contraction's operand in the layout the grouped GEMM reads
+ * (which = 0: A's legs in the order free legs, then axesA, its free legs the
+ * rows; which = 1: B's legs in the order axesB, then free legs, its sector
+ * matrices stored transposed), in the compute type, rows padded to 128-byte
+ * lines and sector bases to 64 elements: the fused operand of eq:multi2.
+ * A tensor in this layout, contracted over its last (A) or first (B) legs in
+ * order, is read in place by sym_contract and its relatives (no fuse, no
+ * workspace), so an operand reused across many contractions is fused once.
+ * Its padding entries must be zero (allocate the buffer zeroed); fill it with
+ * sym_permute_fuse, which writes only its blocks; its data must be 256-byte
+ * aligned.  A contraction's C may also be such a handle when the next
+ * contraction takes it as operand A in compute F32: the GEMM then writes it
+ * directly.  Abelian groups and the rank-4 SU(2) operator form; data may be
+ * NULL. */
+int32_t sym_contract_operand_output(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
+                                    const int32_t* axesA, const int32_t* axesB, int32_t compute, int32_t which,
+                                    void* data, sym_tensor** out);
 
 /* Contraction C = A . B (see above).  compute: SYM_F32 (FP32 MFMA, FP32
  * accumulate) or SYM_BF16 (operands rounded to BF16 on the device, BF16 MFMA,

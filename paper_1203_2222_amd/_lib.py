@@ -60,6 +60,7 @@ SIGNATURES = {
     "sym_su2_permute": (c_int32, [P, P, I32P, I32P, c_int32, P, P]),
     "sym_tensor_leg": (c_int32, [P, c_int32, c_int32, I32P, I32P, I64P, I32P]),
     "sym_su2_fuse_output": (c_int32, [P, P, c_int32, c_int32, P, PP]),
+    "sym_contract_operand_output": (c_int32, [P, P, P, c_int32, I32P, I32P, c_int32, c_int32, P, PP]),
     "sym_su2_fuse": (c_int32, [P, P, c_int32, c_int32, P, P]),
     "sym_su2_split_output": (c_int32, [P, P, c_int32, POINTER(SymLeg), c_int32, P, PP]),
     "sym_su2_split": (c_int32, [P, P, c_int32, P, P]),

@@ -31,11 +31,27 @@ class Chain:
         self.ctx, self.xs, self.compute = ctx, list(xs), compute
         self.axes = [(tuple(a), tuple(b)) for a, b in axes]
         dev = xs[0].data.device
-        # intermediates T_1..T_n as canonical block lists (written by the GEMM epilogue)
+        # intermediates T_1..T_{n-1}: when the next link contracts the last
+        # legs of T_k in order (its fuse would not move a leg) and the chain
+        # runs in FP32, T_k lives in that link's operand layout, so link k's
+        # GEMM writes it and link k + 1's GEMM reads it in place (no split,
+        # no fuse); otherwise, and for T_n, a canonical block list written
+        # by the GEMM epilogue
         self.ts: List[SymTensor] = [xs[0]]
         for k in range(1, len(xs)):
-            spec = ctx.contract_output(self.ts[-1], xs[k], *self.axes[k - 1]).spec
-            self.ts.append(ctx.tensor(spec, len(spec.legs), "f32", device=dev))
+            spec, _ = ctx.result_spec(self.ts[-1], xs[k], *self.axes[k - 1])
+            probe = ctx.describe(spec, len(spec.legs))
+            t = None
+            if k + 1 < len(xs) and compute == "f32":
+                ax = self.axes[k]
+                rank = len(spec.legs)
+                free = [i for i in range(rank) if i not in ax[0]]
+                if free + list(ax[0]) == list(range(rank)):
+                    t = ctx.contract_operand(probe, xs[k + 1], ax[0], ax[1], "f32", "A", fill=False)
+            if t is None:
+                t = ctx.tensor(spec, len(spec.legs), "f32", device=dev)
+            self.ts.append(t)
+            del probe
         # cotangents G_0..G_n and gradients dX_1..dX_n (dX_0 is G_0)
         self.gs = [ctx.tensor(t.spec, t.n_row, "f32", device=dev) for t in self.ts]
         self.dxs = [None] + [ctx.tensor(x.spec, x.n_row, "f32", device=dev) for x in xs[1:]]

@@ -79,6 +79,9 @@ struct ContractPlan {
     // (fuse, GEMM and split programs empty)
     bool small = false;
     SmallProgram small_prog;
+    // user slots whose tensors are operands already in their GEMM layout
+    // (read in place; their data must be 256-byte aligned like a workspace)
+    std::vector<int> direct_slots;
     DevMemPtr ws_in, ws_out;
     int64_t in_elems = 0, out_elems = 0;   // workspace sizes (compute dtype, FP32)
     int grid = 1;
@@ -380,6 +383,12 @@ std::vector<int32_t> inverse(const std::vector<int32_t>& p) {
     return q;
 }
 
+// Equal tensors up to the padding and orientation of their sector matrices.
+bool same_structure(const Desc& a, const Desc& b) {
+    return a.group == b.group && a.rank == b.rank && a.n_row == b.n_row && a.tree == b.tree && a.qtot == b.qtot &&
+           a.dtype == b.dtype && a.legs == b.legs;
+}
+
 // The layout C must have for the GEMM to write it directly.
 bool gemm_can_write(const Desc& want, const Desc& c) {
     return c.dtype == SYM_F32 && !c.opts.trans && c.n_row == want.n_row && c.legs == want.legs &&
@@ -628,22 +637,37 @@ std::shared_ptr<ContractPlan> plan_contract_host(sym_ctx* ctx, int32_t count, co
         }
         DescPtr af = fused_a(a, p, compute, false);
         DescPtr bf = fused_b(b, p, compute, true);   // stored N x K: K contiguous
-        const int64_t a_base = in_off;
-        in_off = align_up(in_off + af->numel, 64);
-        const int64_t b_base = in_off;
-        in_off = align_up(in_off + bf->numel, 64);
-        plan->fuse[a.dtype == SYM_BF16 ? 1 : 0].add(a, *af, p.perm_a, kSlotUser + i, kSlotWsIn, 0, a_base);
-        plan->fuse[b.dtype == SYM_BF16 ? 1 : 0].add(b, *bf, p.perm_b, kSlotUser + count + i, kSlotWsIn, 0, b_base);
+        // an operand already in its GEMM layout (sym_contract_operand_output)
+        // is read in place: no fuse, no workspace
+        int64_t a_base = 0, b_base = 0;
+        int a_slot = kSlotWsIn, b_slot = kSlotWsIn;
+        if (a.key == af->key) {
+            a_slot = kSlotUser + i;
+            plan->direct_slots.push_back(a_slot);
+        } else {
+            a_base = in_off;
+            in_off = align_up(in_off + af->numel, 64);
+            plan->fuse[a.dtype == SYM_BF16 ? 1 : 0].add(a, *af, p.perm_a, kSlotUser + i, kSlotWsIn, 0, a_base);
+        }
+        if (b.key == bf->key) {
+            b_slot = kSlotUser + count + i;
+            plan->direct_slots.push_back(b_slot);
+        } else {
+            b_base = in_off;
+            in_off = align_up(in_off + bf->numel, 64);
+            plan->fuse[b.dtype == SYM_BF16 ? 1 : 0].add(b, *bf, p.perm_b, kSlotUser + count + i, kSlotWsIn, 0,
+                                                        b_base);
+        }
         if (gemm_can_write(*want_c, c)) {
-            plan->gemm.add(c, *af, *bf, kSlotUser + 2 * count + i, kSlotWsIn, kSlotWsIn, 0, a_base, b_base);
+            plan->gemm.add(c, *af, *bf, kSlotUser + 2 * count + i, a_slot, b_slot, 0, a_base, b_base);
         } else if (!split_env_forced() &&
-                   plan->gemm.add_indirect(*want_c, c, *af, *bf, kSlotUser + 2 * count + i, kSlotWsIn, kSlotWsIn,
-                                           a_base, b_base)) {
+                   plan->gemm.add_indirect(*want_c, c, *af, *bf, kSlotUser + 2 * count + i, a_slot, b_slot, a_base,
+                                           b_base)) {
             // C is a canonical block list: the GEMM epilogue performs the split
         } else {
             const int64_t c_base = out_off;
             out_off = align_up(out_off + want_c->numel, 64);
-            plan->gemm.add(*want_c, *af, *bf, kSlotWsOut, kSlotWsIn, kSlotWsIn, c_base, a_base, b_base);
+            plan->gemm.add(*want_c, *af, *bf, kSlotWsOut, a_slot, b_slot, c_base, a_base, b_base);
             plan->split.add(*want_c, c, identity(c.rank), kSlotWsOut, kSlotUser + 2 * count + i, c_base, 0);
         }
     }
@@ -756,6 +780,9 @@ PtrTable contract_table(const ContractPlan& plan, const sym_tensor* const* A, co
 void run_contract_plan(sym_ctx* ctx, const ContractPlan& plan, const sym_tensor* const* A, const sym_tensor* const* B,
                        sym_tensor* const* C, hipStream_t s, bool allow_timing) {
     const PtrTable t = contract_table(plan, A, B, C);
+    for (int slot : plan.direct_slots)
+        if ((reinterpret_cast<uintptr_t>(t.p[slot]) & 255u) != 0)
+            throw Error(SYM_E_ARG, "an operand in GEMM layout needs 256-byte aligned data");
     if (plan.noalloc) {
         // the scratch array holds whatever the last call on this device left
         for (const HostCopy& c : plan.staged)
@@ -1021,7 +1048,12 @@ int32_t sym_permute_fuse(sym_ctx* ctx, const sym_tensor* in, const int32_t* perm
         if (!plan) {
             // validated once per structure; a cached plan implies the same check passed
             DescPtr want = permute_result(*in->d, s, n_row_out, out->d->dtype);
-            if (want->key != out->d->key) throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
+            // out may carry a padded or transposed layout (an operand made by
+            // sym_contract_operand_output): the copy writes its blocks wherever
+            // the layout puts them
+            if (!same_structure(*want, *out->d))
+                throw Error(SYM_E_MISMATCH, "out does not describe the permuted tensor");
+            if (out->d->opts.trans && s.recouple) throw Error(SYM_E_UNSUPPORTED, "no recoupling into a transposed layout");
             plan = std::make_shared<PermutePlan>();
             Allocator alloc = ctx->allocator();
             BuildUploads up;
@@ -1435,6 +1467,24 @@ int32_t sym_contract_output(sym_ctx* ctx, const sym_tensor* A, const sym_tensor*
         }
         t->data = data;
         *C = t;
+    });
+}
+
+int32_t sym_contract_operand_output(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,
+                                    const int32_t* axesA, const int32_t* axesB, int32_t compute, int32_t which,
+                                    void* data, sym_tensor** out) {
+    (void)ctx;
+    return guard([&] {
+        if (!A || !B || !out) throw Error(SYM_E_ARG, "NULL argument");
+        if (compute != SYM_F32 && compute != SYM_BF16) throw Error(SYM_E_DTYPE, "compute must be F32 or BF16");
+        if (which != 0 && which != 1) throw Error(SYM_E_ARG, "which must be 0 (A) or 1 (B)");
+        PairInfo p = check_pair(*A->d, *B->d, n, axesA, axesB);
+        if (p.su2_general) throw Error(SYM_E_UNSUPPORTED, "general SU(2) contractions have no operand layout");
+        DescPtr d = which == 0 ? fused_a(*A->d, p, compute, false) : fused_b(*B->d, p, compute, true);
+        auto* t = new sym_tensor();
+        t->d = std::move(d);
+        t->data = data;
+        *out = t;
     });
 }
 

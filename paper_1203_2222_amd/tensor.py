@@ -371,6 +371,13 @@ class Context:
         aa, ab = L.i32_array(axes_a), L.i32_array(axes_b)
         h = c_void_p()
         L.check(L.lib().sym_contract_output(self.handle, A.handle, B.handle, len(axes_a), aa, ab, None, byref(h)))
+        spec, n_row = self.result_spec(A, B, axes_a, axes_b)
+        return self._wrap_output(h, spec, n_row, L.SYM_F32, data, A.data.device)
+
+    @staticmethod
+    def result_spec(A: SymTensor, B: SymTensor, axes_a, axes_b):
+        """(spec, n_row) of sym_contract_output's result, from the operands'
+        descriptions alone (no library call, no buffer)."""
         fa = [i for i in range(A.rank) if i not in axes_a]
         fb = [i for i in range(B.rank) if i not in axes_b]
         legs = [A.spec.legs[i] for i in fa] + [B.spec.legs[i] for i in fb]
@@ -381,7 +388,7 @@ class Context:
                                           and tuple(axes_a) == (2, 3) and tuple(axes_b) == (0, 1)
                                           and tree in (L.SYM_TREE_OPERATOR, L.SYM_TREE_LEFT)):
             tree, n_row = L.SYM_TREE_CHAIN, len(legs)   # the general route: a CHAIN canonical block list
-        return self._wrap_output(h, _Spec(A.spec.group, legs, tree, qtot), n_row, L.SYM_F32, data, A.data.device)
+        return _Spec(A.spec.group, legs, tree, qtot), n_row
 
     def _axes(self, axes):
         # ctypes arrays of axis lists, made once per list
@@ -390,6 +397,31 @@ class Context:
         if a is None:
             a = self._axes_cache[t] = L.i32_array(t)
         return a
+
+    def contract_operand(self, A: SymTensor, B: SymTensor, axes_a, axes_b, compute="f32", which="A",
+                         fill=True, stream=None) -> SymTensor:
+        """Operand A or B of this contraction in the grouped GEMM's layout
+        (sym_contract_operand_output), zero-initialised and, with fill, holding
+        the operand's values.  Its legs are A's free legs then axes_a (or
+        axes_b then B's free legs); contract it over its last (first) legs in
+        order and the contraction reads it in place, with no fuse."""
+        w = 0 if which == "A" else 1
+        h = c_void_p()
+        L.check(L.lib().sym_contract_operand_output(self.handle, A.handle, B.handle, len(axes_a), self._axes(axes_a),
+                                                    self._axes(axes_b), _dtype_code(compute), w, None, byref(h)))
+        src = A if w == 0 else B
+        free = [i for i in range(src.rank) if i not in (axes_a if w == 0 else axes_b)]
+        perm = free + list(axes_a) if w == 0 else list(axes_b) + free
+        legs = [src.spec.legs[i] for i in perm]
+        n_row = len(free) if w == 0 else len(axes_b)
+        dt = _dtype_code(compute)
+        t = SymTensor(self, h.value, None, _Spec(src.spec.group, legs, getattr(src.spec, "tree", 0),
+                                                  getattr(src.spec, "qtot", 0)), n_row, dt)
+        dev = src.data.device if src.data is not None else torch.device("cuda")
+        t.set_data(torch.zeros(t.numel(), dtype=_TORCH[dt], device=dev))
+        if fill:
+            self.permute_into(src, perm, n_row, t, stream)
+        return t
 
     def contract(self, A: SymTensor, B: SymTensor, axes_a, axes_b, compute="f32", out: SymTensor = None,
                  stream=None) -> SymTensor:

@@ -341,3 +341,42 @@ def test_missing_library_fails_loudly():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=300)
     assert r.returncode != 0
     assert "libsymtensor.so is missing" in r.stderr
+
+
+def test_operand_layout_handles():
+    # the operand handles of a contraction: legs reordered (free then
+    # contracted for A, contracted then free for B), rows padded to 128-byte
+    # lines; structurally the same blocks as the packed permuted tensor
+    from ctypes import byref, c_void_p
+    from paper_1203_2222_amd import _lib as L
+    ctx = _ctx()
+    lq = W.u1_leg(-2, 2, [1, 3, 5, 3, 1], "in")
+    Aspec = W.TensorSpec(W.U1, (lq, lq, lq.flipped(), lq.flipped()))
+    Bspec = W.TensorSpec(W.U1, (lq, lq.flipped(), lq, lq.flipped()))
+    A, B = ctx.describe(Aspec, 4), ctx.describe(Bspec, 4)
+    axa, axb = (0, 3), (1, 2)
+    for which, compute, align in ((0, L.SYM_F32, 32), (1, L.SYM_F32, 32), (0, L.SYM_BF16, 64), (1, L.SYM_BF16, 64)):
+        h = c_void_p()
+        L.check(L.lib().sym_contract_operand_output(ctx.handle, A.handle, B.handle, 2, L.i32_array(axa),
+                                                    L.i32_array(axb), compute, which, None, byref(h)))
+        from paper_1203_2222_amd.tensor import SymTensor
+        t = SymTensor(ctx, h.value, None, None, 2, compute)
+        src, perm = (Aspec, (1, 2, 0, 3)) if which == 0 else (Bspec, (1, 2, 0, 3))
+        legs = [t.leg(i) for i in range(4)]
+        assert legs == [(tuple(src.legs[p].labels), tuple(src.legs[p].degs), src.legs[p].arrow) for p in perm]
+        spec = W.TensorSpec(W.U1, tuple(src.legs[p] for p in perm))
+        t.spec = spec
+        packed = ctx.describe(spec, 2)
+        assert sorted(b.labels for b in t.blocks()) == sorted(b.labels for b in packed.blocks())
+        assert t.numel() >= packed.numel()
+        for lab, rows, cols, off in t.sectors():
+            assert off % 64 == 0
+        lds = {b.strides[1] if which == 0 else b.strides[3] for b in t.blocks()}
+        assert all(x % align == 0 for x in lds if x > 1)
+    # general SU(2) contractions have no operand layout
+    INT = ((0, 1, 2), (2, 1, 1))
+    s2 = W.TensorSpec(W.SU2, tuple(W.Leg(*INT, a) for a in ("in", "in", "out", "out")), tree=T.TREE_OPERATOR)
+    X = ctx.describe(s2, 4)
+    h = c_void_p()
+    assert L.lib().sym_contract_operand_output(ctx.handle, X.handle, X.handle, 1, L.i32_array((2,)), L.i32_array((0,)),
+                                               L.SYM_F32, 0, None, byref(h)) != 0

@@ -292,3 +292,39 @@ def test_small_graph_replays_the_one_kernel(ctx):
         assert np.array_equal(host(C), eager), rep
         ctx.contract(A, B, c.axes_a, c.axes_b, "f32", out=C)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+@pytest.mark.parametrize("axes", [((2, 3), (0, 1)), ((0, 3), (1, 2))])
+def test_operands_in_gemm_layout_are_read_in_place(ctx, compute, axes):
+    # A and B fused once into the grouped GEMM's operand layout: the
+    # contraction reads them in place and gives the bits of the fusing path
+    import paper_1203_2222_amd as P
+    axa, axb = axes
+    say(f"case operands in GEMM layout {compute} axes {axa} {axb}")
+    lq = W.u1_leg(-3, 3, [2, 5, 9, 12, 9, 5, 2], "in")
+    Aspec = W.TensorSpec(W.U1, (lq, lq, lq.flipped(), lq.flipped()))
+    Bspec = W.TensorSpec(W.U1, (lq, lq.flipped(), lq, lq.flipped())) if axa == (0, 3) else Aspec
+    g = W.generator(31, "cuda")
+    a, b = draw(Aspec, g), draw(Bspec, g)
+    A, B = ctx.tensor(Aspec, 4, data=a), ctx.tensor(Bspec, 4, data=b)
+    want = host(to_canonical(ctx, ctx.contract(A, B, axa, axb, compute)))
+    Aop = ctx.contract_operand(A, B, axa, axb, compute, "A")
+    Bop = ctx.contract_operand(A, B, axa, axb, compute, "B")
+    nfa = 4 - len(axa)
+    op_axes = (tuple(range(nfa, 4)), tuple(range(len(axb))))
+    got = host(to_canonical(ctx, ctx.contract(Aop, Bop, *op_axes, compute)))
+    assert np.array_equal(got, want)
+    _, ref = K.contract_pairs(Aspec, a.double().cpu().numpy(), Bspec, b.double().cpu().numpy(), axa, axb)
+    assert rel_err(got, ref) <= (FP32_TOL if compute == "f32" else BF16_TOL)
+    # one operand in place, the other fused as usual
+    got1 = host(to_canonical(ctx, ctx.contract(Aop, ctx.permute_fuse(B, list(axb) + [i for i in range(4) if i not in axb], 4),
+                                               *op_axes, compute)))
+    assert np.array_equal(got1, want)
+    # the GEMM reads such operands with 16-byte loads from 256-byte aligned bases
+    buf = torch.zeros(Aop.numel() + 64, dtype=Aop.data.dtype, device="cuda")
+    Abad = ctx.contract_operand(A, B, axa, axb, compute, "A", fill=False)
+    Abad.set_data(buf[16:])
+    with pytest.raises(P.SymError) as e:
+        ctx.contract(Abad, Bop, *op_axes, compute)
+    assert e.value.status == 1
