@@ -572,8 +572,61 @@ def measured_traffic(kernel):
             "write_bytes": rec["write_bytes"], "source": "profiles/traffic.json"}
 
 
+def write_traffic(fetch_csv, write_csv, out_path, profile_name):
+    """profiles/traffic.json from two rocprofv3 counter runs of the headline
+    command (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`, CSV output, both
+    with --calibrate-copy): per GEMM tile variant, the mean bytes per launch
+    over its full-batch dispatches (those writing at least 90 % of the most
+    any of its dispatches wrote), each counter scaled so that the run's 1 GiB
+    device copy reads and writes 1 GiB; keyed by variant name with the hash
+    of kernels.hip the counters were taken on."""
+    import csv
+    import hashlib
+    import re
+    import paper_1203_2222_amd as P
+
+    def load(path, counter):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            m = re.search(r"(k_gemm_\w+<[^>]*>)", r["Kernel_Name"])
+            name = m.group(1) if m else r["Kernel_Name"].split("(")[0]
+            per.setdefault(name, {})[r["Dispatch_Id"]] = float(r["Counter_Value"]) * 1024.0
+        return per
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    gib = float(1 << 30)
+    copies_f = [v for k, d in fetch.items() if "copyBuffer" in k for v in d.values()]
+    copies_w = [v for k, d in write.items() if "copyBuffer" in k for v in d.values()]
+    scale_f, scale_w = gib / max(copies_f), gib / max(copies_w)
+    digest = hashlib.sha256(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1203_2222_amd",
+                                              "csrc", "kernels.hip"), "rb").read()).hexdigest()
+    out = {}
+    for compute in ("bf16", "f32"):
+        for v in range(P.num_variants(compute)):
+            k = P.variant_kernel(compute, v)
+            if k not in fetch or k not in write:
+                continue
+            w = write[k]
+            top = max(w.values())
+            full = [d for d, x in w.items() if x >= 0.9 * top and d in fetch[k]]
+            if not full:
+                continue
+            out[P.variant_name(compute, v)] = {
+                "kernel": k, "dispatches": len(full), "kernels_hip_sha256": digest, "profile": profile_name,
+                "read_bytes": int(sum(fetch[k][d] for d in full) / len(full) * scale_f),
+                "write_bytes": int(sum(w[d] for d in full) / len(full) * scale_w),
+                "scale": {"FETCH_SIZE": round(scale_f, 4), "WRITE_SIZE": round(scale_w, 4)}}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROFILE"),
+                    help="write profiles/traffic.json from two counter runs (host only) and exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -592,6 +645,12 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
+    if args.traffic_from:
+        out = write_traffic(*args.traffic_from[:2], os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                                 "profiles", "traffic.json"), args.traffic_from[2])
+        print(json.dumps({k: {"read_GB": v["read_bytes"] / 1e9, "write_GB": v["write_bytes"] / 1e9}
+                          for k, v in out.items()}, indent=1))
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this library "

@@ -466,6 +466,10 @@ int32_t sym_num_variants(int32_t compute, int32_t* count);
 /* Name of a tile variant (static storage, never freed), and the variant a
  * context uses for a compute type when nothing was set or tuned. */
 int32_t sym_variant_name(int32_t compute, int32_t variant, const char** name);
+/* The kernel a tile variant launches, as its template instance (for example
+ * "k_gemm_bf16_dl<256, 256, 32, 2, 4, 5, 2>"), the form profilers print
+ * inside the kernel's full name.  Static string; host only. */
+int32_t sym_variant_kernel(int32_t compute, int32_t variant, const char** kernel);
 int32_t sym_default_variant(int32_t compute, int32_t* variant);
 
 /* Block-wise singular value decomposition (section "Factorization of a

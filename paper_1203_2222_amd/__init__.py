@@ -7,7 +7,7 @@ library with ``python -m paper_1203_2222_amd.build``.
 """
 from ._lib import SymError, lib  # noqa: F401
 from .tensor import (Context, Graph, Hold, SymTensor, default_variant, fmove_coeff, noalloc_capacity,  # noqa: F401
-                     num_variants, su2_gamma, variant_name)
+                     num_variants, su2_gamma, variant_kernel, variant_name)
 
 
 def __getattr__(name):

@@ -83,6 +83,7 @@ SIGNATURES = {
     "sym_ctx_set_variant": (c_int32, [P, c_int32, c_int32]),
     "sym_num_variants": (c_int32, [c_int32, I32P]),
     "sym_variant_name": (c_int32, [c_int32, c_int32, POINTER(c_char_p)]),
+    "sym_variant_kernel": (c_int32, [c_int32, c_int32, POINTER(c_char_p)]),
     "sym_svd_sizes": (c_int32, [P, I64P, I64P, I64P]),
     "sym_svd": (c_int32, [P, P, P, P, P, I32P, c_int32, P]),
     "sym_svd_truncate": (c_int32, [P, P, c_int64, c_double, I32P, POINTER(c_double)]),

@@ -1822,6 +1822,14 @@ int32_t sym_variant_name(int32_t compute, int32_t variant, const char** name) {
     });
 }
 
+int32_t sym_variant_kernel(int32_t compute, int32_t variant, const char** kernel) {
+    return guard([&] {
+        if (!kernel || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");
+        if (variant < 0 || variant >= gemm_num_variants(compute)) throw Error(SYM_E_ARG, "no such variant");
+        *kernel = gemm_variant_kernel(compute, variant);
+    });
+}
+
 int32_t sym_default_variant(int32_t compute, int32_t* variant) {
     return guard([&] {
         if (!variant || (compute != SYM_F32 && compute != SYM_BF16)) throw Error(SYM_E_ARG, "bad argument");

@@ -1323,6 +1323,7 @@ int occupancy_dl() {
     X(15, 256, 256, 32, 2, 2, 5, 1)
 
 bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 15; }
+
 int gemm_direct_max_ld() { return kDlMaxLd; }
 
 // BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
@@ -1374,6 +1375,27 @@ GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variant
 // moved from one MI355X to another, which is what the autotuner is for.
 int gemm_default_variant(int compute) { return compute == 0 ? 0 : 10; }
 int gemm_default_variant_wide(int compute) { return compute == 0 ? 0 : 5; }
+
+const char* gemm_variant_kernel(int compute, int variant) {
+    if (compute == 0) {
+        static const char* const f32[] = {"k_gemm_f32<128, 128>", "k_gemm_f32<64, 64>", "k_gemm_f32<128, 64>",
+                                          "k_gemm_f32<256, 128>"};
+        return variant >= 0 && variant < 4 ? f32[variant] : "";
+    }
+    switch (variant) {
+#define SYM_SIG_BIG(V, MT, NT, KT, WGM, WGN, OCC, SA) \
+    case V: return "k_gemm_bf16_big<" #MT ", " #NT ", " #KT ", " #WGM ", " #WGN ", " #OCC ", " #SA ">";
+        SYM_BF16_BIG_VARIANTS(SYM_SIG_BIG)
+#undef SYM_SIG_BIG
+#define SYM_SIG_DL(V, MT, NT, KT, WGM, WGN, ST, OPT) \
+    case V: return "k_gemm_bf16_dl<" #MT ", " #NT ", " #KT ", " #WGM ", " #WGN ", " #ST ", " #OPT ">";
+        SYM_BF16_DL_VARIANTS(SYM_SIG_DL)
+#undef SYM_SIG_DL
+        case 3: return "k_gemm_bf16<128, 128>";
+        case 4: return "k_gemm_bf16<64, 64>";
+        default: return "";
+    }
+}
 
 int gemm_blocks_per_cu(int compute, int variant) {
     int n = 0;
@@ -1856,14 +1878,18 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
 // position is decoded once (mixed radix over the output's dims) into its
 // offset inside the first input and the first output block; blocks that
 // share strides reuse it.
-template <int NB>
+// RK: the block rank when it is exactly 4 (the decode and the address sums
+// then run over 4 dims with no rank test, which is what the element rate of
+// the rank-4 trees needs: the general form measured 1.55 against 1.0 ms on
+// config 5's recoupling), or kMaxRecoupleRank for any rank up to it.
+template <int NB, int RK>
 __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __restrict__ ib,
                                                const FmBlk* __restrict__ ob, const double* __restrict__ cf,
                                                const float* __restrict__ src, float* __restrict__ dst, int start,
                                                int end) {
     constexpr int U = NB <= 2 ? 8 : NB <= 4 ? 4 : NB <= 8 ? 2 : 1;
-    constexpr int R = kMaxRecoupleRank;
-    const int n = g.n, rank = g.rank;
+    constexpr int R = RK;
+    const int n = g.n, rank = RK == 4 ? 4 : g.rank;
     // offsets of position e in block b, for all blocks sharing b's strides or not
     auto decode = [&](int e, int (&t)[R]) {
         int r = e;
@@ -1934,12 +1960,22 @@ __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ gr
     const FmBlk* __restrict__ ob = out_blks + g.out_first;
     const int end = t.start + t.count;
     const int n = g.n;
-    if (n <= 1) recouple_elems<1>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 2) recouple_elems<2>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 4) recouple_elems<4>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 8) recouple_elems<8>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 16) recouple_elems<16>(g, ib, ob, cf, src, dst, t.start, end);
-    else recouple_elems<kMaxRecouple>(g, ib, ob, cf, src, dst, t.start, end);
+    if (g.rank == 4) {
+        if (n <= 1) recouple_elems<1, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 2) recouple_elems<2, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 4) recouple_elems<4, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 8) recouple_elems<8, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 16) recouple_elems<16, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        else recouple_elems<kMaxRecouple, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        return;
+    }
+    constexpr int RG = kMaxRecoupleRank;
+    if (n <= 1) recouple_elems<1, RG>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 2) recouple_elems<2, RG>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 4) recouple_elems<4, RG>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 8) recouple_elems<8, RG>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 16) recouple_elems<16, RG>(g, ib, ob, cf, src, dst, t.start, end);
+    else recouple_elems<kMaxRecouple, RG>(g, ib, ob, cf, src, dst, t.start, end);
 }
 
 // LDS-tiled K9 (see FtGroup): a workgroup moves one box of all n input
@@ -1984,9 +2020,9 @@ __global__ __launch_bounds__(256) void k_recouple_tiled(const FtGroup* __restric
                                                         int out_buf) {
     constexpr int U = 16;
     __shared__ float tile[kFtElems];
-    __shared__ double cf[kMaxRecouple * kMaxRecouple];
-    __shared__ int64_t ibase[kMaxRecouple], obase[kMaxRecouple];
-    __shared__ int32_t istr[kMaxRecouple][3], ostr[kMaxRecouple][3];
+    __shared__ double cf[kMaxRecoupleTiled * kMaxRecoupleTiled];
+    __shared__ int64_t ibase[kMaxRecoupleTiled], obase[kMaxRecoupleTiled];
+    __shared__ int32_t istr[kMaxRecoupleTiled][3], ostr[kMaxRecoupleTiled][3];
     const FtTask t = tasks[blockIdx.x];
     const FtGroup& g = groups[t.group];
     const int n = g.n;
@@ -1997,15 +2033,17 @@ __global__ __launch_bounds__(256) void k_recouple_tiled(const FtGroup* __restric
     if (tid < 2 * n) {
         const bool in = tid < n;
         const int i = in ? tid : tid - n;
-        const FmBlk b = in ? in_blks[g.in_first + i] : out_blks[g.out_first + i];
-        const int64_t base = b.off + static_cast<int64_t>(t.o[0]) * b.stride[a0] +
-                             static_cast<int64_t>(t.o[1]) * b.stride[a1] + static_cast<int64_t>(t.o[2]) * b.stride[a2] +
-                             static_cast<int64_t>(t.o[3]) * b.stride[a3];
+        // read through a pointer: indexing a copy of the record by the
+        // axis numbers would put it in scratch memory
+        const FmBlk* b = in ? in_blks + g.in_first + i : out_blks + g.out_first + i;
+        const int64_t base = b->off + static_cast<int64_t>(t.o[0]) * b->stride[a0] +
+                             static_cast<int64_t>(t.o[1]) * b->stride[a1] +
+                             static_cast<int64_t>(t.o[2]) * b->stride[a2] + static_cast<int64_t>(t.o[3]) * b->stride[a3];
         (in ? ibase : obase)[i] = base;
         int32_t* st = in ? istr[i] : ostr[i];
-        st[0] = b.stride[a1];
-        st[1] = b.stride[a2];
-        st[2] = b.stride[a3];
+        st[0] = b->stride[a1];
+        st[1] = b->stride[a2];
+        st[2] = b->stride[a3];
     }
     __syncthreads();
     // extents of the box inside the blocks (edge tiles are clipped)
@@ -2056,10 +2094,8 @@ __global__ __launch_bounds__(256) void k_recouple_tiled(const FtGroup* __restric
         recouple_combine<4>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else if (n <= 8)
         recouple_combine<8>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
-    else if (n <= 16)
-        recouple_combine<16>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else
-        recouple_combine<kMaxRecouple>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+        recouple_combine<kMaxRecoupleTiled>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
 }
 
 hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,

@@ -10,6 +10,7 @@ namespace sym {
 constexpr int kMaxBufs = 256;       // distinct base pointers one launch may address
 constexpr int kMaxCopyDims = 6;     // dims of a coalesced block copy
 constexpr int kMaxRecouple = 32;    // blocks of one label tuple on either side of a recoupling
+constexpr int kMaxRecoupleTiled = 16;   // the same for the LDS-tiled kernel (its LDS tables scale with it)
 constexpr int kMaxRecoupleRank = 8;
 constexpr int kRecoupleChunk = 4096;   // elements of one label tuple per workgroup task
 
@@ -214,6 +215,9 @@ struct GemmVariant {
 int gemm_num_variants(int compute);
 GemmVariant gemm_variant(int compute, int variant);
 int gemm_default_variant(int compute);
+// The kernel a variant launches, as its template instance (the name tools
+// such as profilers print, without the namespace and parameter list).
+const char* gemm_variant_kernel(int compute, int variant);
 // Default for problems whose row lengths rule out the direct-load variants.
 int gemm_default_variant_wide(int compute);
 // Direct-load BF16 variants address each operand tile through a 32-bit

@@ -664,7 +664,8 @@ void RecoupleProgram::add_group(int rank, const int64_t* dims, const std::vector
     in_blks.insert(in_blks.end(), ins.begin(), ins.end());
     out_blks.insert(out_blks.end(), outs.begin(), outs.end());
     coef.insert(coef.end(), gamma.begin(), gamma.end());
-    if (rank == 4) {
+    if (rank == 4 && n > kMaxRecoupleTiled) tiled_unfit = true;
+    if (rank == 4 && n <= kMaxRecoupleTiled) {
         FtGroup tg{};
         tg.n = n;
         for (int k = 0; k < 4; ++k) tg.dim[k] = g.d[k];
@@ -727,6 +728,7 @@ void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<i
     // moves, the tiled kernel (rank 4) transposes through LDS (full reversal:
     // 2.5 against 0.73 TB/s).
     tiled = rank == 4 && perm[static_cast<size_t>(rank - 1)] != rank - 1;
+    tiled_unfit = false;
     int64_t dims[kMaxRecoupleRank];
     if (in.tree == SYM_TREE_CHAIN || out.tree == SYM_TREE_CHAIN) {
         if (!chain_like(in) || !chain_like(out))
@@ -765,6 +767,7 @@ void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<i
             add_group(rank, dims, ins, outs, gamma);
             i = jend;
         }
+        if (tiled_unfit) tiled = false;
         return;
     }
     if (rank != 4) throw Error(SYM_E_UNSUPPORTED, "rank-4 trees only");
@@ -803,6 +806,7 @@ void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<i
         add_group(4, dims, ins, outs, gamma);
         i = j;
     }
+    if (tiled_unfit) tiled = false;
 }
 
 FusedLeg fuse_legs(const Leg& a, const Leg& b) {

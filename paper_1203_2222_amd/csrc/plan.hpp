@@ -107,6 +107,7 @@ struct RecoupleProgram {
     std::vector<FtGroup> tgroups;   // the same label tuples, for the LDS-tiled kernel
     std::vector<FtTask> ttasks;
     bool tiled = false;             // the permutation moves the input's contiguous (last) leg
+    bool tiled_unfit = false;       // a label tuple has more blocks than the tiled kernel takes
     DevMemPtr d_groups, d_in, d_out, d_coef, d_tasks, d_tgroups, d_ttasks;
     // Gamma(tree, perm, tree') of every label tuple; out's leg k is in's leg
     // perm[k]; the tensors start at element in_base / out_base of their

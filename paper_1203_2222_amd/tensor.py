@@ -603,6 +603,13 @@ def variant_name(compute, variant: int) -> str:
     return name.value.decode()
 
 
+def variant_kernel(compute, variant: int) -> str:
+    """The template instance a tile variant launches (as profilers print it)."""
+    name = c_char_p()
+    L.check(L.lib().sym_variant_kernel(_dtype_code(compute), int(variant), byref(name)))
+    return name.value.decode()
+
+
 def default_variant(compute) -> int:
     n = c_int32()
     L.check(L.lib().sym_default_variant(_dtype_code(compute), byref(n)))

@@ -260,6 +260,8 @@ def test_variant_names_and_default():
         n = P.num_variants(compute)
         names = [P.variant_name(compute, v) for v in range(n)]
         assert len(set(names)) == n and all(names)
+        kernels = [P.variant_kernel(compute, v) for v in range(n)]
+        assert len(set(kernels)) == n and all(k.startswith("k_gemm_") and k.endswith(">") for k in kernels)
         assert 0 <= P.default_variant(compute) < n
     with pytest.raises(P.SymError):
         P.variant_name("bf16", P.num_variants("bf16"))
