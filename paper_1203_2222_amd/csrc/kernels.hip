@@ -294,8 +294,9 @@ __device__ __forceinline__ void tile_copy(const CopyOp* __restrict__ ops, const 
 template <typename Ti>
 struct TransposeShape {
     static constexpr int VI = 16 / sizeof(Ti);
-    static constexpr int NV = (kTile + 2 * VI - 2) / VI;   // vectors that cover one source row segment
-    static constexpr int RW = kTile + 2 * VI + 7 * VI;       // staged row width incl. rotation room
+    static constexpr int VC = vtile_cols(sizeof(Ti));       // tile columns (source-contiguous)
+    static constexpr int NV = (VC + 2 * VI - 2) / VI;       // vectors that cover one source row segment
+    static constexpr int RW = VC + 2 * VI + 7 * VI;          // staged row width incl. rotation room
     static constexpr int TI = vtile_rows(sizeof(Ti));
     static constexpr size_t lds_bytes = static_cast<size_t>(TI) * RW * sizeof(Ti) + TI * sizeof(int);
 };
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(kTvThreads) void k_transpose_vec(const CopyOp* __re
                                                        const TileTask* __restrict__ tasks, int n_tasks,
                                                        PtrTable bufs) {
     using Sh = TransposeShape<Ti>;
-    constexpr int VI = Sh::VI, NV = Sh::NV, RW = Sh::RW, TI = Sh::TI;
+    constexpr int VI = Sh::VI, NV = Sh::NV, RW = Sh::RW, TI = Sh::TI, VC = Sh::VC;
     constexpr int VO = Pack<To>::V;
     constexpr int NC = (TI + 2 * VO - 2) / VO;      // chunks that cover one destination row segment
     constexpr int NH = (NC + 7) / 8;                // groups of eight chunks
@@ -366,9 +367,9 @@ __global__ __launch_bounds__(kTvThreads) void k_transpose_vec(const CopyOp* __re
         c.dJ = op.dstride[J];
         c.dJhi = MERGED && op.jhi >= 0 ? op.dstride[op.jhi] : 0;
         c.i0 = t.it * TI;
-        c.j0 = t.jt * kTile;
+        c.j0 = t.jt * VC;
         c.ni = min(TI, nI - c.i0);
-        c.nj = min(kTile, nJ - c.j0);
+        c.nj = min(VC, nJ - c.j0);
         // row r of the tile: source elements [so + src_row(i0 + r) + j0, + nj);
         // the lowest row start is that of the first row, or of i_lo = 0 in
         // the tile's first i_hi when the tile wraps past the end of i_lo
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(kTvThreads) void k_transpose_vec(const CopyOp* __re
         const bool vec_dst = (reinterpret_cast<uintptr_t>(c.dst) & 15) == 0;
         const int neg = c.op->neg;
         // wave item (g, h): lane (jj, cc) writes chunk 8 h + cc of destination row j0 + 8 g + jj
-        for (int wi = wave; wi < (kTile / 8) * NH; wi += NW) {
+        for (int wi = wave; wi < (VC / 8) * NH; wi += NW) {
             const int g = wi / NH, h = wi - g * NH;
             const int j = 8 * g + (lane >> 3), cc = 8 * h + (lane & 7);
             if (j >= c.nj || cc >= NC) continue;

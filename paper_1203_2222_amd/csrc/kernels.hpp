@@ -67,6 +67,10 @@ constexpr int kTile = 64;
 // cache lines: for BF16 sources 256 rows measured 7 % faster than 128 and
 // 64 rows 23 % slower (batched B operand, 21.4 GB); 512 was slower again.
 constexpr int vtile_rows(int src_elem_bytes) { return src_elem_bytes == 2 ? 256 : 64; }
+// columns (source-contiguous extent) of a vectorized transposing tile: 128
+// BF16 columns (256-byte source segments) measured 2 to 3 % slower on the
+// batched fuse, with 256 rows (one workgroup per CU) or with 128
+constexpr int vtile_cols(int) { return 64; }
 
 // One sector GEMM: C[m][n] = sum_k A[m][k] * B[n][k] (both operands K-contiguous).
 // With `indirect` set, element (m, n) is stored at

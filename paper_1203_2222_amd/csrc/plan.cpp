@@ -180,6 +180,7 @@ void CopyProgram::finalize() {
             // long as one tile's source rows span less than 2^29 bytes
             const int esz = src_dtype == SYM_BF16 ? 2 : 4;
             const int ti = vtile_rows(esz);
+            const int tc = vtile_cols(esz);
             const bool vec = op.dstride[I] == 1 && op.sstride[I] > 0 && op.sstride[I] * ti * esz < (int64_t{1} << 29);
             op.ihi = op.jhi = -1;
             if (vec && static_cast<int64_t>(op.count) * esz < (int64_t{1} << 29)) {
@@ -190,7 +191,7 @@ void CopyProgram::finalize() {
                 for (int d = kMaxCopyDims - 2; d >= kMaxCopyDims - op.ndim; --d) {
                     if (d == op.tj) continue;
                     if (op.ihi < 0 && op.size[I] < ti && op.dstride[d] == op.size[I]) op.ihi = d;
-                    else if (op.jhi < 0 && op.size[op.tj] < kTile && op.sstride[d] == op.size[op.tj]) op.jhi = d;
+                    else if (op.jhi < 0 && op.size[op.tj] < tc && op.sstride[d] == op.size[op.tj]) op.jhi = d;
                 }
             }
             int64_t outer = 1;
@@ -198,10 +199,11 @@ void CopyProgram::finalize() {
                 if (d != op.tj && d != op.ihi && d != op.jhi) outer *= op.size[d];
             const int64_t nI = static_cast<int64_t>(op.size[I]) * (op.ihi >= 0 ? op.size[op.ihi] : 1);
             const int64_t nJ = static_cast<int64_t>(op.size[op.tj]) * (op.jhi >= 0 ? op.size[op.jhi] : 1);
-            const int nj = static_cast<int>((nJ + kTile - 1) / kTile);
+            const int cj = vec ? tc : kTile;
+            const int nj = static_cast<int>((nJ + cj - 1) / cj);
             const int ni = static_cast<int>((nI + (vec ? ti : kTile) - 1) / (vec ? ti : kTile));
             if (vec && op.ihi < 0 && op.jhi < 0 && op.count >= kChunk &&
-                4 * nI * nJ < static_cast<int64_t>(ti) * kTile) {
+                4 * nI * nJ < static_cast<int64_t>(ti) * tc) {
                 // a small transpose that fills under a quarter of a tile and
                 // has no dim to merge: element-wise (the rows sit in L2).
                 // Blocks below one element-wise task stay tiled: the
