@@ -150,3 +150,99 @@ def test_su2_general_contraction_rejects_bf16(ctx):
     B, _ = _tensor(ctx, sb, 2)
     with pytest.raises(Exception):
         ctx.contract(B, A, (2, 3), (1, 2), "bf16")
+
+
+def _random_spec(rng, rank, pool=(HALF, INT, WHOLE)):
+    while True:
+        arrows = [("in", "out")[int(x)] for x in rng.integers(0, 2, size=rank)]
+        legs = [pool[int(x)] for x in rng.integers(0, len(pool), size=rank)]
+        spec = _spec(legs, arrows)
+        if 0 < T.num_elements(spec) <= 60000:
+            return legs, arrows, spec
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_su2_random_permute_matches_projection(ctx, seed):
+    # seeded random ranks (3..6), arrows, spectra, permutations, target
+    # arrows and layouts, against the oracle's projection
+    rng = np.random.default_rng(1000 + seed)
+    rank = int(rng.integers(3, 7))
+    legs, arrows, spec = _random_spec(rng, rank)
+    perm = [int(x) for x in rng.permutation(rank)]
+    ao = [("in", "out")[int(x)] for x in rng.integers(0, 2, size=rank)]
+    _, ref = RC.permute_chain(spec, np.zeros(T.num_elements(spec)), perm, ao)
+    if ref.size == 0:
+        pytest.skip("no invariant block after the permutation")
+    nin = 0
+    while nin < rank and arrows[nin] == "in":
+        nin += 1
+    nout = 0
+    while nout < rank and ao[nout] == "in":
+        nout += 1
+    n_row_in = int(rng.integers(1, nin + 1)) if 1 <= nin < rank else 0
+    n_row_out = int(rng.integers(1, nout + 1)) if 1 <= nout < rank else 0
+    say(f"case random su2_permute seed {seed} rank {rank} perm {perm} rows {n_row_in}->{n_row_out}")
+    t, flat = _tensor(ctx, spec, 50 + seed, n_row_in or None)
+    out = ctx.su2_permute(t, perm, ao, n_row_out)
+    _, ref = RC.permute_chain(spec, flat, perm, ao)
+    assert rel_err(_canonical(ctx, out), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_su2_random_contraction_matches_dense(ctx, seed):
+    rng = np.random.default_rng(2000 + seed)
+    for _ in range(200):
+        ra, rb = int(rng.integers(2, 5)), int(rng.integers(2, 5))
+        la, aa, sa = _random_spec(rng, ra)
+        m = int(rng.integers(1, min(ra, rb)))
+        axa = [int(x) for x in rng.permutation(ra)[:m]]
+        # B: contracted legs carry A's spectra with opposite arrows, the rest random
+        axb = [int(x) for x in rng.permutation(rb)[:m]]
+        lb = [None] * rb
+        ab = [None] * rb
+        for ia, ib in zip(axa, axb):
+            lb[ib] = la[ia]
+            ab[ib] = "out" if aa[ia] == "in" else "in"
+        for i in range(rb):
+            if lb[i] is None:
+                lb[i] = (HALF, INT, WHOLE)[int(rng.integers(0, 3))]
+                ab[i] = ("in", "out")[int(rng.integers(0, 2))]
+        sb = _spec(lb, ab)
+        if 0 < T.num_elements(sb) <= 60000 and m < ra and m < rb:
+            sc = K.result_spec(sa, sb, tuple(axa), tuple(axb))
+            if 0 < T.num_elements(sc):
+                break
+    else:
+        pytest.skip("no admissible random pair")
+    say(f"case random su2 contraction seed {seed} ranks {ra},{rb} axes {axa} {axb}")
+    A, fa = _tensor(ctx, sa, 70 + seed)
+    B, fb = _tensor(ctx, sb, 90 + seed)
+    sc, ref = K.contract_su2_dense(sa, fa, sb, fb, tuple(axa), tuple(axb))
+    C = ctx.contract(A, B, tuple(axa), tuple(axb), "f32")
+    assert rel_err(host(C), ref) <= 1e-5
+
+
+def test_su2_general_contraction_graph_and_noalloc(ctx):
+    # the five steps replayed from a HIP graph, and through the entry point
+    # that allocates nothing: the eager result's bits each time
+    name, la, aa, ta, lb, ab, tb, axa, axb = CONTRACTIONS[0]
+    say("case su2 general contraction graph + no-alloc")
+    sa, sb = _spec(la, aa, ta), _spec(lb, ab, tb)
+    A, _ = _tensor(ctx, sa, 7)
+    B, _ = _tensor(ctx, sb, 8)
+    C = ctx.contract(A, B, axa, axb, "f32")
+    eager = host(C).copy()
+    stream = torch.cuda.Stream()
+    graph = ctx.graph_batched([A], [B], axa, axb, "f32", [C], stream)
+    for rep in range(3):
+        C.data.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        stream.synchronize()
+        assert np.array_equal(host(C), eager), rep
+        ctx.contract(A, B, axa, axb, "f32", out=C)
+        torch.cuda.synchronize()
+    C2 = ctx.contract_output(A, B, axa, axb)
+    C2.data.fill_(float("nan"))
+    ctx.contract_noalloc(A, B, axa, axb, "f32", out=C2)
+    assert np.array_equal(host(C2), eager)
