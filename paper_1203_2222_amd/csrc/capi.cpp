@@ -1895,24 +1895,28 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             return ms;
         };
         // round 1: one launch each; round 2: three more for the variants
-        // within 8 % of the fastest; the smallest sum of round-2 times wins
+        // within 8 % of the fastest, taken round-robin so that a drift of the
+        // clock (power and thermal state) weighs on every candidate alike.
+        // The smallest sum of round-2 times wins, unless the default variant
+        // is within 1 % of it: the default then stays.
         std::vector<float> first(static_cast<size_t>(nv));
         float fastest = 0.f;
         for (int v = 0; v < nv; ++v) {
             first[static_cast<size_t>(v)] = time_gemm(*cand[static_cast<size_t>(v)]);
             if (v == 0 || first[static_cast<size_t>(v)] < fastest) fastest = first[static_cast<size_t>(v)];
         }
-        float best_ms = 0.f;
-        int best = -1;
-        for (int v = 0; v < nv; ++v) {
-            if (first[static_cast<size_t>(v)] > 1.08f * fastest) continue;
-            float total = 0.f;
-            for (int rep = 0; rep < 3; ++rep) total += time_gemm(*cand[static_cast<size_t>(v)]);
-            if (best < 0 || total < best_ms) {
-                best_ms = total;
-                best = v;
-            }
-        }
+        std::vector<int> keep;
+        for (int v = 0; v < nv; ++v)
+            if (first[static_cast<size_t>(v)] <= 1.08f * fastest) keep.push_back(v);
+        const int def = gemm_default_variant(compute);
+        if (std::find(keep.begin(), keep.end(), def) == keep.end()) keep.push_back(def);
+        std::vector<float> total(static_cast<size_t>(nv), 0.f);
+        for (int rep = 0; rep < 3; ++rep)
+            for (int v : keep) total[static_cast<size_t>(v)] += time_gemm(*cand[static_cast<size_t>(v)]);
+        int best = keep[0];
+        for (int v : keep)
+            if (total[static_cast<size_t>(v)] < total[static_cast<size_t>(best)]) best = v;
+        if (total[static_cast<size_t>(def)] <= 1.01f * total[static_cast<size_t>(best)]) best = def;
         const std::string tk = std::to_string(compute) + ":" + std::to_string(std::hash<std::string>{}(key));
         {
             std::lock_guard<std::mutex> lk(ctx->tmu);

@@ -1104,7 +1104,8 @@ __device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, u32x4* lds
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
 
 // OPT bit 0: raise the wave's issue priority while it issues MFMAs; bit 1:
-// interleave the next step's fragment reads with the MFMAs one by one.
+// interleave the next step's fragment reads with the MFMAs one by one; bit
+// 3: one barrier per two K slices (five stages).
 template <int MT, int NT, int KT, int WGM, int WGN, int ST, int OPT>
 __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmProb* __restrict__ probs,
                                                                     const GemmTile* __restrict__ tiles, int n_tiles,
@@ -1209,28 +1210,13 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmPr
             for (int j = 0; j < FN; ++j) bfr[set][j] = Bc[swz16<CH>(wn * WN + j * 32 + r32, c)];
         };
 
-#pragma unroll
-        for (int s = 0; s < ST - 1; ++s) issue(s, s);
-        // slice 0 visible to every wave
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm((ST - 2) * (AV + BV)));
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_sched_barrier(0);
-        frags(0, 0, 0);
-        int sr = 0, sw = ST - 1;
-        for (int kt = 0; kt < nk; ++kt) {
-            // slices kt and kt + 1 have landed for this wave; after the
-            // barrier for every wave, and every wave is done with iteration
-            // kt - 1, so stage sw (slice kt - 1) is free
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm((ST - 3) * (AV + BV)));
-            __builtin_amdgcn_s_barrier();
-            __builtin_amdgcn_sched_barrier(0);
-            issue(kt + ST - 1, sw);
-            __builtin_amdgcn_sched_barrier(0);
-            const int sn = sr + 1 == ST ? 0 : sr + 1;
+        // the MFMAs of the slice in stage sr; its last step reads the first
+        // fragments of the slice in stage sn
+        auto slice = [&](int sr, int sn) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int cs = s & 1;
-                // the last step fetches the first fragments of slice kt + 1,
+                // the last step fetches the first fragments of the next slice,
                 // so the MFMAs never wait on LDS after the barrier
                 const int st = s + 1 < S ? sr : sn, step = s + 1 < S ? s + 1 : 0;
                 if constexpr ((OPT & 2) == 0) {
@@ -1261,8 +1247,59 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmPr
                 if constexpr ((OPT & 1) != 0) __builtin_amdgcn_s_setprio(0);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            sr = sn;
-            sw = sw + 1 == ST ? 0 : sw + 1;
+        };
+        auto wrap = [](int x) { return x >= ST ? x - ST : x; };
+
+        if constexpr ((OPT & 8) != 0) {
+            // one barrier per two slices: slices kt .. kt + 2 are in LDS when
+            // the pair (kt, kt + 1) starts, kt + 3 and kt + 4 go into the
+            // stages the previous pair used (five stages)
+            static_assert(ST == 5, "paired slices need five stages");
+#pragma unroll
+            for (int s = 0; s < 3; ++s) issue(s, s);
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            frags(0, 0, 0);
+            int sr = 0;   // stage of slice kt
+            for (int kt = 0; kt < nk; kt += 2) {
+                // every load issued so far (slices up to kt + 2) has landed
+                // for this wave; after the barrier for every wave, and every
+                // wave is done with slices kt - 2 and kt - 1
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_sched_barrier(0);
+                const int s1 = wrap(sr + 1), s2 = wrap(sr + 2), s3 = wrap(sr + 3), s4 = wrap(sr + 4);
+                issue(kt + 3, s3);
+                issue(kt + 4, s4);
+                __builtin_amdgcn_sched_barrier(0);
+                slice(sr, s1);
+                if (kt + 1 < nk) slice(s1, s2);
+                sr = s2;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < ST - 1; ++s) issue(s, s);
+            // slice 0 visible to every wave
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm((ST - 2) * (AV + BV)));
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            frags(0, 0, 0);
+            int sr = 0, sw = ST - 1;
+            for (int kt = 0; kt < nk; ++kt) {
+                // slices kt and kt + 1 have landed for this wave; after the
+                // barrier for every wave, and every wave is done with iteration
+                // kt - 1, so stage sw (slice kt - 1) is free
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm((ST - 3) * (AV + BV)));
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_sched_barrier(0);
+                issue(kt + ST - 1, sw);
+                __builtin_amdgcn_sched_barrier(0);
+                const int sn = wrap(sr + 1);
+                slice(sr, sn);
+                sr = sn;
+                sw = wrap(sw + 1);
+            }
         }
 
         if (p.indirect) {
@@ -1321,15 +1358,16 @@ int occupancy_dl() {
     X(12, 256, 256, 32, 2, 4, 5, 1)    \
     X(13, 256, 256, 32, 2, 4, 5, 2)    \
     X(14, 256, 256, 32, 2, 4, 5, 3)    \
-    X(15, 256, 256, 32, 2, 2, 5, 1)
+    X(15, 256, 256, 32, 2, 2, 5, 1)    \
+    X(16, 256, 256, 32, 2, 4, 5, 10)
 
-bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 15; }
+bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 16; }
 
 int gemm_direct_max_ld() { return kDlMaxLd; }
 
 // BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
 // grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel;
-// v9-v15 k_gemm_bf16_dl.
+// v9-v16 k_gemm_bf16_dl.
 #define SYM_BF16_BIG_VARIANTS(X)              \
     X(0, 256, 256, 64, 2, 2, 1, 4)            \
     X(1, 256, 128, 64, 2, 2, 1, 4)            \
@@ -1359,10 +1397,11 @@ const GemmVariant kBF16Variants[] = {{256, 256, "k_gemm_bf16_big 256x256 k64 4w"
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio interleaved"},
-                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"}};
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved paired"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 4 : 16; }
+int gemm_num_variants(int compute) { return compute == 0 ? 4 : 17; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
 // FP32: 128x128 by default; 256x128 (two waves per SIMD, each 128 x 64)
 // ran the FP32 batch 4 % faster and config 4's smaller sectors 11 % slower,
@@ -1370,11 +1409,15 @@ GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variant
 // Defaults from measurements on MI355X.  256x256 tiles (operand re-reads
 // beyond L2 fall with the tile size: 128x128 ran the 64-member batch at 377
 // TFLOP/s) with 8 waves, two per SIMD, fed by direct loads through a
-// five-stage LDS ring: 990 to 1024 TFLOP/s on the batch and about 1190 on
+// five-stage LDS ring: 990 to 1060 TFLOP/s on the batch and about 1190 on
 // one 8192^3 product, against 901 on the batch for the register-staged
-// 256x256 kernel on the same GPU.  The ranking of the 256x256 variants
-// moved from one MI355X to another, which is what the autotuner is for.
-int gemm_default_variant(int compute) { return compute == 0 ? 0 : 10; }
+// 256x256 kernel on the same GPU.  With one barrier per two K slices and
+// the fragment reads interleaved with the MFMAs (variant 16) the batch ran
+// at 1031 to 1041 TFLOP/s in five alternating rounds, where the same
+// kernel with a barrier per slice ranged from 979 to 1055 (median 995).
+// The ranking of the 256x256 variants moved from one MI355X to another,
+// which is what the autotuner is for.
+int gemm_default_variant(int compute) { return compute == 0 ? 0 : 16; }
 int gemm_default_variant_wide(int compute) { return compute == 0 ? 0 : 5; }
 
 const char* gemm_variant_kernel(int compute, int variant) {
