@@ -1983,7 +1983,8 @@ __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __
 #pragma unroll
                 for (int i = 0; i < NB; ++i)
                     if (i < n) y = fma(cf[f * n + i], static_cast<double>(xs[u][i]), y);
-                dst[ob[f].off + (g.same_out ? ro0 : rel(ob[f], t))] = static_cast<float>(y);
+                // streaming store: the output is not read again by this kernel
+                __builtin_nontemporal_store(static_cast<float>(y), &dst[ob[f].off + (g.same_out ? ro0 : rel(ob[f], t))]);
             }
         }
     }

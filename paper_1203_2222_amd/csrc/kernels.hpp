@@ -12,7 +12,7 @@ constexpr int kMaxCopyDims = 6;     // dims of a coalesced block copy
 constexpr int kMaxRecouple = 32;    // blocks of one label tuple on either side of a recoupling
 constexpr int kMaxRecoupleTiled = 16;   // the same for the LDS-tiled kernel (its LDS tables scale with it)
 constexpr int kMaxRecoupleRank = 8;
-constexpr int kRecoupleChunk = 4096;   // elements of one label tuple per workgroup task
+constexpr int kRecoupleChunk = 16384;  // elements of one label tuple per workgroup task
 
 // Base pointers of one launch, passed by value as a kernel argument.
 struct PtrTable {
