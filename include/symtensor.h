@@ -481,8 +481,8 @@ int32_t sym_default_variant(int32_t compute, int32_t* variant);
  * no columns skipped): U_s row-major M_s x k_s, s_s k_s values, Vt_s row-major
  * k_s x N_s; sym_svd_sizes gives their element counts.  One-sided Jacobi with
  * plane rotations, all sectors together, until a sweep rotates nothing
- * (for every pair, |a.b| <= 1e-15 |a||b| or |a.b| below 1e-30 of the
- * sector's squared Frobenius norm) or max_sweeps sweeps; sweeps (host,
+ * (for every pair of vectors of length L, |a.b| <= sqrt(L) 2^-53 |a||b|
+ * or |a.b| below 1e-30 of the sector's squared Frobenius norm) or max_sweeps sweeps; sweeps (host,
  * may be NULL) receives the number run.  The call synchronises `stream` once
  * per sweep (the stopping decision is taken on the host).  Singular vectors
  * of zero singular values are returned as zeros.  SYM_E_UNSUPPORTED for a

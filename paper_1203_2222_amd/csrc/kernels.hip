@@ -1569,7 +1569,7 @@ __global__ __launch_bounds__(256) void k_svd_load(const Ti* __restrict__ src, co
 // The vectors are read twice and written once per round instead of once per
 // scalar round, and a sweep has nb - 1 rounds instead of k - 1.  The sweep
 // counts as converged for the pair when the Jacobi sweep on G finds
-// every off-diagonal entry below 1e-15 of the geometric mean of its diagonal
+// every off-diagonal entry below sqrt(L) 2^-53 of the geometric mean of its diagonal
 // entries (the one-sided method's test).  Vectors past k are zero and are
 // never written.
 // A round is two launches over (block pair, slice), with kSvdSlices slices of
@@ -1622,6 +1622,11 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
     // 1e-15 of the largest, and vectors that tend to zero (rank deficiency)
     // would otherwise keep rotating on rounding noise
     const double floor_abs = 1e-30 * scale[lo];
+    // a pair counts as orthogonal once |g_pq| <= sqrt(L) u sqrt(g_pp g_qq)
+    // (u = 2^-53, the unit roundoff): the rounding error of an inner product
+    // of length L grows like sqrt(L) u, the one-sided Jacobi stopping rule of
+    // Drmac and Veselic (the threshold LAPACK's dgesvj uses)
+    const double tol_rel = sqrt(static_cast<double>(L)) * 1.1102230246251565e-16;
     // this slice's entries of the vectors (length L) and of the rows of Q
     // (length k), whole chunks each
     auto span = [&](int len, int& a, int& b) {
@@ -1717,7 +1722,7 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
                 const int pp = a < b ? a : b, qq = a < b ? b : a;
                 const double al = G[pp][pp], be = G[qq][qq], ga = G[pp][qq];
                 double c = 1.0, sn = 0.0;
-                if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(fabs(al * be)) && fabs(ga) > floor_abs) {
+                if (ga != 0.0 && fabs(ga) > tol_rel * sqrt(fabs(al * be)) && fabs(ga) > floor_abs) {
                     const double zeta = (be - al) / (2.0 * ga);
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     c = 1.0 / sqrt(1.0 + t * t);
