@@ -1094,9 +1094,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
                                              0x00020000);
 }
 
-__device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, u32x4* lds_window, uint32_t voffset) {
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_window, 16, voffset, 0, 0,
-                                             0);
+__device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, u32x4* lds_window, uint32_t voffset,
+                                            uint32_t soffset = 0) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_window, 16, voffset,
+                                             static_cast<int>(soffset), 0, 0);
 }
 
 // s_waitcnt immediate that waits until at most n vector memory operations of
@@ -1105,7 +1106,10 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
 
 // OPT bit 0: raise the wave's issue priority while it issues MFMAs; bit 1:
 // interleave the next step's fragment reads with the MFMAs one by one; bit
-// 3: one barrier per two K slices (five stages).
+// 3: one barrier per two K slices (five stages); bit 5: a slice that lies
+// wholly inside the padded rows is loaded with the per-lane offsets of the
+// tile's first slice and the slice's K offset as a scalar offset (no
+// per-load vector arithmetic).
 template <int MT, int NT, int KT, int WGM, int WGN, int ST, int OPT>
 __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmProb* __restrict__ probs,
                                                                     const GemmTile* __restrict__ tiles, int n_tiles,
@@ -1178,6 +1182,17 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmPr
         auto issue = [&](int kt, int stage) {
             const int k0 = kt * KT;
             const bool live = kt < nk;
+            if constexpr ((OPT & 32) != 0) {
+                // uniform: every chunk of the slice is inside the padded rows
+                if (live && k0 + KT <= p.lda && k0 + KT <= p.ldb) {
+                    const uint32_t so = 2u * static_cast<uint32_t>(k0);
+#pragma unroll
+                    for (int i = 0; i < AV; ++i) load_to_lds(ra, As + stage * SA + i * NTHR + wave * 64, a_vo[i], so);
+#pragma unroll
+                    for (int i = 0; i < BV; ++i) load_to_lds(rb, Bs + stage * SB + i * NTHR + wave * 64, b_vo[i], so);
+                    return;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < AV; ++i) {
                 const uint32_t vo = (live && k0 + a_col[i] < p.lda) ? a_vo[i] + 2u * k0 : 0x80000000u;
@@ -1359,15 +1374,16 @@ int occupancy_dl() {
     X(13, 256, 256, 32, 2, 4, 5, 2)    \
     X(14, 256, 256, 32, 2, 4, 5, 3)    \
     X(15, 256, 256, 32, 2, 2, 5, 1)    \
-    X(16, 256, 256, 32, 2, 4, 5, 10)
+    X(16, 256, 256, 32, 2, 4, 5, 10)   \
+    X(17, 256, 256, 32, 2, 4, 5, 42)
 
-bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 16; }
+bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 17; }
 
 int gemm_direct_max_ld() { return kDlMaxLd; }
 
 // BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
 // grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel;
-// v9-v16 k_gemm_bf16_dl.
+// v9-v17 k_gemm_bf16_dl.
 #define SYM_BF16_BIG_VARIANTS(X)              \
     X(0, 256, 256, 64, 2, 2, 1, 4)            \
     X(1, 256, 128, 64, 2, 2, 1, 4)            \
@@ -1398,10 +1414,11 @@ const GemmVariant kBF16Variants[] = {{256, 256, "k_gemm_bf16_big 256x256 k64 4w"
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio interleaved"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"},
-                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved paired"}};
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved paired"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved paired soffset"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 4 : 17; }
+int gemm_num_variants(int compute) { return compute == 0 ? 4 : 18; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
 // FP32: 128x128 by default; 256x128 (two waves per SIMD, each 128 x 64)
 // ran the FP32 batch 4 % faster and config 4's smaller sectors 11 % slower,
@@ -1415,9 +1432,12 @@ GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variant
 // the fragment reads interleaved with the MFMAs (variant 16) the batch ran
 // at 1031 to 1041 TFLOP/s in five alternating rounds, where the same
 // kernel with a barrier per slice ranged from 979 to 1055 (median 995).
+// Loading the slices that lie wholly inside the padded rows with a scalar K
+// offset (variant 17: no per-load vector arithmetic) took the batch from
+// 50.97 to 50.07 ms (median of six alternating rounds, bitwise equal).
 // The ranking of the 256x256 variants moved from one MI355X to another,
 // which is what the autotuner is for.
-int gemm_default_variant(int compute) { return compute == 0 ? 0 : 16; }
+int gemm_default_variant(int compute) { return compute == 0 ? 0 : 17; }
 int gemm_default_variant_wide(int compute) { return compute == 0 ? 0 : 5; }
 
 const char* gemm_variant_kernel(int compute, int variant) {
