@@ -2015,11 +2015,18 @@ __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __
     }
 }
 
-__global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks,
-                                                  const FmBlk* __restrict__ out_blks, const double* __restrict__ coef,
-                                                  const FmTask* __restrict__ tasks, PtrTable bufs, int in_buf,
-                                                  int out_buf) {
-    __shared__ double cf[kMaxRecouple * kMaxRecouple];
+// NBMAX: the largest n (blocks per label tuple) the instance takes.  The
+// plan launches tuples of at most kRecoupleSmallN blocks (93 % of config 5's
+// output elements) through an instance held to 64 VGPRs, eight waves per
+// SIMD: the kernel is bound by memory latency, and its small-n paths need
+// few registers, while one kernel for every n takes the register count of
+// its n = 32 path (112 VGPRs, four waves per SIMD).  The larger tuples go
+// through the general instance.
+template <int NBMAX>
+__global__ __launch_bounds__(256, NBMAX <= kRecoupleSmallN ? 8 : 1) void k_recouple(
+    const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks, const FmBlk* __restrict__ out_blks,
+    const double* __restrict__ coef, const FmTask* __restrict__ tasks, PtrTable bufs, int in_buf, int out_buf) {
+    __shared__ double cf[NBMAX * NBMAX];
     const FmTask t = tasks[blockIdx.x];
     const FmGroup& g = groups[t.group];
     for (int k = threadIdx.x; k < g.n * g.n; k += 256) cf[k] = coef[g.coef_first + k];
@@ -2036,7 +2043,7 @@ __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ gr
         else if (n <= 4) recouple_elems<4, 4>(g, ib, ob, cf, src, dst, t.start, end);
         else if (n <= 8) recouple_elems<8, 4>(g, ib, ob, cf, src, dst, t.start, end);
         else if (n <= 16) recouple_elems<16, 4>(g, ib, ob, cf, src, dst, t.start, end);
-        else recouple_elems<kMaxRecouple, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        else if constexpr (NBMAX > 16) recouple_elems<kMaxRecouple, 4>(g, ib, ob, cf, src, dst, t.start, end);
         return;
     }
     constexpr int RG = kMaxRecoupleRank;
@@ -2045,7 +2052,7 @@ __global__ __launch_bounds__(256) void k_recouple(const FmGroup* __restrict__ gr
     else if (n <= 4) recouple_elems<4, RG>(g, ib, ob, cf, src, dst, t.start, end);
     else if (n <= 8) recouple_elems<8, RG>(g, ib, ob, cf, src, dst, t.start, end);
     else if (n <= 16) recouple_elems<16, RG>(g, ib, ob, cf, src, dst, t.start, end);
-    else recouple_elems<kMaxRecouple, RG>(g, ib, ob, cf, src, dst, t.start, end);
+    else if constexpr (NBMAX > 16) recouple_elems<kMaxRecouple, RG>(g, ib, ob, cf, src, dst, t.start, end);
 }
 
 // LDS-tiled K9 (see FtGroup): a workgroup moves one box of all n input
@@ -2082,17 +2089,18 @@ __device__ __forceinline__ void recouple_combine(const float* __restrict__ tile,
     }
 }
 
-__global__ __launch_bounds__(256) void k_recouple_tiled(const FtGroup* __restrict__ groups,
-                                                        const FmBlk* __restrict__ in_blks,
-                                                        const FmBlk* __restrict__ out_blks,
-                                                        const double* __restrict__ coef,
-                                                        const FtTask* __restrict__ tasks, PtrTable bufs, int in_buf,
-                                                        int out_buf) {
+// NBMAX: the largest n the instance takes; tuples of at most
+// kRecoupleTiledSmallN blocks run in an instance held to eight waves per
+// SIMD (like the element-wise kernel, this one waits on memory latency)
+template <int NBMAX>
+__global__ __launch_bounds__(256, NBMAX <= kRecoupleTiledSmallN ? 8 : 1) void k_recouple_tiled(
+    const FtGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks, const FmBlk* __restrict__ out_blks,
+    const double* __restrict__ coef, const FtTask* __restrict__ tasks, PtrTable bufs, int in_buf, int out_buf) {
     constexpr int U = 16;
     __shared__ float tile[kFtElems];
-    __shared__ double cf[kMaxRecoupleTiled * kMaxRecoupleTiled];
-    __shared__ int64_t ibase[kMaxRecoupleTiled], obase[kMaxRecoupleTiled];
-    __shared__ int32_t istr[kMaxRecoupleTiled][3], ostr[kMaxRecoupleTiled][3];
+    __shared__ double cf[NBMAX * NBMAX];
+    __shared__ int64_t ibase[NBMAX], obase[NBMAX];
+    __shared__ int32_t istr[NBMAX][3], ostr[NBMAX][3];
     const FtTask t = tasks[blockIdx.x];
     const FtGroup& g = groups[t.group];
     const int n = g.n;
@@ -2162,27 +2170,42 @@ __global__ __launch_bounds__(256) void k_recouple_tiled(const FtGroup* __restric
         recouple_combine<2>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else if (n <= 4)
         recouple_combine<4>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
-    else if (n <= 8)
-        recouple_combine<8>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
-    else
-        recouple_combine<kMaxRecoupleTiled>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+    else if constexpr (NBMAX > 4) {
+        if (n <= 8)
+            recouple_combine<8>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+        else
+            recouple_combine<kMaxRecoupleTiled>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1,
+                                                s1);
+    }
 }
 
 hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
-                                 const FtTask* tasks, int32_t n_tasks, const PtrTable& bufs, int32_t in_buf,
-                                 int32_t out_buf, hipStream_t s) {
-    if (n_tasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_recouple_tiled, dim3(static_cast<unsigned>(n_tasks)), dim3(256), 0, s, groups, in_blks,
-                       out_blks, coef, tasks, bufs, in_buf, out_buf);
+                                 const FtTask* tasks, int32_t n_small, int32_t n_tasks, const PtrTable& bufs,
+                                 int32_t in_buf, int32_t out_buf, hipStream_t s) {
+    if (n_small > 0) {
+        hipLaunchKernelGGL(k_recouple_tiled<kRecoupleTiledSmallN>, dim3(static_cast<unsigned>(n_small)), dim3(256), 0,
+                           s, groups, in_blks, out_blks, coef, tasks, bufs, in_buf, out_buf);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_tasks > n_small)
+        hipLaunchKernelGGL(k_recouple_tiled<kMaxRecoupleTiled>, dim3(static_cast<unsigned>(n_tasks - n_small)),
+                           dim3(256), 0, s, groups, in_blks, out_blks, coef, tasks + n_small, bufs, in_buf, out_buf);
     return hipGetLastError();
 }
 
 hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
-                           const FmTask* tasks, int32_t n_tasks, const PtrTable& bufs, int32_t in_buf, int32_t out_buf,
-                           hipStream_t s) {
-    if (n_tasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_recouple, dim3(static_cast<unsigned>(n_tasks)), dim3(256), 0, s, groups, in_blks, out_blks, coef,
-                       tasks, bufs, in_buf, out_buf);
+                           const FmTask* tasks, int32_t n_small, int32_t n_tasks, const PtrTable& bufs,
+                           int32_t in_buf, int32_t out_buf, hipStream_t s) {
+    if (n_small > 0) {
+        hipLaunchKernelGGL(k_recouple<kRecoupleSmallN>, dim3(static_cast<unsigned>(n_small)), dim3(256), 0, s, groups,
+                           in_blks, out_blks, coef, tasks, bufs, in_buf, out_buf);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_tasks > n_small)
+        hipLaunchKernelGGL(k_recouple<kMaxRecouple>, dim3(static_cast<unsigned>(n_tasks - n_small)), dim3(256), 0, s,
+                           groups, in_blks, out_blks, coef, tasks + n_small, bufs, in_buf, out_buf);
     return hipGetLastError();
 }
 

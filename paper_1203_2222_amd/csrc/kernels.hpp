@@ -13,6 +13,7 @@ constexpr int kMaxRecouple = 32;    // blocks of one label tuple on either side 
 constexpr int kMaxRecoupleTiled = 16;   // the same for the LDS-tiled kernel (its LDS tables scale with it)
 constexpr int kMaxRecoupleRank = 8;
 constexpr int kRecoupleChunk = 16384;  // elements of one label tuple per workgroup task
+constexpr int kRecoupleSmallN = 16;   // label tuples of at most this many blocks take the high-occupancy kernel
 
 // Base pointers of one launch, passed by value as a kernel argument.
 struct PtrTable {
@@ -145,7 +146,8 @@ struct FmTask {
 // stride (ld[0], then ld[1], then ld[2]: slots 1..3), so that consecutive
 // lanes read consecutive input addresses; the combination and the stores
 // walk it in output order.
-constexpr int kFtElems = 8192;   // floats of one tile over all n blocks (32 KB of LDS)
+constexpr int kFtElems = 4096;   // floats of one tile over all n blocks (16 KB of LDS)
+constexpr int kRecoupleTiledSmallN = 4;   // tuples of at most this many blocks take the high-occupancy tiled kernel
 struct FtGroup {
     int32_t n;
     int32_t dim[4];      // output block dims, output-axis order
@@ -202,13 +204,16 @@ hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops,
 hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles,
                        int32_t n_tiles, int32_t grid, const EpiRow* rows, const EpiCol* cols,
                        const PtrTable& bufs, hipStream_t s);
+// tasks[0, n_small) belong to tuples of at most kRecoupleTiledSmallN blocks
 hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
-                                 const double* coef, const FtTask* tasks, int32_t n_tasks, const PtrTable& bufs,
-                                 int32_t in_buf, int32_t out_buf, hipStream_t s);
+                                 const double* coef, const FtTask* tasks, int32_t n_small, int32_t n_tasks,
+                                 const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);
 hipError_t launch_contract_small(const SmallTask* tasks, int32_t n_tasks, const SmallPair* pairs,
                                  const PtrTable& bufs, hipStream_t s);
+// tasks[0, n_small) belong to label tuples of at most kRecoupleSmallN blocks,
+// tasks[n_small, n_tasks) to larger ones
 hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
-                           const double* coef, const FmTask* tasks, int32_t n_tasks,
+                           const double* coef, const FmTask* tasks, int32_t n_small, int32_t n_tasks,
                            const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);
 
 // Tile shape of a GEMM variant (rows x cols of C per workgroup).

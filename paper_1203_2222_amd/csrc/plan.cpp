@@ -948,6 +948,11 @@ void RecoupleProgram::build_fuse(const Desc& unf, const Desc& fus, int leg, bool
 }
 
 void RecoupleProgram::upload(const Allocator& alloc, Deferred* deferred) {
+    // the tasks of small tuples first: they run in the high-occupancy kernel
+    auto small = [&](const FmTask& t) { return groups[static_cast<size_t>(t.group)].n <= kRecoupleSmallN; };
+    n_small = static_cast<int32_t>(std::stable_partition(tasks.begin(), tasks.end(), small) - tasks.begin());
+    auto tsmall = [&](const FtTask& t) { return tgroups[static_cast<size_t>(t.group)].n <= kRecoupleTiledSmallN; };
+    n_tsmall = static_cast<int32_t>(std::stable_partition(ttasks.begin(), ttasks.end(), tsmall) - ttasks.begin());
     d_groups = upload_vec(alloc, groups, deferred);
     d_in = upload_vec(alloc, in_blks, deferred);
     d_out = upload_vec(alloc, out_blks, deferred);
@@ -962,12 +967,12 @@ hipError_t RecoupleProgram::launch(const PtrTable& bufs, int in_buf, int out_buf
     if (tiled)
         return launch_recouple_tiled(static_cast<const FtGroup*>(d_tgroups->ptr), static_cast<const FmBlk*>(d_in->ptr),
                                      static_cast<const FmBlk*>(d_out->ptr), static_cast<const double*>(d_coef->ptr),
-                                     static_cast<const FtTask*>(d_ttasks->ptr), static_cast<int32_t>(ttasks.size()),
-                                     bufs, in_buf, out_buf, s);
+                                     static_cast<const FtTask*>(d_ttasks->ptr), n_tsmall,
+                                     static_cast<int32_t>(ttasks.size()), bufs, in_buf, out_buf, s);
     return launch_recouple(static_cast<const FmGroup*>(d_groups->ptr), static_cast<const FmBlk*>(d_in->ptr),
                            static_cast<const FmBlk*>(d_out->ptr), static_cast<const double*>(d_coef->ptr),
-                           static_cast<const FmTask*>(d_tasks->ptr), static_cast<int32_t>(tasks.size()), bufs, in_buf,
-                           out_buf, s);
+                           static_cast<const FmTask*>(d_tasks->ptr), n_small, static_cast<int32_t>(tasks.size()), bufs,
+                           in_buf, out_buf, s);
 }
 
 }  // namespace sym
