@@ -70,6 +70,25 @@ def test_su2_permute_rank5_6_matches_projection(ctx, legs, arrows, perm, arrows_
     assert rel_err(_canonical(ctx, out), ref) <= 1e-6
 
 
+@pytest.mark.parametrize("perm,arrows_out", [
+    ((1, 0, 2, 4, 3, 5), ("in", "in", "in", "out", "out", "out")),
+    ((2, 0, 1, 3, 4, 5), ("in", "out", "in", "out", "in", "out")),
+])
+def test_su2_permute_label_tuple_of_20_blocks(ctx, perm, arrows_out):
+    # six legs of spins 1/2 and 3/2: one label tuple has 20 blocks (20
+    # chains of intermediate spins), more than the high-occupancy recoupling
+    # instance takes, so its tasks run in the general one
+    from collections import Counter
+    say(f"case su2_permute rank 6 tuple of 20 blocks perm {perm}")
+    h, hq = ((1,), (2,)), ((1, 3), (2, 1))
+    spec = _spec([h, hq, hq, hq, hq, hq], ("in", "in", "in", "out", "out", "out"))
+    assert max(Counter(b.labels for b in T.blocks(spec)).values()) == 20
+    t, flat = _tensor(ctx, spec, 23)
+    out = ctx.su2_permute(t, perm, list(arrows_out), 0)
+    _, ref = RC.permute_chain(spec, flat, list(perm), list(arrows_out))
+    assert rel_err(_canonical(ctx, out), ref) <= 1e-6
+
+
 @pytest.mark.parametrize("legs,arrows,leg,n_row", [
     ([HALF, INT, HALF, WHOLE], ("in", "in", "in", "out"), 0, 0),      # first two of the chain: relabelling
     ([HALF, INT, HALF, WHOLE], ("in", "in", "in", "out"), 1, 0),      # inside the chain: one F-move

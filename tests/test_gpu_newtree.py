@@ -59,6 +59,25 @@ def test_permute_tree_matches_oracle(ctx, tree, perm, tree_out, n_in, n_out, deg
     np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-12 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("tree,perm,tree_out", [(OP, (3, 2, 1, 0), LEFT), (LEFT, (0, 1, 3, 2), RIGHT)])
+def test_permute_tree_label_tuples_of_five_blocks(ctx, tree, perm, tree_out):
+    # spins up to 2: label tuples of up to five blocks, so the LDS-tiled
+    # recoupling (the last leg moves) runs both its instances, the one for
+    # tuples of at most four blocks and the general one
+    say(f"case permute_tree spins to 2 {tree}->{tree_out} perm {perm}")
+    spec = W.TensorSpec(W.SU2, tuple(W.su2_leg(4, [2, 2, 1, 1, 1], a) for a in ARROWS[tree]), tree=tree)
+    from collections import Counter
+    assert max(Counter(b.labels for b in T.blocks(spec)).values()) == 5
+    g = W.generator(53, "cuda")
+    a = draw(spec, g)
+    A = ctx.tensor(spec, 4, data=a)
+    R = ctx.permute_tree(A, perm, tree_out, 4)
+    got = host(R)
+    _, ref, _ = RC.permute_tree(spec, a.double().cpu().numpy(), perm, tree_out)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-12 * np.abs(ref).max())
+
+
 def test_reverse_and_back_returns_input(ctx):
     say("case permute_tree reverse round trip")
     spec = _spec(OP, 3, [4, 3, 2, 2])
