@@ -454,9 +454,13 @@ int32_t sym_ctx_phase_ms(sym_ctx* ctx, int32_t phase, float* ms);
  * autotuner's entry point (at most 64 contractions): the plan of this
  * contraction is built once and run once (its fused operands written); each
  * compiled tile variant then gets its own tile list over the same plan and
- * one timed GEMM launch, those within 8 % of the fastest three more, and
- * the smallest sum wins.  The winner becomes the cached plan of the structure
- * (also written to the file named by SYM_TUNE_CACHE, when set).  Writes C. */
+ * one timed GEMM launch, those within 8 % of the fastest (and the default)
+ * three more, taken round-robin, and the smallest sum wins unless the
+ * default variant is within 1 % of it.  When the default variant's tile
+ * list has at least eight tiles per CU, variants whose tiles cover a
+ * quarter of the default's area or less are not timed.  The winner becomes
+ * the cached plan of the structure (also written to the file named by
+ * SYM_TUNE_CACHE, when set).  Writes C. */
 int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A,
                          const sym_tensor* const* B, int32_t n, const int32_t* axesA,
                          const int32_t* axesB, int32_t compute, sym_tensor* const* C, void* stream,

@@ -1875,7 +1875,19 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
         const int nv = gemm_num_variants(compute);
         std::vector<std::shared_ptr<ContractPlan>> cand(static_cast<size_t>(nv));
         Allocator alloc = ctx->allocator();
+        // With at least eight tiles of the default variant per CU there is
+        // parallelism enough for the large tiles, and tiles of a quarter of
+        // their area or less only re-read the operands more often (on the
+        // 64-member batch the 128 x 128 and 64 x 64 kernels ran 2.8 and 5.5
+        // times slower): those are not timed.
+        const GemmVariant dv = gemm_variant(compute, gemm_default_variant(compute));
+        const bool big = static_cast<int64_t>(base->gemm.tiles.size()) >= 8LL * ctx->cus();
+        auto skipped = [&](int v) {
+            const GemmVariant gv = gemm_variant(compute, v);
+            return big && 4LL * gv.mt * gv.nt <= static_cast<int64_t>(dv.mt) * dv.nt;
+        };
         for (int v = 0; v < nv; ++v) {
+            if (skipped(v)) continue;
             auto c = std::make_shared<ContractPlan>(*base);
             c->requested_variant = v;
             c->grid = ctx->cus() * gemm_blocks_per_cu(compute, v);
@@ -1900,14 +1912,15 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
         // The smallest sum of round-2 times wins, unless the default variant
         // is within 1 % of it: the default then stays.
         std::vector<float> first(static_cast<size_t>(nv));
-        float fastest = 0.f;
+        float fastest = -1.f;
         for (int v = 0; v < nv; ++v) {
+            if (!cand[static_cast<size_t>(v)]) continue;
             first[static_cast<size_t>(v)] = time_gemm(*cand[static_cast<size_t>(v)]);
-            if (v == 0 || first[static_cast<size_t>(v)] < fastest) fastest = first[static_cast<size_t>(v)];
+            if (fastest < 0.f || first[static_cast<size_t>(v)] < fastest) fastest = first[static_cast<size_t>(v)];
         }
         std::vector<int> keep;
         for (int v = 0; v < nv; ++v)
-            if (first[static_cast<size_t>(v)] <= 1.08f * fastest) keep.push_back(v);
+            if (cand[static_cast<size_t>(v)] && first[static_cast<size_t>(v)] <= 1.08f * fastest) keep.push_back(v);
         const int def = gemm_default_variant(compute);
         if (std::find(keep.begin(), keep.end(), def) == keep.end()) keep.push_back(def);
         std::vector<float> total(static_cast<size_t>(nv), 0.f);
