@@ -485,12 +485,14 @@ def secondary(ctx, stream, with_cpu=True):
     return out
 
 
-def literal_prefix(ctx, stream, variant, margin_bytes=8 << 30):
+def literal_prefix(ctx, stream, margin_bytes=8 << 30):
     """The batched workload with its drawn per-index dimensions taken
     literally ({64,128,256,512}, no halving): the longest prefix of the
     members, in draw order, whose operands, fused operands, outputs and split
     workspaces fit the free device memory.  One BF16 step of that prefix
-    (plan built and graph captured first), the GEMM's share and fraction."""
+    (plan built and autotuned on this batch, graph captured first), the
+    GEMM's share and fraction.  The prefix is tuned on its own: the tile
+    variant that wins on the halved batch is not the one that wins here."""
     import torch
     import paper_1203_2222_amd as P
     import workloads as W
@@ -521,17 +523,13 @@ def literal_prefix(ctx, stream, variant, margin_bytes=8 << 30):
     Cs = build_outputs(ctx, chosen, As, Bs)
     axes = (chosen[0].axes_a, chosen[0].axes_b)
     flops = sum(ctx.flops(a, b, *axes) for a, b in zip(As, Bs))
-    ctx.set_variant("bf16", variant)
-    try:
-        with torch.cuda.stream(stream):
-            t0 = time.perf_counter()
-            ctx.contract_batched(As, Bs, axes[0], axes[1], "bf16", Cs, stream)
-            torch.cuda.synchronize()
-            first_s = time.perf_counter() - t0
-            _, med, mean = time_graph(ctx, As, Bs, Cs, axes, "bf16", 3, 1, stream)
-            ph = time_phases(ctx, As, Bs, Cs, axes, "bf16", 3, stream)
-    finally:
-        ctx.set_variant("bf16", -1)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        variant = ctx.tune_batched(As, Bs, axes[0], axes[1], "bf16", Cs, stream)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
+        _, med, mean = time_graph(ctx, As, Bs, Cs, axes, "bf16", 3, 1, stream)
+        ph = time_phases(ctx, As, Bs, Cs, axes, "bf16", 3, stream)
     used = torch.cuda.max_memory_allocated()
     res = {
         "members": len(chosen), "chi": [m.extra["chi"] for m in chosen],
@@ -541,8 +539,8 @@ def literal_prefix(ctx, stream, variant, margin_bytes=8 << 30):
         "phases_ms": {"fuse": round(ph[0], 3), "gemm": round(ph[1], 3), "split": round(ph[2], 3)},
         "gemm_TFLOPs": round(flops / ph[1] / 1e9, 2),
         "gemm_frac_bf16_peak": round(flops / ph[1] / 1e9 / PEAK_TFLOPS["bf16"], 4),
-        "first_call_s": round(first_s, 2), "peak_device_bytes": int(used),
-        "gemm_variant": {"index": variant, "name": P.variant_name("bf16", variant)},
+        "plan_and_tune_s": round(tune_s, 2), "peak_device_bytes": int(used),
+        "gemm_variant": {"index": variant, "name": P.variant_name("bf16", variant), "autotuned": True},
         "what": "longest draw-order prefix of the batch with chi in {64,128,256,512} that fits the device; "
                 "outputs of 2^29 entries or more take the separate split pass; inputs are BF16 draws made in "
                 "slices (not the unsliced stream of the tests)",
@@ -858,7 +856,7 @@ def main():
     if not args.no_literal:
         log("literal-dimension prefix of the batch")
         try:
-            result["literal_chi_prefix"] = literal_prefix(ctx, stream, variant)
+            result["literal_chi_prefix"] = literal_prefix(ctx, stream)
         except (RuntimeError, torch.cuda.OutOfMemoryError) as e:   # reported, not fatal
             result["literal_chi_prefix"] = {"error": str(e)[:300]}
             ctx.clear()
