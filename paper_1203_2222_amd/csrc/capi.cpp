@@ -1897,7 +1897,12 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             up.finish(s);
             cand[static_cast<size_t>(v)] = c;
         }
+        // each GEMM launch is timed right after the plan's fuse, as in the
+        // step it serves: on the batch, kernels that ranked first on operands
+        // written long before ran up to 4 ms slower right after the fuse
         auto time_gemm = [&](const ContractPlan& c) {
+            for (const auto& f : base->fuse) HIP_CHECK(f.launch(t, s));
+            for (const auto& r : base->rc_pre) HIP_CHECK(r.prog.launch(t, r.in_slot, r.out_slot, s));
             HIP_CHECK(hipEventRecord(ctx->ev[1], s));
             HIP_CHECK(c.gemm.launch(t, c.grid, s));
             HIP_CHECK(hipEventRecord(ctx->ev[2], s));

@@ -1434,10 +1434,16 @@ GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variant
 // kernel with a barrier per slice ranged from 979 to 1055 (median 995).
 // Loading the slices that lie wholly inside the padded rows with a scalar K
 // offset (variant 17: no per-load vector arithmetic) took the batch from
-// 50.97 to 50.07 ms (median of six alternating rounds, bitwise equal).
-// The ranking of the 256x256 variants moved from one MI355X to another,
-// which is what the autotuner is for.
-int gemm_default_variant(int compute) { return compute == 0 ? 0 : 17; }
+// 50.97 to 50.07 ms (median of six alternating rounds, bitwise equal), but
+// ran the GEMM of the literal-dimension prefix (sectors up to about 26000)
+// at 708 to 767 ms against 590 to 654 for the per-lane-offset kernels.  The
+// default is the interleaved kernel with raised MFMA priority and a barrier
+// per slice (variant 14): on one MI355X, alternating, it ran the batch at
+// 54.0 ms against 55.1 (17), 55.7 (16) and 56.3 (paired with priority),
+// and the prefix at 590 ms against 625 and 652.  The ranking of the 256x256
+// variants moves from one MI355X to another, which is what the autotuner
+// is for.
+int gemm_default_variant(int compute) { return compute == 0 ? 0 : 14; }
 int gemm_default_variant_wide(int compute) { return compute == 0 ? 0 : 5; }
 
 const char* gemm_variant_kernel(int compute, int variant) {
