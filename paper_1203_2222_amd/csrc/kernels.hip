@@ -1109,7 +1109,8 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
 // 3: one barrier per two K slices (five stages); bit 5: a slice that lies
 // wholly inside the padded rows is loaded with the per-lane offsets of the
 // tile's first slice and the slice's K offset as a scalar offset (no
-// per-load vector arithmetic).
+// per-load vector arithmetic); bit 6: the same slices with the K offset
+// added to each lane's offset (one add per load, no range tests).
 template <int MT, int NT, int KT, int WGM, int WGN, int ST, int OPT>
 __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmProb* __restrict__ probs,
                                                                     const GemmTile* __restrict__ tiles, int n_tiles,
@@ -1190,6 +1191,17 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_gemm_bf16_dl(const GemmPr
                     for (int i = 0; i < AV; ++i) load_to_lds(ra, As + stage * SA + i * NTHR + wave * 64, a_vo[i], so);
 #pragma unroll
                     for (int i = 0; i < BV; ++i) load_to_lds(rb, Bs + stage * SB + i * NTHR + wave * 64, b_vo[i], so);
+                    return;
+                }
+            }
+            if constexpr ((OPT & 64) != 0) {
+                // the same test, the K offset added to each lane's offset
+                if (live && k0 + KT <= p.lda && k0 + KT <= p.ldb) {
+                    const uint32_t so = 2u * static_cast<uint32_t>(k0);
+#pragma unroll
+                    for (int i = 0; i < AV; ++i) load_to_lds(ra, As + stage * SA + i * NTHR + wave * 64, a_vo[i] + so);
+#pragma unroll
+                    for (int i = 0; i < BV; ++i) load_to_lds(rb, Bs + stage * SB + i * NTHR + wave * 64, b_vo[i] + so);
                     return;
                 }
             }
@@ -1375,15 +1387,16 @@ int occupancy_dl() {
     X(14, 256, 256, 32, 2, 4, 5, 3)    \
     X(15, 256, 256, 32, 2, 2, 5, 1)    \
     X(16, 256, 256, 32, 2, 4, 5, 10)   \
-    X(17, 256, 256, 32, 2, 4, 5, 42)
+    X(17, 256, 256, 32, 2, 4, 5, 42)   \
+    X(18, 256, 256, 32, 2, 4, 5, 67)
 
-bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 17; }
+bool gemm_variant_direct(int compute, int variant) { return compute == 1 && variant >= 9 && variant <= 18; }
 
 int gemm_direct_max_ld() { return kDlMaxLd; }
 
 // BF16 variants: v0-v2 and v5-v8 are k_gemm_bf16_big instances (tile, wave
 // grid, residency, LDS-store placement); v3, v4 the K=32 padded-LDS kernel;
-// v9-v17 k_gemm_bf16_dl.
+// v9-v18 k_gemm_bf16_dl.
 #define SYM_BF16_BIG_VARIANTS(X)              \
     X(0, 256, 256, 64, 2, 2, 1, 4)            \
     X(1, 256, 128, 64, 2, 2, 1, 4)            \
@@ -1415,10 +1428,11 @@ const GemmVariant kBF16Variants[] = {{256, 256, "k_gemm_bf16_big 256x256 k64 4w"
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio interleaved"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 4w 5-stage prio"},
                                      {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved paired"},
-                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved paired soffset"}};
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage interleaved paired soffset"},
+                                     {256, 256, "k_gemm_bf16_dl 256x256 k32 8w 5-stage prio interleaved koff"}};
 }  // namespace
 
-int gemm_num_variants(int compute) { return compute == 0 ? 4 : 18; }
+int gemm_num_variants(int compute) { return compute == 0 ? 4 : 19; }
 GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variants[v] : kBF16Variants[v]; }
 // FP32: 128x128 by default; 256x128 (two waves per SIMD, each 128 x 64)
 // ran the FP32 batch 4 % faster and config 4's smaller sectors 11 % slower,
@@ -1440,9 +1454,12 @@ GemmVariant gemm_variant(int compute, int v) { return compute == 0 ? kF32Variant
 // default is the interleaved kernel with raised MFMA priority and a barrier
 // per slice (variant 14): on one MI355X, alternating, it ran the batch at
 // 54.0 ms against 55.1 (17), 55.7 (16) and 56.3 (paired with priority),
-// and the prefix at 590 ms against 625 and 652.  The ranking of the 256x256
-// variants moves from one MI355X to another, which is what the autotuner
-// is for.
+// and the prefix at 590 ms against 625 and 652.  The same kernel with the
+// whole-slice loads' K offset added per lane (variant 18) ran the batch at
+// 51.1 against 53.3 ms on another MI355X but the prefix at 615 against 591
+// ms (the paired kernel with that load path: 774 ms).  The ranking of the
+// 256x256 variants moves from one MI355X to another, which is what the
+// autotuner is for.
 int gemm_default_variant(int compute) { return compute == 0 ? 0 : 14; }
 int gemm_default_variant_wide(int compute) { return compute == 0 ? 0 : 5; }
 
