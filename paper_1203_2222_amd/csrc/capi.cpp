@@ -1867,8 +1867,8 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
         std::string key;
         // One host plan for every variant: only the GEMM's tile list depends
         // on the variant, so each candidate is a copy of the plan (sharing its
-        // workspaces and device tables) with its own tiles.  The fused
-        // operands are written once; then only GEMM launches are timed.
+        // workspaces and device tables) with its own tiles.  The plan runs
+        // once; then only GEMM launches are timed.
         auto base = build_contract_plan(ctx, count, A, B, n, axesA, axesB, compute, C, &key, -1, s);
         run_contract_plan(ctx, *base, A, B, C, s, false);
         const PtrTable t = contract_table(*base, A, B, C);
@@ -1897,9 +1897,9 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             up.finish(s);
             cand[static_cast<size_t>(v)] = c;
         }
-        // each GEMM launch is timed right after the plan's fuse, as in the
-        // step it serves: on the batch, kernels that ranked first on operands
-        // written long before ran up to 4 ms slower right after the fuse
+        // each timed GEMM launch follows the plan's fuse (its time not
+        // counted), so that it meets the caches and the clock the way it
+        // does in the call it serves
         auto time_gemm = [&](const ContractPlan& c) {
             for (const auto& f : base->fuse) HIP_CHECK(f.launch(t, s));
             for (const auto& r : base->rc_pre) HIP_CHECK(r.prog.launch(t, r.in_slot, r.out_slot, s));
