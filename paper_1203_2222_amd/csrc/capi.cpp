@@ -1911,11 +1911,12 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
             return ms;
         };
-        // round 1: one launch each; round 2: three more for the variants
-        // within 8 % of the fastest, taken round-robin so that a drift of the
-        // clock (power and thermal state) weighs on every candidate alike.
-        // The smallest sum of round-2 times wins, unless the default variant
-        // is within 1 % of it: the default then stays.
+        // first pass: one launch each; second pass: three more for the
+        // variants within 8 % of the fastest, taken round-robin so that a
+        // drift of the clock (power and thermal state) weighs on every
+        // candidate alike.  The smallest sum of second-pass times wins,
+        // unless the default variant is within 1 % of it: the default then
+        // stays.
         std::vector<float> first(static_cast<size_t>(nv));
         float fastest = -1.f;
         for (int v = 0; v < nv; ++v) {
