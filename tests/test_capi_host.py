@@ -382,3 +382,24 @@ def test_operand_layout_handles():
     h = c_void_p()
     assert L.lib().sym_contract_operand_output(ctx.handle, X.handle, X.handle, 1, L.i32_array((2,)), L.i32_array((0,)),
                                                L.SYM_F32, 0, None, byref(h)) != 0
+
+
+def test_operand_pitch_of_long_bf16_rows():
+    # BF16 operand rows of 32 KB or more whose length is a multiple of 16 KB
+    # get one more 128-byte line; 16 KB rows and FP32 rows keep their pitch
+    from ctypes import byref, c_void_p
+    from paper_1203_2222_amd import _lib as L
+    from paper_1203_2222_amd.tensor import SymTensor
+    ctx = _ctx()
+    for k, compute, pitch in ((16381, L.SYM_BF16, 16384 + 64), (24576, L.SYM_BF16, 24576 + 64),
+                              (8190, L.SYM_BF16, 8192), (16000, L.SYM_BF16, 16000),
+                              (16381, L.SYM_F32, 16384)):
+        lm, lk, ln = (W.u1_leg(0, 0, [d], "in") for d in (300, k, 200))
+        A = ctx.describe(W.TensorSpec(W.U1, (lm, lk.flipped())), 2)
+        B = ctx.describe(W.TensorSpec(W.U1, (lk, ln.flipped())), 2)
+        for which, rows in ((0, 300), (1, 200)):
+            h = c_void_p()
+            L.check(L.lib().sym_contract_operand_output(ctx.handle, A.handle, B.handle, 1, L.i32_array((1,)),
+                                                        L.i32_array((0,)), compute, which, None, byref(h)))
+            t = SymTensor(ctx, h.value, None, None, 1, compute)
+            assert t.numel() == rows * pitch, (k, compute, which, t.numel())

@@ -328,3 +328,22 @@ def test_operands_in_gemm_layout_are_read_in_place(ctx, compute, axes):
     with pytest.raises(P.SymError) as e:
         ctx.contract(Abad, Bop, *op_axes, compute)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("k", [16381, 8190])
+def test_long_rows_padded_pitch_bf16(ctx, k):
+    # one sector, M = 300 and N = 200 (ragged tiles), K = 16381: the BF16
+    # operand rows pad to 16384 columns, a 32 KB pitch, which the layout
+    # lengthens by one cache line; K = 8190 (a 16 KB pitch) keeps its pitch
+    say(f"case long rows bf16 k={k}")
+    lm, lk, ln = (W.u1_leg(0, 0, [d], W.IN) for d in (300, k, 200))
+    sa = W.TensorSpec(W.U1, (lm, lk.flipped()))
+    sb = W.TensorSpec(W.U1, (lk, ln.flipped()))
+    c = W.Contraction(f"long_rows_k{k}", sa, sb, (1,), (0,), seed=7)
+    fa, fb, fc = _run(ctx, c, "bf16")
+    _, ref = K.contract_sectors(sa, fa, sb, fb, (1,), (0,))
+    err = rel_err(fc, ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= BF16_TOL
+    _, ref16 = K.contract_sectors(sa, bf16_round(fa), sb, bf16_round(fb), (1,), (0,))
+    assert rel_err(fc, ref16) <= 1e-5
