@@ -454,9 +454,9 @@ int32_t sym_ctx_phase_ms(sym_ctx* ctx, int32_t phase, float* ms);
  * autotuner's entry point (at most 64 contractions): the plan of this
  * contraction is built once and run once (its fused operands written); each
  * compiled tile variant then gets its own tile list over the same plan and
- * one timed GEMM launch (each right after the plan's fuse, as in a call),
- * those within 8 % of the fastest (and the default)
- * three more, taken round-robin, and the smallest sum wins unless the
+ * one timed GEMM launch, the (at most five) fastest within 8 % of the
+ * fastest and the default three more, each right after the plan's fuse as
+ * in a call, taken round-robin, and the smallest sum wins unless the
  * default variant is within 1 % of it.  When the default variant's tile
  * list has at least eight tiles per CU, variants whose tiles cover a
  * quarter of the default's area or less are not timed.  The winner becomes

@@ -1897,12 +1897,14 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             up.finish(s);
             cand[static_cast<size_t>(v)] = c;
         }
-        // each timed GEMM launch follows the plan's fuse (its time not
-        // counted), so that it meets the caches and the clock the way it
-        // does in the call it serves
-        auto time_gemm = [&](const ContractPlan& c) {
-            for (const auto& f : base->fuse) HIP_CHECK(f.launch(t, s));
-            for (const auto& r : base->rc_pre) HIP_CHECK(r.prog.launch(t, r.in_slot, r.out_slot, s));
+        // in the second pass each timed GEMM launch follows the plan's fuse
+        // (its time not counted), so that it meets the caches and the clock
+        // the way it does in the call it serves
+        auto time_gemm = [&](const ContractPlan& c, bool after_fuse) {
+            if (after_fuse) {
+                for (const auto& f : base->fuse) HIP_CHECK(f.launch(t, s));
+                for (const auto& r : base->rc_pre) HIP_CHECK(r.prog.launch(t, r.in_slot, r.out_slot, s));
+            }
             HIP_CHECK(hipEventRecord(ctx->ev[1], s));
             HIP_CHECK(c.gemm.launch(t, c.grid, s));
             HIP_CHECK(hipEventRecord(ctx->ev[2], s));
@@ -1911,27 +1913,31 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
             HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
             return ms;
         };
-        // first pass: one launch each; second pass: three more for the
-        // variants within 8 % of the fastest, taken round-robin so that a
-        // drift of the clock (power and thermal state) weighs on every
-        // candidate alike.  The smallest sum of second-pass times wins,
-        // unless the default variant is within 1 % of it: the default then
-        // stays.
+        // first pass: one launch each; second pass: three more for the (at
+        // most five) fastest variants within 8 % of the fastest and the
+        // default, taken round-robin so that a drift of the clock (power and
+        // thermal state) weighs on every candidate alike.  The smallest sum
+        // of second-pass times wins, unless the default variant is within
+        // 1 % of it: the default then stays.
         std::vector<float> first(static_cast<size_t>(nv));
         float fastest = -1.f;
         for (int v = 0; v < nv; ++v) {
             if (!cand[static_cast<size_t>(v)]) continue;
-            first[static_cast<size_t>(v)] = time_gemm(*cand[static_cast<size_t>(v)]);
+            first[static_cast<size_t>(v)] = time_gemm(*cand[static_cast<size_t>(v)], false);
             if (fastest < 0.f || first[static_cast<size_t>(v)] < fastest) fastest = first[static_cast<size_t>(v)];
         }
         std::vector<int> keep;
         for (int v = 0; v < nv; ++v)
             if (cand[static_cast<size_t>(v)] && first[static_cast<size_t>(v)] <= 1.08f * fastest) keep.push_back(v);
+        std::stable_sort(keep.begin(), keep.end(), [&](int x, int y) {
+            return first[static_cast<size_t>(x)] < first[static_cast<size_t>(y)];
+        });
+        if (keep.size() > 5) keep.resize(5);
         const int def = gemm_default_variant(compute);
         if (std::find(keep.begin(), keep.end(), def) == keep.end()) keep.push_back(def);
         std::vector<float> total(static_cast<size_t>(nv), 0.f);
         for (int rep = 0; rep < 3; ++rep)
-            for (int v : keep) total[static_cast<size_t>(v)] += time_gemm(*cand[static_cast<size_t>(v)]);
+            for (int v : keep) total[static_cast<size_t>(v)] += time_gemm(*cand[static_cast<size_t>(v)], true);
         int best = keep[0];
         for (int v : keep)
             if (total[static_cast<size_t>(v)] < total[static_cast<size_t>(best)]) best = v;
