@@ -374,7 +374,10 @@ int32_t sym_contract_operand_output(sym_ctx* ctx, const sym_tensor* A, const sym
  * coupled spin of the contracted legs (the Clebsch-Gordan chains of the
  * contracted legs contract to the identity, eq:cgunitary), and the product is
  * recoupled into C, a CHAIN tensor (default layout: the canonical block list)
- * with A's free legs then B's free legs and their arrows.  FP32 only.  sym_contract_output creates C's handle
+ * with A's free legs then B's free legs and their arrows.  Compute F32 needs
+ * FP32 operands; with SYM_BF16 the recoupling of A and B (FP32 or BF16 data,
+ * FP64 sums) writes their GEMM forms rounded once to BF16, and the product
+ * is recoupled from FP32 into C.  sym_contract_output creates C's handle
  * (data may be NULL).  The plan (block matching, offsets, tile list) is built
  * on the first call and cached in the context. */
 int32_t sym_contract_output(sym_ctx* ctx, const sym_tensor* A, const sym_tensor* B, int32_t n,

@@ -604,8 +604,12 @@ std::shared_ptr<ContractPlan> plan_contract_host(sym_ctx* ctx, int32_t count, co
             (c.group == SYM_SU2 && c.tree != want_c->tree) || c.dtype != SYM_F32)
             throw Error(SYM_E_MISMATCH, "C does not describe the contraction result");
         if (p.su2_general) {
-            if (compute != SYM_F32 || a.dtype != SYM_F32 || b.dtype != SYM_F32)
-                throw Error(SYM_E_DTYPE, "general SU(2) contractions run in FP32");
+            // BF16 compute: the recoupling of A and B writes their GEMM
+            // forms rounded to BF16 (from FP32 or BF16 data); FP32 inputs
+            // need FP32 compute
+            if ((compute != SYM_F32 && compute != SYM_BF16) || (compute == SYM_F32 && (a.dtype != SYM_F32 ||
+                                                                                     b.dtype != SYM_F32)))
+                throw Error(SYM_E_DTYPE, "general SU(2) contractions of BF16 data need BF16 compute");
             const Su2Forms f = su2_forms(a, b, p, compute);
             const int64_t a_base = in_off;
             in_off = align_up(in_off + f.ap->numel, 64);

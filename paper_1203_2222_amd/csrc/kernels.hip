@@ -1974,10 +1974,10 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
 // then run over 4 dims with no rank test, which is what the element rate of
 // the rank-4 trees needs: the general form measured 1.55 against 1.0 ms on
 // config 5's recoupling), or kMaxRecoupleRank for any rank up to it.
-template <int NB, int RK>
+template <int NB, int RK, typename Ti, typename To>
 __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __restrict__ ib,
                                                const FmBlk* __restrict__ ob, const double* __restrict__ cf,
-                                               const float* __restrict__ src, float* __restrict__ dst, int start,
+                                               const Ti* __restrict__ src, To* __restrict__ dst, int start,
                                                int end) {
     constexpr int U = NB <= 2 ? 8 : NB <= 4 ? 4 : NB <= 8 ? 2 : 1;
     constexpr int R = RK;
@@ -2016,7 +2016,7 @@ __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __
             const uint32_t ri0 = rel(ib[0], t);
 #pragma unroll
             for (int i = 0; i < NB; ++i)
-                xs[u][i] = i < n ? src[ib[i].off + (g.same_in ? ri0 : rel(ib[i], t))] : 0.f;
+                xs[u][i] = i < n ? Conv<Ti, float>::f(src[ib[i].off + (g.same_in ? ri0 : rel(ib[i], t))]) : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -2032,7 +2032,8 @@ __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __
                 for (int i = 0; i < NB; ++i)
                     if (i < n) y = fma(cf[f * n + i], static_cast<double>(xs[u][i]), y);
                 // streaming store: the output is not read again by this kernel
-                __builtin_nontemporal_store(static_cast<float>(y), &dst[ob[f].off + (g.same_out ? ro0 : rel(ob[f], t))]);
+                __builtin_nontemporal_store(Conv<float, To>::f(static_cast<float>(y)),
+                                            &dst[ob[f].off + (g.same_out ? ro0 : rel(ob[f], t))]);
             }
         }
     }
@@ -2045,7 +2046,7 @@ __device__ __forceinline__ void recouple_elems(const FmGroup& g, const FmBlk* __
 // few registers, while one kernel for every n takes the register count of
 // its n = 32 path (112 VGPRs, four waves per SIMD).  The larger tuples go
 // through the general instance.
-template <int NBMAX>
+template <int NBMAX, typename Ti, typename To>
 __global__ __launch_bounds__(256, NBMAX <= kRecoupleSmallN ? 8 : 1) void k_recouple(
     const FmGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks, const FmBlk* __restrict__ out_blks,
     const double* __restrict__ coef, const FmTask* __restrict__ tasks, PtrTable bufs, int in_buf, int out_buf) {
@@ -2054,28 +2055,28 @@ __global__ __launch_bounds__(256, NBMAX <= kRecoupleSmallN ? 8 : 1) void k_recou
     const FmGroup& g = groups[t.group];
     for (int k = threadIdx.x; k < g.n * g.n; k += 256) cf[k] = coef[g.coef_first + k];
     __syncthreads();
-    const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
-    float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
+    const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[in_buf]);
+    To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[out_buf]));
     const FmBlk* __restrict__ ib = in_blks + g.in_first;
     const FmBlk* __restrict__ ob = out_blks + g.out_first;
     const int end = t.start + t.count;
     const int n = g.n;
     if (g.rank == 4) {
-        if (n <= 1) recouple_elems<1, 4>(g, ib, ob, cf, src, dst, t.start, end);
-        else if (n <= 2) recouple_elems<2, 4>(g, ib, ob, cf, src, dst, t.start, end);
-        else if (n <= 4) recouple_elems<4, 4>(g, ib, ob, cf, src, dst, t.start, end);
-        else if (n <= 8) recouple_elems<8, 4>(g, ib, ob, cf, src, dst, t.start, end);
-        else if (n <= 16) recouple_elems<16, 4>(g, ib, ob, cf, src, dst, t.start, end);
-        else if constexpr (NBMAX > 16) recouple_elems<kMaxRecouple, 4>(g, ib, ob, cf, src, dst, t.start, end);
+        if (n <= 1) recouple_elems<1, 4, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 2) recouple_elems<2, 4, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 4) recouple_elems<4, 4, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 8) recouple_elems<8, 4, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+        else if (n <= 16) recouple_elems<16, 4, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+        else if constexpr (NBMAX > 16) recouple_elems<kMaxRecouple, 4, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
         return;
     }
     constexpr int RG = kMaxRecoupleRank;
-    if (n <= 1) recouple_elems<1, RG>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 2) recouple_elems<2, RG>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 4) recouple_elems<4, RG>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 8) recouple_elems<8, RG>(g, ib, ob, cf, src, dst, t.start, end);
-    else if (n <= 16) recouple_elems<16, RG>(g, ib, ob, cf, src, dst, t.start, end);
-    else if constexpr (NBMAX > 16) recouple_elems<kMaxRecouple, RG>(g, ib, ob, cf, src, dst, t.start, end);
+    if (n <= 1) recouple_elems<1, RG, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 2) recouple_elems<2, RG, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 4) recouple_elems<4, RG, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 8) recouple_elems<8, RG, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+    else if (n <= 16) recouple_elems<16, RG, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
+    else if constexpr (NBMAX > 16) recouple_elems<kMaxRecouple, RG, Ti, To>(g, ib, ob, cf, src, dst, t.start, end);
 }
 
 // LDS-tiled K9 (see FtGroup): a workgroup moves one box of all n input
@@ -2086,10 +2087,10 @@ __global__ __launch_bounds__(256, NBMAX <= kRecoupleSmallN ? 8 : 1) void k_recou
 // and writes the n output blocks in output order.  Per-block offsets and
 // strides are decoded once per task into LDS.  The combination is unrolled
 // for n up to NB (the smallest power of two >= n).
-template <int NB>
+template <int NB, typename To>
 __device__ __forceinline__ void recouple_combine(const float* __restrict__ tile, const double* __restrict__ cf,
                                                  const int64_t* __restrict__ obase, const int32_t (*ostr)[3],
-                                                 float* __restrict__ dst, int n, int E, int T2, int T3, int v1, int v2,
+                                                 To* __restrict__ dst, int n, int E, int T2, int T3, int v1, int v2,
                                                  int v3, uint32_t m0, int s0, uint32_t m1, int s1) {
     for (int q = threadIdx.x; q < E; q += 256) {
         const int r = div_by(q, m0, s0);
@@ -2107,7 +2108,7 @@ __device__ __forceinline__ void recouple_combine(const float* __restrict__ tile,
 #pragma unroll
             for (int i = 0; i < NB; ++i)
                 if (i < n) y = fma(cf[f * n + i], x[i], y);
-            dst[obase[f] + (l1 * ostr[f][0] + l2 * ostr[f][1] + l3 * ostr[f][2])] = static_cast<float>(y);
+            dst[obase[f] + (l1 * ostr[f][0] + l2 * ostr[f][1] + l3 * ostr[f][2])] = Conv<float, To>::f(static_cast<float>(y));
         }
     }
 }
@@ -2115,7 +2116,7 @@ __device__ __forceinline__ void recouple_combine(const float* __restrict__ tile,
 // NBMAX: the largest n the instance takes; tuples of at most
 // kRecoupleTiledSmallN blocks run in an instance held to eight waves per
 // SIMD (like the element-wise kernel, this one waits on memory latency)
-template <int NBMAX>
+template <int NBMAX, typename Ti, typename To>
 __global__ __launch_bounds__(256, NBMAX <= kRecoupleTiledSmallN ? 8 : 1) void k_recouple_tiled(
     const FtGroup* __restrict__ groups, const FmBlk* __restrict__ in_blks, const FmBlk* __restrict__ out_blks,
     const double* __restrict__ coef, const FtTask* __restrict__ tasks, PtrTable bufs, int in_buf, int out_buf) {
@@ -2149,8 +2150,8 @@ __global__ __launch_bounds__(256, NBMAX <= kRecoupleTiledSmallN ? 8 : 1) void k_
     __syncthreads();
     // extents of the box inside the blocks (edge tiles are clipped)
     const int v1 = min(T1, g.dim[a1] - t.o[1]), v2 = min(T2, g.dim[a2] - t.o[2]), v3 = min(T3, g.dim[a3] - t.o[3]);
-    const float* __restrict__ src = static_cast<const float*>(bufs.p[in_buf]);
-    float* __restrict__ dst = static_cast<float*>(const_cast<void*>(bufs.p[out_buf]));
+    const Ti* __restrict__ src = static_cast<const Ti*>(bufs.p[in_buf]);
+    To* __restrict__ dst = static_cast<To*>(const_cast<void*>(bufs.p[out_buf]));
     const int lf = g.ld[0], lm = g.ld[1];
     const int tf = g.t[lf], tm = g.t[lm];
     const int total = n * E;
@@ -2175,7 +2176,7 @@ __global__ __launch_bounds__(256, NBMAX <= kRecoupleTiledSmallN ? 8 : 1) void k_
                 const int l3 = lf == 3 ? uf : (lm == 3 ? um : us);
                 if (l1 < v1 && l2 < v2 && l3 < v3) {
                     const int rel = l1 * istr[i][0] + l2 * istr[i][1] + l3 * istr[i][2];
-                    v[u] = src[ibase[i] + rel];
+                    v[u] = Conv<Ti, float>::f(src[ibase[i] + rel]);
                     pos[u] = i * E + (l1 * T2 + l2) * T3 + l3;
                 }
             }
@@ -2188,48 +2189,85 @@ __global__ __launch_bounds__(256, NBMAX <= kRecoupleTiledSmallN ? 8 : 1) void k_
     const uint32_t m0 = g.mag[0], m1 = g.mag[1];
     const int s0 = g.shf[0], s1 = g.shf[1];
     if (n <= 1)
-        recouple_combine<1>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+        recouple_combine<1, To>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else if (n <= 2)
-        recouple_combine<2>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+        recouple_combine<2, To>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else if (n <= 4)
-        recouple_combine<4>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+        recouple_combine<4, To>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
     else if constexpr (NBMAX > 4) {
         if (n <= 8)
-            recouple_combine<8>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
+            recouple_combine<8, To>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1, s1);
         else
-            recouple_combine<kMaxRecoupleTiled>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1,
+            recouple_combine<kMaxRecoupleTiled, To>(tile, cf, obase, ostr, dst, n, E, T2, T3, v1, v2, v3, m0, s0, m1,
                                                 s1);
     }
 }
 
-hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
-                                 const FtTask* tasks, int32_t n_small, int32_t n_tasks, const PtrTable& bufs,
-                                 int32_t in_buf, int32_t out_buf, hipStream_t s) {
+template <typename Ti, typename To>
+hipError_t launch_rct(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
+                      const FtTask* tasks, int32_t n_small, int32_t n_tasks, const PtrTable& bufs, int32_t in_buf,
+                      int32_t out_buf, hipStream_t s) {
     if (n_small > 0) {
-        hipLaunchKernelGGL(k_recouple_tiled<kRecoupleTiledSmallN>, dim3(static_cast<unsigned>(n_small)), dim3(256), 0,
-                           s, groups, in_blks, out_blks, coef, tasks, bufs, in_buf, out_buf);
+        hipLaunchKernelGGL((k_recouple_tiled<kRecoupleTiledSmallN, Ti, To>), dim3(static_cast<unsigned>(n_small)),
+                           dim3(256), 0, s, groups, in_blks, out_blks, coef, tasks, bufs, in_buf, out_buf);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n_tasks > n_small)
-        hipLaunchKernelGGL(k_recouple_tiled<kMaxRecoupleTiled>, dim3(static_cast<unsigned>(n_tasks - n_small)),
+        hipLaunchKernelGGL((k_recouple_tiled<kMaxRecoupleTiled, Ti, To>), dim3(static_cast<unsigned>(n_tasks - n_small)),
                            dim3(256), 0, s, groups, in_blks, out_blks, coef, tasks + n_small, bufs, in_buf, out_buf);
     return hipGetLastError();
 }
 
-hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
-                           const FmTask* tasks, int32_t n_small, int32_t n_tasks, const PtrTable& bufs,
-                           int32_t in_buf, int32_t out_buf, hipStream_t s) {
+template <typename Ti, typename To>
+hipError_t launch_rce(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks, const double* coef,
+                      const FmTask* tasks, int32_t n_small, int32_t n_tasks, const PtrTable& bufs, int32_t in_buf,
+                      int32_t out_buf, hipStream_t s) {
     if (n_small > 0) {
-        hipLaunchKernelGGL(k_recouple<kRecoupleSmallN>, dim3(static_cast<unsigned>(n_small)), dim3(256), 0, s, groups,
-                           in_blks, out_blks, coef, tasks, bufs, in_buf, out_buf);
+        hipLaunchKernelGGL((k_recouple<kRecoupleSmallN, Ti, To>), dim3(static_cast<unsigned>(n_small)), dim3(256), 0, s,
+                           groups, in_blks, out_blks, coef, tasks, bufs, in_buf, out_buf);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n_tasks > n_small)
-        hipLaunchKernelGGL(k_recouple<kMaxRecouple>, dim3(static_cast<unsigned>(n_tasks - n_small)), dim3(256), 0, s,
-                           groups, in_blks, out_blks, coef, tasks + n_small, bufs, in_buf, out_buf);
+        hipLaunchKernelGGL((k_recouple<kMaxRecouple, Ti, To>), dim3(static_cast<unsigned>(n_tasks - n_small)), dim3(256),
+                           0, s, groups, in_blks, out_blks, coef, tasks + n_small, bufs, in_buf, out_buf);
     return hipGetLastError();
+}
+
+bool recouple_dtypes_supported(int src_dtype, int dst_dtype) {
+    return (src_dtype == 0 && (dst_dtype == 0 || dst_dtype == 1)) || (src_dtype == 1 && dst_dtype == 1);
+}
+
+hipError_t launch_recouple_tiled(int src_dtype, int dst_dtype, const FtGroup* groups, const FmBlk* in_blks,
+                                 const FmBlk* out_blks, const double* coef, const FtTask* tasks, int32_t n_small,
+                                 int32_t n_tasks, const PtrTable& bufs, int32_t in_buf, int32_t out_buf,
+                                 hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    if (src_dtype == 0 && dst_dtype == 0)
+        return launch_rct<float, float>(groups, in_blks, out_blks, coef, tasks, n_small, n_tasks, bufs, in_buf, out_buf, s);
+    if (src_dtype == 0 && dst_dtype == 1)
+        return launch_rct<float, uint16_t>(groups, in_blks, out_blks, coef, tasks, n_small, n_tasks, bufs, in_buf, out_buf,
+                                           s);
+    if (src_dtype == 1 && dst_dtype == 1)
+        return launch_rct<uint16_t, uint16_t>(groups, in_blks, out_blks, coef, tasks, n_small, n_tasks, bufs, in_buf,
+                                              out_buf, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_recouple(int src_dtype, int dst_dtype, const FmGroup* groups, const FmBlk* in_blks,
+                           const FmBlk* out_blks, const double* coef, const FmTask* tasks, int32_t n_small,
+                           int32_t n_tasks, const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    if (src_dtype == 0 && dst_dtype == 0)
+        return launch_rce<float, float>(groups, in_blks, out_blks, coef, tasks, n_small, n_tasks, bufs, in_buf, out_buf, s);
+    if (src_dtype == 0 && dst_dtype == 1)
+        return launch_rce<float, uint16_t>(groups, in_blks, out_blks, coef, tasks, n_small, n_tasks, bufs, in_buf, out_buf,
+                                           s);
+    if (src_dtype == 1 && dst_dtype == 1)
+        return launch_rce<uint16_t, uint16_t>(groups, in_blks, out_blks, coef, tasks, n_small, n_tasks, bufs, in_buf,
+                                              out_buf, s);
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -204,17 +204,22 @@ hipError_t launch_permute_tiled(int src_dtype, int dst_dtype, const CopyOp* ops,
 hipError_t launch_gemm(int compute, int variant, const GemmProb* probs, const GemmTile* tiles,
                        int32_t n_tiles, int32_t grid, const EpiRow* rows, const EpiCol* cols,
                        const PtrTable& bufs, hipStream_t s);
+// Recoupling element types (0 = F32, 1 = BF16; values are combined in FP64
+// and rounded once to the output type): F32 -> F32, F32 -> BF16 and
+// BF16 -> BF16.
+bool recouple_dtypes_supported(int src_dtype, int dst_dtype);
 // tasks[0, n_small) belong to tuples of at most kRecoupleTiledSmallN blocks
-hipError_t launch_recouple_tiled(const FtGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
-                                 const double* coef, const FtTask* tasks, int32_t n_small, int32_t n_tasks,
-                                 const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);
+hipError_t launch_recouple_tiled(int src_dtype, int dst_dtype, const FtGroup* groups, const FmBlk* in_blks,
+                                 const FmBlk* out_blks, const double* coef, const FtTask* tasks, int32_t n_small,
+                                 int32_t n_tasks, const PtrTable& bufs, int32_t in_buf, int32_t out_buf,
+                                 hipStream_t s);
 hipError_t launch_contract_small(const SmallTask* tasks, int32_t n_tasks, const SmallPair* pairs,
                                  const PtrTable& bufs, hipStream_t s);
 // tasks[0, n_small) belong to label tuples of at most kRecoupleSmallN blocks,
 // tasks[n_small, n_tasks) to larger ones
-hipError_t launch_recouple(const FmGroup* groups, const FmBlk* in_blks, const FmBlk* out_blks,
-                           const double* coef, const FmTask* tasks, int32_t n_small, int32_t n_tasks,
-                           const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);
+hipError_t launch_recouple(int src_dtype, int dst_dtype, const FmGroup* groups, const FmBlk* in_blks,
+                           const FmBlk* out_blks, const double* coef, const FmTask* tasks, int32_t n_small,
+                           int32_t n_tasks, const PtrTable& bufs, int32_t in_buf, int32_t out_buf, hipStream_t s);
 
 // Tile shape of a GEMM variant (rows x cols of C per workgroup).
 struct GemmVariant {

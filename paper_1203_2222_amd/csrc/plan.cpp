@@ -722,6 +722,10 @@ void RecoupleProgram::build(const Desc& in, const Desc& out, const std::vector<i
     };
     if (in.group != SYM_SU2 || out.group != SYM_SU2 || in.rank != out.rank || static_cast<int>(perm.size()) != in.rank)
         throw Error(SYM_E_UNSUPPORTED, "recoupling acts on SU(2) tensors of equal rank");
+    src_dtype = in.dtype;
+    dst_dtype = out.dtype;
+    if (!recouple_dtypes_supported(src_dtype, dst_dtype))
+        throw Error(SYM_E_DTYPE, "recoupling takes F32 -> F32, F32 -> BF16 or BF16 -> BF16");
     const int rank = in.rank;
     // Inputs are row-major over their legs in every layout, so the input is
     // contiguous along its last leg.  When that leg stays last the
@@ -833,6 +837,10 @@ FusedLeg fuse_legs(const Leg& a, const Leg& b) {
 void RecoupleProgram::build_fuse(const Desc& unf, const Desc& fus, int leg, bool to_fused) {
     if (unf.tree != SYM_TREE_CHAIN && unf.tree != SYM_TREE_OPERATOR && unf.tree != SYM_TREE_LEFT)
         throw Error(SYM_E_UNSUPPORTED, "FUSE and SPLIT take CHAIN, OPERATOR or LEFT tensors");
+    src_dtype = to_fused ? unf.dtype : fus.dtype;
+    dst_dtype = to_fused ? fus.dtype : unf.dtype;
+    if (!recouple_dtypes_supported(src_dtype, dst_dtype))
+        throw Error(SYM_E_DTYPE, "recoupling takes F32 -> F32, F32 -> BF16 or BF16 -> BF16");
     const int rank = unf.rank;
     const Leg& la = unf.legs[static_cast<size_t>(leg)];
     const Leg& lb = unf.legs[static_cast<size_t>(leg + 1)];
@@ -965,11 +973,13 @@ void RecoupleProgram::upload(const Allocator& alloc, Deferred* deferred) {
 hipError_t RecoupleProgram::launch(const PtrTable& bufs, int in_buf, int out_buf, hipStream_t s) const {
     if (tasks.empty()) return hipSuccess;
     if (tiled)
-        return launch_recouple_tiled(static_cast<const FtGroup*>(d_tgroups->ptr), static_cast<const FmBlk*>(d_in->ptr),
+        return launch_recouple_tiled(src_dtype, dst_dtype, static_cast<const FtGroup*>(d_tgroups->ptr),
+                                     static_cast<const FmBlk*>(d_in->ptr),
                                      static_cast<const FmBlk*>(d_out->ptr), static_cast<const double*>(d_coef->ptr),
                                      static_cast<const FtTask*>(d_ttasks->ptr), n_tsmall,
                                      static_cast<int32_t>(ttasks.size()), bufs, in_buf, out_buf, s);
-    return launch_recouple(static_cast<const FmGroup*>(d_groups->ptr), static_cast<const FmBlk*>(d_in->ptr),
+    return launch_recouple(src_dtype, dst_dtype, static_cast<const FmGroup*>(d_groups->ptr),
+                           static_cast<const FmBlk*>(d_in->ptr),
                            static_cast<const FmBlk*>(d_out->ptr), static_cast<const double*>(d_coef->ptr),
                            static_cast<const FmTask*>(d_tasks->ptr), n_small, static_cast<int32_t>(tasks.size()), bufs,
                            in_buf, out_buf, s);

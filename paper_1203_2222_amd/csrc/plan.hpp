@@ -110,6 +110,7 @@ struct RecoupleProgram {
     bool tiled_unfit = false;       // a label tuple has more blocks than the tiled kernel takes
     int32_t n_small = 0;            // tasks[0, n_small): tuples of at most kRecoupleSmallN blocks (set by upload)
     int32_t n_tsmall = 0;           // ttasks[0, n_tsmall): tuples of at most kRecoupleTiledSmallN blocks
+    int src_dtype = SYM_F32, dst_dtype = SYM_F32;   // element types of the input and the output
     DevMemPtr d_groups, d_in, d_out, d_coef, d_tasks, d_tgroups, d_ttasks;
     // Gamma(tree, perm, tree') of every label tuple; out's leg k is in's leg
     // perm[k]; the tensors start at element in_base / out_base of their

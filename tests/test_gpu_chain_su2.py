@@ -13,7 +13,7 @@ import workloads as W
 from oracle import contract as K
 from oracle import recouple as RC
 from oracle import tensors as T
-from tests.gpu_util import draw, host, rel_err, say
+from tests.gpu_util import bf16_round, draw, host, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -162,13 +162,39 @@ def test_su2_general_contraction_sector_layout_inputs(ctx):
     assert rel_err(host(C), ref) <= 1e-5
 
 
-def test_su2_general_contraction_rejects_bf16(ctx):
-    sa = _spec([INT, INT, INT, WHOLE], ("in", "in", "in", "out"))
-    sb = _spec([WHOLE, INT, INT, INT], ("in", "in", "out", "out"))
-    A, _ = _tensor(ctx, sa, 1)
-    B, _ = _tensor(ctx, sb, 2)
+@pytest.mark.parametrize("name,la,aa,ta,lb,ab,tb,axes_a,axes_b", CONTRACTIONS, ids=[c[0] for c in CONTRACTIONS])
+def test_su2_general_contraction_bf16_matches_dense(ctx, name, la, aa, ta, lb, ab, tb, axes_a, axes_b):
+    # BF16 compute: the recoupled GEMM forms of A and B are rounded once to
+    # BF16, the GEMM accumulates in FP32, C is recoupled in FP64 and stored
+    # in FP32; against the FP64 oracle on the unrounded inputs
+    say(f"case su2 general contraction bf16 {name}")
+    sa, sb = _spec(la, aa, ta), _spec(lb, ab, tb)
+    A, fa = _tensor(ctx, sa, 21)
+    B, fb = _tensor(ctx, sb, 22)
+    _, ref = K.contract_su2_dense(sa, fa, sb, fb, axes_a, axes_b)
+    C = ctx.contract(A, B, axes_a, axes_b, "bf16")
+    err = rel_err(host(C), ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= 3e-3
+
+
+def test_su2_general_contraction_bf16_data(ctx):
+    # BF16 operands (MERA isometry on an operator) need BF16 compute; the
+    # reference takes the BF16-rounded entries
+    name, la, aa, ta, lb, ab, tb, axes_a, axes_b = CONTRACTIONS[1]
+    say(f"case su2 general contraction bf16 data {name}")
+    sa, sb = _spec(la, aa, ta), _spec(lb, ab, tb)
+    A32, fa = _tensor(ctx, sa, 31)
+    B32, fb = _tensor(ctx, sb, 32)
+    A = ctx.tensor(sa, len(la), "bf16", data=A32.data.to(torch.bfloat16))
+    B = ctx.tensor(sb, len(lb), "bf16", data=B32.data.to(torch.bfloat16))
+    _, ref = K.contract_su2_dense(sa, bf16_round(fa), sb, bf16_round(fb), axes_a, axes_b)
+    C = ctx.contract(A, B, axes_a, axes_b, "bf16")
+    err = rel_err(host(C), ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= 3e-3
     with pytest.raises(Exception):
-        ctx.contract(B, A, (2, 3), (1, 2), "bf16")
+        ctx.contract(A, B, axes_a, axes_b, "f32")
 
 
 def _random_spec(rng, rank, pool=(HALF, INT, WHOLE)):
