@@ -371,7 +371,24 @@ def secondary(ctx, stream, with_cpu=True):
             "what": "Gram reads plus rotation reads and writes per round, every pair assumed to rotate"}
         if with_cpu:
             out["svd_u1_chi128_fp64"]["cpu_baseline"] = cpu_baseline_svd(c.A, a4)
-        del A, F, S, a4
+        # block-wise eigen-decomposition of the same sectors' symmetric parts
+        # (the shifted SVD route), with numpy's symmetric eigenvalues beside it
+        ctx.eigh(F, stream=stream)          # plan and workspaces outside the timing
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, w, esweeps, _ = ctx.eigh(F, stream=stream)
+        torch.cuda.synchronize()
+        out["eigh_u1_chi128_fp64"] = {"gpu_s": round(time.perf_counter() - t0, 3), "jacobi_sweeps": int(esweeps),
+                                      "sectors": len(shapes)}
+        if with_cpu:
+            from oracle import svd as SV
+            flat4 = a4.double().cpu().numpy()
+            t0 = time.perf_counter()
+            SV.block_eigenvalues(c.A, flat4, 2)
+            out["eigh_u1_chi128_fp64"]["cpu_baseline"] = {
+                "value": round(time.perf_counter() - t0, 3), "unit": "s", "kind": "oracle",
+                "cores": len(os.sched_getaffinity(0)), "sample": "all 17 sectors, eigenvalues only"}
+        del A, F, S, w, a4
 
         # config 5: SU(2) contraction + recoupling, FP32
         c = W.config5()

@@ -502,6 +502,28 @@ int32_t sym_default_variant(int32_t compute, int32_t* variant);
 int32_t sym_svd_sizes(const sym_tensor* T, int64_t* u_elems, int64_t* s_elems, int64_t* vt_elems);
 int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double* Vt, int32_t* sweeps,
                 int32_t max_sweeps, void* stream);
+/* Block-wise symmetric eigen-decomposition (section "Factorization of a
+ * matrix" of the symmetric tensor network chapter, where an eigen-
+ * decomposition factorises a tensor block by block the same way as eq:svd1):
+ * every sector matrix of T's layout must be square (k_s x k_s;
+ * SYM_E_UNSUPPORTED otherwise, and for k_s > 4096), and the routine
+ * factorises its symmetric part S_s = (T_s + T_s^T) / 2 in FP64 as
+ * S_s = V_s diag(w_s) V_s^T, eigenvalues descending, V_s orthonormal.  V and
+ * w are FP64 device buffers, sector after sector in T's sector order
+ * (sectors with no rows skipped): V_s row-major k_s x k_s with the
+ * eigenvectors as columns, w_s k_s values; sym_eigh_sizes gives their
+ * element counts.  Method: S_s + c_s I, c_s the Frobenius norm of S_s (1 when
+ * S_s = 0), is positive definite, so the one-sided Jacobi SVD of sym_svd
+ * (same stopping rule, same once-per-sweep synchronisation of `stream`)
+ * returns its eigenvectors, taken from the accumulated rotations, and
+ * eigenvalues w = s - c_s; the absolute error of an eigenvalue is a small
+ * multiple of sqrt(k_s) 2^-53 c_s.  sweeps (host, may be NULL) receives the
+ * number of sweeps.  A tensor with no sector returns at once (V, w may be
+ * NULL).  The caller owns the outputs; the workspaces belong to the context,
+ * so calls on one structure must not overlap. */
+int32_t sym_eigh_sizes(const sym_tensor* T, int64_t* v_elems, int64_t* w_elems);
+int32_t sym_eigh(sym_ctx* ctx, const sym_tensor* T, double* V, double* w, int32_t* sweeps, int32_t max_sweeps,
+                 void* stream);
 /* Global truncation of a block SVD (host; S is a host copy of sym_svd's S):
  * the singular values of all sectors are taken in descending order, each
  * counting w_s times (1 for the Abelian groups, 2e + 1 for the SU(2) sector

@@ -74,6 +74,25 @@ def block_singular_values(spec, flat, n_row: int) -> Dict[object, np.ndarray]:
     return {s: np.linalg.svd(m, compute_uv=False) for s, m in sector_matrices(spec, flat, n_row).items()}
 
 
+def symmetric_eigenvalues(m: np.ndarray) -> np.ndarray:
+    """Eigenvalues, descending, of the symmetric part (m + m^T) / 2 of a square
+    matrix (numpy's symmetric eigensolver)."""
+    m = np.asarray(m, dtype=np.float64)
+    if m.ndim != 2 or m.shape[0] != m.shape[1]:
+        raise ValueError("the symmetric part needs a square matrix")
+    return np.linalg.eigvalsh(0.5 * (m + m.T))[::-1]
+
+
+def block_eigenvalues(spec, flat, n_row: int) -> Dict[object, np.ndarray]:
+    """{sector: eigenvalues, descending} of the symmetric part of each sector
+    matrix: the block-wise eigen-decomposition, the same per-sector
+    factorisation as the SVD's (section "Factorization of a matrix").  Row i
+    and column i of a sector are the same label tuple and degeneracy index
+    when the column legs repeat the row legs' spectra, which is when the
+    symmetric part describes an operator."""
+    return {s: symmetric_eigenvalues(m) for s, m in sector_matrices(spec, flat, n_row).items()}
+
+
 def multiplicity(spec, sector) -> int:
     return sector + 1 if spec.group == T.SU2 else 1
 

@@ -122,7 +122,7 @@ struct SvdPlan {
     std::vector<int32_t> pair_start;   // prefix sums of the block pairs per sector
     int32_t max_kp = 0;                // largest (even) block count
     int64_t u_elems = 0, s_elems = 0, vt_elems = 0, w_elems = 0, q_elems = 0;
-    DevMemPtr d_probs, d_pairs, w, q, scale, gpart, flag;
+    DevMemPtr d_probs, d_pairs, w, q, scale, shift, gpart, flag;
     int32_t flag_host = 0;
 };
 
@@ -1970,12 +1970,16 @@ int32_t sym_tune_batched(sym_ctx* ctx, int32_t count, const sym_tensor* const* A
 
 namespace {
 
-std::shared_ptr<SvdPlan> svd_plan_of(const Desc& d) {
+// eig: the eigen-decomposition of each sector's symmetric part, which needs
+// square sector matrices
+std::shared_ptr<SvdPlan> svd_plan_of(const Desc& d, bool eig) {
     auto plan = std::make_shared<SvdPlan>();
     if (d.opts.trans) throw Error(SYM_E_UNSUPPORTED, "transposed layouts have no SVD");
     for (const Sector& sc : d.sectors) {
         if (sc.rows == 0 || sc.cols == 0) continue;
+        if (eig && sc.rows != sc.cols) throw Error(SYM_E_UNSUPPORTED, "eigen-decomposition needs square sector matrices");
         SvdProb p{};
+        p.sym = eig ? 1 : 0;
         p.M = static_cast<int32_t>(sc.rows);
         p.N = static_cast<int32_t>(sc.cols);
         p.ld = static_cast<int32_t>(sc.ld);
@@ -2012,12 +2016,62 @@ std::shared_ptr<SvdPlan> svd_plan_of(const Desc& d) {
 int32_t sym_svd_sizes(const sym_tensor* T, int64_t* u_elems, int64_t* s_elems, int64_t* vt_elems) {
     return guard([&] {
         if (!T || !u_elems || !s_elems || !vt_elems) throw Error(SYM_E_ARG, "NULL argument");
-        auto plan = svd_plan_of(*T->d);
+        auto plan = svd_plan_of(*T->d, false);
         *u_elems = plan->u_elems;
         *s_elems = plan->s_elems;
         *vt_elems = plan->vt_elems;
     });
 }
+
+namespace {
+
+// the cached plan of T's structure (one per mode), built and uploaded on the
+// first call
+std::shared_ptr<SvdPlan> svd_plan_cached(sym_ctx* ctx, const sym_tensor* T, bool eig, hipStream_t stream) {
+    const std::string key = (eig ? "E|" : "S|") + T->d->key;
+    std::shared_ptr<SvdPlan> plan;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->svd_plans.find(key);
+        if (it != ctx->svd_plans.end()) plan = it->second;
+    }
+    if (plan) return plan;
+    plan = svd_plan_of(*T->d, eig);
+    Allocator alloc = ctx->allocator();
+    if (!plan->probs.empty()) {
+        BuildUploads up;
+        plan->d_probs = alloc(plan->probs.size() * sizeof(SvdProb));
+        up.copies.push_back({plan->d_probs->ptr, plan->probs.data(), plan->probs.size() * sizeof(SvdProb)});
+        plan->d_pairs = alloc(plan->pair_start.size() * sizeof(int32_t));
+        up.copies.push_back({plan->d_pairs->ptr, plan->pair_start.data(), plan->pair_start.size() * sizeof(int32_t)});
+        up.finish(stream);
+        plan->w = alloc(static_cast<size_t>(plan->w_elems) * sizeof(double));
+        plan->q = alloc(static_cast<size_t>(plan->q_elems) * sizeof(double));
+        plan->flag = alloc(sizeof(int32_t));
+        plan->scale = alloc(plan->probs.size() * sizeof(double));
+        if (eig) plan->shift = alloc(plan->probs.size() * sizeof(double));
+        plan->gpart = alloc(static_cast<size_t>(std::max<int32_t>(1, plan->pair_start.back())) * kSvdSlices *
+                            (4 * kSvdBlock * kSvdBlock) * sizeof(double));
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->svd_plans[key] = plan;
+    return plan;
+}
+
+void run_svd(const sym_tensor* T, SvdPlan& plan, double* U, double* S, double* Vt, int32_t* sweeps, int32_t max_sweeps,
+             hipStream_t stream) {
+    int32_t done = 0;
+    HIP_CHECK(launch_svd(T->d->dtype, T->data, static_cast<const SvdProb*>(plan.d_probs->ptr),
+                         static_cast<const int32_t*>(plan.d_pairs->ptr), static_cast<int32_t>(plan.probs.size()),
+                         plan.pair_start.back(), plan.max_kp, static_cast<double*>(plan.w->ptr),
+                         static_cast<double*>(plan.q->ptr), U, S, Vt, static_cast<double*>(plan.scale->ptr),
+                         plan.shift ? static_cast<double*>(plan.shift->ptr) : nullptr,
+                         static_cast<double*>(plan.gpart->ptr), static_cast<int32_t*>(plan.flag->ptr),
+                         &plan.flag_host, max_sweeps, &done, stream));
+    if (sweeps) *sweeps = done;
+}
+
+}  // namespace
 
 int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double* Vt, int32_t* sweeps,
                 int32_t max_sweeps, void* stream) {
@@ -2027,47 +2081,36 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
         if (!ctx || !T) throw Error(SYM_E_ARG, "NULL argument");
         if (!has_data(T)) throw Error(SYM_E_ARG, "tensor has no data pointer");
         if (max_sweeps < 1) throw Error(SYM_E_ARG, "max_sweeps must be >= 1");
-        const std::string key = "S|" + T->d->key;
-        std::shared_ptr<SvdPlan> plan;
-        {
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            auto it = ctx->svd_plans.find(key);
-            if (it != ctx->svd_plans.end()) plan = it->second;
-        }
-        if (!plan) {
-            plan = svd_plan_of(*T->d);
-            Allocator alloc = ctx->allocator();
-            if (!plan->probs.empty()) {
-                BuildUploads up;
-                plan->d_probs = alloc(plan->probs.size() * sizeof(SvdProb));
-                up.copies.push_back({plan->d_probs->ptr, plan->probs.data(), plan->probs.size() * sizeof(SvdProb)});
-                plan->d_pairs = alloc(plan->pair_start.size() * sizeof(int32_t));
-                up.copies.push_back(
-                    {plan->d_pairs->ptr, plan->pair_start.data(), plan->pair_start.size() * sizeof(int32_t)});
-                up.finish(static_cast<hipStream_t>(stream));
-                plan->w = alloc(static_cast<size_t>(plan->w_elems) * sizeof(double));
-                plan->q = alloc(static_cast<size_t>(plan->q_elems) * sizeof(double));
-                plan->flag = alloc(sizeof(int32_t));
-                plan->scale = alloc(plan->probs.size() * sizeof(double));
-                plan->gpart = alloc(static_cast<size_t>(std::max<int32_t>(1, plan->pair_start.back())) * kSvdSlices *
-                                    (4 * kSvdBlock * kSvdBlock) * sizeof(double));
-            }
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->svd_plans[key] = plan;
-        }
+        auto plan = svd_plan_cached(ctx, T, false, static_cast<hipStream_t>(stream));
         if (sweeps) *sweeps = 0;
         if (plan->probs.empty()) return;   // no sector: nothing to factorise or write
         if (!U || !S || !Vt) throw Error(SYM_E_ARG, "NULL argument");
         ctx->note(plan);
-        int32_t done = 0;
-        HIP_CHECK(launch_svd(T->d->dtype, T->data, static_cast<const SvdProb*>(plan->d_probs->ptr),
-                             static_cast<const int32_t*>(plan->d_pairs->ptr), static_cast<int32_t>(plan->probs.size()),
-                             plan->pair_start.back(), plan->max_kp, static_cast<double*>(plan->w->ptr),
-                             static_cast<double*>(plan->q->ptr), U, S, Vt, static_cast<double*>(plan->scale->ptr),
-                             static_cast<double*>(plan->gpart->ptr),
-                             static_cast<int32_t*>(plan->flag->ptr),
-                             &plan->flag_host, max_sweeps, &done, static_cast<hipStream_t>(stream)));
-        if (sweeps) *sweeps = done;
+        run_svd(T, *plan, U, S, Vt, sweeps, max_sweeps, static_cast<hipStream_t>(stream));
+    });
+}
+
+int32_t sym_eigh_sizes(const sym_tensor* T, int64_t* v_elems, int64_t* w_elems) {
+    return guard([&] {
+        if (!T || !v_elems || !w_elems) throw Error(SYM_E_ARG, "NULL argument");
+        auto plan = svd_plan_of(*T->d, true);
+        *v_elems = plan->u_elems;
+        *w_elems = plan->s_elems;
+    });
+}
+
+int32_t sym_eigh(sym_ctx* ctx, const sym_tensor* T, double* V, double* w, int32_t* sweeps, int32_t max_sweeps,
+                 void* stream) {
+    return guard([&] {
+        if (!ctx || !T) throw Error(SYM_E_ARG, "NULL argument");
+        if (!has_data(T)) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        if (max_sweeps < 1) throw Error(SYM_E_ARG, "max_sweeps must be >= 1");
+        auto plan = svd_plan_cached(ctx, T, true, static_cast<hipStream_t>(stream));
+        if (sweeps) *sweeps = 0;
+        if (plan->probs.empty()) return;
+        if (!V || !w) throw Error(SYM_E_ARG, "NULL argument");
+        ctx->note(plan);
+        run_svd(T, *plan, V, w, nullptr, sweeps, max_sweeps, static_cast<hipStream_t>(stream));
     });
 }
 
@@ -2076,7 +2119,7 @@ int32_t sym_svd_truncate(const sym_tensor* T, const double* S, int64_t chi_max, 
     return guard([&] {
         if (!T || !S || !keep) throw Error(SYM_E_ARG, "NULL argument");
         if (chi_max < 0) throw Error(SYM_E_ARG, "chi_max must be >= 0");
-        auto plan = svd_plan_of(*T->d);
+        auto plan = svd_plan_of(*T->d, false);
         // (value, weight, sector) over every singular value; an SU(2) sector
         // of coupled spin e (label 2e) stands for 2e + 1 equal values
         struct Item { double v; int32_t w; int32_t s; };

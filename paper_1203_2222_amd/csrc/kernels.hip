@@ -1584,7 +1584,9 @@ __global__ __launch_bounds__(256) void k_svd_load(const Ti* __restrict__ src, co
             const int j = static_cast<int>(idx / p.L), x = static_cast<int>(idx - static_cast<int64_t>(j) * p.L);
             const int64_t e =
                 p.rows_are_vectors ? static_cast<int64_t>(j) * p.ld + x : static_cast<int64_t>(x) * p.ld + j;
-            const double v = as_f64(src[p.src_off + e]);
+            double v = as_f64(src[p.src_off + e]);
+            // eigen mode: the symmetric part of the square sector matrix
+            if (p.sym) v = 0.5 * (v + as_f64(src[p.src_off + static_cast<int64_t>(x) * p.ld + j]));
             Wg[p.w_off + idx] = v;
             ss = fma(v, v, ss);
         } else {
@@ -1596,6 +1598,20 @@ __global__ __launch_bounds__(256) void k_svd_load(const Ti* __restrict__ src, co
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = ss;
     __syncthreads();
     if (threadIdx.x == 0) atomicAdd(&scale[blockIdx.y], part[0] + part[1] + part[2] + part[3]);
+}
+
+// Eigen mode: the symmetric part S of a sector becomes S + c I with c its
+// Frobenius norm (1 when S = 0), which is symmetric positive definite (the
+// spectral norm is at most c), so its singular value decomposition is its
+// eigen-decomposition: U = V are the eigenvectors of S and each singular
+// value is an eigenvalue of S plus c.  One workgroup per sector.
+__global__ __launch_bounds__(256) void k_eig_shift(const SvdProb* __restrict__ probs, double* __restrict__ Wg,
+                                                   const double* __restrict__ scale, double* __restrict__ shift) {
+    const SvdProb p = probs[blockIdx.x];
+    const double fro = sqrt(scale[blockIdx.x]);
+    const double c = fro > 0.0 ? fro : 1.0;
+    for (int j = threadIdx.x; j < p.k; j += 256) Wg[p.w_off + static_cast<int64_t>(j) * p.L + j] += c;
+    if (threadIdx.x == 0) shift[blockIdx.x] = c;
 }
 
 // One round of block Jacobi over every sector: the vectors of a sector form blocks
@@ -1851,7 +1867,8 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
 // workgroup per sector
 __global__ __launch_bounds__(512) void k_svd_finish(const SvdProb* __restrict__ probs, const double* __restrict__ Wg,
                                                      const double* __restrict__ Qg, double* __restrict__ Ug,
-                                                     double* __restrict__ Sg, double* __restrict__ Vtg) {
+                                                     double* __restrict__ Sg, double* __restrict__ Vtg,
+                                                     const double* __restrict__ shift) {
     constexpr int NT = 512, NW = NT / 64;
     __shared__ double sval[kSvdMaxK];
     __shared__ int order[kSvdMaxK];
@@ -1891,9 +1908,11 @@ __global__ __launch_bounds__(512) void k_svd_finish(const SvdProb* __restrict__ 
             }
             __syncthreads();
         }
-    for (int j = tid; j < k; j += NT) Sg[p.s_off + j] = sval[j];
-    // normalised vectors on one side, rotation rows on the other
-    for (int64_t idx = tid; idx < static_cast<int64_t>(k) * L; idx += NT) {
+    const double c = shift ? shift[blockIdx.x] : 0.0;
+    for (int j = tid; j < k; j += NT) Sg[p.s_off + j] = sval[j] - c;
+    // normalised vectors on one side, rotation rows on the other (in eigen
+    // mode the vectors are rows and only the rotation side, U, is wanted)
+    for (int64_t idx = tid; Vtg != nullptr && idx < static_cast<int64_t>(k) * L; idx += NT) {
         const int j = static_cast<int>(idx / L), x = static_cast<int>(idx - static_cast<int64_t>(j) * L);
         const double sv = sval[j];
         const double val = sv > 0.0 ? W[static_cast<int64_t>(order[j]) * L + x] / sv : 0.0;
@@ -1915,7 +1934,7 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 
 hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
-                      double* Vt, double* scale, double* Gpart, int32_t* flag, int32_t* flag_host,
+                      double* Vt, double* scale, double* shift, double* Gpart, int32_t* flag, int32_t* flag_host,
                       int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s) {
     if (n_probs <= 0) return hipSuccess;
     dim3 lgrid(256, static_cast<unsigned>(n_probs));
@@ -1927,6 +1946,8 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
     else
         hipLaunchKernelGGL((k_svd_load<uint16_t>), lgrid, dim3(256), 0, s, static_cast<const uint16_t*>(src), probs, W,
                            Q, scale);
+    if (shift)
+        hipLaunchKernelGGL(k_eig_shift, dim3(static_cast<unsigned>(n_probs)), dim3(256), 0, s, probs, W, scale, shift);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int sweep = 0;
@@ -1951,7 +1972,8 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
         if (*flag_host == 0) break;
     }
     if (sweeps_done) *sweeps_done = sweep;
-    hipLaunchKernelGGL(k_svd_finish, dim3(static_cast<unsigned>(n_probs)), dim3(512), 0, s, probs, W, Q, U, S, Vt);
+    hipLaunchKernelGGL(k_svd_finish, dim3(static_cast<unsigned>(n_probs)), dim3(512), 0, s, probs, W, Q, U, S, Vt,
+                       static_cast<const double*>(shift));
     return hipGetLastError();
 }
 

@@ -245,16 +245,22 @@ struct SvdProb {
     int64_t src_off;              // element offset of the sector matrix (row-major, ld)
     int64_t w_off, q_off;         // FP64 workspace: vectors (k x L), rotations (k x k)
     int64_t u_off, s_off, vt_off; // outputs: U (M x k), S (k), Vt (k x N), row-major
-    int32_t M, N, ld, k, L, rows_are_vectors, pad0, pad1;
+    int32_t M, N, ld, k, L, rows_are_vectors;
+    int32_t sym;                  // eigen mode: load (T + T^T) / 2 of a square sector, then shift it
+    int32_t pad1;
 };
 constexpr int kSvdMaxK = 4096;    // k sorted in LDS
 constexpr int kSvdBlock = 8;      // vectors per block of the block-Jacobi rounds
 constexpr int kSvdSlices = 1;     // workgroups per pair of blocks (slices of the vector entries)
 // Jacobi sweeps until one rotates nothing or max_sweeps; synchronises the
 // stream once per sweep (the stopping decision is taken on the host).
+// shift != NULL selects the eigen mode (every problem has sym set): each
+// symmetric part S is factorised as S + c I, c its Frobenius norm (1 for a
+// zero matrix, c per problem written to shift), S is returned as the
+// singular values minus c and U holds the eigenvectors; Vt may be NULL.
 hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
-                      double* Vt, double* scale, double* Gpart, int32_t* flag, int32_t* flag_host,
+                      double* Vt, double* scale, double* shift, double* Gpart, int32_t* flag, int32_t* flag_host,
                       int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s);
 
 // Resident workgroups per CU of a variant (persistent grid sizing).

@@ -481,6 +481,24 @@ class Context:
                                 c_void_p(Vt.data_ptr()), byref(sweeps), int(max_sweeps), _stream(stream)))
         return U, S, Vt, sweeps.value, shapes
 
+    def eigh(self, t: SymTensor, max_sweeps: int = 60, stream=None):
+        """FP64 eigen-decomposition of the symmetric part of every (square)
+        sector matrix of ``t``.  Returns (V, w, sweeps, shapes): flat FP64
+        device buffers sector after sector (V_s row-major k x k with the
+        eigenvectors as columns, w_s descending), the number of Jacobi sweeps
+        run, and [(label, k)] per sector used.  Synchronises the stream once
+        per sweep."""
+        v, w = c_int64(), c_int64()
+        L.check(L.lib().sym_eigh_sizes(t.handle, byref(v), byref(w)))
+        shapes = [(lab, m) for lab, m, n, _ in t.sectors() if m > 0 and n > 0]
+        dev = t.data.device
+        V = torch.empty(max(1, v.value), dtype=torch.float64, device=dev)[: v.value]
+        W = torch.empty(max(1, w.value), dtype=torch.float64, device=dev)[: w.value]
+        sweeps = c_int32()
+        L.check(L.lib().sym_eigh(self.handle, t.handle, c_void_p(V.data_ptr()), c_void_p(W.data_ptr()), byref(sweeps),
+                                 int(max_sweeps), _stream(stream)))
+        return V, W, sweeps.value, shapes
+
     def svd_truncate(self, t: SymTensor, s_host, chi_max: int, tol: float = 0.0):
         """Global weighted cut of a block SVD: (kept per sector of t, discarded weight)."""
         import numpy as np

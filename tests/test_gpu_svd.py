@@ -1,7 +1,9 @@
 """GPU parity of the block-wise FP64 SVD and its global truncation against the
 oracle (numpy's SVD of each sector matrix built from the canonical blocks),
 plus the properties every SVD has: U diag(S) Vt rebuilds the sector matrix,
-U and Vt have orthonormal columns and rows."""
+U and Vt have orthonormal columns and rows.  The same for the block-wise
+eigen-decomposition of the sectors' symmetric parts (numpy's symmetric
+eigensolver; V diag(w) V^T rebuilds the symmetric part, V is orthonormal)."""
 import numpy as np
 import pytest
 import torch
@@ -93,3 +95,93 @@ def test_global_truncation_matches_oracle(ctx, name):
         rkeep, rlost = SV.truncate(spec, ref, chi)
         assert {secs[i][0]: n for i, n in enumerate(keep) if secs[i][1] > 0 and secs[i][2] > 0} == rkeep
         assert abs(lost - rlost) <= 1e-9 * max(1.0, rlost)
+
+
+def _eig_run(ctx, spec, seed, scale=1.0):
+    g = W.generator(seed, "cuda")
+    a = W.gaussian(T.num_elements(spec), g, "cuda") * scale
+    A = ctx.tensor(spec, 4, data=a)
+    F = ctx.permute_fuse(A, (0, 1, 2, 3), 2)
+    V, w, sweeps, shapes = ctx.eigh(F)
+    torch.cuda.synchronize()
+    return a.double().cpu().numpy(), F, V.cpu().numpy(), w.cpu().numpy(), sweeps, shapes
+
+
+def _check_eig(F, V, w, shapes, ref, orth_tol=1e-12, eig_tol=1e-12):
+    """Per sector: eigenvalues against the oracle's, V diag(w) V^T against the
+    symmetric part of the library's own sector matrix, V^T V = I.  The
+    bounds: the eigenvalues come from the SVD of B = S + c I (c = |S|_F), so
+    their absolute error is a small multiple of sqrt(k) 2^-53 c (about 5e-15 c
+    at k = 2000), and 1e-12 c leaves a wide margin; the decomposition's
+    backward error is relative to B, whose Frobenius norm is about sqrt(k) c,
+    so V diag(w) V^T - S is held to 1e-12 |B|_F."""
+    fused = F.data.double().cpu().numpy()
+    secs = [s for s in F.sectors() if s[1] > 0 and s[2] > 0]
+    assert len(secs) == len(shapes) == len(ref)
+    vo = wo = 0
+    worst = 0.0
+    for (lab, m, n, off), (lab2, k) in zip(secs, shapes):
+        assert lab == lab2 and m == n == k
+        t = fused[off:off + k * k].reshape(k, k)
+        sym = 0.5 * (t + t.T)
+        c = np.linalg.norm(sym) or 1.0
+        wk = w[wo:wo + k]
+        v = V[vo:vo + k * k].reshape(k, k)
+        assert np.all(np.diff(wk) <= 1e-12 * c), lab
+        np.testing.assert_allclose(wk, ref[lab], rtol=0, atol=eig_tol * c, err_msg=str(lab))
+        assert np.linalg.norm((v * wk) @ v.T - sym) <= 1e-12 * np.linalg.norm(sym + c * np.eye(k)), lab
+        assert np.abs(v.T @ v - np.eye(k)).max() <= orth_tol, lab
+        worst = max(worst, float(np.max(np.abs(wk - ref[lab])) / c))
+        vo, wo = vo + k * k, wo + k
+    return worst
+
+
+@pytest.mark.parametrize("name", ["u1_chi20", "u1_chi45", "su2_operator"])
+def test_block_eigh_matches_oracle(ctx, name):
+    say(f"case block eigh {name}")
+    spec = _cases()[name]
+    flat, F, V, w, sweeps, shapes = _eig_run(ctx, spec, 51)
+    worst = _check_eig(F, V, w, shapes, SV.block_eigenvalues(spec, flat, 2))
+    say(f"  {sweeps} sweeps, largest eigenvalue error over c {worst:.2e}")
+    assert 1 <= sweeps < 60
+
+
+def test_block_eigh_of_zero_and_scaled_tensors(ctx):
+    say("case block eigh zero tensor and 1e-30 scaling")
+    spec = _cases()["u1_chi45"]
+    _, F, V, w, sweeps, shapes = _eig_run(ctx, spec, 52, 0.0)
+    assert np.all(w == 0.0)
+    vo = 0
+    for _, k in shapes:
+        v = V[vo:vo + k * k].reshape(k, k)
+        assert np.abs(v.T @ v - np.eye(k)).max() <= 1e-12
+        vo += k * k
+    flat, F, V, w, sweeps, shapes = _eig_run(ctx, spec, 53, 1e-30)
+    _check_eig(F, V, w, shapes, SV.block_eigenvalues(spec, flat, 2))
+
+
+def test_block_eigh_rejects_rectangular_sectors(ctx):
+    say("case block eigh of a covariant tensor (rectangular sectors)")
+    spec = _cases()["u1_covariant"]
+    A = ctx.tensor(spec, 4)
+    F = ctx.permute_fuse(A, (0, 1, 2, 3), 2)
+    with pytest.raises(Exception):
+        ctx.eigh(F)
+
+
+def test_config4_block_eigh_full_size(ctx):
+    """The eigen-decomposition of the symmetric parts of config 4's sectors
+    (17, up to 1976 x 1976), every eigenvalue against numpy's."""
+    say("case config4 full size block eigh")
+    c = W.config4()
+    flat, F, V, w, sweeps, shapes = _eig_run(ctx, c.A, c.seed)
+    assert len(shapes) == 17
+    # at this size rounding accumulates over the rounds: each round applies
+    # a 16 x 16 rotation whose orthogonality is off by about 15 u, and a
+    # vector takes one per round, 14 sweeps x 247 rounds, a random walk of
+    # about sqrt(3458) 15 u = 1e-13 in its norm, so the eigenvalues of
+    # S + c I (up to 2c) move by a few 1e-13 c; the bounds 5e-12 c on the
+    # eigenvalues and 1e-11 on V's orthogonality (as for the SVD's vectors)
+    worst = _check_eig(F, V, w, shapes, SV.block_eigenvalues(c.A, flat, 2), orth_tol=1e-11, eig_tol=5e-12)
+    say(f"  {sweeps} sweeps, largest eigenvalue error over c {worst:.2e}")
+    assert 1 <= sweeps < 60

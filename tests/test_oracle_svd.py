@@ -1,9 +1,13 @@
-"""Oracle pins for the block-wise SVD and its global truncation.
+"""Oracle pins for the block-wise SVD, its global truncation and the
+block-wise symmetric eigen-decomposition.
 
 Pinned against the dense matrix of the same tensor (rows = the first two
 legs): its singular values are the union of the sector values, each SU(2)
 sector's values repeated 2e + 1 times; the truncation's discarded weight is
-the dense tail beyond the kept count (Eckart-Young)."""
+the dense tail beyond the kept count (Eckart-Young); the eigenvalues of its
+symmetric part are the union of the sectors' eigenvalues.  The symmetric part
+itself is pinned by the closed-form spectrum of a tridiagonal Toeplitz
+matrix."""
 import numpy as np
 import pytest
 
@@ -73,3 +77,31 @@ def test_truncation_discards_the_dense_tail(which):
         np.testing.assert_allclose(lost, float(np.sum(dense[used:] ** 2)), rtol=1e-10, atol=1e-12)
         if chi >= dense.size:
             assert lost < 1e-20
+
+
+def test_symmetric_part_of_tridiagonal_toeplitz():
+    # diagonal a, superdiagonal b + d, subdiagonal b - d: the symmetric part is
+    # the Toeplitz matrix (a, b), eigenvalues a + 2 b cos(k pi / (n + 1))
+    n, a, b, d = 37, 0.3, -1.25, 0.8
+    m = a * np.eye(n) + (b + d) * np.eye(n, k=1) + (b - d) * np.eye(n, k=-1)
+    ref = np.sort(a + 2 * b * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1]
+    np.testing.assert_allclose(SV.symmetric_eigenvalues(m), ref, rtol=0, atol=1e-13)
+    # the lower triangle alone (a planted mistake) gives the (a, b - d) spectrum
+    wrong = np.linalg.eigvalsh(m)[::-1]
+    assert np.max(np.abs(wrong - ref)) > 0.5
+    with pytest.raises(ValueError):
+        SV.symmetric_eigenvalues(np.zeros((3, 4)))
+
+
+@pytest.mark.parametrize("which", ["u1", "su2"])
+def test_block_eigenvalues_are_the_dense_spectrum(which):
+    spec = W.config1().A if which == "u1" else W.su2_pair(2, [2, 1, 2])[0]
+    flat = np.random.default_rng(5).standard_normal(T.num_elements(spec))
+    vals = SV.block_eigenvalues(spec, flat, 2)
+    d = _dense_matrix(spec, flat)
+    assert d.shape[0] == d.shape[1]
+    dense = np.linalg.eigvalsh(0.5 * (d + d.T))[::-1]
+    blocks = _spectrum(vals, spec)
+    # every dense row lies in one sector, so nothing is left over
+    assert blocks.size == dense.size
+    np.testing.assert_allclose(dense, blocks, rtol=0, atol=1e-12 * np.abs(dense).max())
