@@ -354,21 +354,30 @@ def secondary(ctx, stream, with_cpu=True):
         gpu_s = time.perf_counter() - t0
         out["svd_u1_chi128_fp64"] = {"gpu_s": round(gpu_s, 3), "jacobi_sweeps": int(sweeps),
                                      "sectors": len(shapes), "max_k": max(k for _, _, _, k in shapes)}
-        # HBM roofline of the Jacobi rounds: a round reads every vector for
-        # the Gram phase (k x L FP64 per sector) and reads and writes the
+        # Roofline of the Jacobi rounds.  Bytes: a round reads every vector
+        # for the Gram phase (k x L FP64 per sector) and reads and writes the
         # vectors and the rows of Q of every pair that rotates (counted here
-        # as if all did, so the rate is an upper estimate); the rounds of one
-        # sweep are one fewer than the blocks of 8 vectors, rounded up to even
+        # as if all did, so the rate is an upper estimate).  FP64 arithmetic:
+        # a pair of blocks (2b vectors) forms its full 2b x 2b Gram matrix
+        # over L entries and multiplies its vectors and rows of Q (L + k
+        # entries) by the 2b x 2b rotation, 2 (2b)^2 (2L + k) flops, over
+        # k / 2b pairs per sector.  The rounds of one sweep are one fewer than
+        # the blocks of b = 16 vectors, rounded up to even.
+        b = 16
         kmax = max(k for _, _, _, k in shapes)
-        nb = -(-kmax // 8)
+        nb = -(-kmax // b)
         rounds = int(sweeps) * (nb + nb % 2 - 1)
         gram_b = sum(8 * k * max(m, n) for _, m, n, k in shapes)
         upd_b = sum(16 * (k * max(m, n) + k * k) for _, m, n, k in shapes)
+        flops = sum(4 * b * k * (2 * max(m, n) + k) for _, m, n, k in shapes)
         out["svd_u1_chi128_fp64"]["roofline"] = {
             "bound": "hbm", "rounds": rounds, "bytes_per_round_upper": gram_b + upd_b,
             "achieved_GBps_upper": round(rounds * (gram_b + upd_b) / gpu_s / 1e9, 1), "peak_GBps": 8000.0,
             "frac_upper": round(rounds * (gram_b + upd_b) / gpu_s / 8e12, 3),
-            "what": "Gram reads plus rotation reads and writes per round, every pair assumed to rotate"}
+            "flops_per_round": flops, "achieved_fp64_TFLOPs": round(rounds * flops / gpu_s / 1e12, 2),
+            "peak_fp64_TFLOPs": 78.6, "fp64_frac": round(rounds * flops / gpu_s / 78.6e12, 3),
+            "what": "full Gram products and rotation updates per round (FP64); Gram reads plus rotation reads "
+                    "and writes per round, every pair assumed to rotate (HBM)"}
         if with_cpu:
             out["svd_u1_chi128_fp64"]["cpu_baseline"] = cpu_baseline_svd(c.A, a4)
         # block-wise eigen-decomposition of the same sectors' symmetric parts

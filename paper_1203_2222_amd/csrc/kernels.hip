@@ -1638,7 +1638,11 @@ __global__ __launch_bounds__(256) void k_eig_shift(const SvdProb* __restrict__ p
 // Jacobi sweep and updates its slice of the vectors and of Q.  Two launches
 // of one slice each measured faster than one launch doing both phases (and
 // than four slices, or more inner sweeps per round) on the largest SVD
-// workload.
+// workload.  Blocks of 16 vectors halve the rounds of a sweep against
+// blocks of 8 for the same bytes per round (config 4's SVD: 0.52 against
+// 0.65 s); a round then does four times the arithmetic per entry, which the
+// update keeps in registers by reading each row of V from LDS once per
+// chunk (holding all of V, 32 x 8 doubles per thread, spilled).
 template <int PHASE>
 __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ probs, int n_probs,
                                                      const int32_t* __restrict__ pair_start, int r,
@@ -1840,22 +1844,34 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
         for (int x0 = ua; x0 < ub; x0 += XC) {
             stage(base, Lx, x0, ub);
             __syncthreads();
-            for (int v = 0; v < XC / 64; ++v) {
-                const int xx = lane + 64 * v;
-                double y[JW];
+            // all NV entries of the thread at once, so that each row of V
+            // is read once per chunk (a copy of V in registers would take
+            // 2b x JW doubles)
+            constexpr int NV = XC / 64;
+            double y[NV][JW];
 #pragma unroll
-                for (int u = 0; u < JW; ++u) y[u] = 0.0;
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < B2; ++i) {
-                    const double t = T[i][xx];
+                for (int u = 0; u < JW; ++u) y[v][u] = 0.0;
+#pragma unroll 2
+            for (int i = 0; i < B2; ++i) {
+                double vr[JW];
 #pragma unroll
-                    for (int u = 0; u < JW; ++u) y[u] = fma(t, V[i][j0 + u], y[u]);
+                for (int u = 0; u < JW; ++u) vr[u] = V[i][j0 + u];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double t = T[i][lane + 64 * v];
+#pragma unroll
+                    for (int u = 0; u < JW; ++u) y[v][u] = fma(t, vr[u], y[v][u]);
                 }
-                const int x = x0 + xx;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int x = x0 + lane + 64 * v;
 #pragma unroll
                 for (int u = 0; u < JW; ++u) {
                     const int c = col(j0 + u);
-                    if (c < k && x < ub) base[static_cast<int64_t>(c) * Lx + x] = y[u];
+                    if (c < k && x < ub) base[static_cast<int64_t>(c) * Lx + x] = y[v][u];
                 }
             }
             __syncthreads();

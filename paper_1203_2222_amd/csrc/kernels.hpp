@@ -250,7 +250,7 @@ struct SvdProb {
     int32_t pad1;
 };
 constexpr int kSvdMaxK = 4096;    // k sorted in LDS
-constexpr int kSvdBlock = 8;      // vectors per block of the block-Jacobi rounds
+constexpr int kSvdBlock = 16;     // vectors per block of the block-Jacobi rounds
 constexpr int kSvdSlices = 1;     // workgroups per pair of blocks (slices of the vector entries)
 // Jacobi sweeps until one rotates nothing or max_sweeps; synchronises the
 // stream once per sweep (the stopping decision is taken on the host).

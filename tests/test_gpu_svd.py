@@ -177,9 +177,9 @@ def test_config4_block_eigh_full_size(ctx):
     flat, F, V, w, sweeps, shapes = _eig_run(ctx, c.A, c.seed)
     assert len(shapes) == 17
     # at this size rounding accumulates over the rounds: each round applies
-    # a 16 x 16 rotation whose orthogonality is off by about 15 u, and a
-    # vector takes one per round, 14 sweeps x 247 rounds, a random walk of
-    # about sqrt(3458) 15 u = 1e-13 in its norm, so the eigenvalues of
+    # a 32 x 32 rotation whose orthogonality is off by about 31 u, and a
+    # vector takes one per round, 15 sweeps x 123 rounds, a random walk of
+    # about sqrt(1845) 31 u = 1.5e-13 in its norm, so the eigenvalues of
     # S + c I (up to 2c) move by a few 1e-13 c; the bounds 5e-12 c on the
     # eigenvalues and 1e-11 on V's orthogonality (as for the SVD's vectors)
     worst = _check_eig(F, V, w, shapes, SV.block_eigenvalues(c.A, flat, 2), orth_tol=1e-11, eig_tol=5e-12)
