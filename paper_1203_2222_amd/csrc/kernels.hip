@@ -1636,13 +1636,16 @@ __global__ __launch_bounds__(256) void k_eig_shift(const SvdProb* __restrict__ p
 // matrix to Gpart; PHASE 1 sums the partials in a fixed order (every slice
 // gets the same G, so results do not depend on scheduling), makes the small
 // Jacobi sweep and updates its slice of the vectors and of Q.  Two launches
-// of one slice each measured faster than one launch doing both phases (and
-// than four slices, or more inner sweeps per round) on the largest SVD
-// workload.  Blocks of 16 vectors halve the rounds of a sweep against
-// blocks of 8 for the same bytes per round (config 4's SVD: 0.52 against
-// 0.65 s); a round then does four times the arithmetic per entry, which the
-// update keeps in registers by reading each row of V from LDS once per
-// chunk (holding all of V, 32 x 8 doubles per thread, spilled).
+// measured faster than one launch doing both phases (or more inner sweeps
+// per round) on the largest SVD workload.  Blocks of 16 vectors halve the
+// rounds of a sweep against blocks of 8 for the same bytes per round
+// (config 4's SVD: 0.52 against 0.65 s); a round then does four times the
+// arithmetic per entry, which the update keeps in registers by reading each
+// row of V from LDS once per chunk (holding all of V, 32 x 8 doubles per
+// thread, spilled).  With 16-vector blocks the largest workload has about
+// 450 block pairs per round, under two workgroups per CU: two slices per
+// pair measured 223 us per round against 250 us with one and 249 us with
+// four.
 template <int PHASE>
 __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ probs, int n_probs,
                                                      const int32_t* __restrict__ pair_start, int r,

@@ -251,7 +251,7 @@ struct SvdProb {
 };
 constexpr int kSvdMaxK = 4096;    // k sorted in LDS
 constexpr int kSvdBlock = 16;     // vectors per block of the block-Jacobi rounds
-constexpr int kSvdSlices = 1;     // workgroups per pair of blocks (slices of the vector entries)
+constexpr int kSvdSlices = 2;     // workgroups per pair of blocks (slices of the vector entries)
 // Jacobi sweeps until one rotates nothing or max_sweeps; synchronises the
 // stream once per sweep (the stopping decision is taken on the host).
 // shift != NULL selects the eigen mode (every problem has sym set): each
