@@ -397,6 +397,15 @@ def secondary(ctx, stream, with_cpu=True):
             out["eigh_u1_chi128_fp64"]["cpu_baseline"] = {
                 "value": round(time.perf_counter() - t0, 3), "unit": "s", "kind": "oracle",
                 "cores": len(os.sched_getaffinity(0)), "sample": "all 17 sectors, eigenvalues only"}
+        # block-wise polar decomposition of the same sectors (the SVD, then
+        # W = U Vt and P = V diag(S) Vt as FP64 products on the device)
+        ctx.polar(F, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, psweeps, _ = ctx.polar(F, stream=stream)
+        torch.cuda.synchronize()
+        out["polar_u1_chi128_fp64"] = {"gpu_s": round(time.perf_counter() - t0, 3), "jacobi_sweeps": int(psweeps),
+                                       "sectors": len(shapes)}
         del A, F, S, w, a4
 
         # config 5: SU(2) contraction + recoupling, FP32

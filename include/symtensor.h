@@ -524,6 +524,26 @@ int32_t sym_svd(sym_ctx* ctx, const sym_tensor* T, double* U, double* S, double*
 int32_t sym_eigh_sizes(const sym_tensor* T, int64_t* v_elems, int64_t* w_elems);
 int32_t sym_eigh(sym_ctx* ctx, const sym_tensor* T, double* V, double* w, int32_t* sweeps, int32_t max_sweeps,
                  void* stream);
+/* Block-wise polar decomposition (section "Factorization of a matrix": like
+ * the spectral decomposition, it is obtained by factorising every block on
+ * its own): each sector matrix T_s (M_s x N_s, rows = T's first n_row legs)
+ * is written as T_s = W_s P_s when M_s >= N_s, or T_s = P_s W_s when
+ * M_s < N_s, with W_s = U_s Vt_s (M_s x N_s, orthonormal columns or rows)
+ * and P_s = V_s diag(s_s) Vt_s or U_s diag(s_s) U_s^T (k_s x k_s, symmetric
+ * positive semidefinite), from the block SVD of sym_svd (same method and
+ * stopping rule, same once-per-sweep synchronisation of `stream`) followed
+ * by FP64 products on the device.  W and P are FP64 device buffers, sector
+ * after sector in T's sector order (sectors with no rows or no columns
+ * skipped), row-major; sym_polar_sizes gives their element counts.  P may be
+ * NULL (only W is written).  For a rank-deficient sector W_s is zero on the
+ * null space (the singular vectors of zero singular values are zero), so it
+ * is a partial isometry.  sweeps (host, may be NULL) receives the number of
+ * sweeps.  SYM_E_UNSUPPORTED for a sector with min(M_s, N_s) > 4096.  The
+ * U, S and Vt workspaces belong to the context, so calls on one structure
+ * must not overlap. */
+int32_t sym_polar_sizes(const sym_tensor* T, int64_t* w_elems, int64_t* p_elems);
+int32_t sym_polar(sym_ctx* ctx, const sym_tensor* T, double* W, double* P, int32_t* sweeps, int32_t max_sweeps,
+                  void* stream);
 /* Global truncation of a block SVD (host; S is a host copy of sym_svd's S):
  * the singular values of all sectors are taken in descending order, each
  * counting w_s times (1 for the Abelian groups, 2e + 1 for the SU(2) sector

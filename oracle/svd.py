@@ -93,6 +93,24 @@ def block_eigenvalues(spec, flat, n_row: int) -> Dict[object, np.ndarray]:
     return {s: symmetric_eigenvalues(m) for s, m in sector_matrices(spec, flat, n_row).items()}
 
 
+def polar_factors(m: np.ndarray):
+    """(W, P) of the polar decomposition of a matrix from numpy's SVD
+    m = U diag(s) Vt: W = U Vt, and P = V diag(s) Vt with m = W P when
+    rows >= columns, else P = U diag(s) U^T with m = P W."""
+    m = np.asarray(m, dtype=np.float64)
+    u, sv, vt = np.linalg.svd(m, full_matrices=False)
+    w = u @ vt
+    p = (vt.T * sv) @ vt if m.shape[0] >= m.shape[1] else (u * sv) @ u.T
+    return w, p
+
+
+def block_polar(spec, flat, n_row: int) -> Dict[object, tuple]:
+    """{sector: (W, P)} of each sector matrix (section "Factorization of a
+    matrix": the polar decomposition, like the SVD, is taken block by
+    block)."""
+    return {s: polar_factors(m) for s, m in sector_matrices(spec, flat, n_row).items()}
+
+
 def multiplicity(spec, sector) -> int:
     return sector + 1 if spec.group == T.SU2 else 1
 

@@ -89,6 +89,8 @@ SIGNATURES = {
     "sym_svd_truncate": (c_int32, [P, P, c_int64, c_double, I32P, POINTER(c_double)]),
     "sym_eigh_sizes": (c_int32, [P, I64P, I64P]),
     "sym_eigh": (c_int32, [P, P, P, P, I32P, c_int32, P]),
+    "sym_polar_sizes": (c_int32, [P, I64P, I64P]),
+    "sym_polar": (c_int32, [P, P, P, P, I32P, c_int32, P]),
     "sym_default_variant": (c_int32, [c_int32, I32P]),
     "sym_fmove_coeff": (c_double, [c_int32] * 6),
     "sym_last_error": (c_char_p, []),

@@ -124,6 +124,13 @@ struct SvdPlan {
     int64_t u_elems = 0, s_elems = 0, vt_elems = 0, w_elems = 0, q_elems = 0;
     DevMemPtr d_probs, d_pairs, w, q, scale, shift, gpart, flag;
     int32_t flag_host = 0;
+    // polar mode: the products that turn U, S, Vt (kept in uv and s) into
+    // W and P; tiles of the W products first
+    std::vector<PolarGemm> pgemm;
+    std::vector<PolarTile> ptiles;
+    int32_t n_wtiles = 0;
+    int64_t pw_elems = 0, pp_elems = 0;
+    DevMemPtr uv, s, d_pgemm, d_ptiles;
 };
 
 // Plans kept alive for as long as a caller needs them (sym_hold_*): a graph
@@ -2011,6 +2018,63 @@ std::shared_ptr<SvdPlan> svd_plan_of(const Desc& d, bool eig) {
     return plan;
 }
 
+// W = U Vt (M x N) and P = V diag(S) Vt (rows >= columns) or U diag(S) U^T
+// (k x k) of every sector, with U at offset 0 and Vt at offset u_elems of
+// one buffer
+void polar_tables(SvdPlan& plan) {
+    std::vector<PolarGemm> wp, pp;
+    for (const SvdProb& p : plan.probs) {
+        const int64_t vt0 = plan.u_elems + p.vt_off;
+        PolarGemm w{};
+        w.a_off = p.u_off;
+        w.as0 = p.k;
+        w.as1 = 1;
+        w.b_off = vt0;
+        w.bs0 = p.N;
+        w.bs1 = 1;
+        w.m = p.M;
+        w.n = p.N;
+        w.kk = p.k;
+        w.d_off = -1;
+        w.c_off = plan.pw_elems;
+        w.ldc = p.N;
+        w.which = 0;
+        plan.pw_elems += static_cast<int64_t>(p.M) * p.N;
+        wp.push_back(w);
+        PolarGemm q{};
+        if (p.M >= p.N) {   // V diag(S) Vt: A(i, l) = Vt[l][i], B(l, j) = Vt[l][j]
+            q.a_off = vt0;
+            q.as0 = 1;
+            q.as1 = p.N;
+            q.b_off = vt0;
+            q.bs0 = p.N;
+            q.bs1 = 1;
+        } else {            // U diag(S) U^T: A(i, l) = U[i][l], B(l, j) = U[j][l]
+            q.a_off = p.u_off;
+            q.as0 = p.k;
+            q.as1 = 1;
+            q.b_off = p.u_off;
+            q.bs0 = 1;
+            q.bs1 = p.k;
+        }
+        q.m = q.n = q.kk = p.k;
+        q.d_off = p.s_off;
+        q.c_off = plan.pp_elems;
+        q.ldc = p.k;
+        q.which = 1;
+        plan.pp_elems += static_cast<int64_t>(p.k) * p.k;
+        pp.push_back(q);
+    }
+    plan.pgemm = wp;
+    plan.pgemm.insert(plan.pgemm.end(), pp.begin(), pp.end());
+    for (size_t g = 0; g < plan.pgemm.size(); ++g) {
+        const PolarGemm& q = plan.pgemm[g];
+        for (int32_t i0 = 0; i0 < q.m; i0 += kPolarTile)
+            for (int32_t j0 = 0; j0 < q.n; j0 += kPolarTile) plan.ptiles.push_back({static_cast<int32_t>(g), i0, j0, 0});
+        if (g + 1 == wp.size()) plan.n_wtiles = static_cast<int32_t>(plan.ptiles.size());
+    }
+}
+
 }  // namespace
 
 int32_t sym_svd_sizes(const sym_tensor* T, int64_t* u_elems, int64_t* s_elems, int64_t* vt_elems) {
@@ -2027,8 +2091,9 @@ namespace {
 
 // the cached plan of T's structure (one per mode), built and uploaded on the
 // first call
-std::shared_ptr<SvdPlan> svd_plan_cached(sym_ctx* ctx, const sym_tensor* T, bool eig, hipStream_t stream) {
-    const std::string key = (eig ? "E|" : "S|") + T->d->key;
+std::shared_ptr<SvdPlan> svd_plan_cached(sym_ctx* ctx, const sym_tensor* T, bool eig, hipStream_t stream,
+                                         bool polar = false) {
+    const std::string key = (eig ? "E|" : polar ? "P|" : "S|") + T->d->key;
     std::shared_ptr<SvdPlan> plan;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -2050,6 +2115,17 @@ std::shared_ptr<SvdPlan> svd_plan_cached(sym_ctx* ctx, const sym_tensor* T, bool
         plan->flag = alloc(sizeof(int32_t));
         plan->scale = alloc(plan->probs.size() * sizeof(double));
         if (eig) plan->shift = alloc(plan->probs.size() * sizeof(double));
+        if (polar) {
+            polar_tables(*plan);
+            plan->uv = alloc(static_cast<size_t>(plan->u_elems + plan->vt_elems) * sizeof(double));
+            plan->s = alloc(static_cast<size_t>(plan->s_elems) * sizeof(double));
+            BuildUploads pu;
+            plan->d_pgemm = alloc(plan->pgemm.size() * sizeof(PolarGemm));
+            pu.copies.push_back({plan->d_pgemm->ptr, plan->pgemm.data(), plan->pgemm.size() * sizeof(PolarGemm)});
+            plan->d_ptiles = alloc(plan->ptiles.size() * sizeof(PolarTile));
+            pu.copies.push_back({plan->d_ptiles->ptr, plan->ptiles.data(), plan->ptiles.size() * sizeof(PolarTile)});
+            pu.finish(stream);
+        }
         plan->gpart = alloc(static_cast<size_t>(std::max<int32_t>(1, plan->pair_start.back())) * kSvdSlices *
                             (4 * kSvdBlock * kSvdBlock) * sizeof(double));
     }
@@ -2111,6 +2187,38 @@ int32_t sym_eigh(sym_ctx* ctx, const sym_tensor* T, double* V, double* w, int32_
         if (!V || !w) throw Error(SYM_E_ARG, "NULL argument");
         ctx->note(plan);
         run_svd(T, *plan, V, w, nullptr, sweeps, max_sweeps, static_cast<hipStream_t>(stream));
+    });
+}
+
+int32_t sym_polar_sizes(const sym_tensor* T, int64_t* w_elems, int64_t* p_elems) {
+    return guard([&] {
+        if (!T || !w_elems || !p_elems) throw Error(SYM_E_ARG, "NULL argument");
+        auto plan = svd_plan_of(*T->d, false);
+        polar_tables(*plan);
+        *w_elems = plan->pw_elems;
+        *p_elems = plan->pp_elems;
+    });
+}
+
+int32_t sym_polar(sym_ctx* ctx, const sym_tensor* T, double* W, double* P, int32_t* sweeps, int32_t max_sweeps,
+                  void* stream) {
+    return guard([&] {
+        if (!ctx || !T) throw Error(SYM_E_ARG, "NULL argument");
+        if (!has_data(T)) throw Error(SYM_E_ARG, "tensor has no data pointer");
+        if (max_sweeps < 1) throw Error(SYM_E_ARG, "max_sweeps must be >= 1");
+        auto plan = svd_plan_cached(ctx, T, false, static_cast<hipStream_t>(stream), true);
+        if (sweeps) *sweeps = 0;
+        if (plan->probs.empty()) return;
+        if (!W) throw Error(SYM_E_ARG, "NULL argument");
+        ctx->note(plan);
+        double* uv = static_cast<double*>(plan->uv->ptr);
+        double* sv = static_cast<double*>(plan->s->ptr);
+        run_svd(T, *plan, uv, sv, uv + plan->u_elems, sweeps, max_sweeps, static_cast<hipStream_t>(stream));
+        // the W products always; the P products only when P is wanted
+        const int32_t n = P ? static_cast<int32_t>(plan->ptiles.size()) : plan->n_wtiles;
+        HIP_CHECK(launch_polar(static_cast<const PolarGemm*>(plan->d_pgemm->ptr),
+                               static_cast<const PolarTile*>(plan->d_ptiles->ptr), n, uv, sv, W, P,
+                               static_cast<hipStream_t>(stream)));
     });
 }
 

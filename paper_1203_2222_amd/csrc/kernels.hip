@@ -1996,6 +1996,74 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
     return hipGetLastError();
 }
 
+// Polar decomposition from the block SVD (T = U diag(S) Vt): the isometric
+// factor W = U Vt and the positive factor P = V diag(S) Vt (T = W P, rows >=
+// columns) or U diag(S) U^T (T = P W), as FP64 products over 64 x 64 output
+// tiles, 16-deep slices of the inner dimension staged in LDS, 4 x 4 outputs
+// per thread.
+__global__ __launch_bounds__(256) void k_polar_gemm(const PolarGemm* __restrict__ probs,
+                                                    const PolarTile* __restrict__ tiles,
+                                                    const double* __restrict__ uv, const double* __restrict__ S,
+                                                    double* __restrict__ W, double* __restrict__ P) {
+    constexpr int TT = kPolarTile, TK = 16;
+    __shared__ double As[TK][TT + 1];
+    __shared__ double Bs[TK][TT + 1];
+    const PolarTile t = tiles[blockIdx.x];
+    const PolarGemm p = probs[t.prob];
+    const int tid = static_cast<int>(threadIdx.x), tx = tid & 15, ty = tid >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int l0 = 0; l0 < p.kk; l0 += TK) {
+        for (int e = tid; e < TT * TK; e += 256) {
+            const int i = e % TT, l = e / TT, gi = t.i0 + i, gl = l0 + l;
+            double v = 0.0;
+            if (gi < p.m && gl < p.kk) {
+                v = uv[p.a_off + static_cast<int64_t>(gi) * p.as0 + static_cast<int64_t>(gl) * p.as1];
+                if (p.d_off >= 0) v *= S[p.d_off + gl];
+            }
+            As[l][i] = v;
+        }
+        for (int e = tid; e < TT * TK; e += 256) {
+            const int j = e % TT, l = e / TT, gj = t.j0 + j, gl = l0 + l;
+            Bs[l][j] = (gj < p.n && gl < p.kk)
+                           ? uv[p.b_off + static_cast<int64_t>(gl) * p.bs0 + static_cast<int64_t>(gj) * p.bs1]
+                           : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int l = 0; l < TK; ++l) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[l][ty + 16 * r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[l][tx + 16 * c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+    double* C = p.which == 0 ? W : P;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int gi = t.i0 + ty + 16 * r, gj = t.j0 + tx + 16 * c;
+            if (gi < p.m && gj < p.n) C[p.c_off + static_cast<int64_t>(gi) * p.ldc + gj] = acc[r][c];
+        }
+}
+
+hipError_t launch_polar(const PolarGemm* probs, const PolarTile* tiles, int32_t n_tiles, const double* uv,
+                        const double* S, double* W, double* P, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_polar_gemm, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s, probs, tiles, uv, S, W, P);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // K9: SU(2) PERMUTE with recoupling.  For one label tuple, the n input
 // blocks P^e are combined with the FP64 coefficients Gamma[f][e] of the

@@ -262,6 +262,21 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
                       double* Vt, double* scale, double* shift, double* Gpart, int32_t* flag, int32_t* flag_host,
                       int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s);
+// Polar factors from a block SVD: per sector one or two FP64 products
+// C = A diag(d) B with A(i, l) = a[a_off + i as0 + l as1] and
+// B(l, j) = a[b_off + l bs0 + j bs1], both read from one buffer (U then Vt),
+// d = S (or none when d_off < 0), C row-major with leading dimension ldc in
+// out[which].
+struct PolarGemm {
+    int64_t a_off, b_off, c_off, d_off;
+    int32_t m, n, kk, as0, as1, bs0, bs1, ldc, which, pad;
+};
+struct PolarTile {
+    int32_t prob, i0, j0, pad;
+};
+constexpr int kPolarTile = 64;    // output tile edge of the polar products
+hipError_t launch_polar(const PolarGemm* probs, const PolarTile* tiles, int32_t n_tiles, const double* uv,
+                        const double* S, double* W, double* P, hipStream_t s);
 
 // Resident workgroups per CU of a variant (persistent grid sizing).
 int gemm_blocks_per_cu(int compute, int variant);

@@ -499,6 +499,24 @@ class Context:
                                  int(max_sweeps), _stream(stream)))
         return V, W, sweeps.value, shapes
 
+    def polar(self, t: SymTensor, max_sweeps: int = 60, want_p: bool = True, stream=None):
+        """FP64 polar decomposition of every sector matrix of ``t``: T_s = W_s P_s
+        (rows >= columns) or P_s W_s.  Returns (W, P, sweeps, shapes): flat
+        FP64 device buffers sector after sector (W_s row-major M x N, P_s
+        row-major k x k, P None unless want_p), the number of Jacobi sweeps,
+        and [(label, M, N, k)] per sector used."""
+        w, p = c_int64(), c_int64()
+        L.check(L.lib().sym_polar_sizes(t.handle, byref(w), byref(p)))
+        shapes = [(lab, m, n, min(m, n)) for lab, m, n, _ in t.sectors() if m > 0 and n > 0]
+        dev = t.data.device
+        W = torch.empty(max(1, w.value), dtype=torch.float64, device=dev)[: w.value]
+        P = torch.empty(max(1, p.value), dtype=torch.float64, device=dev)[: p.value] if want_p else None
+        sweeps = c_int32()
+        L.check(L.lib().sym_polar(self.handle, t.handle, c_void_p(W.data_ptr()),
+                                  c_void_p(P.data_ptr()) if want_p else None, byref(sweeps), int(max_sweeps),
+                                  _stream(stream)))
+        return W, P, sweeps.value, shapes
+
     def svd_truncate(self, t: SymTensor, s_host, chi_max: int, tol: float = 0.0):
         """Global weighted cut of a block SVD: (kept per sector of t, discarded weight)."""
         import numpy as np

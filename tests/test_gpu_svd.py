@@ -185,3 +185,66 @@ def test_config4_block_eigh_full_size(ctx):
     worst = _check_eig(F, V, w, shapes, SV.block_eigenvalues(c.A, flat, 2), orth_tol=1e-11, eig_tol=5e-12)
     say(f"  {sweeps} sweeps, largest eigenvalue error over c {worst:.2e}")
     assert 1 <= sweeps < 60
+
+
+def _check_polar(F, W, P, shapes, ref_sv, orth_tol=1e-12, rec_tol=1e-12):
+    """Per sector, against the oracle's singular values of the canonical
+    input: W is an isometry, trace(W^T T) is the sum of the singular values
+    (the polar factor maximises it over isometries, and only it reaches it
+    for a full-rank T), P is symmetric with the singular values as its
+    eigenvalues, and W P (or P W) rebuilds the library's sector matrix."""
+    fused = F.data.double().cpu().numpy()
+    secs = [s for s in F.sectors() if s[1] > 0 and s[2] > 0]
+    assert len(secs) == len(shapes) == len(ref_sv)
+    wo = po = 0
+    for (lab, m, n, off), (_, _, _, k) in zip(secs, shapes):
+        t = fused[off:off + m * n].reshape(m, n)
+        w = W[wo:wo + m * n].reshape(m, n)
+        p = P[po:po + k * k].reshape(k, k)
+        r = ref_sv[lab]
+        scale = max(1.0, r[0])
+        g = w.T @ w if m >= n else w @ w.T
+        assert np.abs(g - np.eye(k)).max() <= orth_tol, lab
+        assert abs(np.sum(w * t) - r.sum()) <= 1e-12 * scale * k, lab
+        assert np.abs(p - p.T).max() <= 1e-12 * scale, lab
+        np.testing.assert_allclose(np.linalg.eigvalsh(0.5 * (p + p.T))[::-1], r, rtol=0, atol=1e-11 * scale,
+                                   err_msg=str(lab))
+        rec = w @ p if m >= n else p @ w
+        assert np.linalg.norm(rec - t) <= rec_tol * max(1.0, np.linalg.norm(t)), lab
+        wo, po = wo + m * n, po + k * k
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_block_polar_matches_oracle(ctx, name):
+    say(f"case block polar {name}")
+    spec = _cases()[name]
+    g = W.generator(61, "cuda")
+    a = W.gaussian(T.num_elements(spec), g, "cuda")
+    A = ctx.tensor(spec, 4, data=a)
+    F = ctx.permute_fuse(A, (0, 1, 2, 3), 2)
+    Wd, Pd, sweeps, shapes = ctx.polar(F)
+    torch.cuda.synchronize()
+    _check_polar(F, Wd.cpu().numpy(), Pd.cpu().numpy(), shapes,
+                 SV.block_singular_values(spec, a.double().cpu().numpy(), 2))
+    # W alone (no P buffer) gives the same W
+    W2, P2, _, _ = ctx.polar(F, want_p=False)
+    torch.cuda.synchronize()
+    assert P2 is None and torch.allclose(W2, Wd, rtol=0, atol=1e-13)
+    assert 1 <= sweeps < 60
+
+
+def test_config4_block_polar_full_size(ctx):
+    """Polar factors of config 4's 17 sectors (up to 1976 x 1976)."""
+    say("case config4 full size block polar")
+    c = W.config4()
+    g = W.generator(c.seed, "cuda")
+    a = W.gaussian(T.num_elements(c.A), g, "cuda")
+    A = ctx.tensor(c.A, 4, data=a)
+    F = ctx.permute_fuse(A, (0, 1, 2, 3), 2)
+    Wd, Pd, sweeps, shapes = ctx.polar(F)
+    torch.cuda.synchronize()
+    say(f"  {len(shapes)} sectors, {sweeps} sweeps")
+    # orthogonality and reconstruction at this size as for the SVD's vectors
+    # (a random walk of the rounds' rounding)
+    _check_polar(F, Wd.cpu().numpy(), Pd.cpu().numpy(), shapes,
+                 SV.block_singular_values(c.A, a.double().cpu().numpy(), 2), orth_tol=1e-11, rec_tol=1e-11)

@@ -105,3 +105,41 @@ def test_block_eigenvalues_are_the_dense_spectrum(which):
     # every dense row lies in one sector, so nothing is left over
     assert blocks.size == dense.size
     np.testing.assert_allclose(dense, blocks, rtol=0, atol=1e-12 * np.abs(dense).max())
+
+
+@pytest.mark.parametrize("shape", [(9, 6), (6, 9), (7, 7)])
+def test_polar_factors_of_a_built_matrix(shape):
+    # m = Qa diag(s) Qb^T with orthonormal Qa, Qb: the polar factor is
+    # Qa Qb^T and the positive factor Qb diag(s) Qb^T (rows >= columns) or
+    # Qa diag(s) Qa^T
+    rng = np.random.default_rng(11)
+    M, N = shape
+    k = min(M, N)
+    qa, _ = np.linalg.qr(rng.standard_normal((M, k)))
+    qb, _ = np.linalg.qr(rng.standard_normal((N, k)))
+    s = np.linspace(3.0, 0.5, k)
+    m = (qa * s) @ qb.T
+    w, p = SV.polar_factors(m)
+    np.testing.assert_allclose(w, qa @ qb.T, atol=1e-13)
+    pref = (qb * s) @ qb.T if M >= N else (qa * s) @ qa.T
+    np.testing.assert_allclose(p, pref, atol=1e-13)
+    np.testing.assert_allclose(w @ p if M >= N else p @ w, m, atol=1e-13)
+    # a transposed right factor (a planted mistake) is not the polar factor
+    if M == N:
+        u, _, vt = np.linalg.svd(m)
+        assert np.abs(u @ vt.T - qa @ qb.T).max() > 1e-3
+
+
+def test_polar_of_a_scalar_is_its_sign_and_size():
+    w, p = SV.polar_factors(np.array([[-3.0]]))
+    assert w[0, 0] == pytest.approx(-1.0) and p[0, 0] == pytest.approx(3.0)
+
+
+def test_block_polar_rebuilds_every_sector():
+    spec = _u1_cases()[1]          # sectors of unequal rows and columns
+    flat = np.random.default_rng(6).standard_normal(T.num_elements(spec))
+    mats = SV.sector_matrices(spec, flat, 2)
+    for sec, (w, p) in SV.block_polar(spec, flat, 2).items():
+        m = mats[sec]
+        np.testing.assert_allclose(w @ p if m.shape[0] >= m.shape[1] else p @ w, m, atol=1e-12)
+        np.testing.assert_allclose(p, p.T, atol=1e-13)
