@@ -331,6 +331,34 @@ def test_svd_size_limit_and_sizes():
     assert (u.value, s.value, v.value) == (0, 0, 0)
 
 
+def test_eigh_and_polar_sizes():
+    # sym_eigh_sizes: square sectors only (V k x k, w k); sym_polar_sizes:
+    # W M x N and P k x k per sector; both planned on the host
+    from ctypes import byref, c_int64
+    L = _lib_or_skip()
+    ctx = _ctx()
+
+    def desc(m, n):
+        spec = W.TensorSpec(W.U1, (W.u1_leg(0, 0, [m], "in"), W.u1_leg(0, 0, [n], "out")))
+        return ctx.describe(spec, 1)
+
+    a, b = c_int64(), c_int64()
+    assert L.lib().sym_eigh_sizes(desc(37, 37).handle, byref(a), byref(b)) == 0
+    assert (a.value, b.value) == (37 * 37, 37)
+    assert L.lib().sym_eigh_sizes(desc(37, 40).handle, byref(a), byref(b)) == 8      # rectangular
+    assert L.lib().sym_eigh_sizes(desc(4097, 4097).handle, byref(a), byref(b)) == 8  # beyond 4096
+    for m, n in ((30, 50), (50, 30), (16, 16)):
+        assert L.lib().sym_polar_sizes(desc(m, n).handle, byref(a), byref(b)) == 0
+        assert (a.value, b.value) == (m * n, min(m, n) ** 2)
+    c4 = W.config4().A
+    t = ctx.describe(c4, 2)
+    ks = [m for _, m, n, _ in t.sectors() if m > 0]
+    assert L.lib().sym_eigh_sizes(t.handle, byref(a), byref(b)) == 0
+    assert (a.value, b.value) == (sum(k * k for k in ks), sum(ks))
+    assert L.lib().sym_polar_sizes(t.handle, byref(a), byref(b)) == 0
+    assert (a.value, b.value) == (sum(k * k for k in ks), sum(k * k for k in ks))
+
+
 def test_missing_library_fails_loudly():
     # no CPU fallback: without libsymtensor.so the first library call raises
     import subprocess
