@@ -1,5 +1,6 @@
-"""Block-wise singular value decomposition with a global truncation (oracle;
-test infrastructure only).
+"""Block-wise singular value decomposition with a global truncation, and the
+block-wise eigen (spectral) and polar decompositions (oracle; test
+infrastructure only).
 
 A symmetric matrix is block diagonal in its sectors, so its SVD is the SVD
 of each degeneracy matrix on its own (section "Factorization of a matrix";
@@ -8,6 +9,11 @@ singular values of the whole matrix are those of every T_s, each repeated
 w_s times (w_s = 1 for the Abelian groups, 2e + 1 for the SU(2) sector of
 coupled spin e).  Truncating the whole matrix to its largest values is then
 a cut over all sectors' values counted with those multiplicities.
+
+The thesis obtains the spectral and polar decompositions the same way, one
+block at a time: here the eigenvalues of each sector's symmetric part, and
+the polar factors W = U Vt and P = V diag(s) Vt (or U diag(s) U^T) of each
+sector from numpy's SVD.
 
 Sector matrices are built here from the canonical block list directly: rows
 are the label tuples of the first n_row legs (with the internal spin for
