@@ -146,6 +146,25 @@ def test_block_eigh_matches_oracle(ctx, name):
     assert 1 <= sweeps < 60
 
 
+def test_block_eigh_of_bf16_data(ctx):
+    # BF16 storage: the symmetric parts of the stored (rounded) values
+    say("case block eigh bf16 storage")
+    spec = _cases()["u1_chi45"]
+    g = W.generator(54, "cuda")
+    a = W.gaussian(T.num_elements(spec), g, "cuda").to(torch.bfloat16)
+    A = ctx.tensor(spec, 4, "bf16", data=a)
+    F = ctx.permute_fuse(A, (0, 1, 2, 3), 2)
+    V, w, sweeps, shapes = ctx.eigh(F)
+    torch.cuda.synchronize()
+    flat = a.float().double().cpu().numpy()
+    ref = SV.block_eigenvalues(spec, flat, 2)
+    wo = 0
+    for lab, k in shapes:
+        c = np.linalg.norm(ref[lab])      # the Frobenius norm of the symmetric part
+        np.testing.assert_allclose(w.cpu().numpy()[wo:wo + k], ref[lab], rtol=0, atol=1e-12 * c, err_msg=str(lab))
+        wo += k
+
+
 def test_block_eigh_of_zero_and_scaled_tensors(ctx):
     say("case block eigh zero tensor and 1e-30 scaling")
     spec = _cases()["u1_chi45"]
