@@ -955,12 +955,35 @@ void RecoupleProgram::build_fuse(const Desc& unf, const Desc& fus, int leg, bool
     }
 }
 
+namespace {
+
+// One workgroup per task, dispatched in order, workgroup w on XCD w % 8:
+// inside each window of g tasks (about the workgroups resident at once),
+// XCD x takes a contiguous run of g / 8 tasks, so that neighbouring tasks,
+// which share the cache lines at their edges, meet in one L2.  Measured on
+// config 5: the tiled kernel's full reversal 0.973 against 1.00 ms; the
+// element-wise kernel's tasks (16384 consecutive output entries each, few
+// shared lines) ran 2 to 3 % slower that way and keep their order.
+template <typename Task>
+void xcd_runs(std::vector<Task>& v, size_t begin, size_t end) {
+    constexpr int64_t g = 2048, per = g / 8;
+    std::vector<Task> seq(v.begin() + static_cast<std::ptrdiff_t>(begin), v.begin() + static_cast<std::ptrdiff_t>(end));
+    const int64_t n = static_cast<int64_t>(seq.size());
+    for (int64_t r0 = 0; r0 + g <= n; r0 += g)
+        for (int64_t w = 0; w < g; ++w)
+            v[begin + static_cast<size_t>(r0 + w)] = seq[static_cast<size_t>(r0 + (w % 8) * per + w / 8)];
+}
+
+}  // namespace
+
 void RecoupleProgram::upload(const Allocator& alloc, Deferred* deferred) {
     // the tasks of small tuples first: they run in the high-occupancy kernel
     auto small = [&](const FmTask& t) { return groups[static_cast<size_t>(t.group)].n <= kRecoupleSmallN; };
     n_small = static_cast<int32_t>(std::stable_partition(tasks.begin(), tasks.end(), small) - tasks.begin());
     auto tsmall = [&](const FtTask& t) { return tgroups[static_cast<size_t>(t.group)].n <= kRecoupleTiledSmallN; };
     n_tsmall = static_cast<int32_t>(std::stable_partition(ttasks.begin(), ttasks.end(), tsmall) - ttasks.begin());
+    xcd_runs(ttasks, 0, static_cast<size_t>(n_tsmall));
+    xcd_runs(ttasks, static_cast<size_t>(n_tsmall), ttasks.size());
     d_groups = upload_vec(alloc, groups, deferred);
     d_in = upload_vec(alloc, in_blks, deferred);
     d_out = upload_vec(alloc, out_blks, deferred);
