@@ -178,6 +178,26 @@ def test_su2_general_contraction_bf16_matches_dense(ctx, name, la, aa, ta, lb, a
     assert err <= 3e-3
 
 
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+def test_su2_general_contraction_with_tuples_of_20_blocks(ctx, compute, tol):
+    # A of six legs (spins 1/2 and 3/2) has label tuples of 20 blocks, so its
+    # recoupling into the GEMM form runs in the general recoupling instance,
+    # in BF16 compute writing BF16
+    from collections import Counter
+    say(f"case su2 general contraction, tuples of 20 blocks, {compute}")
+    h, hq = ((1,), (2,)), ((1, 3), (2, 1))
+    sa = _spec([h, hq, hq, hq, hq, hq], ("in", "in", "in", "out", "out", "out"))
+    sb = _spec([hq, hq, INT, WHOLE], ("in", "in", "out", "out"))
+    assert max(Counter(b.labels for b in T.blocks(sa)).values()) == 20
+    A, fa = _tensor(ctx, sa, 41)
+    B, fb = _tensor(ctx, sb, 42)
+    _, ref = K.contract_su2_dense(sa, fa, sb, fb, (4, 5), (0, 1))
+    C = ctx.contract(A, B, (4, 5), (0, 1), compute)
+    err = rel_err(host(C), ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= tol
+
+
 def test_su2_general_contraction_bf16_data(ctx):
     # BF16 operands (MERA isometry on an operator) need BF16 compute; the
     # reference takes the BF16-rounded entries
