@@ -122,7 +122,7 @@ struct SvdPlan {
     std::vector<int32_t> pair_start;   // prefix sums of the block pairs per sector
     int32_t max_kp = 0;                // largest (even) block count
     int64_t u_elems = 0, s_elems = 0, vt_elems = 0, w_elems = 0, q_elems = 0;
-    DevMemPtr d_probs, d_pairs, w, q, scale, shift, gpart, flag;
+    DevMemPtr d_probs, d_pairs, w, q, scale, shift, gpart, flag, lastrot;
     int32_t flag_host = 0;
     // polar mode: the products that turn U, S, Vt (kept in uv and s) into
     // W and P; tiles of the W products first
@@ -2113,6 +2113,7 @@ std::shared_ptr<SvdPlan> svd_plan_cached(sym_ctx* ctx, const sym_tensor* T, bool
         plan->w = alloc(static_cast<size_t>(plan->w_elems) * sizeof(double));
         plan->q = alloc(static_cast<size_t>(plan->q_elems) * sizeof(double));
         plan->flag = alloc(sizeof(int32_t));
+        plan->lastrot = alloc(static_cast<size_t>(std::max<int32_t>(1, 2 * plan->pair_start.back())) * sizeof(int32_t));
         plan->scale = alloc(plan->probs.size() * sizeof(double));
         if (eig) plan->shift = alloc(plan->probs.size() * sizeof(double));
         if (polar) {
@@ -2142,7 +2143,8 @@ void run_svd(const sym_tensor* T, SvdPlan& plan, double* U, double* S, double* V
                          plan.pair_start.back(), plan.max_kp, static_cast<double*>(plan.w->ptr),
                          static_cast<double*>(plan.q->ptr), U, S, Vt, static_cast<double*>(plan.scale->ptr),
                          plan.shift ? static_cast<double*>(plan.shift->ptr) : nullptr,
-                         static_cast<double*>(plan.gpart->ptr), static_cast<int32_t*>(plan.flag->ptr),
+                         static_cast<double*>(plan.gpart->ptr), static_cast<int32_t*>(plan.lastrot->ptr),
+                         static_cast<int32_t*>(plan.flag->ptr),
                          &plan.flag_host, max_sweeps, &done, stream));
     if (sweeps) *sweeps = done;
 }

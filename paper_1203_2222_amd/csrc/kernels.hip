@@ -1651,7 +1651,8 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
                                                      const int32_t* __restrict__ pair_start, int r,
                                                      double* __restrict__ Wg, double* __restrict__ Qg,
                                                      const double* __restrict__ scale, double* __restrict__ Gpart,
-                                                     int32_t* __restrict__ rotated) {
+                                                     int32_t* __restrict__ rotated, int32_t* __restrict__ lastrot,
+                                                     int gidx, int R) {
     constexpr int B = kSvdBlock, B2 = 2 * B, NP = B2 / 2;
     constexpr int XC = 4096 / B2;              // chunk entries: 16 loads per thread
     constexpr int NB4 = B2 / 4;                // 4 x 4 blocks of G per row
@@ -1680,6 +1681,14 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
     if (k < 2 || r >= nbp - 1) return;
     const int pi = pid - pair_start[lo];
     const int P = rr_player(pi, r, nbp), Qb = rr_player(nbp - 1 - pi, r, nbp);
+    // the pair met R rounds ago (same round of the previous sweep) and was
+    // left alone then; if neither block has rotated since, its Gram matrix
+    // is unchanged and the pair would again be left alone: skip it (both
+    // launches take the same decision, the rotation launch records the
+    // round in which a block last rotated)
+    int32_t* lr = lastrot + 2 * pair_start[lo];
+    const int prev = gidx - R;
+    if (prev >= 0 && lr[P] < prev && lr[Qb] < prev) return;
     auto col = [&](int i) { return i < B ? P * B + i : Qb * B + (i - B); };
     double* W = Wg + p.w_off;
     double* Qm = Qg + p.q_off;
@@ -1835,6 +1844,10 @@ __global__ __launch_bounds__(256) void k_svd_bround(const SvdProb* __restrict__ 
         if (!rot) break;
     }
     if (!s_any) return;
+    if (tid == 0) {
+        lr[P] = gidx;
+        lr[Qb] = gidx;
+    }
 
     // 3. vectors and rows of Q times V: thread (wave w, lane) makes entries
     //    x0 + lane + 64 v of the new vectors JW w .. JW w + JW - 1
@@ -1953,8 +1966,8 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 
 hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
-                      double* Vt, double* scale, double* shift, double* Gpart, int32_t* flag, int32_t* flag_host,
-                      int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s) {
+                      double* Vt, double* scale, double* shift, double* Gpart, int32_t* lastrot, int32_t* flag,
+                      int32_t* flag_host, int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s) {
     if (n_probs <= 0) return hipSuccess;
     dim3 lgrid(256, static_cast<unsigned>(n_probs));
     hipLaunchKernelGGL(k_fill_i32, dim3(static_cast<unsigned>((2 * n_probs + 63) / 64)), dim3(64), 0, s,
@@ -1965,6 +1978,8 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
     else
         hipLaunchKernelGGL((k_svd_load<uint16_t>), lgrid, dim3(256), 0, s, static_cast<const uint16_t*>(src), probs, W,
                            Q, scale);
+    hipLaunchKernelGGL(k_fill_i32, dim3(static_cast<unsigned>((2 * n_pairs + 255) / 256)), dim3(256), 0, s, lastrot,
+                       2 * n_pairs, -1);
     if (shift)
         hipLaunchKernelGGL(k_eig_shift, dim3(static_cast<unsigned>(n_probs)), dim3(256), 0, s, probs, W, scale, shift);
     hipError_t e = hipGetLastError();
@@ -1975,10 +1990,11 @@ hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, cons
     while (sweep < max_sweeps && max_kp > 1 && n_pairs > 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flag, 1, 0);
         for (int r = 0; r < max_kp - 1; ++r) {
+            const int gidx = sweep * (max_kp - 1) + r;
             hipLaunchKernelGGL(k_svd_bround<0>, rgrid, dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, scale, Gpart,
-                               flag);
+                               flag, lastrot, gidx, max_kp - 1);
             hipLaunchKernelGGL(k_svd_bround<1>, rgrid, dim3(256), 0, s, probs, n_probs, pair_start, r, W, Q, scale, Gpart,
-                               flag);
+                               flag, lastrot, gidx, max_kp - 1);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -260,8 +260,8 @@ constexpr int kSvdSlices = 2;     // workgroups per pair of blocks (slices of th
 // singular values minus c and U holds the eigenvectors; Vt may be NULL.
 hipError_t launch_svd(int src_dtype, const void* src, const SvdProb* probs, const int32_t* pair_start,
                       int32_t n_probs, int32_t n_pairs, int32_t max_kp, double* W, double* Q, double* U, double* S,
-                      double* Vt, double* scale, double* shift, double* Gpart, int32_t* flag, int32_t* flag_host,
-                      int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s);
+                      double* Vt, double* scale, double* shift, double* Gpart, int32_t* lastrot, int32_t* flag,
+                      int32_t* flag_host, int32_t max_sweeps, int32_t* sweeps_done, hipStream_t s);
 // Polar factors from a block SVD: per sector one or two FP64 products
 // C = A diag(d) B with A(i, l) = a[a_off + i as0 + l as1] and
 // B(l, j) = a[b_off + l bs0 + j bs1], both read from one buffer (U then Vt),
